@@ -1,0 +1,193 @@
+"""Benchmark: time and QPs/s to relKKT <= 1e-4 with restarted PDHCG on one GPU.
+
+Default workload (one step = one full solve of the hot path: stacked [Q|A']
+pass, inexact CG, projected dual step, averaging, restart evaluation):
+random sparse convex QP with n = 100 000, m = 50 000, Q = R'R + 1e-2 I
+(R 5e4 x 1e5 at density 2e-5), A 5e4 x 1e5 at density 2e-4, N(0,1) values,
+b = A x0 + U[0,1]; FP32 products with FP64 reductions and an FP64-certified
+relKKT; cold start from (0, 0).  The problem is uploaded and set up
+(pdhcg_create: A' build, plan, ||A|| power iteration) before the timed region.
+
+Prints one JSON line.  Besides the contract fields it carries the roofline
+of the dominant kernel (the persistent solve kernel, timed with HIP events on
+its own stream), the FP64 CPU oracle timed on this host (a bounded sample),
+standalone SpMV bandwidths, and the in-run comparison with CG capped at one
+step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--precision", type=int, default=1)
+    ap.add_argument("--num-blocks", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip SpMV and CG-cap-1 side measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (for scaling the FETCH/WRITE counters)")
+    return ap.parse_args()
+
+
+def workload():
+    from paper_2405_16160_amd import instances as I
+    return I.random_qp(100_000, 50_000, 50_000, 2e-5, 2e-4, family=2, instance=0)
+
+
+def csr_bytes(nnz, nrows, ncols, sv, sx):
+    """Compulsory bytes of y = M x: matrix once (values + int32 columns +
+    int32 row pointers), x once, y once."""
+    return nnz * (sv + 4) + 4 * (nrows + 1) + ncols * sx + nrows * sx
+
+
+def solve_bytes(qp, r, precision):
+    """Algorithmic HBM bytes of one solve, from the counts the solver reports.
+    Per iteration: the n-side pass [Q|A'][x;y] in FP64 (r0 and relKKT), the
+    dual step y = proj(y + sigma(A(2x+ - x) - b)) with its vectors, and the
+    average update; per CG step nnz(Q)(sv+4) + 4(n+1) + 11 n sx (product, dot,
+    axpy and direction update with their vectors); per restart evaluation the
+    n-side pass and an A product at the average."""
+    n, m = qp.n, qp.m
+    nq, na = qp.Q.nnz, qp.A.nnz
+    sv = sx = 4 if precision == 1 else 8
+    a1 = (nq + na) * 12 + 8 * (n + 1) + (n + m) * 8 + 2 * n * 8           # matrices, x, y, c, r
+    dual = csr_bytes(na, m, n, sv, sx) - m * sx + 7 * m * 8 + 3 * n * 8   # + y, ax, b, ya (r/w); xa update
+    cg = nq * (sv + 4) + 4 * (n + 1) + 11 * n * sx
+    ev = (nq + na) * 12 + 8 * (n + 1) + (n + m) * 8 + n * 8 + csr_bytes(na, m, n, 8, 8) + 2 * m * 8
+    return r["iters"] * (a1 + dual) + r["cg_iters_total"] * cg + r["kkt_evals"] * ev
+
+
+def cpu_baseline(qp, tol):
+    """FP64 CPU oracle on this host: one full solve of the same instance to
+    the same tolerance (about 5-15 s of CPU work)."""
+    from oracle import oracle as O
+    O.build()
+    t = time.perf_counter()
+    r = O.solve(qp, O.Settings(tol=tol))
+    dt = time.perf_counter() - t
+    return {"value": 1.0 / dt, "unit": "QPs/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"one full FP64 solve of the benchmark instance to relKKT <= {tol:g} "
+                      f"({r.iters} iterations, {r.cg_steps} CG steps, {dt:.2f} s)",
+            "seconds_per_solve": dt, "status": r.status}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
+              "the solver does not shard a QP across GPUs.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2405_16160_amd import pdhcg
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 8, "copies": 3}))
+        return
+
+    qp = workload()
+    settings = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, num_blocks=args.num_blocks)
+    solver = pdhcg.Solver(qp, settings)
+    plan = solver.plan_info()
+    for _ in range(args.warmup):
+        x, y, r = solver.solve()
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, y, r = solver.solve()
+        results.append(r)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert all(rr["status"] == 0 for rr in results), [rr["status_name"] for rr in results]
+    r = results[-1]
+    kernel_s = float(np.mean([rr["kernel_s"] for rr in results]))
+    launches = 1   # one solve-kernel launch per solve at this size (5000-iteration chunks)
+    bytes_alg = solve_bytes(qp, r, args.precision)
+    achieved = bytes_alg / kernel_s / 1e9
+    line = {
+        "metric": "time & QPs/s to rel. KKT<=1e-4 (batched/warm-start vs plain); SpMV HBM GB/s",
+        "value": args.steps / dt,
+        "unit": "QPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain PDHCG, random sparse convex QP n=1e5 m=5e4 (R 5e4x1e5 at 2e-5, "
+                               "A at 2e-4), FP32 products + FP64 reductions, cold start, tol 1e-4",
+                   "n": qp.n, "m": qp.m, "nnz_Q": qp.Q.nnz, "nnz_A": qp.A.nnz, "tol": args.tol,
+                   "precision": "fp32-products/fp64-reductions" if args.precision == 1 else "fp64",
+                   "plan": plan},
+        "solve": {"iters": r["iters"], "cg_steps": r["cg_iters_total"], "restarts": r["restarts"],
+                  "kkt_evals": r["kkt_evals"], "rel_kkt": r["rel_kkt"], "setup_s": r["setup_s"],
+                  "kernel_ms": kernel_s * 1e3, "launches_per_solve": launches},
+        "roofline": {"kernel": "pdhcg_solve_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_alg / launches},
+    }
+    if not args.no_extras:
+        extras = {}
+        rng = np.random.default_rng(0)
+        xn, xm = rng.standard_normal(qp.n), rng.standard_normal(qp.m)
+        for which, name, nnz, nr, nc, v in ((0, "Q", qp.Q.nnz, qp.n, qp.n, xn), (1, "A", qp.A.nnz, qp.m, qp.n, xn),
+                                            (2, "At", qp.A.nnz, qp.n, qp.m, xm)):
+            for prec in (0, 1):
+                reps = 200
+                solver.spmv(which, v, precision=prec, repeats=5)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                solver.spmv(which, v, precision=prec, repeats=reps)
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) * 1e3 / reps
+                sv = sx = 4 if prec else 8
+                gbs = csr_bytes(nnz, nr, nc, sv, 8) / (us * 1e-6) / 1e9
+                extras[f"spmv_{name}_{'fp32' if prec else 'fp64'}"] = {"us": us, "GB/s": gbs,
+                                                                        "frac": gbs / HBM_PEAK_GBS}
+        # in-run comparison: CG capped at one step (linearised primal step)
+        s1 = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, num_blocks=args.num_blocks,
+                            max_cg_iters=1, cg_rule=1, max_iters=200_000)
+        solver.set_settings(s1)
+        t = time.perf_counter()
+        _, _, r1 = solver.solve()
+        torch.cuda.synchronize()
+        extras["cg_cap_1"] = {"seconds": time.perf_counter() - t, "iters": r1["iters"], "status": r1["status_name"],
+                              "speedup_of_pdhcg": (time.perf_counter() - t) / (dt / args.steps)}
+        solver.set_settings(settings)
+        line["extras"] = extras
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(qp, args.tol)
+    print(json.dumps(line), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

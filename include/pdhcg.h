@@ -1,0 +1,162 @@
+/*
+ * pdhcg.h -- C ABI of the MI355X (gfx950) restarted PDHCG library.
+ *
+ * Solves the convex QP  min 1/2 x'Qx + c'x  s.t.  Ax <= b  (problem (1) of
+ * Huang et al., "Restarted Primal-Dual Hybrid Conjugate Gradient Method for
+ * Large-Scale Quadratic Programming") with Alg. 1 (restarted PDHCG): each
+ * iteration solves the proximal primal subproblem inexactly by conjugate
+ * gradient, then takes the projected dual step at the extrapolated point,
+ * averages the iterates, and restarts adaptively on the relative KKT error
+ * (Sec. 4).  Every step of the iteration runs in the library's own HIP
+ * kernels on the GPU; the library allocates its device workspace itself.
+ *
+ * Conventions for every function:
+ *  - Return 0 on success or a negative error code (PDHCG_ERR_*).  No C++
+ *    exception crosses this boundary.  pdhcg_last_error() gives a message
+ *    for the last failure on the calling thread.
+ *  - Solve outcomes (converged, iteration or time limit, non-finite values)
+ *    are not errors: they are reported in pdhcg_result.status.
+ *  - The caller owns every buffer it passes.  pdhcg_create copies the problem
+ *    data, so inputs may be freed or reused after it returns.
+ *  - Pointers flagged "on_device" point to device memory of the current HIP
+ *    device (for example the data_ptr() of a torch tensor); otherwise they are
+ *    host pointers.  All device work is issued on the stream given to
+ *    pdhcg_create; functions return after that stream has finished the work.
+ *  - A handle is not thread-safe.  Separate handles are independent.
+ */
+#ifndef PDHCG_H
+#define PDHCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PDHCG_OK = 0,
+    PDHCG_ERR_INVALID_ARGUMENT = -1, /* bad shape, unsorted/duplicate/out-of-range columns,
+                                        rowptr not monotone, Q not exactly symmetric, sizes
+                                        beyond int32 indexing */
+    PDHCG_ERR_OUT_OF_MEMORY = -2,
+    PDHCG_ERR_HIP = -3               /* a HIP runtime call or a kernel failed */
+};
+
+enum {
+    PDHCG_STATUS_OPTIMAL = 0,        /* relKKT <= tol_rel_kkt (Sec. 4 progress metric) */
+    PDHCG_STATUS_ITERATION_LIMIT = 1,
+    PDHCG_STATUS_TIME_LIMIT = 2,
+    PDHCG_STATUS_NUMERICAL_ERROR = 3 /* NaN/Inf appeared; the epoch's anchor point is returned */
+};
+
+/* Sparse matrix in CSR form: row i holds entries rowptr[i] .. rowptr[i+1]-1,
+ * column indices strictly increasing within a row.  rowptr has nrows+1 entries
+ * with rowptr[0] = 0 and rowptr[nrows] = nnz.  Values are FP64. */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    const int64_t* rowptr;
+    const int32_t* col;
+    const double* val;
+    int32_t on_device;               /* 1: the three arrays are device pointers */
+} pdhcg_csr;
+
+/* Solver settings.  pdhcg_default_settings fills the defaults noted here. */
+typedef struct {
+    double tol_rel_kkt;              /* 1e-4; stop when relKKT <= tol (Sec. 4, progress metric) */
+    int64_t max_iters;               /* 100000; cap on PDHCG iterations (inner steps, all epochs) */
+    int32_t max_cg_iters;            /* 100; N, the CG step cap per iteration (Sec. 2) */
+    int32_t cg_rule;                 /* 0: adaptive epsilon_k tolerance (Sec. 4), 1: always N steps
+                                        (PDHCG-fixed, Thm 1); N = 1 gives a linearised primal step */
+    double cg_eps_factor;            /* 0.05: epsilon_k = epsilon_{k-1} + 0.05 relKKT (Sec. 4) */
+    double beta_sufficient;          /* 0.2  (Sec. 4, adaptive restart) */
+    double beta_necessary;           /* 0.8 */
+    double beta_artificial;          /* 0.2 */
+    int32_t restart_to;              /* 0: better of current and average, 1: average (Alg. 1) */
+    int32_t eval_period;             /* 64: iterations between restart evaluations */
+    double primal_weight_theta;      /* 0.2 (Sec. 4, primal weight adjustment); 0 freezes omega */
+    double primal_weight_init;       /* 1.0 */
+    double step_eta_factor;          /* 0.5: eta = 0.5/||A||_2, tau = eta/omega, sigma = eta*omega
+                                        (sigma = tau = 1/(2||A||) at omega = 1, Thm 2) */
+    int32_t power_iters;             /* 100: power-iteration steps for ||A||_2 */
+    int32_t precision;               /* 0: FP64 throughout.  1: FP32 matrix values and FP32 copies
+                                        of the vectors in the CG and dual-step products, FP64
+                                        accumulation, FP64 scalars, FP64 relKKT; termination is
+                                        certified against the FP64 data */
+    double time_limit_s;             /* 0 = none */
+    int32_t num_blocks;              /* 0 = planner's choice; else workgroups of the solve kernel */
+    int32_t verbose;                 /* 0 = silent */
+} pdhcg_settings;
+
+typedef struct {
+    int32_t status;                  /* PDHCG_STATUS_* */
+    int32_t returned_average;        /* 1 if the running average was returned */
+    double rel_primal, rel_dual, rel_gap, rel_kkt;  /* of the returned point, FP64 data */
+    double primal_obj, dual_obj;     /* 1/2 x'Qx + c'x and -1/2 x'Qx - b'y */
+    int64_t iters;                   /* PDHCG iterations */
+    int64_t cg_iters_total;          /* CG steps over all iterations */
+    int64_t restarts;
+    double norm_A;                   /* power-iteration estimate of ||A||_2 */
+    double setup_s;                  /* wall time of pdhcg_create */
+    double solve_s;                  /* wall time of the solve */
+    double kernel_s;                 /* device time of the solve kernel launches (HIP events on the
+                                        handle's stream) */
+    int64_t kkt_evals;               /* restart evaluations (relKKT of the average) performed */
+} pdhcg_result;
+
+typedef struct pdhcg_handle pdhcg_handle;
+
+void pdhcg_default_settings(pdhcg_settings* s);
+
+/* Copy the problem to the device, build A' (CSR), plan the kernels' row
+ * partitions, and estimate ||A||_2.  Q (n x n) must hold both triangles and
+ * be exactly symmetric; A is m x n (m may be 0).  b (m) and c (n) are FP64,
+ * on the device when vec_on_device = 1.  hip_stream may be NULL (the default
+ * stream).  On success *h owns all device memory of the problem. */
+int pdhcg_create(pdhcg_handle** h, const pdhcg_csr* Q, const pdhcg_csr* A, const double* b,
+                 const double* c, int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream);
+
+/* Replace the settings of a handle (e.g. a different tolerance or CG cap). */
+int pdhcg_set_settings(pdhcg_handle* h, const pdhcg_settings* s);
+
+/* Replace b (length m) of an existing problem, keeping Q, A, c and the plan
+ * (used for a family of QPs that differ only in b). */
+int pdhcg_set_b(pdhcg_handle* h, const double* b, int32_t vec_on_device);
+
+/* Run restarted PDHCG from (x0, y0) (NULL = zero; y0 is projected onto
+ * y >= 0) and write the returned point to x_out (n) and y_out (m).  Vectors
+ * are device pointers when vec_on_device = 1.  r may be NULL. */
+int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_out, double* y_out,
+                int32_t vec_on_device, pdhcg_result* r);
+
+/* Solve `count` independent QPs (host CSR and host vectors).  Instances are
+ * packed once, then solved by one workgroup per instance in a persistent
+ * kernel; every instance gets its own status in rs[i].  x0s/y0s may be NULL
+ * (cold start) or hold NULL entries. */
+int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
+                      const double* const* bs, const double* const* cs,
+                      const double* const* x0s, const double* const* y0s,
+                      double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                      const pdhcg_settings* s, void* hip_stream);
+
+/* y = M x with the library's SpMV kernel on the handle's device copy of
+ * M = Q (which = 0), A (1) or A' (2), in FP64 (precision 0) or with FP32
+ * values and an FP32 copy of x (precision 1, FP64 accumulation).  x and y are
+ * FP64 device pointers.  repeats > 1 launches the same product back to back
+ * (for timing).  Test and measurement entry point. */
+int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* x, double* y,
+               int32_t repeats);
+
+/* Grid size and row-split parameters the planner chose (for reporting). */
+int pdhcg_plan_info(const pdhcg_handle* h, int32_t* num_blocks, int32_t* group_n, int32_t* group_q,
+                    int32_t* group_m, int64_t* long_rows);
+
+void pdhcg_destroy(pdhcg_handle* h);
+
+const char* pdhcg_error_string(int code);
+const char* pdhcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDHCG_H */

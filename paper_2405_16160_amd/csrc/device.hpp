@@ -1,0 +1,186 @@
+// Device building blocks: NaN-propagating max, wavefront/workgroup
+// reductions, a grid barrier for cooperative launches, and the row-split CSR
+// row reduction used by every sparse product of the solver.
+#pragma once
+#include "internal.hpp"
+
+namespace pdhcg {
+
+// max that propagates NaN (the hardware max returns the non-NaN operand, which
+// would hide a diverged iterate from the termination test)
+__device__ __forceinline__ double maxp(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
+}
+
+__device__ __forceinline__ double group_sum(double v, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, width);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = kWave >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = kWave >> 1; off > 0; off >>= 1) v = maxp(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Workgroup reduction of NS sums and NM maxima at once.  Every thread ends
+// with the results; the combination order is fixed, so equal inputs give
+// bit-equal outputs in every workgroup.  lds must hold kWaves*(NS+NM) doubles.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce(double* s, double* mx, double* lds) {
+  constexpr int W = NS + NM;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s[k] = wave_sum(s[k]);
+#pragma unroll
+  for (int k = 0; k < NM; ++k) mx[k] = wave_max(mx[k]);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) lds[w * W + k] = s[k];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) lds[w * W + NS + k] = mx[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double a = lds[k];
+    for (int j = 1; j < kWaves; ++j) a += lds[j * W + k];
+    s[k] = a;
+  }
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    double a = lds[NS + k];
+    for (int j = 1; j < kWaves; ++j) a = maxp(a, lds[j * W + NS + k]);
+    mx[k] = a;
+  }
+  __syncthreads();
+}
+
+// Sum of per-workgroup partials part[slot*nb + j], j < nb, reduced in a
+// fixed order (identical in every workgroup).  NS slots are summed, NM slots
+// maximised; slots are given by index lists.
+template <int NS, int NM>
+__device__ __forceinline__ void reduce_partials(const double* part, int nb, const int* sum_slots,
+                                                const int* max_slots, double* s, double* mx, double* lds) {
+#pragma unroll
+  for (int k = 0; k < NS; ++k) s[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NM; ++k) mx[k] = 0.0;
+  for (int j = threadIdx.x; j < nb; j += kBlock) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s[k] += part[sum_slots[k] * nb + j];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) mx[k] = maxp(mx[k], part[max_slots[k] * nb + j]);
+  }
+  block_reduce<NS, NM>(s, mx, lds);
+}
+
+// ------------------------------------------------------------ grid barrier
+//
+// Hierarchical arrival counters: workgroup w arrives on group counter w % 8
+// (one per XCD under the round-robin dispatch of workgroups), the last arrival
+// of a group arrives on the global counter, and the last group publishes the
+// new generation.  Waiters poll the generation with relaxed loads and take one
+// acquire fence at the end; arrivals take one release fence.  Counters grow
+// monotonically within a launch (64-bit), so no reset race exists.  Every wait
+// is bounded by a wall-clock limit: on expiry the workgroup raises the abort
+// word and returns false, and every other waiter then returns false too.
+namespace bar {
+constexpr int kCount = 0, kGen = 32, kAbort = 64, kGroup = 96;  // word offsets (256-byte apart)
+constexpr int kWords = kGroup + 8 * 32;
+}  // namespace bar
+
+#define PDHCG_LD(p) __hip_atomic_load((p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+#define PDHCG_ST(p, v) __hip_atomic_store((p), (v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+#define PDHCG_ADD(p, v) __hip_atomic_fetch_add((p), (v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+
+struct GridSync {
+  uint64_t* w;
+  uint32_t nb;
+  uint64_t epoch;
+  static constexpr uint64_t kTimeoutTicks = 500000000ull;  // 5 s of the 100 MHz wall clock
+
+  __device__ bool sync() {
+    __shared__ int ok_s;
+    __syncthreads();
+    ++epoch;
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      if (nb > 1) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t g = blockIdx.x & 7u;
+        const uint32_t ngroups = nb < 8u ? nb : 8u;
+        const uint64_t gsize = (nb - g + 7u) / 8u;
+        const uint64_t a = PDHCG_ADD(&w[bar::kGroup + 32 * g], 1ull);
+        if (a == gsize * epoch - 1) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          const uint64_t t = PDHCG_ADD(&w[bar::kCount], 1ull);
+          if (t == ngroups * epoch - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            PDHCG_ST(&w[bar::kGen], epoch);
+          }
+        }
+        const uint64_t t0 = wall_clock64();
+        while (PDHCG_LD(&w[bar::kGen]) < epoch) {
+          if (PDHCG_LD(&w[bar::kAbort]) != 0ull) { ok = 0; break; }
+          if (wall_clock64() - t0 > kTimeoutTicks) {
+            PDHCG_ST(&w[bar::kAbort], 1ull);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+  }
+};
+
+// ------------------------------------------------------- row-split products
+
+// Value loaders: FP64 or FP32 matrix values, FP64 or FP32 gathered vectors;
+// products are accumulated in FP64.
+template <typename V>
+__device__ __forceinline__ double ldv(const V* p, int k) { return (double)p[k]; }
+
+// sum_k M[i,k] * g(col[k]) for the entries [beg, end) of one row, computed by
+// `width` lanes starting at lane `lane` (partial sums; reduce with group_sum)
+template <typename V, typename Gather>
+__device__ __forceinline__ double row_partial(const int32_t* col, const V* val, int beg, int end, int lane,
+                                              int width, const Gather& g) {
+  double s = 0.0;
+  for (int k = beg + lane; k < end; k += width) s += ldv(val, k) * g(col[k]);
+  return s;
+}
+
+template <typename T>
+struct GatherVec {
+  const T* v;
+  __device__ __forceinline__ double operator()(int j) const { return (double)v[j]; }
+};
+
+// p_j = r_j + beta p_prev_j, formed at gather time (the CG direction update is
+// folded into the next product, which saves a grid barrier per CG step)
+template <typename T>
+struct GatherDir {
+  const T* r;
+  const T* pp;
+  double beta;
+  int first;
+  __device__ __forceinline__ double operator()(int j) const {
+    return first ? (double)r[j] : (double)r[j] + beta * (double)pp[j];
+  }
+};
+
+}  // namespace pdhcg

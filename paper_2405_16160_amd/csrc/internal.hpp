@@ -1,0 +1,128 @@
+// Internal definitions shared by the host library and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdhcg {
+
+constexpr int kBlock = 256;       // threads per workgroup of every solver kernel
+constexpr int kWave = 64;         // CDNA wavefront
+constexpr int kWaves = kBlock / kWave;
+constexpr int kLongRow = 1024;    // rows longer than this are reduced by the whole workgroup
+
+// Device CSR with 32-bit indices; val32 is an FP32 copy of val (or null).
+struct DevMat {
+  int32_t nrows, ncols;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  const float* val32;
+};
+
+// Static partition of a row space over the workgroups of a solve kernel.
+// Workgroup w owns rows [bounds[w], bounds[w+1]); rows of that range longer
+// than kLongRow are listed in long_rows[long_ptr[w] .. long_ptr[w+1]) and are
+// reduced cooperatively by the whole workgroup; the others are reduced by
+// groups of `group` lanes (a power of two <= 64).
+struct Part {
+  const int32_t* bounds;
+  const int32_t* long_ptr;
+  const int32_t* long_rows;
+  int32_t group;
+};
+
+// Partial-result slots.  Every workgroup writes one value per slot; after a
+// grid barrier every workgroup reduces all of them in the same fixed order,
+// so every workgroup holds bit-identical scalars and takes the same decisions.
+enum Slot {
+  // n-side pass at the current point: g = Qx + A'y + c
+  S_GG = 0,      // sum g^2                (= rho_0 of CG: r_0 = -g)
+  S_MG,          // max |g|
+  S_MQX,         // max |Qx|
+  S_MATY,        // max |A'y|
+  S_XQX,         // sum x.Qx
+  S_CX,          // sum c.x
+  // m-side pass at the current point: u = Ax
+  S_MVIOL,       // max (u - b)^+
+  S_MAX,         // max |u|
+  S_BY,          // sum b.y
+  // the same nine quantities at the running average
+  S_AVG0,
+  S_AVG_END = S_AVG0 + 9,
+  // CG and restart
+  S_PQ = S_AVG_END,  // sum p.q
+  S_RR,          // sum r.r
+  S_DX,          // sum (x_c - x_anchor)^2
+  S_DY,          // sum (y_c - y_anchor)^2
+  S_FLAG,        // max of a per-workgroup flag (time limit)
+  S_PW,          // power iteration: sum w^2
+  NSLOT
+};
+
+// Scalar state of a solve; every workgroup keeps an identical copy in
+// registers, workgroup 0 stores it here when a launch ends.
+struct SolverState {
+  int64_t k;            // iterations in the current epoch
+  int64_t k_total;      // iterations in all epochs
+  int64_t cg_total;     // CG steps
+  int64_t restarts;
+  int64_t evals;        // restart evaluations
+  double eps;           // CG tolerance epsilon_k of the current epoch
+  double K_anchor;      // relKKT of the epoch's starting point (NaN: not yet known)
+  double K_prev;        // candidate relKKT at the previous evaluation of this epoch
+  double omega, tau, sigma;
+  int32_t done;         // 1 once a final status is set
+  int32_t status;
+  int32_t returned_average;
+  int32_t mixed;        // 1 while FP32 products are in use
+  double r_p, r_d, r_g, kkt, pobj, dobj;  // of the returned point
+  uint64_t t_start;     // wall_clock64() at the start of the solve
+};
+
+struct SolveParams {
+  DevMat Q, A, At;
+  const double* b;
+  const double* c;
+  int32_t n, m;
+  // iterate state (FP64)
+  double *x, *y, *xa, *ya, *ax, *ax_avg, *x_anc, *y_anc;
+  // CG work vectors (FP64)
+  double *r, *p0, *p1, *q;
+  // FP32 copies used by the mixed-precision products
+  float *x32, *r32, *p32_0, *p32_1;
+  double* part;         // [NSLOT][nb]
+  uint64_t* bar;        // grid barrier words (zeroed before each launch)
+  SolverState* st;
+  Part pn1, pcg, pm;
+  // settings
+  double tol, eps_factor, beta_suf, beta_nec, beta_art, theta, eta;
+  int64_t max_iters;
+  int64_t iters_this_launch;   // bound on iterations per launch
+  uint64_t time_limit_ticks;   // 0 = none; wall_clock64() ticks
+  int32_t max_cg, cg_rule, restart_to, eval_period;
+  int32_t mixed_allowed;
+};
+
+struct PowerParams {
+  DevMat A, At;
+  double* v;     // n
+  double* w;     // n
+  double* u;     // m
+  double* part;
+  uint64_t* bar;
+  double* out;   // [0] = ||A|| estimate
+  Part pn, pm;
+  int32_t iters;
+};
+
+hipError_t launch_solve(const SolveParams& p, int nb, double nb_inf, double nc_inf, hipStream_t s);
+hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s);
+hipError_t launch_init_point(const SolveParams& p, const double* x0, const double* y0, int nb, hipStream_t s);
+hipError_t launch_spmv(const DevMat& M, const Part& pt, int nb, int precision, const double* x, float* x32,
+                       double* y, hipStream_t s);
+hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+// workgroups per CU that the persistent kernels can keep resident (the
+// smaller of the solve and power kernels)
+hipError_t solve_occupancy(int* per_cu);
+
+}  // namespace pdhcg

@@ -1,0 +1,709 @@
+// Persistent cooperative kernel for one QP: the whole restarted PDHCG loop
+// (Alg. 1 with the practical rules of Sec. 4) runs on the device.  Each
+// workgroup owns fixed row ranges of Q, A' and A; phases are separated by
+// grid barriers; scalars (CG alpha/beta/rho, relKKT, restart tests, step
+// sizes) are FP64 and computed redundantly by every workgroup from the same
+// per-workgroup partials, so every workgroup takes the same branch.
+#include <math.h>
+
+#include "device.hpp"
+
+namespace pdhcg {
+
+namespace {
+
+struct Block {
+  int b, nb, tid;
+};
+
+__device__ __forceinline__ double rel_div(double num, double den) { return num / (1.0 + den); }
+
+// (v)^+ that keeps a NaN visible
+__device__ __forceinline__ double pos_part(double v) { return v > 0.0 ? v : (v == v ? 0.0 : v); }
+
+// ------------------------------------------------------------------ phases
+
+// n-side product at (xv, yv): g = Q xv + A' yv + c, row by row over the
+// workgroup's rows of the partition `pt`.  Writes r = -g (and its FP32 copy)
+// when r != null and stores the six n-side partials at slot0.
+__device__ void phase_nside(const SolveParams& P, const Part& pt, const Block& B, const double* xv,
+                            const double* yv, double* r, float* r32, int slot0, double* lds) {
+  const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
+  const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
+  double s[3] = {0.0, 0.0, 0.0};   // g.g, x.Qx, c.x
+  double mx[3] = {0.0, 0.0, 0.0};  // |g|, |Qx|, |A'y|
+  GatherVec<double> gx{xv}, gy{yv};
+  auto epi = [&](int i, double qx, double aty) {
+    const double ci = P.c[i];
+    const double g = qx + aty + ci;
+    if (r) {
+      r[i] = -g;
+      if (r32) r32[i] = (float)(-g);
+    }
+    s[0] += g * g;
+    s[1] += xv[i] * qx;
+    s[2] += ci * xv[i];
+    mx[0] = maxp(mx[0], fabs(g));
+    mx[1] = maxp(mx[1], fabs(qx));
+    mx[2] = maxp(mx[2], fabs(aty));
+  };
+  for (int base = r0; base < r1; base += ng) {
+    const int i = base + B.tid / G;
+    const bool act = i < r1;
+    int qb = 0, qe = 0, tb = 0, te = 0;
+    if (act) {
+      qb = P.Q.rowptr[i];
+      qe = P.Q.rowptr[i + 1];
+      if (P.m > 0) {
+        tb = P.At.rowptr[i];
+        te = P.At.rowptr[i + 1];
+      }
+    }
+    const bool use = act && (qe - qb) + (te - tb) <= kLongRow;
+    double sq = 0.0, st = 0.0;
+    if (use) {
+      sq = row_partial(P.Q.col, P.Q.val, qb, qe, lane, G, gx);
+      st = row_partial(P.At.col, P.At.val, tb, te, lane, G, gy);
+    }
+    sq = group_sum(sq, G);
+    st = group_sum(st, G);
+    if (use && lane == 0) epi(i, sq, st);
+  }
+  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+    const int i = pt.long_rows[t];
+    double v[2] = {row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gx),
+                   P.m > 0 ? row_partial(P.At.col, P.At.val, P.At.rowptr[i], P.At.rowptr[i + 1], B.tid, kBlock, gy)
+                           : 0.0};
+    double dummy[1] = {0.0};
+    block_reduce<2, 0>(v, dummy, lds);
+    if (B.tid == 0) epi(i, v[0], v[1]);
+  }
+  block_reduce<3, 3>(s, mx, lds);
+  if (B.tid == 0) {
+    P.part[(slot0 + S_GG) * B.nb + B.b] = s[0];
+    P.part[(slot0 + S_XQX) * B.nb + B.b] = s[1];
+    P.part[(slot0 + S_CX) * B.nb + B.b] = s[2];
+    P.part[(slot0 + S_MG) * B.nb + B.b] = mx[0];
+    P.part[(slot0 + S_MQX) * B.nb + B.b] = mx[1];
+    P.part[(slot0 + S_MATY) * B.nb + B.b] = mx[2];
+  }
+}
+
+// m-side product u = A xg over the workgroup's rows of pm, with a per-row
+// epilogue epi(i, u) that returns nothing and accumulates the three m-side
+// partials (max (u-b)^+, max |u|, sum b.y) through the references given.
+template <typename V, typename Tx, typename Epi>
+__device__ void mside_rows(const SolveParams& P, const Block& B, const V* aval, const Tx* xg, double* lds,
+                           Epi epi) {
+  const Part& pt = P.pm;
+  const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
+  const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
+  GatherVec<Tx> gx{xg};
+  for (int base = r0; base < r1; base += ng) {
+    const int i = base + B.tid / G;
+    const bool act = i < r1;
+    int ab = 0, ae = 0;
+    if (act) {
+      ab = P.A.rowptr[i];
+      ae = P.A.rowptr[i + 1];
+    }
+    const bool use = act && (ae - ab) <= kLongRow;
+    double su = use ? row_partial(P.A.col, aval, ab, ae, lane, G, gx) : 0.0;
+    su = group_sum(su, G);
+    if (use && lane == 0) epi(i, su);
+  }
+  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+    const int i = pt.long_rows[t];
+    double v[1] = {row_partial(P.A.col, aval, P.A.rowptr[i], P.A.rowptr[i + 1], B.tid, kBlock, gx)};
+    double dummy[1] = {0.0};
+    block_reduce<1, 0>(v, dummy, lds);
+    if (B.tid == 0) epi(i, v[0]);
+  }
+}
+
+__device__ void store_mside(const SolveParams& P, const Block& B, int slot0, double* s1, double* mx, double* lds) {
+  block_reduce<1, 2>(s1, mx, lds);
+  if (B.tid == 0) {
+    P.part[(slot0 + S_MVIOL) * B.nb + B.b] = mx[0];
+    P.part[(slot0 + S_MAX) * B.nb + B.b] = mx[1];
+    P.part[(slot0 + S_BY) * B.nb + B.b] = s1[0];
+  }
+}
+
+// ax = A x and the m-side partials of the current point (start of a solve)
+__device__ void phase_ax(const SolveParams& P, const Block& B, double* lds) {
+  double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
+  mside_rows(P, B, P.A.val, P.x, lds, [&](int i, double u) {
+    P.ax[i] = u;
+    mx[0] = maxp(mx[0], pos_part(u - P.b[i]));
+    mx[1] = maxp(mx[1], fabs(u));
+    s1[0] += P.b[i] * P.y[i];
+  });
+  store_mside(P, B, 0, s1, mx, lds);
+}
+
+// relKKT pieces of the average: n-side at (xa, ya), m-side u = A xa (kept in ax_avg)
+__device__ void phase_eval_avg(const SolveParams& P, const Block& B, double* lds) {
+  phase_nside(P, P.pn1, B, P.xa, P.ya, nullptr, nullptr, S_AVG0, lds);
+  double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
+  mside_rows(P, B, P.A.val, P.xa, lds, [&](int i, double u) {
+    P.ax_avg[i] = u;
+    mx[0] = maxp(mx[0], pos_part(u - P.b[i]));
+    mx[1] = maxp(mx[1], fabs(u));
+    s1[0] += P.b[i] * P.ya[i];
+  });
+  store_mside(P, B, S_AVG0, s1, mx, lds);
+}
+
+// CG product: p = r + beta p_prev on the owned rows (FP64, stored), and
+// q = (Q + I/tau) p with p gathered through GatherDir; partial p.q.
+template <typename V, typename T>
+__device__ void phase_cg_spmv(const SolveParams& P, const Block& B, const V* qval, const T* rg, const T* ppg,
+                              const double* pprev, double* pcur, float* pcur32, double beta, int first,
+                              double inv_tau, double* lds) {
+  const Part& pt = P.pcg;
+  const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
+  const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
+  GatherDir<T> gp{rg, ppg, beta, first};
+  double s[1] = {0.0};
+  auto epi = [&](int i, double qp) {
+    const double pi = first ? P.r[i] : P.r[i] + beta * pprev[i];
+    const double qi = qp + pi * inv_tau;
+    pcur[i] = pi;
+    if (pcur32) pcur32[i] = (float)pi;
+    P.q[i] = qi;
+    s[0] += pi * qi;
+  };
+  for (int base = r0; base < r1; base += ng) {
+    const int i = base + B.tid / G;
+    const bool act = i < r1;
+    int qb = 0, qe = 0;
+    if (act) {
+      qb = P.Q.rowptr[i];
+      qe = P.Q.rowptr[i + 1];
+    }
+    const bool use = act && (qe - qb) <= kLongRow;
+    double sq = use ? row_partial(P.Q.col, qval, qb, qe, lane, G, gp) : 0.0;
+    sq = group_sum(sq, G);
+    if (use && lane == 0) epi(i, sq);
+  }
+  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+    const int i = pt.long_rows[t];
+    double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gp)};
+    double dummy[1] = {0.0};
+    block_reduce<1, 0>(v, dummy, lds);
+    if (B.tid == 0) epi(i, v[0]);
+  }
+  double dummy[1] = {0.0};
+  block_reduce<1, 0>(s, dummy, lds);
+  if (B.tid == 0) P.part[S_PQ * B.nb + B.b] = s[0];
+}
+
+// CG update on the owned rows: x += alpha p, r -= alpha q; partial r.r
+__device__ void phase_cg_update(const SolveParams& P, const Block& B, const double* pcur, double alpha, int mixed,
+                                double* lds) {
+  const int r0 = P.pcg.bounds[B.b], r1 = P.pcg.bounds[B.b + 1];
+  double s[1] = {0.0};
+  for (int i = r0 + B.tid; i < r1; i += kBlock) {
+    const double xi = P.x[i] + alpha * pcur[i];
+    const double ri = P.r[i] - alpha * P.q[i];
+    P.x[i] = xi;
+    P.r[i] = ri;
+    if (mixed) {
+      P.x32[i] = (float)xi;
+      P.r32[i] = (float)ri;
+    }
+    s[0] += ri * ri;
+  }
+  double dummy[1] = {0.0};
+  block_reduce<1, 0>(s, dummy, lds);
+  if (B.tid == 0) P.part[S_RR * B.nb + B.b] = s[0];
+}
+
+// Dual step and averages (Alg. 1): u = A x^{k+1};
+// y <- max(0, y + sigma (2u - A x^k - b)); A x^k <- u; ya += w (y - ya);
+// xa += w (x - xa) on an n-slice; m-side partials of the new point.
+template <typename V, typename Tx>
+__device__ void phase_dual(const SolveParams& P, const Block& B, const V* aval, const Tx* xg, double sigma, double w,
+                           double* lds) {
+  double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
+  mside_rows(P, B, aval, xg, lds, [&](int i, double u) {
+    const double bi = P.b[i];
+    double yn = P.y[i] + sigma * (2.0 * u - P.ax[i] - bi);
+    yn = pos_part(yn);
+    P.y[i] = yn;
+    P.ax[i] = u;
+    P.ya[i] += w * (yn - P.ya[i]);
+    mx[0] = maxp(mx[0], pos_part(u - bi));
+    mx[1] = maxp(mx[1], fabs(u));
+    s1[0] += bi * yn;
+  });
+  const int r0 = P.pcg.bounds[B.b], r1 = P.pcg.bounds[B.b + 1];
+  for (int j = r0 + B.tid; j < r1; j += kBlock) P.xa[j] += w * (P.x[j] - P.xa[j]);
+  store_mside(P, B, 0, s1, mx, lds);
+}
+
+// Restart: move to the candidate (average when use_avg), measure the
+// movement from the previous anchor, and make the candidate the new anchor
+// and the new (empty) average.
+__device__ void phase_restart(const SolveParams& P, const Block& B, int use_avg, int mixed, double* lds) {
+  double s[2] = {0.0, 0.0};
+  const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
+  for (int j = n0 + B.tid; j < n1; j += kBlock) {
+    const double xc = use_avg ? P.xa[j] : P.x[j];
+    const double d = xc - P.x_anc[j];
+    s[0] += d * d;
+    P.x[j] = xc;
+    if (mixed) P.x32[j] = (float)xc;
+    P.x_anc[j] = xc;
+    P.xa[j] = xc;
+  }
+  const int m0 = P.pm.bounds[B.b], m1 = P.pm.bounds[B.b + 1];
+  for (int i = m0 + B.tid; i < m1; i += kBlock) {
+    const double yc = use_avg ? P.ya[i] : P.y[i];
+    const double d = yc - P.y_anc[i];
+    s[1] += d * d;
+    P.y[i] = yc;
+    P.y_anc[i] = yc;
+    P.ya[i] = yc;
+    if (use_avg) P.ax[i] = P.ax_avg[i];
+  }
+  double dummy[1] = {0.0};
+  block_reduce<2, 0>(s, dummy, lds);
+  if (B.tid == 0) {
+    P.part[S_DX * B.nb + B.b] = s[0];
+    P.part[S_DY * B.nb + B.b] = s[1];
+    if (use_avg) {
+      P.part[S_MVIOL * B.nb + B.b] = P.part[(S_AVG0 + S_MVIOL) * B.nb + B.b];
+      P.part[S_MAX * B.nb + B.b] = P.part[(S_AVG0 + S_MAX) * B.nb + B.b];
+      P.part[S_BY * B.nb + B.b] = P.part[(S_AVG0 + S_BY) * B.nb + B.b];
+    }
+  }
+}
+
+// copy src -> dst on the workgroup's n- and m-slices (returning the average
+// or restoring the anchor at the end of a solve)
+__device__ void phase_copy_point(const SolveParams& P, const Block& B, const double* xs, const double* ys) {
+  const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
+  for (int j = n0 + B.tid; j < n1; j += kBlock) P.x[j] = xs[j];
+  const int m0 = P.pm.bounds[B.b], m1 = P.pm.bounds[B.b + 1];
+  for (int i = m0 + B.tid; i < m1; i += kBlock) P.y[i] = ys[i];
+}
+
+// relKKT (Sec. 4, progress metric) from the reduced partials of one point.
+struct Kkt {
+  double rp, rd, rg, kkt, pobj, dobj;
+};
+
+__device__ Kkt kkt_from(const double* s, const double* mx, double nb_inf, double nc_inf) {
+  // s: g.g, x.Qx, c.x, b.y ; mx: |g|, |Qx|, |A'y|, (u-b)^+, |u|
+  Kkt k;
+  const double xqx = s[1], cx = s[2], by = s[3];
+  k.rp = rel_div(mx[3], maxp(mx[4], nb_inf));
+  k.rd = rel_div(mx[0], maxp(mx[1], maxp(mx[2], nc_inf)));
+  k.rg = fabs(xqx + cx + by) / (1.0 + maxp(fabs(0.5 * xqx + cx), fabs(0.5 * xqx + by)));
+  k.kkt = maxp(k.rp, maxp(k.rd, k.rg));
+  k.pobj = 0.5 * xqx + cx;
+  k.dobj = -0.5 * xqx - by;
+  return k;
+}
+
+__device__ Kkt reduce_kkt(const SolveParams& P, const Block& B, int slot0, double nb_inf, double nc_inf, double* gg,
+                          double* flag, double* lds) {
+  const int ss[4] = {slot0 + S_GG, slot0 + S_XQX, slot0 + S_CX, slot0 + S_BY};
+  const int ms[6] = {slot0 + S_MG, slot0 + S_MQX, slot0 + S_MATY, slot0 + S_MVIOL, slot0 + S_MAX, S_FLAG};
+  double s[4], mx[6];
+  reduce_partials<4, 6>(P.part, B.nb, ss, ms, s, mx, lds);
+  if (gg) *gg = s[0];
+  if (flag) *flag = mx[5];
+  Kkt k = kkt_from(s, mx, nb_inf, nc_inf);
+  // a NaN anywhere in g shows in g.g even where the max would not see it
+  if (!(s[0] == s[0])) k.kkt = s[0];
+  return k;
+}
+
+__device__ double reduce_one(const SolveParams& P, const Block& B, int slot, double* lds) {
+  const int ss[1] = {slot};
+  const int ms[1] = {0};
+  double s[1], mx[1];
+  reduce_partials<1, 0>(P.part, B.nb, ss, ms, s, mx, lds);
+  return s[0];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- main kernel
+
+__global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, double nb_inf, double nc_inf) {
+  __shared__ double lds[kWaves * 16];
+  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
+  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  SolverState S = *P.st;
+  if (S.done) return;
+  bool ok = true;
+
+  if (S.K_anchor != S.K_anchor) {  // first launch of a solve: m-side of the start point
+    phase_ax(P, B, lds);
+    ok = gs.sync();
+  }
+
+  int64_t budget = P.iters_this_launch;
+  Kkt kc{}, ka{};
+  bool have_avg = false;
+  while (ok && !S.done && budget > 0) {
+    // ---- n-side pass at z^{n,k}: r0 = -(Qx + A'y + c), relKKT(z^{n,k})
+    phase_nside(P, P.pn1, B, P.x, P.y, P.r, S.mixed ? P.r32 : nullptr, 0, lds);
+    if (B.tid == 0) {
+      double f = 0.0;
+      if (B.b == 0 && P.time_limit_ticks && wall_clock64() - S.t_start > P.time_limit_ticks) f = 1.0;
+      P.part[S_FLAG * B.nb + B.b] = f;
+    }
+    if (!(ok = gs.sync())) break;
+    double rho, tflag;
+    kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, &rho, &tflag, lds);
+    have_avg = false;
+    if (S.K_anchor != S.K_anchor) {
+      S.K_anchor = kc.kkt;
+    }
+    if (!(kc.kkt == kc.kkt) || isinf(kc.kkt)) {  // NUMERICAL_ERROR: back to the anchor
+      S.done = 1;
+      S.status = 3;
+      phase_copy_point(P, B, P.x_anc, P.y_anc);
+      S.r_p = S.r_d = S.r_g = NAN;
+      S.kkt = kc.kkt;
+      S.pobj = S.dobj = NAN;
+      break;
+    }
+    if (kc.kkt <= P.tol && S.mixed) {
+      // the m-side partials came from FP32 products: certify r_primal with
+      // an FP64 product, and finish in FP64 if the certificate fails
+      phase_ax(P, B, lds);
+      if (!(ok = gs.sync())) break;
+      kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, nullptr, nullptr, lds);
+      if (kc.kkt > P.tol) S.mixed = 0;
+    }
+    if (kc.kkt <= P.tol) {
+      S.done = 1;
+      S.status = 0;
+      S.returned_average = 0;
+      S.r_p = kc.rp; S.r_d = kc.rd; S.r_g = kc.rg; S.kkt = kc.kkt; S.pobj = kc.pobj; S.dobj = kc.dobj;
+      break;
+    }
+    // ---- restart evaluation (Sec. 4, adaptive restart)
+    if (S.k > 0 && S.k % P.eval_period == 0) {
+      phase_eval_avg(P, B, lds);
+      if (!(ok = gs.sync())) break;
+      ka = reduce_kkt(P, B, S_AVG0, nb_inf, nc_inf, nullptr, nullptr, lds);
+      have_avg = true;
+      S.evals += 1;
+      if (ka.kkt <= P.tol) {
+        S.done = 1;
+        S.status = 0;
+        S.returned_average = 1;
+        S.r_p = ka.rp; S.r_d = ka.rd; S.r_g = ka.rg; S.kkt = ka.kkt; S.pobj = ka.pobj; S.dobj = ka.dobj;
+        phase_copy_point(P, B, P.xa, P.ya);
+        break;
+      }
+      const int use_avg = (P.restart_to == 1) || (ka.kkt < kc.kkt);
+      const double Kc = use_avg ? ka.kkt : kc.kkt;
+      int why = 0;
+      if (Kc <= P.beta_suf * S.K_anchor) why = 1;
+      else if (Kc <= P.beta_nec * S.K_anchor && Kc > S.K_prev) why = 2;
+      else if ((double)S.k >= P.beta_art * (double)S.k_total) why = 3;
+      S.K_prev = Kc;
+      if (why) {
+        phase_restart(P, B, use_avg, S.mixed, lds);
+        if (!(ok = gs.sync())) break;
+        const int ss[2] = {S_DX, S_DY};
+        const int ms[1] = {0};
+        double s2[2], m0[1];
+        reduce_partials<2, 0>(P.part, B.nb, ss, ms, s2, m0, lds);
+        const double dx = sqrt(s2[0]), dy = sqrt(s2[1]);
+        if (P.theta > 0.0 && dx > 1e-10 && dy > 1e-10)
+          S.omega = exp(P.theta * log(dy / dx) + (1.0 - P.theta) * log(S.omega));
+        S.tau = P.eta / S.omega;
+        S.sigma = P.eta * S.omega;
+        S.K_anchor = Kc;
+        S.K_prev = INFINITY;
+        S.k = 0;
+        S.eps = 0.0;
+        S.restarts += 1;
+        have_avg = false;
+        if (use_avg) continue;  // the point moved: redo the n-side pass there
+      }
+    }
+    // ---- limits
+    const bool at_cap = S.k_total >= P.max_iters;
+    const bool at_time = tflag > 0.0;
+    if (at_cap || at_time) {
+      if (S.mixed) {  // exact FP64 m-side partials for the reported relKKT
+        phase_ax(P, B, lds);
+        if (!(ok = gs.sync())) break;
+        kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, nullptr, nullptr, lds);
+      }
+      if (S.k > 0 && !have_avg) {
+        phase_eval_avg(P, B, lds);
+        if (!(ok = gs.sync())) break;
+        ka = reduce_kkt(P, B, S_AVG0, nb_inf, nc_inf, nullptr, nullptr, lds);
+        have_avg = true;
+      }
+      S.done = 1;
+      const bool avg = have_avg && ka.kkt < kc.kkt;
+      const Kkt& k = avg ? ka : kc;
+      S.status = k.kkt <= P.tol ? 0 : (at_cap ? 1 : 2);
+      S.returned_average = avg ? 1 : 0;
+      S.r_p = k.rp; S.r_d = k.rd; S.r_g = k.rg; S.kkt = k.kkt; S.pobj = k.pobj; S.dobj = k.dobj;
+      if (avg) phase_copy_point(P, B, P.xa, P.ya);
+      break;
+    }
+    // ---- primal step: inexact CG on (Q + I/tau) x = x^k/tau - c - A'y^k (Alg. 1)
+    S.eps += P.eps_factor * kc.kkt;
+    const double inv_tau = 1.0 / S.tau;
+    int steps = 0;
+    if (rho > 0.0) {
+      double beta = 0.0;
+      int first = 1, cur = 0;
+      for (int l = 1; l <= P.max_cg; ++l) {
+        double* pc = cur ? P.p1 : P.p0;
+        const double* pp = cur ? P.p0 : P.p1;
+        if (S.mixed) {
+          float* pc32 = cur ? P.p32_1 : P.p32_0;
+          const float* pp32 = cur ? P.p32_0 : P.p32_1;
+          phase_cg_spmv(P, B, P.Q.val32, (const float*)P.r32, pp32, pp, pc, pc32, beta, first, inv_tau, lds);
+        } else {
+          phase_cg_spmv(P, B, P.Q.val, (const double*)P.r, pp, pp, pc, nullptr, beta, first, inv_tau, lds);
+        }
+        if (!(ok = gs.sync())) break;
+        const double pq = reduce_one(P, B, S_PQ, lds);
+        const double alpha = rho / pq;
+        phase_cg_update(P, B, pc, alpha, S.mixed, lds);
+        if (!(ok = gs.sync())) break;
+        const double rho_new = reduce_one(P, B, S_RR, lds);
+        steps = l;
+        if (l == P.max_cg) break;
+        if (P.cg_rule == 0 && S.tau * sqrt(rho_new) <= S.eps) break;
+        if (!(rho_new > 0.0)) break;
+        beta = rho_new / rho;
+        rho = rho_new;
+        first = 0;
+        cur ^= 1;
+      }
+      if (!ok) break;
+    }
+    S.cg_total += steps;
+    // ---- dual step at 2x^{k+1} - x^k and averages with weight 1/(k+1)
+    const double w = 1.0 / (double)(S.k + 1);
+    if (S.mixed)
+      phase_dual(P, B, P.A.val32, (const float*)P.x32, S.sigma, w, lds);
+    else
+      phase_dual(P, B, P.A.val, (const double*)P.x, S.sigma, w, lds);
+    if (!(ok = gs.sync())) break;
+    S.k += 1;
+    S.k_total += 1;
+    budget -= 1;
+  }
+  if (!ok) {
+    if (B.b == 0 && B.tid == 0) P.st->done = -1;  // barrier failure: reported as a HIP error
+    return;
+  }
+  if (B.b == 0 && B.tid == 0) *P.st = S;
+}
+
+// -------------------------------------------------------- power iteration
+
+// ||A||_2 by power iteration on A'A (the step-size rule of Thm 2 needs it;
+// the paper does not say how it is obtained): start from
+// v_j = 0.5 + ((j * 40503) mod 1024) / 1024, normalised; each step
+// u = A v, w = A'u, lambda = ||w||, v = w / lambda; ||A|| ~ sqrt(lambda).
+__global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) {
+  __shared__ double lds[kWaves * 8];
+  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
+  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  const int n0 = P.pn.bounds[B.b], n1 = P.pn.bounds[B.b + 1];
+  double s[1] = {0.0}, dummy[1] = {0.0};
+  for (int j = n0 + B.tid; j < n1; j += kBlock) {
+    const double v = 0.5 + (double)(((uint64_t)j * 40503ull) % 1024ull) / 1024.0;
+    P.w[j] = v;
+    s[0] += v * v;
+  }
+  block_reduce<1, 0>(s, dummy, lds);
+  if (B.tid == 0) P.part[S_PW * B.nb + B.b] = s[0];
+  if (!gs.sync()) return;
+  const int ss[1] = {S_PW};
+  const int ms[1] = {0};
+  double tot[1], m0[1];
+  reduce_partials<1, 0>(P.part, B.nb, ss, ms, tot, m0, lds);
+  double scale = 1.0 / sqrt(tot[0]);
+  double lam = 0.0;
+  for (int it = 0; it < P.iters; ++it) {
+    // v = w * scale on owned rows (scale = 1/||w||)
+    for (int j = n0 + B.tid; j < n1; j += kBlock) P.v[j] = P.w[j] * scale;
+    if (!gs.sync()) return;
+    // u = A v
+    {
+      const Part& pt = P.pm;
+      const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
+      const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
+      GatherVec<double> gv{P.v};
+      for (int base = r0; base < r1; base += ng) {
+        const int i = base + B.tid / G;
+        const bool act = i < r1;
+        int ab = 0, ae = 0;
+        if (act) { ab = P.A.rowptr[i]; ae = P.A.rowptr[i + 1]; }
+        const bool use = act && (ae - ab) <= kLongRow;
+        double su = use ? row_partial(P.A.col, P.A.val, ab, ae, lane, G, gv) : 0.0;
+        su = group_sum(su, G);
+        if (use && lane == 0) P.u[i] = su;
+      }
+      for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+        const int i = pt.long_rows[t];
+        double v[1] = {row_partial(P.A.col, P.A.val, P.A.rowptr[i], P.A.rowptr[i + 1], B.tid, kBlock, gv)};
+        block_reduce<1, 0>(v, dummy, lds);
+        if (B.tid == 0) P.u[i] = v[0];
+      }
+    }
+    if (!gs.sync()) return;
+    // w = A'u, partial ||w||^2
+    {
+      const Part& pt = P.pn;
+      const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
+      GatherVec<double> gu{P.u};
+      double sw[1] = {0.0};
+      for (int base = n0; base < n1; base += ng) {
+        const int i = base + B.tid / G;
+        const bool act = i < n1;
+        int tb = 0, te = 0;
+        if (act) { tb = P.At.rowptr[i]; te = P.At.rowptr[i + 1]; }
+        const bool use = act && (te - tb) <= kLongRow;
+        double st = use ? row_partial(P.At.col, P.At.val, tb, te, lane, G, gu) : 0.0;
+        st = group_sum(st, G);
+        if (use && lane == 0) {
+          P.w[i] = st;
+          sw[0] += st * st;
+        }
+      }
+      for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+        const int i = pt.long_rows[t];
+        double v[1] = {row_partial(P.At.col, P.At.val, P.At.rowptr[i], P.At.rowptr[i + 1], B.tid, kBlock, gu)};
+        block_reduce<1, 0>(v, dummy, lds);
+        if (B.tid == 0) {
+          P.w[i] = v[0];
+          sw[0] += v[0] * v[0];
+        }
+      }
+      block_reduce<1, 0>(sw, dummy, lds);
+      if (B.tid == 0) P.part[S_PW * B.nb + B.b] = sw[0];
+    }
+    if (!gs.sync()) return;
+    reduce_partials<1, 0>(P.part, B.nb, ss, ms, tot, m0, lds);
+    lam = sqrt(tot[0]);
+    if (!(lam > 0.0)) break;
+    scale = 1.0 / lam;
+  }
+  if (B.b == 0 && B.tid == 0) P.out[0] = sqrt(lam);
+}
+
+// ------------------------------------------------------ small helper kernels
+
+__global__ void init_point_kernel(SolveParams P, const double* x0, const double* y0) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < P.n; j += stride) {
+    const double v = x0 ? x0[j] : 0.0;
+    P.x[j] = v;
+    P.xa[j] = v;
+    P.x_anc[j] = v;
+    if (P.x32) P.x32[j] = (float)v;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P.m; i += stride) {
+    double v = y0 ? y0[i] : 0.0;
+    v = v > 0.0 ? v : (v == v ? 0.0 : v);
+    P.y[i] = v;
+    P.ya[i] = v;
+    P.y_anc[i] = v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.st->t_start = wall_clock64();
+}
+
+template <typename V, typename T>
+__global__ void __launch_bounds__(kBlock) spmv_kernel(DevMat M, Part pt, const V* val, const T* x, double* y) {
+  __shared__ double lds[kWaves * 4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int r0 = pt.bounds[b], r1 = pt.bounds[b + 1];
+  const int G = pt.group, lane = tid & (G - 1), ng = kBlock / G;
+  GatherVec<T> gx{x};
+  for (int base = r0; base < r1; base += ng) {
+    const int i = base + tid / G;
+    const bool act = i < r1;
+    int rb = 0, re = 0;
+    if (act) { rb = M.rowptr[i]; re = M.rowptr[i + 1]; }
+    const bool use = act && (re - rb) <= kLongRow;
+    double s = use ? row_partial(M.col, val, rb, re, lane, G, gx) : 0.0;
+    s = group_sum(s, G);
+    if (use && lane == 0) y[i] = s;
+  }
+  for (int t = pt.long_ptr[b]; t < pt.long_ptr[b + 1]; ++t) {
+    const int i = pt.long_rows[t];
+    double v[1] = {row_partial(M.col, val, M.rowptr[i], M.rowptr[i + 1], tid, kBlock, gx)};
+    double dummy[1] = {0.0};
+    block_reduce<1, 0>(v, dummy, lds);
+    if (tid == 0) y[i] = v[0];
+  }
+}
+
+__global__ void to_f32_kernel(const double* in, float* out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride) out[j] = (float)in[j];
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_solve(const SolveParams& p, int nb, double nb_inf, double nc_inf, hipStream_t s) {
+  SolveParams pc = p;
+  void* args[] = {&pc, &nb_inf, &nc_inf};
+  return hipLaunchCooperativeKernel((const void*)pdhcg_solve_kernel, dim3(nb), dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s) {
+  PowerParams pc = p;
+  void* args[] = {&pc};
+  return hipLaunchCooperativeKernel((const void*)pdhcg_power_kernel, dim3(nb), dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_init_point(const SolveParams& p, const double* x0, const double* y0, int nb, hipStream_t s) {
+  int64_t len = p.n > p.m ? p.n : p.m;
+  int grid = (int)((len + kBlock - 1) / kBlock);
+  if (grid < 1) grid = 1;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(init_point_kernel, dim3(grid), dim3(kBlock), 0, s, p, x0, y0);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(const DevMat& M, const Part& pt, int nb, int precision, const double* x, float* x32,
+                       double* y, hipStream_t s) {
+  if (precision == 1) {
+    hipLaunchKernelGGL((spmv_kernel<float, float>), dim3(nb), dim3(kBlock), 0, s, M, pt, M.val32,
+                       (const float*)x32, y);
+  } else {
+    hipLaunchKernelGGL((spmv_kernel<double, double>), dim3(nb), dim3(kBlock), 0, s, M, pt, M.val, x, y);
+  }
+  return hipGetLastError();
+}
+
+hipError_t solve_occupancy(int* per_cu) {
+  int a = 0, b = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)pdhcg_solve_kernel, kBlock, 0);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)pdhcg_power_kernel, kBlock, 0);
+  if (e != hipSuccess) return e;
+  *per_cu = a < b ? a : b;
+  return hipSuccess;
+}
+
+hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  int grid = (int)((n + kBlock - 1) / kBlock);
+  if (grid < 1) grid = 1;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid), dim3(kBlock), 0, s, in, out, n);
+  return hipGetLastError();
+}
+}  // namespace pdhcg

@@ -1,0 +1,262 @@
+"""Python binding of the C ABI in ``include/pdhcg.h`` (argument marshalling only).
+
+Every step of the solver runs in the HIP library ``libpdhcg.so``; this module
+only converts arrays and settings.  Device-resident data are torch tensors on
+the current HIP device and are handed over by pointer together with torch's
+current stream.  There is no CPU fallback: if the library cannot be loaded,
+``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class pdhcg_csr(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class pdhcg_settings(C.Structure):
+    _fields_ = [("tol_rel_kkt", C.c_double), ("max_iters", C.c_int64), ("max_cg_iters", C.c_int32),
+                ("cg_rule", C.c_int32), ("cg_eps_factor", C.c_double), ("beta_sufficient", C.c_double),
+                ("beta_necessary", C.c_double), ("beta_artificial", C.c_double), ("restart_to", C.c_int32),
+                ("eval_period", C.c_int32), ("primal_weight_theta", C.c_double),
+                ("primal_weight_init", C.c_double), ("step_eta_factor", C.c_double), ("power_iters", C.c_int32),
+                ("precision", C.c_int32), ("time_limit_s", C.c_double), ("num_blocks", C.c_int32),
+                ("verbose", C.c_int32)]
+
+
+class pdhcg_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("returned_average", C.c_int32), ("rel_primal", C.c_double),
+                ("rel_dual", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double),
+                ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("iters", C.c_int64),
+                ("cg_iters_total", C.c_int64), ("restarts", C.c_int64), ("norm_A", C.c_double),
+                ("setup_s", C.c_double), ("solve_s", C.c_double), ("kernel_s", C.c_double),
+                ("kkt_evals", C.c_int64)]
+
+
+STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
+EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
+           "pdhcg_solve_batch", "pdhcg_spmv", "pdhcg_plan_info", "pdhcg_destroy", "pdhcg_error_string",
+           "pdhcg_last_error"]
+
+
+class PdhcgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pdhcg error {code}: {msg}")
+        self.code = code
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def lib():
+    """Load libpdhcg.so (building it first only when it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        P = C.c_void_p
+        L.pdhcg_default_settings.argtypes = [C.POINTER(pdhcg_settings)]
+        L.pdhcg_default_settings.restype = None
+        L.pdhcg_create.argtypes = [C.POINTER(P), C.POINTER(pdhcg_csr), C.POINTER(pdhcg_csr), P, P, C.c_int32,
+                                   C.POINTER(pdhcg_settings), P]
+        L.pdhcg_set_settings.argtypes = [P, C.POINTER(pdhcg_settings)]
+        L.pdhcg_set_b.argtypes = [P, P, C.c_int32]
+        L.pdhcg_solve.argtypes = [P, P, P, P, P, C.c_int32, C.POINTER(pdhcg_result)]
+        L.pdhcg_solve_batch.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
+        L.pdhcg_spmv.argtypes = [P, C.c_int32, C.c_int32, P, P, C.c_int32]
+        L.pdhcg_plan_info.argtypes = [P, P, P, P, P, P]
+        L.pdhcg_destroy.argtypes = [P]
+        L.pdhcg_destroy.restype = None
+        L.pdhcg_error_string.argtypes = [C.c_int]
+        L.pdhcg_error_string.restype = C.c_char_p
+        L.pdhcg_last_error.argtypes = []
+        L.pdhcg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PdhcgError(rc, lib().pdhcg_last_error().decode())
+
+
+@dataclasses.dataclass
+class Settings:
+    """Mirror of pdhcg_settings (defaults as pdhcg_default_settings)."""
+    tol_rel_kkt: float = 1e-4
+    max_iters: int = 100000
+    max_cg_iters: int = 100
+    cg_rule: int = 0
+    cg_eps_factor: float = 0.05
+    beta_sufficient: float = 0.2
+    beta_necessary: float = 0.8
+    beta_artificial: float = 0.2
+    restart_to: int = 0
+    eval_period: int = 64
+    primal_weight_theta: float = 0.2
+    primal_weight_init: float = 1.0
+    step_eta_factor: float = 0.5
+    power_iters: int = 100
+    precision: int = 0
+    time_limit_s: float = 0.0
+    num_blocks: int = 0
+    verbose: int = 0
+
+    def c(self) -> pdhcg_settings:
+        s = pdhcg_settings()
+        for f in dataclasses.fields(self):
+            setattr(s, f.name, getattr(self, f.name))
+        return s
+
+
+def default_settings() -> Settings:
+    s = pdhcg_settings()
+    lib().pdhcg_default_settings(C.byref(s))
+    return Settings(**{f.name: getattr(s, f.name) for f in dataclasses.fields(Settings)})
+
+
+def _result_dict(r: pdhcg_result) -> dict:
+    d = {name: getattr(r, name) for name, _ in pdhcg_result._fields_}
+    d["status_name"] = STATUS.get(r.status, str(r.status))
+    return d
+
+
+def _stream_ptr():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Solver:
+    """One QP on the GPU: ``Solver(qp, settings)`` then ``solve()``.
+
+    ``qp`` is an ``instances.QP`` (host CSR, FP64).  The matrices and vectors
+    are first moved to torch device tensors and handed to pdhcg_create as
+    device pointers."""
+
+    def __init__(self, qp, settings: Settings | None = None):
+        import torch
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.n, self.m = qp.Q.nrows, qp.A.nrows
+        self.settings = settings or Settings()
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.dev)
+        keep = []
+
+        def csr(M):
+            rp, col, val = t(M.rowptr, torch.int64), t(M.col, torch.int32), t(M.val, torch.float64)
+            keep.extend([rp, col, val])
+            return pdhcg_csr(M.nrows, M.ncols, int(M.rowptr[-1]), rp.data_ptr(), col.data_ptr() if col.numel() else None,
+                             val.data_ptr() if val.numel() else None, 1)
+
+        Qc, Ac = csr(qp.Q), csr(qp.A)
+        b = t(qp.b, torch.float64) if self.m else torch.zeros(1, dtype=torch.float64, device=self.dev)
+        c = t(qp.c, torch.float64)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        _check(lib().pdhcg_create(C.byref(h), C.byref(Qc), C.byref(Ac), b.data_ptr(), c.data_ptr(), 1,
+                                  C.byref(self.settings.c()), _stream_ptr()))
+        self.h = h
+        del keep
+
+    def set_settings(self, settings: Settings):
+        self.settings = settings
+        _check(lib().pdhcg_set_settings(self.h, C.byref(settings.c())))
+
+    def set_b(self, b):
+        import torch
+        bt = torch.as_tensor(np.ascontiguousarray(b), dtype=torch.float64).to(self.dev)
+        _check(lib().pdhcg_set_b(self.h, bt.data_ptr(), 1))
+
+    def solve(self, x0=None, y0=None, out=None):
+        """Returns (x, y, result) with x, y as float64 device tensors."""
+        import torch
+        if out is None:
+            x = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+            y = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.dev)
+        else:
+            x, y = out
+        dv = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64).to(self.dev).contiguous()
+        x0t, y0t = dv(x0), dv(y0)
+        r = pdhcg_result()
+        _check(lib().pdhcg_solve(self.h, None if x0t is None else x0t.data_ptr(),
+                                 None if y0t is None else y0t.data_ptr(), x.data_ptr(), y.data_ptr(), 1, C.byref(r)))
+        return x, y[: self.m], _result_dict(r)
+
+    def spmv(self, which: int, x, precision: int = 0, repeats: int = 1, out=None):
+        import torch
+        nrows = self.n if which in (0, 2) else self.m
+        xt = torch.as_tensor(x, dtype=torch.float64).to(self.dev).contiguous()
+        y = out if out is not None else torch.empty(max(nrows, 1), dtype=torch.float64, device=self.dev)
+        _check(lib().pdhcg_spmv(self.h, which, precision, xt.data_ptr(), y.data_ptr(), repeats))
+        return y[:nrows]
+
+    def plan_info(self) -> dict:
+        v = [C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()]
+        _check(lib().pdhcg_plan_info(self.h, *[C.byref(a) for a in v]))
+        return dict(num_blocks=v[0].value, group_n=v[1].value, group_q=v[2].value, group_m=v[3].value,
+                    long_rows=v[4].value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pdhcg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None):
+    """Solve a list of QPs with pdhcg_solve_batch (host arrays in and out).
+    Returns a list of (x, y, result) with numpy arrays."""
+    settings = settings or Settings()
+    cnt = len(qps)
+    keep = []
+    Qs = (pdhcg_csr * cnt)()
+    As = (pdhcg_csr * cnt)()
+    bs = (C.c_void_p * cnt)()
+    cs = (C.c_void_p * cnt)()
+    xo = (C.c_void_p * cnt)()
+    yo = (C.c_void_p * cnt)()
+    x0 = (C.c_void_p * cnt)() if x0s is not None else None
+    y0 = (C.c_void_p * cnt)() if y0s is not None else None
+    outs = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    for i, qp in enumerate(qps):
+        for M, dst in ((qp.Q, Qs), (qp.A, As)):
+            rp, col, val = arr(M.rowptr, np.int64), arr(M.col, np.int32), arr(M.val, np.float64)
+            dst[i] = pdhcg_csr(M.nrows, M.ncols, int(M.rowptr[-1]), rp.ctypes.data, col.ctypes.data,
+                               val.ctypes.data, 0)
+        bs[i] = arr(qp.b if qp.A.nrows else np.zeros(1), np.float64).ctypes.data
+        cs[i] = arr(qp.c, np.float64).ctypes.data
+        xv = np.zeros(qp.Q.nrows)
+        yv = np.zeros(max(qp.A.nrows, 1))
+        outs.append((xv, yv))
+        xo[i] = xv.ctypes.data
+        yo[i] = yv.ctypes.data
+        if x0 is not None and x0s[i] is not None:
+            x0[i] = arr(x0s[i], np.float64).ctypes.data
+        if y0 is not None and y0s[i] is not None:
+            y0[i] = arr(y0s[i], np.float64).ctypes.data
+    rs = (pdhcg_result * cnt)()
+    _check(lib().pdhcg_solve_batch(cnt, Qs, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()),
+                                   _stream_ptr()))
+    return [(outs[i][0], outs[i][1][: qps[i].A.nrows], _result_dict(rs[i])) for i in range(cnt)]

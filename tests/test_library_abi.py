@@ -1,0 +1,45 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/pdhcg.h declares, and returns the documented defaults (no GPU work)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pdhcg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdhcg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for n in ["pdhcg_create", "pdhcg_solve", "pdhcg_solve_batch", "pdhcg_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2405_16160_amd import pdhcg
+    L = pdhcg.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(pdhcg.EXPORTS)
+
+
+def test_default_settings_match_the_paper_constants():
+    from paper_2405_16160_amd import pdhcg
+    s = pdhcg.default_settings()
+    assert s.cg_eps_factor == 0.05
+    assert (s.beta_sufficient, s.beta_necessary, s.beta_artificial) == (0.2, 0.8, 0.2)
+    assert s.primal_weight_theta == 0.2
+    assert s.step_eta_factor == 0.5
+    assert s == pdhcg.Settings()
+
+
+def test_error_strings():
+    from paper_2405_16160_amd import pdhcg
+    L = pdhcg.lib()
+    assert L.pdhcg_error_string(-1) == b"invalid argument"
+    assert L.pdhcg_error_string(-3) == b"HIP error"
