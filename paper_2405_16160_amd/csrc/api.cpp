@@ -8,6 +8,8 @@
 #include <chrono>
 #include <cstdio>
 #include <limits>
+#include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -52,6 +54,25 @@ struct HostCsr {
   std::vector<double> val;
 };
 
+// CSR structure checks on host arrays: rowptr[0] = 0, rowptr[nrows] = nnz,
+// monotone rowptr, columns in range and strictly increasing within a row.
+int check_structure(const int64_t* rowptr, const int32_t* col, int64_t nrows, int64_t ncols, int64_t nnz,
+                    const std::string& name) {
+  if (rowptr[0] != 0 || rowptr[nrows] != nnz)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, name + ": rowptr[0] != 0 or rowptr[nrows] != nnz");
+  for (int64_t i = 0; i < nrows; ++i) {
+    if (rowptr[i + 1] < rowptr[i])
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, name + ": rowptr not monotone at row " + std::to_string(i));
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      if (col[k] < 0 || col[k] >= ncols)
+        return fail(PDHCG_ERR_INVALID_ARGUMENT, name + ": column out of range in row " + std::to_string(i));
+      if (k > rowptr[i] && col[k] <= col[k - 1])
+        return fail(PDHCG_ERR_INVALID_ARGUMENT, name + ": columns not strictly increasing in row " + std::to_string(i));
+    }
+  }
+  return 0;
+}
+
 int fetch_csr(const pdhcg_csr* M, HostCsr& H, const char* name) {
   if (!M) return fail(PDHCG_ERR_INVALID_ARGUMENT, std::string(name) + ": null matrix");
   if (M->nrows < 0 || M->ncols < 0 || M->nnz < 0)
@@ -71,20 +92,7 @@ int fetch_csr(const pdhcg_csr* M, HostCsr& H, const char* name) {
     HIPX(hipMemcpy(H.col.data(), M->col, sizeof(int32_t) * M->nnz, kind));
     HIPX(hipMemcpy(H.val.data(), M->val, sizeof(double) * M->nnz, kind));
   }
-  if (H.rowptr[0] != 0 || H.rowptr[H.nrows] != M->nnz)
-    return fail(PDHCG_ERR_INVALID_ARGUMENT, std::string(name) + ": rowptr[0] != 0 or rowptr[nrows] != nnz");
-  for (int64_t i = 0; i < H.nrows; ++i) {
-    if (H.rowptr[i + 1] < H.rowptr[i])
-      return fail(PDHCG_ERR_INVALID_ARGUMENT, std::string(name) + ": rowptr not monotone at row " + std::to_string(i));
-    for (int64_t k = H.rowptr[i]; k < H.rowptr[i + 1]; ++k) {
-      if (H.col[k] < 0 || H.col[k] >= H.ncols)
-        return fail(PDHCG_ERR_INVALID_ARGUMENT, std::string(name) + ": column out of range in row " + std::to_string(i));
-      if (k > H.rowptr[i] && H.col[k] <= H.col[k - 1])
-        return fail(PDHCG_ERR_INVALID_ARGUMENT,
-                    std::string(name) + ": columns not strictly increasing in row " + std::to_string(i));
-    }
-  }
-  return 0;
+  return check_structure(H.rowptr.data(), H.col.data(), H.nrows, H.ncols, M->nnz, name);
 }
 
 // transpose by counting sort on the column index (rows of the result keep
@@ -193,6 +201,7 @@ struct pdhcg_handle {
   double *part = nullptr, *tmp_x0 = nullptr, *tmp_y0 = nullptr, *scratch = nullptr;
   uint64_t* bar = nullptr;
   SolverState* st = nullptr;
+  SolveParams* d_params = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   DevPart pn1, pcg, pm, pt;                // parts for the persistent kernels
   DevPart sq, sa, st_;                     // parts for the standalone products
@@ -352,6 +361,9 @@ SolveParams make_params(pdhcg_handle* h) {
   p.pn1 = h->pn1.view();
   p.pcg = h->pcg.view();
   p.pm = h->pm.view();
+  p.pt = h->pt.view();
+  p.nb_inf = h->nb_inf;
+  p.nc_inf = h->nc_inf;
   const pdhcg_settings& s = h->s;
   p.tol = s.tol_rel_kkt;
   p.eps_factor = s.cg_eps_factor;
@@ -359,7 +371,6 @@ SolveParams make_params(pdhcg_handle* h) {
   p.beta_nec = s.beta_necessary;
   p.beta_art = s.beta_artificial;
   p.theta = s.primal_weight_theta;
-  p.eta = s.step_eta_factor / (h->norm_A > 0.0 ? h->norm_A : 1.0);
   p.max_iters = s.max_iters;
   p.iters_this_launch = 5000;
   p.time_limit_ticks = s.time_limit_s > 0.0 ? (uint64_t)(s.time_limit_s * 1e8) : 0;  // 100 MHz clock
@@ -475,6 +486,7 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
   if ((rc = h->alloc(&h->part, (int64_t)NSLOT * 4096))) return bail(rc);
   if ((rc = h->alloc(&h->bar, 512))) return bail(rc);
   if ((rc = h->alloc(&h->st, 1))) return bail(rc);
+  if ((rc = h->alloc(&h->d_params, 1))) return bail(rc);
   if ((rc = upload(h, h->b, hb.data(), m))) return bail(rc);
   if ((rc = upload(h, h->c, hc.data(), n))) return bail(rc);
   if ((rc = plan(h, Q, A, T))) return bail(rc);
@@ -536,20 +548,25 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
     dy0 = h->tmp_y0;
   }
   SolveParams p = make_params(h);
+  p.x0 = dx0;
+  p.y0 = dy0;
   SolverState st{};
   st.K_anchor = std::numeric_limits<double>::quiet_NaN();
   st.K_prev = std::numeric_limits<double>::infinity();
   st.omega = h->s.primal_weight_init;
-  st.tau = p.eta / st.omega;
-  st.sigma = p.eta * st.omega;
+  st.eta = h->s.step_eta_factor / (h->norm_A > 0.0 ? h->norm_A : 1.0);
+  st.tau = st.eta / st.omega;
+  st.sigma = st.eta * st.omega;
+  st.norm_A = h->norm_A;
   st.mixed = h->s.precision == 1 ? 1 : 0;
   HIPX(hipMemcpyAsync(h->st, &st, sizeof(st), hipMemcpyHostToDevice, h->stream));
-  HIPX(launch_init_point(p, dx0, dy0, h->nb, h->stream));
+  HIPX(hipMemcpyAsync(h->d_params, &p, sizeof(p), hipMemcpyHostToDevice, h->stream));
+  HIPX(launch_init_point(h->d_params, h->n, h->m, h->stream));
   double kernel_ms = 0.0;
   for (;;) {
     HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * 512, h->stream));
     HIPX(hipEventRecord(h->ev0, h->stream));
-    HIPX(launch_solve(p, h->nb, h->nb_inf, h->nc_inf, h->stream));
+    HIPX(launch_solve(h->d_params, h->nb, h->stream));
     HIPX(hipEventRecord(h->ev1, h->stream));
     HIPX(hipMemcpyAsync(&st, h->st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
     HIPX(hipStreamSynchronize(h->stream));
@@ -638,11 +655,366 @@ const char* pdhcg_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
 
+
+namespace {
+
+// host-side bookkeeping of one QP of a batch: offsets into the packed arrays
+struct BatchInst {
+  int32_t n = 0, m = 0;
+  int32_t dense = 0;
+  int32_t g_n1 = 1, g_cg = 1, g_m = 1, g_t = 1;
+  int32_t x0_given = 0, y0_given = 0;
+  int64_t q_rp = 0, q_nz = 0, a_rp = 0, a_nz = 0, t_rp = 0, t_nz = 0;
+  int64_t voff_n = 0, voff_m = 0;
+  int64_t part_off = 0;
+  double nb_inf = 0.0, nc_inf = 0.0;
+};
+
+// exact symmetry of a host CSR given by pointers (dense: direct index check)
+bool symmetric_ptrs(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n, bool dense) {
+  if (dense) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = i + 1; j < n; ++j)
+        if (memcmp(&val[i * n + j], &val[j * n + i], sizeof(double)) != 0) return false;
+    return true;
+  }
+  HostCsr H;
+  H.nrows = H.ncols = n;
+  H.rowptr.assign(rowptr, rowptr + n + 1);
+  H.col.assign(col, col + rowptr[n]);
+  H.val.assign(val, val + rowptr[n]);
+  return exactly_symmetric(H);
+}
+
+bool is_dense(const int64_t* rowptr, int64_t n) {
+  if (rowptr[n] != n * n) return false;
+  for (int64_t i = 0; i <= n; ++i)
+    if (rowptr[i] != i * n) return false;
+  return true;
+}
+
+// row partitions of one workgroup covering all rows (see BatchInst)
+void batch_parts(const int64_t* qrp, bool dense, int64_t n, const HostCsr& A, const HostCsr& T,
+                 std::vector<int32_t>& out, int32_t g[4]) {
+  const int64_t m = A.nrows;
+  auto qlen = [&](int64_t i) -> int64_t { return dense ? 0 : qrp[i + 1] - qrp[i]; };
+  auto tlen = [&](int64_t i) -> int64_t { return m ? T.rowptr[i + 1] - T.rowptr[i] : 0; };
+  auto alen = [&](int64_t i) -> int64_t { return A.rowptr[i + 1] - A.rowptr[i]; };
+  HostPart p1 = build_part(n, 1, [&](int64_t i) { return qlen(i) + tlen(i); });
+  HostPart p2 = build_part(n, 1, qlen);
+  HostPart p3 = build_part(m, 1, alen);
+  HostPart p4 = build_part(n, 1, tlen);
+  const HostPart* ps[4] = {&p1, &p2, &p3, &p4};
+  for (int k = 0; k < 4; ++k) {
+    out.push_back(ps[k]->bounds[0]);
+    out.push_back(ps[k]->bounds[1]);
+    out.push_back(0);
+    out.push_back((int32_t)ps[k]->long_rows.size());
+    g[k] = ps[k]->group;
+  }
+  for (int k = 0; k < 4; ++k) out.insert(out.end(), ps[k]->long_rows.begin(), ps[k]->long_rows.end());
+  if (dense) g[0] = pow2_ceil(m ? (double)T.rowptr[n] / (double)n : 1.0);
+}
+
+struct DevBuf {
+  std::vector<void*> ptrs;
+  ~DevBuf() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  int alloc(T** p, int64_t count) {
+    *p = nullptr;
+    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(PDHCG_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    ptrs.push_back(*p);
+    return 0;
+  }
+};
+
+}  // namespace
+
 extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As, const double* const* bs,
                                  const double* const* cs, const double* const* x0s, const double* const* y0s,
                                  double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
                                  const pdhcg_settings* s, void* hip_stream) {
-  (void)count; (void)Qs; (void)As; (void)bs; (void)cs; (void)x0s; (void)y0s; (void)x_outs; (void)y_outs;
-  (void)rs; (void)s; (void)hip_stream;
-  return fail(PDHCG_ERR_INVALID_ARGUMENT, "batched solve kernel not built yet");
+  const double t0 = now_s();
+  int rc;
+  if ((rc = check_settings(s))) return rc;
+  if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
+  if (count == 0) return 0;
+  if (!Qs || !As || !bs || !cs || !x_outs || !y_outs)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const bool mixed = s->precision == 1;
+
+  // ---- validate, detect dense Q, build A', de-duplicate shared matrices
+  std::vector<BatchInst> inst(count);
+  std::vector<HostCsr> At(count);
+  std::vector<int32_t> parts;
+  struct Key {
+    const void *a, *b, *c;
+    bool operator<(const Key& o) const { return std::tie(a, b, c) < std::tie(o.a, o.b, o.c); }
+  };
+  std::map<Key, int> q_seen, a_seen;
+  std::vector<int> q_first(count, -1), a_first(count, -1);
+  int64_t rp_tot = 0, nz_tot = 0, vn_tot = 0, vm_tot = 0;
+  for (int i = 0; i < count; ++i) {
+    const pdhcg_csr& Q = Qs[i];
+    const pdhcg_csr& A = As[i];
+    const std::string tag = "instance " + std::to_string(i);
+    if (Q.on_device || A.on_device) return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": batch inputs must be host arrays");
+    if (Q.nrows != Q.ncols || Q.nrows < 1 || A.ncols != Q.nrows || A.nrows < 0)
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": bad shapes");
+    if (Q.nrows >= (1 << 30) || A.nrows >= (1 << 30) || Q.nnz >= (1ll << 31) || A.nnz >= (1ll << 31))
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": sizes beyond 32-bit indexing");
+    if (!Q.rowptr || !A.rowptr || (Q.nnz && (!Q.col || !Q.val)) || (A.nnz && (!A.col || !A.val)) || !cs[i] ||
+        (A.nrows && !bs[i]) || !x_outs[i] || (A.nrows && !y_outs[i]))
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": null array");
+    BatchInst& I = inst[i];
+    I.n = (int32_t)Q.nrows;
+    I.m = (int32_t)A.nrows;
+    const Key qk{Q.rowptr, Q.col, Q.val}, ak{A.rowptr, A.col, A.val};
+    auto qit = q_seen.find(qk);
+    if (qit == q_seen.end()) {
+      if ((rc = check_structure(Q.rowptr, Q.col, Q.nrows, Q.ncols, Q.nnz, tag + " Q"))) return rc;
+      const bool dense = is_dense(Q.rowptr, Q.nrows);
+      if (!symmetric_ptrs(Q.rowptr, Q.col, Q.val, Q.nrows, dense))
+        return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": Q is not exactly symmetric");
+      I.dense = dense ? 1 : 0;
+      I.q_rp = dense ? 0 : rp_tot;
+      I.q_nz = nz_tot;
+      if (!dense) rp_tot += Q.nrows + 1;
+      nz_tot += Q.nnz;
+      q_seen[qk] = i;
+      q_first[i] = i;
+    } else {
+      const BatchInst& F = inst[qit->second];
+      I.dense = F.dense; I.q_rp = F.q_rp; I.q_nz = F.q_nz;
+      q_first[i] = qit->second;
+    }
+    auto ait = a_seen.find(ak);
+    if (ait == a_seen.end()) {
+      if ((rc = check_structure(A.rowptr, A.col, A.nrows, A.ncols, A.nnz, tag + " A"))) return rc;
+      HostCsr Ah;
+      Ah.nrows = A.nrows;
+      Ah.ncols = A.ncols;
+      Ah.rowptr.assign(A.rowptr, A.rowptr + A.nrows + 1);
+      Ah.col.assign(A.col, A.col + A.nnz);
+      Ah.val.assign(A.val, A.val + A.nnz);
+      At[i] = transpose(Ah);
+      I.a_rp = rp_tot; rp_tot += A.nrows + 1;
+      I.t_rp = rp_tot; rp_tot += Q.nrows + 1;
+      I.a_nz = nz_tot; nz_tot += A.nnz;
+      I.t_nz = nz_tot; nz_tot += A.nnz;
+      a_seen[ak] = i;
+      a_first[i] = i;
+    } else {
+      const BatchInst& F = inst[ait->second];
+      I.a_rp = F.a_rp; I.t_rp = F.t_rp; I.a_nz = F.a_nz; I.t_nz = F.t_nz;
+      a_first[i] = ait->second;
+    }
+    I.voff_n = vn_tot; vn_tot += I.n;
+    I.voff_m = vm_tot; vm_tot += I.m;
+    I.nc_inf = max_abs_nan(cs[i], I.n);
+    I.nb_inf = max_abs_nan(bs[i], I.m);
+    I.x0_given = (x0s && x0s[i]) ? 1 : 0;
+    I.y0_given = (y0s && y0s[i] && I.m) ? 1 : 0;
+  }
+  // partitions (per distinct (Q, A) pair the lists are identical; built per instance for simplicity)
+  for (int i = 0; i < count; ++i) {
+    BatchInst& I = inst[i];
+    const HostCsr& T = At[a_first[i]];
+    HostCsr Ah;
+    Ah.nrows = As[i].nrows;
+    Ah.ncols = As[i].ncols;
+    Ah.rowptr.assign(As[i].rowptr, As[i].rowptr + As[i].nrows + 1);
+    I.part_off = (int64_t)parts.size();
+    int32_t g[4];
+    batch_parts(Qs[q_first[i]].rowptr, I.dense != 0, I.n, Ah, T, parts, g);
+    I.g_n1 = g[0]; I.g_cg = g[1]; I.g_m = g[2]; I.g_t = g[3];
+  }
+  // largest first: estimated work ~ entries of Q plus twice those of A
+  std::vector<int32_t> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double wa = (double)Qs[a].nnz + 2.0 * (double)As[a].nnz + inst[a].n;
+    const double wb = (double)Qs[b].nnz + 2.0 * (double)As[b].nnz + inst[b].n;
+    return wa > wb;
+  });
+
+  // ---- device buffers
+  DevBuf D;
+  int32_t *d_rp, *d_col, *d_parts, *d_order;
+  double* d_val;
+  float* d_val32 = nullptr;
+  SolveParams* d_params;
+  SolverState* d_st;
+  uint64_t* d_t0;
+  double *d_b, *d_c, *d_x0 = nullptr, *d_y0 = nullptr, *d_part;
+  double* nv[8];  // x xa x_anc r p0 p1 q (+ spare)
+  double* mv[5];  // y ya ax ax_avg y_anc
+  float* fv[4] = {nullptr, nullptr, nullptr, nullptr};
+  if ((rc = D.alloc(&d_rp, rp_tot))) return rc;
+  if ((rc = D.alloc(&d_col, nz_tot))) return rc;
+  if ((rc = D.alloc(&d_val, nz_tot))) return rc;
+  if (mixed && (rc = D.alloc(&d_val32, nz_tot))) return rc;
+  if ((rc = D.alloc(&d_parts, (int64_t)parts.size()))) return rc;
+  if ((rc = D.alloc(&d_params, count))) return rc;
+  if ((rc = D.alloc(&d_st, count))) return rc;
+  if ((rc = D.alloc(&d_t0, 1))) return rc;
+  if ((rc = D.alloc(&d_b, vm_tot))) return rc;
+  if ((rc = D.alloc(&d_c, vn_tot))) return rc;
+  if ((rc = D.alloc(&d_part, (int64_t)count * NSLOT))) return rc;
+  if ((rc = D.alloc(&d_order, count))) return rc;
+  for (int k = 0; k < 7; ++k)
+    if ((rc = D.alloc(&nv[k], vn_tot))) return rc;
+  for (int k = 0; k < 5; ++k)
+    if ((rc = D.alloc(&mv[k], vm_tot))) return rc;
+  if (mixed)
+    for (int k = 0; k < 4; ++k)
+      if ((rc = D.alloc(&fv[k], vn_tot))) return rc;
+  bool any_x0 = false, any_y0 = false;
+  for (int i = 0; i < count; ++i) {
+    any_x0 |= inst[i].x0_given != 0;
+    any_y0 |= inst[i].y0_given != 0;
+  }
+  if (any_x0 && (rc = D.alloc(&d_x0, vn_tot))) return rc;
+  if (any_y0 && (rc = D.alloc(&d_y0, vm_tot))) return rc;
+
+  // ---- uploads (matrix blocks straight from the caller's arrays)
+  auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (bytes) HIPX(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+    return 0;
+  };
+  std::vector<std::vector<int32_t>> rp_keep;
+  for (int i = 0; i < count; ++i) {
+    const BatchInst& I = inst[i];
+    if (q_first[i] == i) {
+      const pdhcg_csr& Q = Qs[i];
+      if (!I.dense) {
+        rp_keep.emplace_back(Q.rowptr, Q.rowptr + Q.nrows + 1);
+        if ((rc = up(d_rp + I.q_rp, rp_keep.back().data(), sizeof(int32_t) * (Q.nrows + 1)))) return rc;
+        if ((rc = up(d_col + I.q_nz, Q.col, sizeof(int32_t) * Q.nnz))) return rc;
+      }
+      if ((rc = up(d_val + I.q_nz, Q.val, sizeof(double) * Q.nnz))) return rc;
+    }
+    if (a_first[i] == i) {
+      const pdhcg_csr& A = As[i];
+      const HostCsr& T = At[i];
+      rp_keep.emplace_back(A.rowptr, A.rowptr + A.nrows + 1);
+      if ((rc = up(d_rp + I.a_rp, rp_keep.back().data(), sizeof(int32_t) * (A.nrows + 1)))) return rc;
+      rp_keep.emplace_back(T.rowptr.begin(), T.rowptr.end());
+      if ((rc = up(d_rp + I.t_rp, rp_keep.back().data(), sizeof(int32_t) * (T.nrows + 1)))) return rc;
+      if ((rc = up(d_col + I.a_nz, A.col, sizeof(int32_t) * A.nnz))) return rc;
+      if ((rc = up(d_val + I.a_nz, A.val, sizeof(double) * A.nnz))) return rc;
+      if ((rc = up(d_col + I.t_nz, T.col.data(), sizeof(int32_t) * A.nnz))) return rc;
+      if ((rc = up(d_val + I.t_nz, T.val.data(), sizeof(double) * A.nnz))) return rc;
+    }
+    if ((rc = up(d_c + I.voff_n, cs[i], sizeof(double) * I.n))) return rc;
+    if (I.m && (rc = up(d_b + I.voff_m, bs[i], sizeof(double) * I.m))) return rc;
+    if (I.x0_given && (rc = up(d_x0 + I.voff_n, x0s[i], sizeof(double) * I.n))) return rc;
+    if (I.y0_given && (rc = up(d_y0 + I.voff_m, y0s[i], sizeof(double) * I.m))) return rc;
+  }
+  // one parameter block per QP, all pointers resolved against the packed arrays
+  std::vector<SolveParams> hp(count);
+  for (int i = 0; i < count; ++i) {
+    const BatchInst& I = inst[i];
+    SolveParams& P = hp[i];
+    P.Q = DevMat{I.n, I.n, I.dense ? nullptr : d_rp + I.q_rp, I.dense ? nullptr : d_col + I.q_nz, d_val + I.q_nz,
+                 d_val32 ? d_val32 + I.q_nz : nullptr, I.dense};
+    P.A = DevMat{I.m, I.n, d_rp + I.a_rp, d_col + I.a_nz, d_val + I.a_nz, d_val32 ? d_val32 + I.a_nz : nullptr, 0};
+    P.At = DevMat{I.n, I.m, d_rp + I.t_rp, d_col + I.t_nz, d_val + I.t_nz, d_val32 ? d_val32 + I.t_nz : nullptr, 0};
+    P.n = I.n;
+    P.m = I.m;
+    P.b = d_b + I.voff_m;
+    P.c = d_c + I.voff_n;
+    P.x = nv[0] + I.voff_n; P.xa = nv[1] + I.voff_n; P.x_anc = nv[2] + I.voff_n; P.r = nv[3] + I.voff_n;
+    P.p0 = nv[4] + I.voff_n; P.p1 = nv[5] + I.voff_n; P.q = nv[6] + I.voff_n;
+    P.y = mv[0] + I.voff_m; P.ya = mv[1] + I.voff_m; P.ax = mv[2] + I.voff_m; P.ax_avg = mv[3] + I.voff_m;
+    P.y_anc = mv[4] + I.voff_m;
+    if (mixed) {
+      P.x32 = fv[0] + I.voff_n; P.r32 = fv[1] + I.voff_n; P.p32_0 = fv[2] + I.voff_n; P.p32_1 = fv[3] + I.voff_n;
+    }
+    P.part = d_part + (int64_t)i * NSLOT;
+    const int32_t* pb = d_parts + I.part_off;
+    const int32_t* hb = parts.data() + I.part_off;
+    const int32_t* lr = pb + 16;
+    P.pn1 = Part{pb + 0, pb + 2, lr, I.g_n1};
+    P.pcg = Part{pb + 4, pb + 6, lr + hb[3], I.g_cg};
+    P.pm = Part{pb + 8, pb + 10, lr + hb[3] + hb[7], I.g_m};
+    P.pt = Part{pb + 12, pb + 14, lr + hb[3] + hb[7] + hb[11], I.g_t};
+    P.nb_inf = I.nb_inf;
+    P.nc_inf = I.nc_inf;
+    P.x0 = I.x0_given ? d_x0 + I.voff_n : nullptr;
+    P.y0 = I.y0_given ? d_y0 + I.voff_m : nullptr;
+    P.tol = s->tol_rel_kkt; P.eps_factor = s->cg_eps_factor; P.beta_suf = s->beta_sufficient;
+    P.beta_nec = s->beta_necessary; P.beta_art = s->beta_artificial; P.theta = s->primal_weight_theta;
+    P.max_iters = s->max_iters;
+    P.iters_this_launch = s->max_iters;
+    P.time_limit_ticks = s->time_limit_s > 0.0 ? (uint64_t)(s->time_limit_s * 1e8) : 0;
+    P.max_cg = s->max_cg_iters; P.cg_rule = s->cg_rule; P.restart_to = s->restart_to;
+    P.eval_period = s->eval_period;
+    P.mixed_allowed = mixed ? 1 : 0;
+  }
+  if ((rc = up(d_parts, parts.data(), sizeof(int32_t) * parts.size()))) return rc;
+  if ((rc = up(d_order, order.data(), sizeof(int32_t) * count))) return rc;
+  if ((rc = up(d_params, hp.data(), sizeof(SolveParams) * count))) return rc;
+  if (mixed) HIPX(launch_to_f32(d_val, d_val32, nz_tot, stream));
+  HIPX(hipStreamSynchronize(stream));
+  rp_keep.clear();
+
+  BatchParams bp{};
+  bp.params = d_params;
+  bp.order = d_order;
+  bp.st = d_st;
+  bp.t0 = d_t0;
+  bp.pw_init = s->primal_weight_init;
+  bp.eta_factor = s->step_eta_factor;
+  bp.power_iters = s->power_iters;
+  bp.mixed = mixed ? 1 : 0;
+
+  const double t_setup = now_s() - t0;
+  hipEvent_t e0, e1;
+  HIPX(hipEventCreate(&e0));
+  HIPX(hipEventCreate(&e1));
+  HIPX(hipEventRecord(e0, stream));
+  HIPX(launch_batch(bp, count, stream));
+  HIPX(hipEventRecord(e1, stream));
+  HIPX(hipStreamSynchronize(stream));
+  float ms = 0.0f;
+  HIPX(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const double t_solve = now_s() - t0 - t_setup;
+
+  // ---- results
+  std::vector<SolverState> st(count);
+  std::vector<double> hx(vn_tot), hy(std::max<int64_t>(vm_tot, 1));
+  HIPX(hipMemcpyAsync(st.data(), d_st, sizeof(SolverState) * count, hipMemcpyDeviceToHost, stream));
+  HIPX(hipMemcpyAsync(hx.data(), nv[0], sizeof(double) * vn_tot, hipMemcpyDeviceToHost, stream));
+  if (vm_tot) HIPX(hipMemcpyAsync(hy.data(), mv[0], sizeof(double) * vm_tot, hipMemcpyDeviceToHost, stream));
+  HIPX(hipStreamSynchronize(stream));
+  for (int i = 0; i < count; ++i) {
+    const BatchInst& I = inst[i];
+    memcpy(x_outs[i], hx.data() + I.voff_n, sizeof(double) * I.n);
+    if (I.m) memcpy(y_outs[i], hy.data() + I.voff_m, sizeof(double) * I.m);
+    if (rs) {
+      const SolverState& S = st[i];
+      pdhcg_result& r = rs[i];
+      r.status = S.status;
+      r.returned_average = S.returned_average;
+      r.rel_primal = S.r_p; r.rel_dual = S.r_d; r.rel_gap = S.r_g; r.rel_kkt = S.kkt;
+      r.primal_obj = S.pobj; r.dual_obj = S.dobj;
+      r.iters = S.k_total; r.cg_iters_total = S.cg_total; r.restarts = S.restarts;
+      r.norm_A = S.norm_A;
+      r.setup_s = t_setup;
+      r.solve_s = t_solve;
+      r.kernel_s = ms * 1e-3;
+      r.kkt_evals = S.evals;
+    }
+  }
+  return 0;
 }

@@ -11,13 +11,19 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kLongRow = 1024;    // rows longer than this are reduced by the whole workgroup
 
 // Device CSR with 32-bit indices; val32 is an FP32 copy of val (or null).
+// dense = 1 marks a square matrix stored as nrows*ncols row-major values
+// (rowptr and col unused); only the one-workgroup-per-QP kernel takes it.
 struct DevMat {
   int32_t nrows, ncols;
   const int32_t* rowptr;
   const int32_t* col;
   const double* val;
   const float* val32;
+  int32_t dense;
 };
+
+constexpr int kDenseTile = 2048;  // doubles of the LDS tile that stages the vector of a dense product
+constexpr int kDenseRows = 4;     // rows per thread in one pass of a dense product
 
 // Static partition of a row space over the workgroups of a solve kernel.
 // Workgroup w owns rows [bounds[w], bounds[w+1]); rows of that range longer
@@ -71,11 +77,13 @@ struct SolverState {
   double K_anchor;      // relKKT of the epoch's starting point (NaN: not yet known)
   double K_prev;        // candidate relKKT at the previous evaluation of this epoch
   double omega, tau, sigma;
+  double eta;           // eta_factor / ||A||_2
   int32_t done;         // 1 once a final status is set
   int32_t status;
   int32_t returned_average;
   int32_t mixed;        // 1 while FP32 products are in use
   double r_p, r_d, r_g, kkt, pobj, dobj;  // of the returned point
+  double norm_A;        // ||A||_2 estimate (batched solves)
   uint64_t t_start;     // wall_clock64() at the start of the solve
 };
 
@@ -93,9 +101,13 @@ struct SolveParams {
   double* part;         // [NSLOT][nb]
   uint64_t* bar;        // grid barrier words (zeroed before each launch)
   SolverState* st;
-  Part pn1, pcg, pm;
+  Part pn1, pcg, pm, pt;  // n-side pass, CG (rows of Q), A rows, A' rows
+  double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf (enter every relKKT)
+  // start point of a batched solve (null: zero)
+  const double* x0;
+  const double* y0;
   // settings
-  double tol, eps_factor, beta_suf, beta_nec, beta_art, theta, eta;
+  double tol, eps_factor, beta_suf, beta_nec, beta_art, theta;
   int64_t max_iters;
   int64_t iters_this_launch;   // bound on iterations per launch
   uint64_t time_limit_ticks;   // 0 = none; wall_clock64() ticks
@@ -115,9 +127,24 @@ struct PowerParams {
   int32_t iters;
 };
 
-hipError_t launch_solve(const SolveParams& p, int nb, double nb_inf, double nc_inf, hipStream_t s);
+// Batched solve: params[i] describes QP i (pointers into the packed device
+// arrays, its row partitions for one workgroup, its x0/y0); workgroup g
+// solves QP order[g].  Parameter blocks are written by the host before the
+// launch and only read by the kernel.
+struct BatchParams {
+  const SolveParams* params;
+  const int32_t* order;
+  SolverState* st;           // [count] results
+  uint64_t* t0;              // wall clock at the start of the batch
+  double pw_init, eta_factor;
+  int32_t power_iters;
+  int32_t mixed;
+};
+
+hipError_t launch_batch(const BatchParams& p, int count, hipStream_t s);
+hipError_t launch_solve(const SolveParams* p_dev, int nb, hipStream_t s);
 hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s);
-hipError_t launch_init_point(const SolveParams& p, const double* x0, const double* y0, int nb, hipStream_t s);
+hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hipStream_t s);
 hipError_t launch_spmv(const DevMat& M, const Part& pt, int nb, int precision, const double* x, float* x32,
                        double* y, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);

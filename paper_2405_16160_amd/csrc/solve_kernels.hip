@@ -23,11 +23,90 @@ __device__ __forceinline__ double pos_part(double v) { return v > 0.0 ? v : (v =
 
 // ------------------------------------------------------------------ phases
 
+// One workgroup computes out_i = sum_j M[i,j] v_j for a dense symmetric n x n
+// matrix stored row-major.  Symmetry lets thread t own rows i = t + kBlock*k
+// and stream M row by row: for each j the workgroup reads M[j, i0..] (=
+// M[i0.., j]) with unit stride across threads, and v_j is broadcast from an
+// LDS tile.  No cross-lane reduction is needed.  gen(j) produces v_j (FP64)
+// and is called once per j per row pass; epi(i, sum) receives each row.
+template <typename V, typename Gen, typename Epi>
+__device__ void dense_rows(const V* M, int n, double* svec, Gen gen, Epi epi) {
+  for (int i0 = 0; i0 < n; i0 += kBlock * kDenseRows) {
+    double acc[kDenseRows];
+#pragma unroll
+    for (int k = 0; k < kDenseRows; ++k) acc[k] = 0.0;
+    for (int j0 = 0; j0 < n; j0 += kDenseTile) {
+      const int jt = n - j0 < kDenseTile ? n - j0 : kDenseTile;
+      __syncthreads();
+      for (int j = threadIdx.x; j < jt; j += kBlock) svec[j] = gen(j0 + j, i0 == 0);
+      __syncthreads();
+      const V* row = M + (int64_t)j0 * n + i0 + threadIdx.x;
+      int j = 0;
+      for (; j + 4 <= jt; j += 4, row += 4 * (int64_t)n) {
+#pragma unroll
+        for (int k = 0; k < kDenseRows; ++k) {
+          const int i = i0 + threadIdx.x + k * kBlock;
+          if (i < n) {
+            acc[k] += ldv(row, k * kBlock) * svec[j] + ldv(row + n, k * kBlock) * svec[j + 1] +
+                      ldv(row + 2 * (int64_t)n, k * kBlock) * svec[j + 2] +
+                      ldv(row + 3 * (int64_t)n, k * kBlock) * svec[j + 3];
+          }
+        }
+      }
+      for (; j < jt; ++j, row += n) {
+#pragma unroll
+        for (int k = 0; k < kDenseRows; ++k) {
+          const int i = i0 + threadIdx.x + k * kBlock;
+          if (i < n) acc[k] += ldv(row, k * kBlock) * svec[j];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kDenseRows; ++k) {
+      const int i = i0 + threadIdx.x + k * kBlock;
+      if (i < n) epi(i, acc[k]);
+    }
+  }
+  __syncthreads();
+}
+
+// q = Q xv for a dense Q owned by one workgroup
+__device__ __attribute__((noinline)) void dense_qx(const SolveParams& P, const double* xv, double* svec) {
+  dense_rows(P.Q.val, P.n, svec, [&](int j, bool) { return xv[j]; }, [&](int i, double v) { P.q[i] = v; });
+}
+
+// CG product for a dense Q owned by one workgroup: stage p in LDS, stream Q
+template <typename V>
+__device__ __attribute__((noinline)) void dense_cg_spmv(const SolveParams& P, const Block& B, const V* qd,
+                                                        const double* pprev, double* pcur, double beta, int first,
+                                                        double inv_tau, double* lds, double* svec) {
+  double s[1] = {0.0}, dummy[1] = {0.0};
+  dense_rows(
+      qd, P.n, svec,
+      [&](int j, bool first_pass) {
+        const double pj = first ? P.r[j] : P.r[j] + beta * pprev[j];
+        if (first_pass) pcur[j] = pj;
+        return pj;
+      },
+      [&](int i, double qp) {
+        const double pi = first ? P.r[i] : P.r[i] + beta * pprev[i];
+        const double qi = qp + pi * inv_tau;
+        P.q[i] = qi;
+        s[0] += pi * qi;
+      });
+  block_reduce<1, 0>(s, dummy, lds);
+  if (B.tid == 0) P.part[S_PQ * B.nb + B.b] = s[0];
+}
+
 // n-side product at (xv, yv): g = Q xv + A' yv + c, row by row over the
 // workgroup's rows of the partition `pt`.  Writes r = -g (and its FP32 copy)
 // when r != null and stores the six n-side partials at slot0.
-__device__ void phase_nside(const SolveParams& P, const Part& pt, const Block& B, const double* xv,
-                            const double* yv, double* r, float* r32, int slot0, double* lds) {
+template <bool DENSE>
+__device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, const Part& pt, const Block& B, const double* xv,
+                            const double* yv, double* r, float* r32, int slot0, double* lds, double* svec) {
+  // dense Q (one workgroup per QP): Q xv first, into the free CG buffer q
+  constexpr bool dense = DENSE;
+  if (dense) dense_qx(P, xv, svec);
   const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
   const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
   double s[3] = {0.0, 0.0, 0.0};   // g.g, x.Qx, c.x
@@ -52,8 +131,10 @@ __device__ void phase_nside(const SolveParams& P, const Part& pt, const Block& B
     const bool act = i < r1;
     int qb = 0, qe = 0, tb = 0, te = 0;
     if (act) {
-      qb = P.Q.rowptr[i];
-      qe = P.Q.rowptr[i + 1];
+      if (!dense) {
+        qb = P.Q.rowptr[i];
+        qe = P.Q.rowptr[i + 1];
+      }
       if (P.m > 0) {
         tb = P.At.rowptr[i];
         te = P.At.rowptr[i + 1];
@@ -67,16 +148,16 @@ __device__ void phase_nside(const SolveParams& P, const Part& pt, const Block& B
     }
     sq = group_sum(sq, G);
     st = group_sum(st, G);
-    if (use && lane == 0) epi(i, sq, st);
+    if (use && lane == 0) epi(i, dense ? P.q[i] : sq, st);
   }
   for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
     const int i = pt.long_rows[t];
-    double v[2] = {row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gx),
+    double v[2] = {dense ? 0.0 : row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gx),
                    P.m > 0 ? row_partial(P.At.col, P.At.val, P.At.rowptr[i], P.At.rowptr[i + 1], B.tid, kBlock, gy)
                            : 0.0};
     double dummy[1] = {0.0};
     block_reduce<2, 0>(v, dummy, lds);
-    if (B.tid == 0) epi(i, v[0], v[1]);
+    if (B.tid == 0) epi(i, dense ? P.q[i] : v[0], v[1]);
   }
   block_reduce<3, 3>(s, mx, lds);
   if (B.tid == 0) {
@@ -131,7 +212,7 @@ __device__ void store_mside(const SolveParams& P, const Block& B, int slot0, dou
 }
 
 // ax = A x and the m-side partials of the current point (start of a solve)
-__device__ void phase_ax(const SolveParams& P, const Block& B, double* lds) {
+__device__ __attribute__((noinline)) void phase_ax(const SolveParams& P, const Block& B, double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(P, B, P.A.val, P.x, lds, [&](int i, double u) {
     P.ax[i] = u;
@@ -143,8 +224,9 @@ __device__ void phase_ax(const SolveParams& P, const Block& B, double* lds) {
 }
 
 // relKKT pieces of the average: n-side at (xa, ya), m-side u = A xa (kept in ax_avg)
-__device__ void phase_eval_avg(const SolveParams& P, const Block& B, double* lds) {
-  phase_nside(P, P.pn1, B, P.xa, P.ya, nullptr, nullptr, S_AVG0, lds);
+template <bool DENSE>
+__device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, const Block& B, double* lds, double* svec) {
+  phase_nside<DENSE>(P, P.pn1, B, P.xa, P.ya, nullptr, nullptr, S_AVG0, lds, svec);
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(P, B, P.A.val, P.xa, lds, [&](int i, double u) {
     P.ax_avg[i] = u;
@@ -157,10 +239,14 @@ __device__ void phase_eval_avg(const SolveParams& P, const Block& B, double* lds
 
 // CG product: p = r + beta p_prev on the owned rows (FP64, stored), and
 // q = (Q + I/tau) p with p gathered through GatherDir; partial p.q.
-template <typename V, typename T>
-__device__ void phase_cg_spmv(const SolveParams& P, const Block& B, const V* qval, const T* rg, const T* ppg,
+template <bool DENSE, typename V, typename T>
+__device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, const Block& B, const V* qval, const T* rg, const T* ppg,
                               const double* pprev, double* pcur, float* pcur32, double beta, int first,
-                              double inv_tau, double* lds) {
+                              double inv_tau, double* lds, double* svec) {
+  if constexpr (DENSE) {
+    dense_cg_spmv(P, B, qval, pprev, pcur, beta, first, inv_tau, lds, svec);
+    return;
+  }
   const Part& pt = P.pcg;
   const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
   const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
@@ -200,7 +286,7 @@ __device__ void phase_cg_spmv(const SolveParams& P, const Block& B, const V* qva
 }
 
 // CG update on the owned rows: x += alpha p, r -= alpha q; partial r.r
-__device__ void phase_cg_update(const SolveParams& P, const Block& B, const double* pcur, double alpha, int mixed,
+__device__ __attribute__((noinline)) void phase_cg_update(const SolveParams& P, const Block& B, const double* pcur, double alpha, int mixed,
                                 double* lds) {
   const int r0 = P.pcg.bounds[B.b], r1 = P.pcg.bounds[B.b + 1];
   double s[1] = {0.0};
@@ -224,7 +310,7 @@ __device__ void phase_cg_update(const SolveParams& P, const Block& B, const doub
 // y <- max(0, y + sigma (2u - A x^k - b)); A x^k <- u; ya += w (y - ya);
 // xa += w (x - xa) on an n-slice; m-side partials of the new point.
 template <typename V, typename Tx>
-__device__ void phase_dual(const SolveParams& P, const Block& B, const V* aval, const Tx* xg, double sigma, double w,
+__device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, const Block& B, const V* aval, const Tx* xg, double sigma, double w,
                            double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(P, B, aval, xg, lds, [&](int i, double u) {
@@ -246,7 +332,7 @@ __device__ void phase_dual(const SolveParams& P, const Block& B, const V* aval, 
 // Restart: move to the candidate (average when use_avg), measure the
 // movement from the previous anchor, and make the candidate the new anchor
 // and the new (empty) average.
-__device__ void phase_restart(const SolveParams& P, const Block& B, int use_avg, int mixed, double* lds) {
+__device__ __attribute__((noinline)) void phase_restart(const SolveParams& P, const Block& B, int use_avg, int mixed, double* lds) {
   double s[2] = {0.0, 0.0};
   const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
   for (int j = n0 + B.tid; j < n1; j += kBlock) {
@@ -283,7 +369,7 @@ __device__ void phase_restart(const SolveParams& P, const Block& B, int use_avg,
 
 // copy src -> dst on the workgroup's n- and m-slices (returning the average
 // or restoring the anchor at the end of a solve)
-__device__ void phase_copy_point(const SolveParams& P, const Block& B, const double* xs, const double* ys) {
+__device__ __attribute__((noinline)) void phase_copy_point(const SolveParams& P, const Block& B, const double* xs, const double* ys) {
   const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
   for (int j = n0 + B.tid; j < n1; j += kBlock) P.x[j] = xs[j];
   const int m0 = P.pm.bounds[B.b], m1 = P.pm.bounds[B.b + 1];
@@ -308,7 +394,7 @@ __device__ Kkt kkt_from(const double* s, const double* mx, double nb_inf, double
   return k;
 }
 
-__device__ Kkt reduce_kkt(const SolveParams& P, const Block& B, int slot0, double nb_inf, double nc_inf, double* gg,
+__device__ __attribute__((noinline)) Kkt reduce_kkt(const SolveParams& P, const Block& B, int slot0, double nb_inf, double nc_inf, double* gg,
                           double* flag, double* lds) {
   const int ss[4] = {slot0 + S_GG, slot0 + S_XQX, slot0 + S_CX, slot0 + S_BY};
   const int ms[6] = {slot0 + S_MG, slot0 + S_MQX, slot0 + S_MATY, slot0 + S_MVIOL, slot0 + S_MAX, S_FLAG};
@@ -322,7 +408,7 @@ __device__ Kkt reduce_kkt(const SolveParams& P, const Block& B, int slot0, doubl
   return k;
 }
 
-__device__ double reduce_one(const SolveParams& P, const Block& B, int slot, double* lds) {
+__device__ __attribute__((noinline)) double reduce_one(const SolveParams& P, const Block& B, int slot, double* lds) {
   const int ss[1] = {slot};
   const int ms[1] = {0};
   double s[1], mx[1];
@@ -334,12 +420,14 @@ __device__ double reduce_one(const SolveParams& P, const Block& B, int slot, dou
 
 // ------------------------------------------------------------- main kernel
 
-__global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, double nb_inf, double nc_inf) {
-  __shared__ double lds[kWaves * 16];
-  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
-  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
-  SolverState S = *P.st;
-  if (S.done) return;
+// The restarted PDHCG loop (Alg. 1 with the practical rules of Sec. 4),
+// shared by the cooperative single-QP kernel (many workgroups, grid
+// barriers) and the batched kernel (one workgroup per QP, nb = 1, where a
+// barrier is a workgroup barrier).  Runs at most `budget` iterations from
+// state S; returns false only if a grid barrier failed.
+template <bool DENSE>
+__device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, SolverState& S, double nb_inf,
+                      double nc_inf, double* lds, double* svec, int64_t budget) {
   bool ok = true;
 
   if (S.K_anchor != S.K_anchor) {  // first launch of a solve: m-side of the start point
@@ -347,12 +435,11 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, doub
     ok = gs.sync();
   }
 
-  int64_t budget = P.iters_this_launch;
   Kkt kc{}, ka{};
   bool have_avg = false;
   while (ok && !S.done && budget > 0) {
     // ---- n-side pass at z^{n,k}: r0 = -(Qx + A'y + c), relKKT(z^{n,k})
-    phase_nside(P, P.pn1, B, P.x, P.y, P.r, S.mixed ? P.r32 : nullptr, 0, lds);
+    phase_nside<DENSE>(P, P.pn1, B, P.x, P.y, P.r, S.mixed ? P.r32 : nullptr, 0, lds, svec);
     if (B.tid == 0) {
       double f = 0.0;
       if (B.b == 0 && P.time_limit_ticks && wall_clock64() - S.t_start > P.time_limit_ticks) f = 1.0;
@@ -391,7 +478,7 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, doub
     }
     // ---- restart evaluation (Sec. 4, adaptive restart)
     if (S.k > 0 && S.k % P.eval_period == 0) {
-      phase_eval_avg(P, B, lds);
+      phase_eval_avg<DENSE>(P, B, lds, svec);
       if (!(ok = gs.sync())) break;
       ka = reduce_kkt(P, B, S_AVG0, nb_inf, nc_inf, nullptr, nullptr, lds);
       have_avg = true;
@@ -421,8 +508,8 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, doub
         const double dx = sqrt(s2[0]), dy = sqrt(s2[1]);
         if (P.theta > 0.0 && dx > 1e-10 && dy > 1e-10)
           S.omega = exp(P.theta * log(dy / dx) + (1.0 - P.theta) * log(S.omega));
-        S.tau = P.eta / S.omega;
-        S.sigma = P.eta * S.omega;
+        S.tau = S.eta / S.omega;
+        S.sigma = S.eta * S.omega;
         S.K_anchor = Kc;
         S.K_prev = INFINITY;
         S.k = 0;
@@ -442,7 +529,7 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, doub
         kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, nullptr, nullptr, lds);
       }
       if (S.k > 0 && !have_avg) {
-        phase_eval_avg(P, B, lds);
+        phase_eval_avg<DENSE>(P, B, lds, svec);
         if (!(ok = gs.sync())) break;
         ka = reduce_kkt(P, B, S_AVG0, nb_inf, nc_inf, nullptr, nullptr, lds);
         have_avg = true;
@@ -469,9 +556,9 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, doub
         if (S.mixed) {
           float* pc32 = cur ? P.p32_1 : P.p32_0;
           const float* pp32 = cur ? P.p32_0 : P.p32_1;
-          phase_cg_spmv(P, B, P.Q.val32, (const float*)P.r32, pp32, pp, pc, pc32, beta, first, inv_tau, lds);
+          phase_cg_spmv<DENSE>(P, B, P.Q.val32, (const float*)P.r32, pp32, pp, pc, pc32, beta, first, inv_tau, lds, svec);
         } else {
-          phase_cg_spmv(P, B, P.Q.val, (const double*)P.r, pp, pp, pc, nullptr, beta, first, inv_tau, lds);
+          phase_cg_spmv<DENSE>(P, B, P.Q.val, (const double*)P.r, pp, pp, pc, nullptr, beta, first, inv_tau, lds, svec);
         }
         if (!(ok = gs.sync())) break;
         const double pq = reduce_one(P, B, S_PQ, lds);
@@ -502,11 +589,24 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, doub
     S.k_total += 1;
     budget -= 1;
   }
-  if (!ok) {
-    if (B.b == 0 && B.tid == 0) P.st->done = -1;  // barrier failure: reported as a HIP error
-    return;
+  return ok;
+}
+
+__global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
+  const SolveParams& P = *Pg;
+  const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
+  __shared__ double lds[kWaves * 16];
+  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
+  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  SolverState S = *P.st;
+  if (S.done) return;
+  const bool ok = drive<false>(P, B, gs, S, nb_inf, nc_inf, lds, nullptr, P.iters_this_launch);
+  if (B.b == 0 && B.tid == 0) {
+    if (!ok)
+      P.st->done = -1;  // barrier failure: reported as a HIP error
+    else
+      *P.st = S;
   }
-  if (B.b == 0 && B.tid == 0) *P.st = S;
 }
 
 // -------------------------------------------------------- power iteration
@@ -515,97 +615,160 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(SolveParams P, doub
 // the paper does not say how it is obtained): start from
 // v_j = 0.5 + ((j * 40503) mod 1024) / 1024, normalised; each step
 // u = A v, w = A'u, lambda = ||w||, v = w / lambda; ||A|| ~ sqrt(lambda).
-__global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) {
-  __shared__ double lds[kWaves * 8];
-  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
-  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
-  const int n0 = P.pn.bounds[B.b], n1 = P.pn.bounds[B.b + 1];
+// v, w (n) and u (m) are work vectors; pn partitions the rows of A', pm
+// those of A.  Returns false if a grid barrier failed.
+__device__ bool power_norm(const DevMat& A, const DevMat& At, double* v, double* w, double* u, double* part,
+                           const Part& pn, const Part& pm, int iters, const Block& B, GridSync& gs, double* lds,
+                           double* out) {
+  const int n0 = pn.bounds[B.b], n1 = pn.bounds[B.b + 1];
   double s[1] = {0.0}, dummy[1] = {0.0};
   for (int j = n0 + B.tid; j < n1; j += kBlock) {
-    const double v = 0.5 + (double)(((uint64_t)j * 40503ull) % 1024ull) / 1024.0;
-    P.w[j] = v;
-    s[0] += v * v;
+    const double vj = 0.5 + (double)(((uint64_t)j * 40503ull) % 1024ull) / 1024.0;
+    w[j] = vj;
+    s[0] += vj * vj;
   }
   block_reduce<1, 0>(s, dummy, lds);
-  if (B.tid == 0) P.part[S_PW * B.nb + B.b] = s[0];
-  if (!gs.sync()) return;
+  if (B.tid == 0) part[S_PW * B.nb + B.b] = s[0];
+  if (!gs.sync()) return false;
   const int ss[1] = {S_PW};
   const int ms[1] = {0};
   double tot[1], m0[1];
-  reduce_partials<1, 0>(P.part, B.nb, ss, ms, tot, m0, lds);
+  reduce_partials<1, 0>(part, B.nb, ss, ms, tot, m0, lds);
   double scale = 1.0 / sqrt(tot[0]);
   double lam = 0.0;
-  for (int it = 0; it < P.iters; ++it) {
-    // v = w * scale on owned rows (scale = 1/||w||)
-    for (int j = n0 + B.tid; j < n1; j += kBlock) P.v[j] = P.w[j] * scale;
-    if (!gs.sync()) return;
-    // u = A v
-    {
-      const Part& pt = P.pm;
-      const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
-      const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
-      GatherVec<double> gv{P.v};
+  for (int it = 0; it < iters; ++it) {
+    for (int j = n0 + B.tid; j < n1; j += kBlock) v[j] = w[j] * scale;
+    if (!gs.sync()) return false;
+    {  // u = A v
+      const int r0 = pm.bounds[B.b], r1 = pm.bounds[B.b + 1];
+      const int G = pm.group, lane = B.tid & (G - 1), ng = kBlock / G;
+      GatherVec<double> gv{v};
       for (int base = r0; base < r1; base += ng) {
         const int i = base + B.tid / G;
         const bool act = i < r1;
         int ab = 0, ae = 0;
-        if (act) { ab = P.A.rowptr[i]; ae = P.A.rowptr[i + 1]; }
+        if (act) { ab = A.rowptr[i]; ae = A.rowptr[i + 1]; }
         const bool use = act && (ae - ab) <= kLongRow;
-        double su = use ? row_partial(P.A.col, P.A.val, ab, ae, lane, G, gv) : 0.0;
+        double su = use ? row_partial(A.col, A.val, ab, ae, lane, G, gv) : 0.0;
         su = group_sum(su, G);
-        if (use && lane == 0) P.u[i] = su;
+        if (use && lane == 0) u[i] = su;
       }
-      for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
-        const int i = pt.long_rows[t];
-        double v[1] = {row_partial(P.A.col, P.A.val, P.A.rowptr[i], P.A.rowptr[i + 1], B.tid, kBlock, gv)};
-        block_reduce<1, 0>(v, dummy, lds);
-        if (B.tid == 0) P.u[i] = v[0];
+      for (int t = pm.long_ptr[B.b]; t < pm.long_ptr[B.b + 1]; ++t) {
+        const int i = pm.long_rows[t];
+        double vv[1] = {row_partial(A.col, A.val, A.rowptr[i], A.rowptr[i + 1], B.tid, kBlock, gv)};
+        block_reduce<1, 0>(vv, dummy, lds);
+        if (B.tid == 0) u[i] = vv[0];
       }
     }
-    if (!gs.sync()) return;
-    // w = A'u, partial ||w||^2
-    {
-      const Part& pt = P.pn;
-      const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
-      GatherVec<double> gu{P.u};
+    if (!gs.sync()) return false;
+    {  // w = A'u, partial ||w||^2
+      const int G = pn.group, lane = B.tid & (G - 1), ng = kBlock / G;
+      GatherVec<double> gu{u};
       double sw[1] = {0.0};
       for (int base = n0; base < n1; base += ng) {
         const int i = base + B.tid / G;
         const bool act = i < n1;
         int tb = 0, te = 0;
-        if (act) { tb = P.At.rowptr[i]; te = P.At.rowptr[i + 1]; }
+        if (act) { tb = At.rowptr[i]; te = At.rowptr[i + 1]; }
         const bool use = act && (te - tb) <= kLongRow;
-        double st = use ? row_partial(P.At.col, P.At.val, tb, te, lane, G, gu) : 0.0;
+        double st = use ? row_partial(At.col, At.val, tb, te, lane, G, gu) : 0.0;
         st = group_sum(st, G);
         if (use && lane == 0) {
-          P.w[i] = st;
+          w[i] = st;
           sw[0] += st * st;
         }
       }
-      for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
-        const int i = pt.long_rows[t];
-        double v[1] = {row_partial(P.At.col, P.At.val, P.At.rowptr[i], P.At.rowptr[i + 1], B.tid, kBlock, gu)};
-        block_reduce<1, 0>(v, dummy, lds);
+      for (int t = pn.long_ptr[B.b]; t < pn.long_ptr[B.b + 1]; ++t) {
+        const int i = pn.long_rows[t];
+        double vv[1] = {row_partial(At.col, At.val, At.rowptr[i], At.rowptr[i + 1], B.tid, kBlock, gu)};
+        block_reduce<1, 0>(vv, dummy, lds);
         if (B.tid == 0) {
-          P.w[i] = v[0];
-          sw[0] += v[0] * v[0];
+          w[i] = vv[0];
+          sw[0] += vv[0] * vv[0];
         }
       }
       block_reduce<1, 0>(sw, dummy, lds);
-      if (B.tid == 0) P.part[S_PW * B.nb + B.b] = sw[0];
+      if (B.tid == 0) part[S_PW * B.nb + B.b] = sw[0];
     }
-    if (!gs.sync()) return;
-    reduce_partials<1, 0>(P.part, B.nb, ss, ms, tot, m0, lds);
+    if (!gs.sync()) return false;
+    reduce_partials<1, 0>(part, B.nb, ss, ms, tot, m0, lds);
     lam = sqrt(tot[0]);
     if (!(lam > 0.0)) break;
     scale = 1.0 / lam;
   }
-  if (B.b == 0 && B.tid == 0) P.out[0] = sqrt(lam);
+  *out = sqrt(lam);
+  return true;
+}
+
+__global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) {
+  __shared__ double lds[kWaves * 8];
+  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
+  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  double nrm = 0.0;
+  if (power_norm(P.A, P.At, P.v, P.w, P.u, P.part, P.pn, P.pm, P.iters, B, gs, lds, &nrm) && B.b == 0 &&
+      B.tid == 0)
+    P.out[0] = nrm;
+}
+
+// ------------------------------------------------------------ batched solve
+
+// One workgroup per QP: workgroup g solves instance order[g] (the host sorts
+// instances by decreasing work, so the dispatcher hands out the largest
+// first).  Each workgroup runs the same loop as the cooperative kernel with
+// nb = 1 (a grid barrier degenerates to a workgroup barrier), on its own slice
+// of the packed matrices and vectors; dense Q blocks use the streaming dense
+// product.  ||A|| comes from the same power iteration, per instance.
+__global__ void __launch_bounds__(kBlock) pdhcg_batch_kernel(BatchParams BP) {
+  __shared__ double lds[kWaves * 16];
+  __shared__ double svec[kDenseTile];
+  const int idx = BP.order[blockIdx.x];
+  const SolveParams& P = BP.params[idx];
+  Block B{0, 1, (int)threadIdx.x};
+  GridSync gs{nullptr, 1u, 0};
+  // start point (x0 or 0; y0 projected onto y >= 0, or 0)
+  for (int j = B.tid; j < P.n; j += kBlock) {
+    const double v = P.x0 ? P.x0[j] : 0.0;
+    P.x[j] = v;
+    P.xa[j] = v;
+    P.x_anc[j] = v;
+    if (BP.mixed) P.x32[j] = (float)v;
+  }
+  for (int i = B.tid; i < P.m; i += kBlock) {
+    const double v = pos_part(P.y0 ? P.y0[i] : 0.0);
+    P.y[i] = v;
+    P.ya[i] = v;
+    P.y_anc[i] = v;
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  if (P.m > 0) power_norm(P.A, P.At, P.p0, P.p1, P.ax_avg, P.part, P.pt, P.pm, BP.power_iters, B, gs, lds, &nrm);
+  SolverState S{};
+  S.K_anchor = NAN;
+  S.K_prev = INFINITY;
+  S.omega = BP.pw_init;
+  S.eta = BP.eta_factor / (nrm > 0.0 ? nrm : 1.0);
+  S.tau = S.eta / S.omega;
+  S.sigma = S.eta * S.omega;
+  S.mixed = BP.mixed;
+  S.t_start = *BP.t0;
+  S.norm_A = nrm;
+  if (P.Q.dense)
+    drive<true>(P, B, gs, S, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
+  else
+    drive<false>(P, B, gs, S, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
+  if (B.tid == 0) BP.st[idx] = S;
+}
+
+__global__ void batch_clock_kernel(uint64_t* t0) {
+  if (threadIdx.x == 0) *t0 = wall_clock64();
 }
 
 // ------------------------------------------------------ small helper kernels
 
-__global__ void init_point_kernel(SolveParams P, const double* x0, const double* y0) {
+__global__ void init_point_kernel(const SolveParams* __restrict__ Pg) {
+  const SolveParams& P = *Pg;
+  const double* x0 = P.x0;
+  const double* y0 = P.y0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < P.n; j += stride) {
     const double v = x0 ? x0[j] : 0.0;
@@ -657,9 +820,9 @@ __global__ void to_f32_kernel(const double* in, float* out, int64_t n) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_solve(const SolveParams& p, int nb, double nb_inf, double nc_inf, hipStream_t s) {
-  SolveParams pc = p;
-  void* args[] = {&pc, &nb_inf, &nc_inf};
+hipError_t launch_solve(const SolveParams* p_dev, int nb, hipStream_t s) {
+  const SolveParams* pc = p_dev;
+  void* args[] = {&pc};
   return hipLaunchCooperativeKernel((const void*)pdhcg_solve_kernel, dim3(nb), dim3(kBlock), args, 0, s);
 }
 
@@ -669,12 +832,18 @@ hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s) {
   return hipLaunchCooperativeKernel((const void*)pdhcg_power_kernel, dim3(nb), dim3(kBlock), args, 0, s);
 }
 
-hipError_t launch_init_point(const SolveParams& p, const double* x0, const double* y0, int nb, hipStream_t s) {
-  int64_t len = p.n > p.m ? p.n : p.m;
+hipError_t launch_batch(const BatchParams& p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(batch_clock_kernel, dim3(1), dim3(64), 0, s, p.t0);
+  hipLaunchKernelGGL(pdhcg_batch_kernel, dim3(count), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hipStream_t s) {
+  int64_t len = n > m ? n : m;
   int grid = (int)((len + kBlock - 1) / kBlock);
   if (grid < 1) grid = 1;
   if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(init_point_kernel, dim3(grid), dim3(kBlock), 0, s, p, x0, y0);
+  hipLaunchKernelGGL(init_point_kernel, dim3(grid), dim3(kBlock), 0, s, p_dev);
   return hipGetLastError();
 }
 
