@@ -84,6 +84,8 @@ typedef struct {
                                         certified against the FP64 data */
     double time_limit_s;             /* 0 = none */
     int32_t num_blocks;              /* 0 = planner's choice; else workgroups of the solve kernel */
+    int32_t warm_fallback;           /* 1: if relKKT at a given (x0, y0) exceeds relKKT at (0, 0),
+                                        start from (0, 0) instead (a cold start) */
     int32_t verbose;                 /* 0 = silent */
 } pdhcg_settings;
 
@@ -101,6 +103,7 @@ typedef struct {
     double kernel_s;                 /* device time of the solve kernel launches (HIP events on the
                                         handle's stream) */
     int64_t kkt_evals;               /* restart evaluations (relKKT of the average) performed */
+    int32_t cold_fallback;           /* 1 if the given start point was replaced by (0, 0) */
 } pdhcg_result;
 
 typedef struct pdhcg_handle pdhcg_handle;

@@ -1,0 +1,62 @@
+/*
+ * pdhcg_mlp.h -- C ABI of the warm-start network for parametric QP families.
+ *
+ * A multilayer perceptron n_in -> n_hid -> n_hid -> n_out (ReLU on the two
+ * hidden layers, linear output) that maps the parameter of a QP family to a
+ * predicted primal-dual pair (x, y), used as the start point of restarted
+ * PDHCG.  Weights and activations are bfloat16 in the matrix products (MFMA,
+ * FP32 accumulation); FP32 master weights are updated by Adam.  Training and
+ * inference run in the library's HIP kernels.
+ *
+ * Parameter packing (FP32, used by set/get and by the gradient output):
+ * W1 (n_in x n_hid, row-major), b1 (n_hid), W2 (n_hid x n_hid), b2 (n_hid),
+ * W3 (n_hid x n_out), b3 (n_out); a layer maps a row batch H to H W + b.
+ *
+ * Conventions: return 0 on success or a negative PDHCG_ERR_* code (see
+ * pdhcg.h); pdhcg_last_error() gives the message.  X, T and Y are FP32
+ * row-major device arrays (batch rows).  All work is issued on the stream
+ * given at creation, and each call returns after that stream has finished.
+ * The handle owns its device buffers; it is not thread-safe.
+ */
+#ifndef PDHCG_MLP_H
+#define PDHCG_MLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdhcg_mlp pdhcg_mlp;
+
+/* Allocate a network and its workspace for batches of up to max_batch rows.
+ * Weights start at zero: call pdhcg_mlp_set_params before use. */
+int pdhcg_mlp_create(pdhcg_mlp** h, int32_t n_in, int32_t n_hid, int32_t n_out, int32_t max_batch,
+                     void* hip_stream);
+
+/* Number of FP32 values in the packed parameter vector. */
+int64_t pdhcg_mlp_num_params(const pdhcg_mlp* h);
+
+/* Copy packed FP32 parameters from / to host memory; set also resets Adam. */
+int pdhcg_mlp_set_params(pdhcg_mlp* h, const float* params);
+int pdhcg_mlp_get_params(const pdhcg_mlp* h, float* params);
+
+/* Y (batch x n_out, FP32) = network(X (batch x n_in)). */
+int pdhcg_mlp_forward(pdhcg_mlp* h, const float* X, int32_t batch, float* Y);
+
+/* Mean-squared-error loss of network(X) against targets T (batch x n_out)
+ * and its gradient with respect to every parameter (kept on the device for
+ * pdhcg_mlp_adam_step; copied to host `grads` in the packed layout unless
+ * grads is NULL).  *loss receives the loss (may be NULL). */
+int pdhcg_mlp_loss_grad(pdhcg_mlp* h, const float* X, const float* T, int32_t batch, float* loss, float* grads);
+
+/* One Adam step with the gradient of the last pdhcg_mlp_loss_grad call. */
+int pdhcg_mlp_adam_step(pdhcg_mlp* h, float lr, float beta1, float beta2, float eps);
+
+void pdhcg_mlp_destroy(pdhcg_mlp* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDHCG_MLP_H */

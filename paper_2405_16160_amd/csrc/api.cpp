@@ -27,6 +27,12 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+int pdhcg::set_error(int code, const char* msg) { return fail(code, msg); }
+
+namespace {
+
 #define HIPX(call)                                                                         \
   do {                                                                                     \
     hipError_t e_ = (call);                                                                \
@@ -35,6 +41,18 @@ int fail(int code, const std::string& msg) {
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// relKKT at x = 0, y = 0: Ax = Qx = A'y = 0, so r_primal = max((-b)^+) /
+// (1 + ||b||_inf), r_dual = ||c||_inf / (1 + ||c||_inf), r_gap = 0
+double kkt_at_zero(const double* b, int64_t m, const double* c, int64_t n) {
+  double viol = 0.0, bi = 0.0, ci = 0.0;
+  for (int64_t i = 0; i < m; ++i) {
+    viol = std::max(viol, -b[i]);
+    bi = std::max(bi, fabs(b[i]));
+  }
+  for (int64_t j = 0; j < n; ++j) ci = std::max(ci, fabs(c[j]));
+  return std::max(viol / (1.0 + bi), ci / (1.0 + ci));
 }
 
 double max_abs_nan(const double* v, int64_t n) {
@@ -124,7 +142,7 @@ bool exactly_symmetric(const HostCsr& Q) {
 }
 
 struct HostPart {
-  std::vector<int32_t> bounds, long_ptr, long_rows;
+  std::vector<int32_t> bounds, long_ptr, long_rows, tile_ptr, tiles;
   int32_t group = 1;
 };
 
@@ -134,12 +152,17 @@ int pow2_ceil(double v) {
   return g;
 }
 
-// Contiguous row ranges of near-equal work (row length + 2 per row) for nb
-// workgroups; rows longer than kLongRow are listed per workgroup.  The lane
-// group is the power of two at or above the mean length of the other rows.
-template <typename Len>
-HostPart build_part(int64_t nrows, int nb, Len len) {
+// Row partition for nb workgroups over the rows of one or two matrices with
+// the same rows (rp1, rp2: host row pointers, either may be null): contiguous
+// ranges of near-equal work (entries + 2 per row); rows with more than
+// kLongRow entries listed per workgroup; the other rows cut into tiles of at
+// most kTileNnz entries and kTileRows rows.  The lane group is the power of
+// two at or above the mean length of the short rows.
+HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp2) {
   HostPart P;
+  auto len = [&](int64_t i) -> int64_t {
+    return (rp1 ? rp1[i + 1] - rp1[i] : 0) + (rp2 ? rp2[i + 1] - rp2[i] : 0);
+  };
   std::vector<int64_t> pref(nrows + 1, 0);
   int64_t short_nnz = 0, short_rows = 0;
   for (int64_t i = 0; i < nrows; ++i) {
@@ -160,10 +183,30 @@ HostPart build_part(int64_t nrows, int nb, Len len) {
   P.bounds[nb] = (int32_t)nrows;
   for (int b = 1; b <= nb; ++b) P.bounds[b] = std::max(P.bounds[b], P.bounds[b - 1]);
   P.long_ptr.assign(nb + 1, 0);
+  P.tile_ptr.assign(nb + 1, 0);
+  int32_t ntiles = 0;
   for (int b = 0; b < nb; ++b) {
-    for (int64_t i = P.bounds[b]; i < P.bounds[b + 1]; ++i)
-      if (len(i) > kLongRow) P.long_rows.push_back((int32_t)i);
+    int64_t i = P.bounds[b];
+    const int64_t end = P.bounds[b + 1];
+    while (i < end) {
+      if (len(i) > kLongRow) {
+        P.long_rows.push_back((int32_t)i);
+        ++i;
+        continue;
+      }
+      const int64_t start = i;
+      int64_t acc = 0;
+      while (i < end && len(i) <= kLongRow && acc + len(i) <= kTileNnz && i - start < kTileRows) {
+        acc += len(i);
+        ++i;
+      }
+      const int32_t t[6] = {(int32_t)start, (int32_t)i, (int32_t)(rp1 ? rp1[start] : 0), (int32_t)(rp1 ? rp1[i] : 0),
+                            (int32_t)(rp2 ? rp2[start] : 0), (int32_t)(rp2 ? rp2[i] : 0)};
+      P.tiles.insert(P.tiles.end(), t, t + 6);
+      ++ntiles;
+    }
     P.long_ptr[b + 1] = (int32_t)P.long_rows.size();
+    P.tile_ptr[b + 1] = ntiles;
   }
   const double mean = short_rows ? (double)short_nnz / (double)short_rows : 1.0;
   P.group = pow2_ceil(mean);
@@ -176,9 +219,11 @@ struct DevPart {
   int32_t* bounds = nullptr;
   int32_t* long_ptr = nullptr;
   int32_t* long_rows = nullptr;
+  int32_t* tile_ptr = nullptr;
+  int32_t* tiles = nullptr;
   int32_t group = 1;
   int64_t nlong = 0;
-  Part view() const { return Part{bounds, long_ptr, long_rows, group}; }
+  Part view() const { return Part{bounds, long_ptr, long_rows, tile_ptr, tiles, group}; }
 };
 
 struct pdhcg_handle {
@@ -188,7 +233,7 @@ struct pdhcg_handle {
   pdhcg_settings s{};
   int nb = 0;                 // workgroups of the persistent kernels
   int nb_spmv = 0;            // workgroups of the standalone product kernels
-  double norm_A = 0.0, nb_inf = 0.0, nc_inf = 0.0, setup_s = 0.0;
+  double norm_A = 0.0, nb_inf = 0.0, nc_inf = 0.0, setup_s = 0.0, kkt_zero = 0.0;
   // device data
   int32_t *q_rowptr = nullptr, *q_col = nullptr, *a_rowptr = nullptr, *a_col = nullptr, *t_rowptr = nullptr,
           *t_col = nullptr;
@@ -206,6 +251,7 @@ struct pdhcg_handle {
   DevPart pn1, pcg, pm, pt;                // parts for the persistent kernels
   DevPart sq, sa, st_;                     // parts for the standalone products
   std::vector<void*> allocs;
+  std::vector<double> c_host;  // c, for relKKT(0, 0) when b changes
 
   ~pdhcg_handle() {
     if (ev0) (void)hipEventDestroy(ev0);
@@ -240,6 +286,13 @@ int upload_part(pdhcg_handle* h, const HostPart& H, DevPart& D) {
   if ((rc = h->alloc(&D.bounds, (int64_t)H.bounds.size()))) return rc;
   if ((rc = h->alloc(&D.long_ptr, (int64_t)H.long_ptr.size()))) return rc;
   if ((rc = h->alloc(&D.long_rows, (int64_t)H.long_rows.size()))) return rc;
+  if ((rc = h->alloc(&D.tile_ptr, (int64_t)H.tile_ptr.size()))) return rc;
+  if ((rc = h->alloc(&D.tiles, (int64_t)H.tiles.size()))) return rc;
+  HIPX(hipMemcpyAsync(D.tile_ptr, H.tile_ptr.data(), sizeof(int32_t) * H.tile_ptr.size(), hipMemcpyHostToDevice,
+                      h->stream));
+  if (!H.tiles.empty())
+    HIPX(hipMemcpyAsync(D.tiles, H.tiles.data(), sizeof(int32_t) * H.tiles.size(), hipMemcpyHostToDevice,
+                        h->stream));
   HIPX(hipMemcpyAsync(D.bounds, H.bounds.data(), sizeof(int32_t) * H.bounds.size(), hipMemcpyHostToDevice, h->stream));
   HIPX(hipMemcpyAsync(D.long_ptr, H.long_ptr.data(), sizeof(int32_t) * H.long_ptr.size(), hipMemcpyHostToDevice,
                       h->stream));
@@ -322,24 +375,21 @@ int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) 
   }
   nb = std::min(nb, max_nb);
   h->nb = nb;
-  const HostCsr* Ap = &A;
-  const HostCsr* Tp = &T;
-  auto qlen = [&](int64_t i) { return Q.rowptr[i + 1] - Q.rowptr[i]; };
-  auto alen = [&](int64_t i) { return Ap->nrows ? Ap->rowptr[i + 1] - Ap->rowptr[i] : 0; };
-  auto tlen = [&](int64_t i) { return Ap->nrows ? Tp->rowptr[i + 1] - Tp->rowptr[i] : 0; };
-  auto n1len = [&](int64_t i) { return qlen(i) + tlen(i); };
-  if ((rc = upload_part(h, build_part(h->n, nb, n1len), h->pn1))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nb, qlen), h->pcg))) return rc;
-  if ((rc = upload_part(h, build_part(h->m, nb, alen), h->pm))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nb, tlen), h->pt))) return rc;
+  const int64_t* qrp = Q.rowptr.data();
+  const int64_t* arp = A.nrows ? A.rowptr.data() : nullptr;
+  const int64_t* trp = A.nrows ? T.rowptr.data() : nullptr;
+  if ((rc = upload_part(h, build_part(h->n, nb, qrp, trp), h->pn1))) return rc;
+  if ((rc = upload_part(h, build_part(h->n, nb, qrp, nullptr), h->pcg))) return rc;
+  if ((rc = upload_part(h, build_part(h->m, nb, arp, nullptr), h->pm))) return rc;
+  if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr), h->pt))) return rc;
   // standalone products: enough workgroups to fill the chip
   int nbs = 64;
   const double w = (double)std::max<int64_t>(h->nnzQ, h->nnzA) + (double)std::max(h->n, h->m);
   while (nbs < 8192 && w / nbs > 2048.0) nbs <<= 1;
   h->nb_spmv = nbs;
-  if ((rc = upload_part(h, build_part(h->n, nbs, qlen), h->sq))) return rc;
-  if ((rc = upload_part(h, build_part(h->m, nbs, alen), h->sa))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nbs, tlen), h->st_))) return rc;
+  if ((rc = upload_part(h, build_part(h->n, nbs, qrp, nullptr), h->sq))) return rc;
+  if ((rc = upload_part(h, build_part(h->m, nbs, arp, nullptr), h->sa))) return rc;
+  if ((rc = upload_part(h, build_part(h->n, nbs, trp, nullptr), h->st_))) return rc;
   return 0;
 }
 
@@ -432,6 +482,7 @@ void pdhcg_default_settings(pdhcg_settings* s) {
   s->precision = 0;
   s->time_limit_s = 0.0;
   s->num_blocks = 0;
+  s->warm_fallback = 1;
   s->verbose = 0;
 }
 
@@ -471,6 +522,8 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
     return bail(fail(PDHCG_ERR_HIP, "copy of c failed"));
   h->nb_inf = max_abs_nan(hb.data(), h->m);
   h->nc_inf = max_abs_nan(hc.data(), h->n);
+  h->kkt_zero = kkt_at_zero(hb.data(), h->m, hc.data(), h->n);
+  h->c_host = hc;
 
   if ((rc = upload_csr(h, Q, &h->q_rowptr, &h->q_col, &h->q_val))) return bail(rc);
   if ((rc = upload_csr(h, A, &h->a_rowptr, &h->a_col, &h->a_val))) return bail(rc);
@@ -526,6 +579,7 @@ int pdhcg_set_b(pdhcg_handle* h, const double* b, int32_t vec_on_device) {
     HIPX(hipStreamSynchronize(h->stream));
   }
   h->nb_inf = max_abs_nan(hb.data(), h->m);
+  h->kkt_zero = kkt_at_zero(hb.data(), h->m, h->c_host.data(), h->n);
   return 0;
 }
 
@@ -550,6 +604,7 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
   SolveParams p = make_params(h);
   p.x0 = dx0;
   p.y0 = dy0;
+  p.kkt_zero = (h->s.warm_fallback && (dx0 || dy0)) ? h->kkt_zero : 0.0;
   SolverState st{};
   st.K_anchor = std::numeric_limits<double>::quiet_NaN();
   st.K_prev = std::numeric_limits<double>::infinity();
@@ -600,6 +655,7 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
     res->solve_s = now_s() - t0;
     res->kernel_s = kernel_ms * 1e-3;
     res->kkt_evals = st.evals;
+    res->cold_fallback = st.cold_fallback;
   }
   return 0;
 }
@@ -667,7 +723,8 @@ struct BatchInst {
   int64_t q_rp = 0, q_nz = 0, a_rp = 0, a_nz = 0, t_rp = 0, t_nz = 0;
   int64_t voff_n = 0, voff_m = 0;
   int64_t part_off = 0;
-  double nb_inf = 0.0, nc_inf = 0.0;
+  int64_t sub_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // long lists and tiles, relative to part_off
+  double nb_inf = 0.0, nc_inf = 0.0, kkt_zero = 0.0;
 };
 
 // exact symmetry of a host CSR given by pointers (dense: direct index check)
@@ -693,26 +750,39 @@ bool is_dense(const int64_t* rowptr, int64_t n) {
   return true;
 }
 
-// row partitions of one workgroup covering all rows (see BatchInst)
+// Row partitions of one workgroup covering all rows, packed as: for each of
+// the n-side, CG, A and A' partitions six ints (bounds[0..1], long_ptr[0..1],
+// tile_ptr[0..1], the last two relative), then the four long-row lists, then
+// the four tile arrays.
 void batch_parts(const int64_t* qrp, bool dense, int64_t n, const HostCsr& A, const HostCsr& T,
-                 std::vector<int32_t>& out, int32_t g[4]) {
+                 std::vector<int32_t>& out, int32_t g[4], int64_t off[8]) {
   const int64_t m = A.nrows;
-  auto qlen = [&](int64_t i) -> int64_t { return dense ? 0 : qrp[i + 1] - qrp[i]; };
-  auto tlen = [&](int64_t i) -> int64_t { return m ? T.rowptr[i + 1] - T.rowptr[i] : 0; };
-  auto alen = [&](int64_t i) -> int64_t { return A.rowptr[i + 1] - A.rowptr[i]; };
-  HostPart p1 = build_part(n, 1, [&](int64_t i) { return qlen(i) + tlen(i); });
-  HostPart p2 = build_part(n, 1, qlen);
-  HostPart p3 = build_part(m, 1, alen);
-  HostPart p4 = build_part(n, 1, tlen);
+  const int64_t* q = dense ? nullptr : qrp;
+  const int64_t* arp = m ? A.rowptr.data() : nullptr;
+  const int64_t* trp = m ? T.rowptr.data() : nullptr;
+  HostPart p1 = build_part(n, 1, q, trp);
+  HostPart p2 = build_part(n, 1, q, nullptr);
+  HostPart p3 = build_part(m, 1, arp, nullptr);
+  HostPart p4 = build_part(n, 1, trp, nullptr);
   const HostPart* ps[4] = {&p1, &p2, &p3, &p4};
+  const int64_t base = (int64_t)out.size();
   for (int k = 0; k < 4; ++k) {
     out.push_back(ps[k]->bounds[0]);
     out.push_back(ps[k]->bounds[1]);
     out.push_back(0);
     out.push_back((int32_t)ps[k]->long_rows.size());
+    out.push_back(0);
+    out.push_back(ps[k]->tile_ptr[1]);
     g[k] = ps[k]->group;
   }
-  for (int k = 0; k < 4; ++k) out.insert(out.end(), ps[k]->long_rows.begin(), ps[k]->long_rows.end());
+  for (int k = 0; k < 4; ++k) {
+    off[k] = (int64_t)out.size() - base;
+    out.insert(out.end(), ps[k]->long_rows.begin(), ps[k]->long_rows.end());
+  }
+  for (int k = 0; k < 4; ++k) {
+    off[4 + k] = (int64_t)out.size() - base;
+    out.insert(out.end(), ps[k]->tiles.begin(), ps[k]->tiles.end());
+  }
   if (dense) g[0] = pow2_ceil(m ? (double)T.rowptr[n] / (double)n : 1.0);
 }
 
@@ -822,6 +892,7 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     I.nb_inf = max_abs_nan(bs[i], I.m);
     I.x0_given = (x0s && x0s[i]) ? 1 : 0;
     I.y0_given = (y0s && y0s[i] && I.m) ? 1 : 0;
+    I.kkt_zero = (s->warm_fallback && (I.x0_given || I.y0_given)) ? kkt_at_zero(bs[i], I.m, cs[i], I.n) : 0.0;
   }
   // partitions (per distinct (Q, A) pair the lists are identical; built per instance for simplicity)
   for (int i = 0; i < count; ++i) {
@@ -833,7 +904,7 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     Ah.rowptr.assign(As[i].rowptr, As[i].rowptr + As[i].nrows + 1);
     I.part_off = (int64_t)parts.size();
     int32_t g[4];
-    batch_parts(Qs[q_first[i]].rowptr, I.dense != 0, I.n, Ah, T, parts, g);
+    batch_parts(Qs[q_first[i]].rowptr, I.dense != 0, I.n, Ah, T, parts, g, I.sub_off);
     I.g_n1 = g[0]; I.g_cg = g[1]; I.g_m = g[2]; I.g_t = g[3];
   }
   // largest first: estimated work ~ entries of Q plus twice those of A
@@ -940,14 +1011,16 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     }
     P.part = d_part + (int64_t)i * NSLOT;
     const int32_t* pb = d_parts + I.part_off;
-    const int32_t* hb = parts.data() + I.part_off;
-    const int32_t* lr = pb + 16;
-    P.pn1 = Part{pb + 0, pb + 2, lr, I.g_n1};
-    P.pcg = Part{pb + 4, pb + 6, lr + hb[3], I.g_cg};
-    P.pm = Part{pb + 8, pb + 10, lr + hb[3] + hb[7], I.g_m};
-    P.pt = Part{pb + 12, pb + 14, lr + hb[3] + hb[7] + hb[11], I.g_t};
+    auto part = [&](int k, int32_t g) {
+      return Part{pb + 6 * k, pb + 6 * k + 2, pb + I.sub_off[k], pb + 6 * k + 4, pb + I.sub_off[4 + k], g};
+    };
+    P.pn1 = part(0, I.g_n1);
+    P.pcg = part(1, I.g_cg);
+    P.pm = part(2, I.g_m);
+    P.pt = part(3, I.g_t);
     P.nb_inf = I.nb_inf;
     P.nc_inf = I.nc_inf;
+    P.kkt_zero = I.kkt_zero;
     P.x0 = I.x0_given ? d_x0 + I.voff_n : nullptr;
     P.y0 = I.y0_given ? d_y0 + I.voff_m : nullptr;
     P.tol = s->tol_rel_kkt; P.eps_factor = s->cg_eps_factor; P.beta_suf = s->beta_sufficient;
@@ -1014,6 +1087,7 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
       r.solve_s = t_solve;
       r.kernel_s = ms * 1e-3;
       r.kkt_evals = S.evals;
+      r.cold_fallback = S.cold_fallback;
     }
   }
   return 0;

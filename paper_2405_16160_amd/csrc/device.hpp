@@ -183,4 +183,115 @@ struct GatherDir {
   }
 };
 
+// ----------------------------------------------------- LDS-staged tiles
+
+struct TileLds {
+  double prod[kTileNnz];
+  int32_t rp[kTileRows + 1];
+  int32_t rp2[kTileRows + 1];
+};
+
+// the workgroup's single LDS staging area for tiles
+__device__ __forceinline__ TileLds& tile_lds() {
+  __shared__ TileLds L;
+  return L;
+}
+
+constexpr int kStageUnroll = 8;  // loads in flight per thread while staging
+
+// prod[base + k] = M[z0 + k] * g(col[z0 + k]) for k < nz: every thread issues
+// kStageUnroll index/value loads, then kStageUnroll gathers, then the stores.
+template <typename V, typename Gather>
+__device__ __forceinline__ void stage_products(const int32_t* col, const V* val, int z0, int nz, const Gather& g,
+                                               double* prod) {
+  for (int k0 = 0; k0 < nz; k0 += kBlock * kStageUnroll) {
+    int c[kStageUnroll];
+    double v[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = k0 + u * kBlock + (int)threadIdx.x;
+      c[u] = 0;
+      v[u] = 0.0;
+      if (k < nz) {
+        c[u] = col[z0 + k];
+        v[u] = ldv(val, z0 + k);
+      }
+    }
+    double gv[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = k0 + u * kBlock + (int)threadIdx.x;
+      gv[u] = k < nz ? g(c[u]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = k0 + u * kBlock + (int)threadIdx.x;
+      if (k < nz) prod[k] = v[u] * gv[u];
+    }
+  }
+}
+
+__device__ __forceinline__ void stage_rowptr(const int32_t* rowptr, int ra, int nr, int z0, int32_t* rp) {
+  for (int i = threadIdx.x; i <= nr; i += kBlock) rp[i] = rowptr[ra + i] - z0;
+}
+
+// One tile of a single matrix: epi(row, sum) is called by lane 0 of the
+// row's G-lane group.
+template <typename V, typename Gather, typename Epi>
+__device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* col, const V* val, const int32_t* t,
+                                          int G, const Gather& g, Epi epi) {
+  TileLds& L = tile_lds();
+  const int ra = t[0], nr = t[1] - t[0], z0 = t[2], nz = t[3] - t[2];
+  stage_rowptr(rowptr, ra, nr, z0, L.rp);
+  stage_products(col, val, z0, nz, g, L.prod);
+  __syncthreads();
+  const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
+  for (int base = 0; base < nr; base += ng) {
+    const int i = base + (int)threadIdx.x / G;
+    const bool act = i < nr;
+    double s = 0.0;
+    if (act)
+      for (int k = L.rp[i] + lane; k < L.rp[i + 1]; k += G) s += L.prod[k];
+    s = group_sum(s, G);
+    if (act && lane == 0) epi(ra + i, s);
+  }
+  __syncthreads();
+}
+
+// One tile of two matrices over the same rows (the stacked [Q | A'] pass):
+// epi(row, sum1, sum2).  M2 may be absent (rowptr2 == nullptr: sum2 = 0).
+template <typename Gather1, typename Gather2, typename Epi>
+__device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t* col1, const double* val1,
+                                           const Gather1& g1, const int32_t* rowptr2, const int32_t* col2,
+                                           const double* val2, const Gather2& g2, const int32_t* t, int G, Epi epi) {
+  TileLds& L = tile_lds();
+  const int ra = t[0], nr = t[1] - t[0];
+  const int z0 = t[2], nz = t[3] - t[2], w0 = t[4], nw = t[5] - t[4];
+  if (rowptr1) {
+    stage_rowptr(rowptr1, ra, nr, z0, L.rp);
+    stage_products(col1, val1, z0, nz, g1, L.prod);
+  }
+  if (rowptr2) {
+    stage_rowptr(rowptr2, ra, nr, w0 - nz, L.rp2);
+    stage_products(col2, val2, w0, nw, g2, L.prod + nz);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
+  for (int base = 0; base < nr; base += ng) {
+    const int i = base + (int)threadIdx.x / G;
+    const bool act = i < nr;
+    double s1 = 0.0, s2 = 0.0;
+    if (act) {
+      if (rowptr1)
+        for (int k = L.rp[i] + lane; k < L.rp[i + 1]; k += G) s1 += L.prod[k];
+      if (rowptr2)
+        for (int k = L.rp2[i] + lane; k < L.rp2[i + 1]; k += G) s2 += L.prod[k];
+    }
+    s1 = group_sum(s1, G);
+    s2 = group_sum(s2, G);
+    if (act && lane == 0) epi(ra + i, s1, s2);
+  }
+  __syncthreads();
+}
+
 }  // namespace pdhcg

@@ -30,12 +30,24 @@ constexpr int kDenseRows = 4;     // rows per thread in one pass of a dense prod
 // than kLongRow are listed in long_rows[long_ptr[w] .. long_ptr[w+1]) and are
 // reduced cooperatively by the whole workgroup; the others are reduced by
 // groups of `group` lanes (a power of two <= 64).
+//
+// The other rows of a workgroup's range are cut into tiles of at most
+// kTileNnz entries and kTileRows rows: tiles[6*t .. 6*t+5] = first row, end
+// row, entry range in the first matrix, entry range in the second matrix (for
+// the stacked [Q | A'] pass; zero otherwise); workgroup w owns tiles
+// tile_ptr[w] .. tile_ptr[w+1]-1.  A tile's products are staged in LDS with
+// all loads in flight at once and then reduced row by row from LDS.
 struct Part {
   const int32_t* bounds;
   const int32_t* long_ptr;
   const int32_t* long_rows;
+  const int32_t* tile_ptr;
+  const int32_t* tiles;
   int32_t group;
 };
+
+constexpr int kTileNnz = 4096;    // staged products per tile (FP64 in LDS)
+constexpr int kTileRows = 2048;   // rows per tile
 
 // Partial-result slots.  Every workgroup writes one value per slot; after a
 // grid barrier every workgroup reduces all of them in the same fixed order,
@@ -82,6 +94,8 @@ struct SolverState {
   int32_t status;
   int32_t returned_average;
   int32_t mixed;        // 1 while FP32 products are in use
+  int32_t start_checked;  // the start point's relKKT has been compared with (0, 0)'s
+  int32_t cold_fallback;  // the start point was replaced by (0, 0)
   double r_p, r_d, r_g, kkt, pobj, dobj;  // of the returned point
   double norm_A;        // ||A||_2 estimate (batched solves)
   uint64_t t_start;     // wall_clock64() at the start of the solve
@@ -103,6 +117,7 @@ struct SolveParams {
   SolverState* st;
   Part pn1, pcg, pm, pt;  // n-side pass, CG (rows of Q), A rows, A' rows
   double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf (enter every relKKT)
+  double kkt_zero;        // relKKT(0, 0) when the warm-start fallback applies, else 0
   // start point of a batched solve (null: zero)
   const double* x0;
   const double* y0;
@@ -140,6 +155,9 @@ struct BatchParams {
   int32_t power_iters;
   int32_t mixed;
 };
+
+// records the message returned by pdhcg_last_error() and returns code
+int set_error(int code, const char* msg);
 
 hipError_t launch_batch(const BatchParams& p, int count, hipStream_t s);
 hipError_t launch_solve(const SolveParams* p_dev, int nb, hipStream_t s);

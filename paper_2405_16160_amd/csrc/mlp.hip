@@ -1,0 +1,368 @@
+// Warm-start network on the GPU: bfloat16 matrix products on MFMA with FP32
+// accumulation, fused bias / ReLU / ReLU-derivative epilogues, MSE gradient,
+// bias-gradient column sums and Adam on FP32 master weights.  Host side of
+// include/pdhcg_mlp.h at the end of the file.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pdhcg.h"
+#include "../../include/pdhcg_mlp.h"
+#include "internal.hpp"
+
+namespace pdhcg {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16, round to nearest, ties to even (NaN kept quiet)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+constexpr int GB = 64;   // block tile (rows and columns)
+constexpr int GK = 32;   // k per LDS stage
+constexpr int GP = 8;    // LDS row padding (bf16 elements)
+
+// C = A B on bfloat16 operands with FP32 accumulation.  A(m,k) = A[m*sam +
+// k*sak], B(k,n) = B[k*sbk + n*sbn], so transposed operands need no copy.
+// Each of the four waves owns a 32 x 32 quarter of the 64 x 64 block tile as
+// 2 x 2 MFMA 16x16x16 tiles.  Epilogue: + bias[n]; ReLU; zero where
+// mask(m,n) <= 0 (ReLU derivative); FP32 and/or bfloat16 output.
+__global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int64_t sam,
+                                                 int64_t sak, const uint16_t* __restrict__ Bm, int64_t sbk,
+                                                 int64_t sbn, const float* __restrict__ bias, int relu,
+                                                 const uint16_t* __restrict__ mask, float* __restrict__ Cf,
+                                                 uint16_t* __restrict__ Cb, int64_t ldc) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GB][GK + GP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bt[GB][GK + GP];  // B tile stored as [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * GB, n0 = blockIdx.x * GB;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int e = tid; e < GB * GK; e += 256) {
+      const int r = sak == 1 ? e / GK : e % GB;
+      const int c = sak == 1 ? e % GK : e / GB;
+      const int gm = m0 + r, gk = k0 + c;
+      As[r][c] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : (uint16_t)0;
+    }
+    for (int e = tid; e < GB * GK; e += 256) {
+      const int nn = sbn == 1 ? e % GB : e / GK;
+      const int kk = sbn == 1 ? e / GB : e % GK;
+      const int gn = n0 + nn, gk = k0 + kk;
+      Bt[nn][kk] = (gn < N && gk < K) ? Bm[gk * sbk + gn * sbn] : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 16) {
+      bf16x4 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x4*>(&As[wm * 32 + i * 16 + (lane & 15)][kk + 4 * (lane >> 4)]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x4*>(&Bt[wn * 32 + j * 16 + (lane & 15)][kk + 4 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (m < M && n < N) {
+          float v = acc[i][j][r];
+          if (bias) v += bias[n];
+          if (relu) v = v > 0.f ? v : 0.f;
+          if (mask && !(from_bf16(mask[(int64_t)m * ldc + n]) > 0.f)) v = 0.f;
+          if (Cf) Cf[(int64_t)m * ldc + n] = v;
+          if (Cb) Cb[(int64_t)m * ldc + n] = to_bf16(v);
+        }
+      }
+}
+
+__global__ void f32_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = to_bf16(in[i]);
+}
+
+// G = 2 (O - T) / count (FP32 and bfloat16 copies); per-block partial sums of (O - T)^2
+__global__ void mse_grad(const float* __restrict__ O, const float* __restrict__ T, int64_t n, float scale,
+                         float* __restrict__ G, uint16_t* __restrict__ Gb, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = O[i] - T[i];
+    s += (double)d * (double)d;
+    const float g = 2.0f * d * scale;
+    G[i] = g;
+    Gb[i] = to_bf16(g);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void sum_partials(const double* __restrict__ partial, int n, double scale, float* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partial[i];
+    *out = (float)(s * scale);
+  }
+}
+
+// out[c] = sum_r M[r, c] (bias gradients), fixed row order
+__global__ void colsum(const float* __restrict__ Mx, int rows, int cols, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += Mx[(int64_t)r * cols + c];
+  out[c] = s;
+}
+
+// Adam on FP32 masters; refreshes the bfloat16 copy where wb != null
+__global__ void adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                     int64_t n, float lr, float b1, float b2, float eps, float c1, float c2,
+                     uint16_t* __restrict__ wb) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = to_bf16(wi);
+  }
+}
+
+int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 2048) g = 2048;
+  return (int)g;
+}
+
+}  // namespace
+}  // namespace pdhcg
+
+using namespace pdhcg;
+
+struct pdhcg_mlp {
+  int n_in = 0, n_hid = 0, n_out = 0, cap = 0;
+  hipStream_t stream = nullptr;
+  int64_t np = 0;
+  int64_t off[6] = {0, 0, 0, 0, 0, 0};  // W1 b1 W2 b2 W3 b3 in the packed vector
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t* wb = nullptr;               // bfloat16 copy of the packed vector (weights used)
+  int64_t t = 0;
+  uint16_t *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *gob = nullptr, *d2b = nullptr, *d1b = nullptr;
+  float *out = nullptr, *go = nullptr, *d2 = nullptr, *d1 = nullptr, *loss = nullptr;
+  double* partial = nullptr;
+  std::vector<void*> allocs;
+  ~pdhcg_mlp() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  template <typename T>
+  bool alloc(T** p, int64_t count) {
+    if (hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    allocs.push_back(*p);
+    return true;
+  }
+};
+
+namespace {
+
+#define MLPX(call)                                                                                  \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) return set_error(PDHCG_ERR_HIP, (std::string(#call) + ": " + hipGetErrorString(e_)).c_str()); \
+  } while (0)
+
+hipError_t gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+                int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, float* Cf, uint16_t* Cb,
+                int64_t ldc) {
+  dim3 grid((N + GB - 1) / GB, (M + GB - 1) / GB);
+  hipLaunchKernelGGL(gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, relu, mask, Cf, Cb,
+                     ldc);
+  return hipGetLastError();
+}
+
+int check_batch(const pdhcg_mlp* h, int32_t batch) {
+  if (!h) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null network handle");
+  if (batch < 1 || batch > h->cap) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "batch outside 1..max_batch");
+  return 0;
+}
+
+// forward pass of `batch` rows of X (device FP32) into h->out; keeps the
+// bfloat16 activations for the backward pass
+int run_forward(pdhcg_mlp* h, const float* X, int batch) {
+  const int a = h->n_in, d = h->n_hid, o = h->n_out;
+  hipLaunchKernelGGL(f32_to_bf16, dim3(grid_for((int64_t)batch * a)), dim3(256), 0, h->stream, X, h->xb,
+                     (int64_t)batch * a);
+  MLPX(hipGetLastError());
+  MLPX(gemm(h->stream, batch, d, a, h->xb, a, 1, h->wb + h->off[0], d, 1, h->w + h->off[1], 1, nullptr, nullptr, h->h1,
+            d));
+  MLPX(gemm(h->stream, batch, d, d, h->h1, d, 1, h->wb + h->off[2], d, 1, h->w + h->off[3], 1, nullptr, nullptr, h->h2,
+            d));
+  MLPX(gemm(h->stream, batch, o, d, h->h2, d, 1, h->wb + h->off[4], o, 1, h->w + h->off[5], 0, nullptr, h->out,
+            nullptr, o));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdhcg_mlp_create(pdhcg_mlp** out, int32_t n_in, int32_t n_hid, int32_t n_out, int32_t max_batch,
+                     void* hip_stream) {
+  if (!out) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null handle pointer");
+  *out = nullptr;
+  if (n_in < 1 || n_hid < 1 || n_out < 1 || max_batch < 1)
+    return set_error(PDHCG_ERR_INVALID_ARGUMENT, "network sizes and max_batch must be >= 1");
+  pdhcg_mlp* h = new pdhcg_mlp();
+  h->n_in = n_in;
+  h->n_hid = n_hid;
+  h->n_out = n_out;
+  h->cap = max_batch;
+  h->stream = (hipStream_t)hip_stream;
+  const int64_t sizes[6] = {(int64_t)n_in * n_hid, n_hid, (int64_t)n_hid * n_hid, n_hid, (int64_t)n_hid * n_out, n_out};
+  int64_t acc = 0;
+  for (int k = 0; k < 6; ++k) {
+    h->off[k] = acc;
+    acc += sizes[k];
+  }
+  h->np = acc;
+  const int64_t B = max_batch;
+  bool ok = h->alloc(&h->w, acc) && h->alloc(&h->g, acc) && h->alloc(&h->m, acc) && h->alloc(&h->v, acc) &&
+            h->alloc(&h->wb, acc) && h->alloc(&h->xb, B * n_in) && h->alloc(&h->h1, B * n_hid) &&
+            h->alloc(&h->h2, B * n_hid) && h->alloc(&h->gob, B * n_out) && h->alloc(&h->d2b, B * n_hid) &&
+            h->alloc(&h->d1b, B * n_hid) && h->alloc(&h->out, B * n_out) && h->alloc(&h->go, B * n_out) &&
+            h->alloc(&h->d2, B * n_hid) && h->alloc(&h->d1, B * n_hid) && h->alloc(&h->loss, 1) &&
+            h->alloc(&h->partial, 2048);
+  if (!ok) {
+    delete h;
+    return set_error(PDHCG_ERR_OUT_OF_MEMORY, "hipMalloc failed for the network");
+  }
+  if (hipMemsetAsync(h->w, 0, sizeof(float) * acc, h->stream) != hipSuccess ||
+      hipMemsetAsync(h->wb, 0, sizeof(uint16_t) * acc, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    delete h;
+    return set_error(PDHCG_ERR_HIP, "initialising the network failed");
+  }
+  *out = h;
+  return 0;
+}
+
+int64_t pdhcg_mlp_num_params(const pdhcg_mlp* h) { return h ? h->np : 0; }
+
+int pdhcg_mlp_set_params(pdhcg_mlp* h, const float* params) {
+  if (!h || !params) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null argument");
+  MLPX(hipMemcpyAsync(h->w, params, sizeof(float) * h->np, hipMemcpyHostToDevice, h->stream));
+  MLPX(hipMemsetAsync(h->m, 0, sizeof(float) * h->np, h->stream));
+  MLPX(hipMemsetAsync(h->v, 0, sizeof(float) * h->np, h->stream));
+  hipLaunchKernelGGL(f32_to_bf16, dim3(grid_for(h->np)), dim3(256), 0, h->stream, h->w, h->wb, h->np);
+  MLPX(hipGetLastError());
+  MLPX(hipStreamSynchronize(h->stream));
+  h->t = 0;
+  return 0;
+}
+
+int pdhcg_mlp_get_params(const pdhcg_mlp* h, float* params) {
+  if (!h || !params) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null argument");
+  MLPX(hipMemcpyAsync(params, h->w, sizeof(float) * h->np, hipMemcpyDeviceToHost, h->stream));
+  MLPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+int pdhcg_mlp_forward(pdhcg_mlp* h, const float* X, int32_t batch, float* Y) {
+  int rc;
+  if ((rc = check_batch(h, batch))) return rc;
+  if (!X || !Y) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null X or Y");
+  if ((rc = run_forward(h, X, batch))) return rc;
+  MLPX(hipMemcpyAsync(Y, h->out, sizeof(float) * (int64_t)batch * h->n_out, hipMemcpyDeviceToDevice, h->stream));
+  MLPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+int pdhcg_mlp_loss_grad(pdhcg_mlp* h, const float* X, const float* T, int32_t batch, float* loss, float* grads) {
+  int rc;
+  if ((rc = check_batch(h, batch))) return rc;
+  if (!X || !T) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null X or T");
+  if ((rc = run_forward(h, X, batch))) return rc;
+  const int a = h->n_in, d = h->n_hid, o = h->n_out;
+  const int64_t no = (int64_t)batch * o;
+  const int pg = 512;
+  hipLaunchKernelGGL(mse_grad, dim3(pg), dim3(256), 0, h->stream, h->out, T, no, (float)(1.0 / (double)no), h->go,
+                     h->gob, h->partial);
+  MLPX(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, h->stream, h->partial, pg, 1.0 / (double)no, h->loss);
+  MLPX(hipGetLastError());
+  float* g = h->g;
+  // layer 3: dW3 = H2' G, db3 = colsum G, dH2 = (G W3') masked by H2 > 0
+  MLPX(gemm(h->stream, d, o, batch, h->h2, 1, d, h->gob, o, 1, nullptr, 0, nullptr, g + h->off[4], nullptr, o));
+  hipLaunchKernelGGL(colsum, dim3((o + 255) / 256), dim3(256), 0, h->stream, h->go, batch, o, g + h->off[5]);
+  MLPX(hipGetLastError());
+  MLPX(gemm(h->stream, batch, d, o, h->gob, o, 1, h->wb + h->off[4], 1, o, nullptr, 0, h->h2, h->d2, h->d2b, d));
+  // layer 2
+  MLPX(gemm(h->stream, d, d, batch, h->h1, 1, d, h->d2b, d, 1, nullptr, 0, nullptr, g + h->off[2], nullptr, d));
+  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d2, batch, d, g + h->off[3]);
+  MLPX(hipGetLastError());
+  MLPX(gemm(h->stream, batch, d, d, h->d2b, d, 1, h->wb + h->off[2], 1, d, nullptr, 0, h->h1, h->d1, h->d1b, d));
+  // layer 1
+  MLPX(gemm(h->stream, a, d, batch, h->xb, 1, a, h->d1b, d, 1, nullptr, 0, nullptr, g + h->off[0], nullptr, d));
+  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d1, batch, d, g + h->off[1]);
+  MLPX(hipGetLastError());
+  if (loss) MLPX(hipMemcpyAsync(loss, h->loss, sizeof(float), hipMemcpyDeviceToHost, h->stream));
+  if (grads) MLPX(hipMemcpyAsync(grads, g, sizeof(float) * h->np, hipMemcpyDeviceToHost, h->stream));
+  MLPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+int pdhcg_mlp_adam_step(pdhcg_mlp* h, float lr, float beta1, float beta2, float eps) {
+  if (!h) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null network handle");
+  h->t += 1;
+  const float c1 = (float)(1.0 - pow((double)beta1, (double)h->t));
+  const float c2 = (float)(1.0 - pow((double)beta2, (double)h->t));
+  hipLaunchKernelGGL(adam, dim3(grid_for(h->np)), dim3(256), 0, h->stream, h->w, h->g, h->m, h->v, h->np, lr, beta1,
+                     beta2, eps, c1, c2, h->wb);
+  MLPX(hipGetLastError());
+  MLPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+void pdhcg_mlp_destroy(pdhcg_mlp* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+}  // extern "C"

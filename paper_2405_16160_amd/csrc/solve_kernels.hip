@@ -107,8 +107,7 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
   // dense Q (one workgroup per QP): Q xv first, into the free CG buffer q
   constexpr bool dense = DENSE;
   if (dense) dense_qx(P, xv, svec);
-  const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
-  const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
+  const int G = pt.group;
   double s[3] = {0.0, 0.0, 0.0};   // g.g, x.Qx, c.x
   double mx[3] = {0.0, 0.0, 0.0};  // |g|, |Qx|, |A'y|
   GatherVec<double> gx{xv}, gy{yv};
@@ -126,30 +125,9 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
     mx[1] = maxp(mx[1], fabs(qx));
     mx[2] = maxp(mx[2], fabs(aty));
   };
-  for (int base = r0; base < r1; base += ng) {
-    const int i = base + B.tid / G;
-    const bool act = i < r1;
-    int qb = 0, qe = 0, tb = 0, te = 0;
-    if (act) {
-      if (!dense) {
-        qb = P.Q.rowptr[i];
-        qe = P.Q.rowptr[i + 1];
-      }
-      if (P.m > 0) {
-        tb = P.At.rowptr[i];
-        te = P.At.rowptr[i + 1];
-      }
-    }
-    const bool use = act && (qe - qb) + (te - tb) <= kLongRow;
-    double sq = 0.0, st = 0.0;
-    if (use) {
-      sq = row_partial(P.Q.col, P.Q.val, qb, qe, lane, G, gx);
-      st = row_partial(P.At.col, P.At.val, tb, te, lane, G, gy);
-    }
-    sq = group_sum(sq, G);
-    st = group_sum(st, G);
-    if (use && lane == 0) epi(i, dense ? P.q[i] : sq, st);
-  }
+  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
+    tile_rows2(dense ? nullptr : P.Q.rowptr, P.Q.col, P.Q.val, gx, P.m > 0 ? P.At.rowptr : nullptr, P.At.col,
+               P.At.val, gy, pt.tiles + 6 * t, G, [&](int i, double qx, double aty) { epi(i, dense ? P.q[i] : qx, aty); });
   for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
     const int i = pt.long_rows[t];
     double v[2] = {dense ? 0.0 : row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gx),
@@ -177,22 +155,9 @@ template <typename V, typename Tx, typename Epi>
 __device__ void mside_rows(const SolveParams& P, const Block& B, const V* aval, const Tx* xg, double* lds,
                            Epi epi) {
   const Part& pt = P.pm;
-  const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
-  const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
   GatherVec<Tx> gx{xg};
-  for (int base = r0; base < r1; base += ng) {
-    const int i = base + B.tid / G;
-    const bool act = i < r1;
-    int ab = 0, ae = 0;
-    if (act) {
-      ab = P.A.rowptr[i];
-      ae = P.A.rowptr[i + 1];
-    }
-    const bool use = act && (ae - ab) <= kLongRow;
-    double su = use ? row_partial(P.A.col, aval, ab, ae, lane, G, gx) : 0.0;
-    su = group_sum(su, G);
-    if (use && lane == 0) epi(i, su);
-  }
+  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
+    tile_rows(P.A.rowptr, P.A.col, aval, pt.tiles + 6 * t, pt.group, gx, epi);
   for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.A.col, aval, P.A.rowptr[i], P.A.rowptr[i + 1], B.tid, kBlock, gx)};
@@ -248,8 +213,6 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, co
     return;
   }
   const Part& pt = P.pcg;
-  const int r0 = pt.bounds[B.b], r1 = pt.bounds[B.b + 1];
-  const int G = pt.group, lane = B.tid & (G - 1), ng = kBlock / G;
   GatherDir<T> gp{rg, ppg, beta, first};
   double s[1] = {0.0};
   auto epi = [&](int i, double qp) {
@@ -260,19 +223,8 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, co
     P.q[i] = qi;
     s[0] += pi * qi;
   };
-  for (int base = r0; base < r1; base += ng) {
-    const int i = base + B.tid / G;
-    const bool act = i < r1;
-    int qb = 0, qe = 0;
-    if (act) {
-      qb = P.Q.rowptr[i];
-      qe = P.Q.rowptr[i + 1];
-    }
-    const bool use = act && (qe - qb) <= kLongRow;
-    double sq = use ? row_partial(P.Q.col, qval, qb, qe, lane, G, gp) : 0.0;
-    sq = group_sum(sq, G);
-    if (use && lane == 0) epi(i, sq);
-  }
+  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
+    tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tiles + 6 * t, pt.group, gp, epi);
   for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gp)};
@@ -376,6 +328,23 @@ __device__ __attribute__((noinline)) void phase_copy_point(const SolveParams& P,
   for (int i = m0 + B.tid; i < m1; i += kBlock) P.y[i] = ys[i];
 }
 
+// x, y, their averages and anchors, Ax and the FP32 copy of x set to zero
+__device__ __attribute__((noinline)) void phase_zero_point(const SolveParams& P, const Block& B) {
+  const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
+  for (int j = n0 + B.tid; j < n1; j += kBlock) {
+    P.x[j] = 0.0;
+    P.xa[j] = 0.0;
+    P.x_anc[j] = 0.0;
+    if (P.x32) P.x32[j] = 0.0f;
+  }
+  const int m0 = P.pm.bounds[B.b], m1 = P.pm.bounds[B.b + 1];
+  for (int i = m0 + B.tid; i < m1; i += kBlock) {
+    P.y[i] = 0.0;
+    P.ya[i] = 0.0;
+    P.y_anc[i] = 0.0;
+  }
+}
+
 // relKKT (Sec. 4, progress metric) from the reduced partials of one point.
 struct Kkt {
   double rp, rd, rg, kkt, pobj, dobj;
@@ -449,6 +418,18 @@ __device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, Solver
     double rho, tflag;
     kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, &rho, &tflag, lds);
     have_avg = false;
+    if (!S.start_checked) {
+      S.start_checked = 1;
+      if (P.kkt_zero > 0.0 && !(kc.kkt <= P.kkt_zero)) {
+        // the given start point is worse than (0, 0): start cold
+        phase_zero_point(P, B);
+        if (!(ok = gs.sync())) break;
+        phase_ax(P, B, lds);
+        if (!(ok = gs.sync())) break;
+        S.cold_fallback = 1;
+        continue;
+      }
+    }
     if (S.K_anchor != S.K_anchor) {
       S.K_anchor = kc.kkt;
     }
@@ -640,19 +621,9 @@ __device__ bool power_norm(const DevMat& A, const DevMat& At, double* v, double*
     for (int j = n0 + B.tid; j < n1; j += kBlock) v[j] = w[j] * scale;
     if (!gs.sync()) return false;
     {  // u = A v
-      const int r0 = pm.bounds[B.b], r1 = pm.bounds[B.b + 1];
-      const int G = pm.group, lane = B.tid & (G - 1), ng = kBlock / G;
       GatherVec<double> gv{v};
-      for (int base = r0; base < r1; base += ng) {
-        const int i = base + B.tid / G;
-        const bool act = i < r1;
-        int ab = 0, ae = 0;
-        if (act) { ab = A.rowptr[i]; ae = A.rowptr[i + 1]; }
-        const bool use = act && (ae - ab) <= kLongRow;
-        double su = use ? row_partial(A.col, A.val, ab, ae, lane, G, gv) : 0.0;
-        su = group_sum(su, G);
-        if (use && lane == 0) u[i] = su;
-      }
+      for (int t = pm.tile_ptr[B.b]; t < pm.tile_ptr[B.b + 1]; ++t)
+        tile_rows(A.rowptr, A.col, A.val, pm.tiles + 6 * t, pm.group, gv, [&](int i, double su) { u[i] = su; });
       for (int t = pm.long_ptr[B.b]; t < pm.long_ptr[B.b + 1]; ++t) {
         const int i = pm.long_rows[t];
         double vv[1] = {row_partial(A.col, A.val, A.rowptr[i], A.rowptr[i + 1], B.tid, kBlock, gv)};
@@ -662,22 +633,13 @@ __device__ bool power_norm(const DevMat& A, const DevMat& At, double* v, double*
     }
     if (!gs.sync()) return false;
     {  // w = A'u, partial ||w||^2
-      const int G = pn.group, lane = B.tid & (G - 1), ng = kBlock / G;
       GatherVec<double> gu{u};
       double sw[1] = {0.0};
-      for (int base = n0; base < n1; base += ng) {
-        const int i = base + B.tid / G;
-        const bool act = i < n1;
-        int tb = 0, te = 0;
-        if (act) { tb = At.rowptr[i]; te = At.rowptr[i + 1]; }
-        const bool use = act && (te - tb) <= kLongRow;
-        double st = use ? row_partial(At.col, At.val, tb, te, lane, G, gu) : 0.0;
-        st = group_sum(st, G);
-        if (use && lane == 0) {
+      for (int t = pn.tile_ptr[B.b]; t < pn.tile_ptr[B.b + 1]; ++t)
+        tile_rows(At.rowptr, At.col, At.val, pn.tiles + 6 * t, pn.group, gu, [&](int i, double st) {
           w[i] = st;
           sw[0] += st * st;
-        }
-      }
+        });
       for (int t = pn.long_ptr[B.b]; t < pn.long_ptr[B.b + 1]; ++t) {
         const int i = pn.long_rows[t];
         double vv[1] = {row_partial(At.col, At.val, At.rowptr[i], At.rowptr[i + 1], B.tid, kBlock, gu)};
@@ -791,19 +753,9 @@ template <typename V, typename T>
 __global__ void __launch_bounds__(kBlock) spmv_kernel(DevMat M, Part pt, const V* val, const T* x, double* y) {
   __shared__ double lds[kWaves * 4];
   const int b = blockIdx.x, tid = threadIdx.x;
-  const int r0 = pt.bounds[b], r1 = pt.bounds[b + 1];
-  const int G = pt.group, lane = tid & (G - 1), ng = kBlock / G;
   GatherVec<T> gx{x};
-  for (int base = r0; base < r1; base += ng) {
-    const int i = base + tid / G;
-    const bool act = i < r1;
-    int rb = 0, re = 0;
-    if (act) { rb = M.rowptr[i]; re = M.rowptr[i + 1]; }
-    const bool use = act && (re - rb) <= kLongRow;
-    double s = use ? row_partial(M.col, val, rb, re, lane, G, gx) : 0.0;
-    s = group_sum(s, G);
-    if (use && lane == 0) y[i] = s;
-  }
+  for (int t = pt.tile_ptr[b]; t < pt.tile_ptr[b + 1]; ++t)
+    tile_rows(M.rowptr, M.col, val, pt.tiles + 6 * t, pt.group, gx, [&](int i, double v) { y[i] = v; });
   for (int t = pt.long_ptr[b]; t < pt.long_ptr[b + 1]; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(M.col, val, M.rowptr[i], M.rowptr[i + 1], tid, kBlock, gx)};

@@ -31,7 +31,7 @@ class pdhcg_settings(C.Structure):
                 ("eval_period", C.c_int32), ("primal_weight_theta", C.c_double),
                 ("primal_weight_init", C.c_double), ("step_eta_factor", C.c_double), ("power_iters", C.c_int32),
                 ("precision", C.c_int32), ("time_limit_s", C.c_double), ("num_blocks", C.c_int32),
-                ("verbose", C.c_int32)]
+                ("warm_fallback", C.c_int32), ("verbose", C.c_int32)]
 
 
 class pdhcg_result(C.Structure):
@@ -40,7 +40,7 @@ class pdhcg_result(C.Structure):
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("iters", C.c_int64),
                 ("cg_iters_total", C.c_int64), ("restarts", C.c_int64), ("norm_A", C.c_double),
                 ("setup_s", C.c_double), ("solve_s", C.c_double), ("kernel_s", C.c_double),
-                ("kkt_evals", C.c_int64)]
+                ("kkt_evals", C.c_int64), ("cold_fallback", C.c_int32)]
 
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
@@ -112,6 +112,7 @@ class Settings:
     precision: int = 0
     time_limit_s: float = 0.0
     num_blocks: int = 0
+    warm_fallback: int = 1
     verbose: int = 0
 
     def c(self) -> pdhcg_settings:

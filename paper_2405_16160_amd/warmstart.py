@@ -1,0 +1,144 @@
+"""Learned warm start for a parametric QP family (growth path of the solver).
+
+For a family whose Q, A and c are fixed and whose b depends on a parameter
+theta (here the initial state of a linear MPC problem), a network maps theta
+to a predicted primal-dual pair (x, y) that restarted PDHCG starts from.  The
+training targets are PDHCG's own solutions, computed by the batched solver;
+the network is trained by the library's bfloat16 kernels.  A prediction never
+costs accuracy: the solve that starts from it stops on the same relKKT test,
+and a start point whose relKKT exceeds that of (0, 0) is replaced by (0, 0)
+(the solver's warm_fallback setting).
+
+Data preparation on the host (numpy): the dual targets are made canonical on
+each +/- row pair (a pair (a'x <= u, -a'x <= -u) encoding one equality admits
+(y+ + t, y- + t) for every t), keeping max(y+ - y-, 0) and max(y- - y+, 0),
+which leaves A'y and b'y unchanged; inputs and targets are standardised per
+dimension.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import instances as I
+from . import mlp as _mlp
+from . import pdhcg as _pd
+
+
+@dataclasses.dataclass
+class Dataset:
+    theta: np.ndarray     # (N, 20) initial states
+    X: np.ndarray         # (N, n) primal solutions
+    Y: np.ndarray         # (N, m) canonical dual solutions
+    iters: np.ndarray     # (N,) PDHCG iterations of each solve
+    seconds: float        # batched solve wall time
+
+
+def pair_index(fam: I.MPCFamily):
+    """Row pairs (i, j) of A with row_j = -row_i: dynamics (+, -) blocks and the
+    two sides of every box limit, in the row order of instances.mpc_family."""
+    T, nx, nu = fam.T, fam.nx, fam.nu
+    e = T * nx
+    u = T * nu
+    plus = np.concatenate([np.arange(e), 2 * e + np.arange(u), 2 * e + 2 * u + np.arange(e)])
+    minus = np.concatenate([e + np.arange(e), 2 * e + u + np.arange(u), 2 * e + 2 * u + e + np.arange(e)])
+    return plus, minus
+
+
+def canonical_duals(Y, plus, minus):
+    Y = np.array(Y, dtype=np.float64, copy=True)
+    d = Y[..., plus] - Y[..., minus]
+    Y[..., plus] = np.maximum(d, 0.0)
+    Y[..., minus] = np.maximum(-d, 0.0)
+    return Y
+
+
+def family_qps(fam: I.MPCFamily, ids):
+    thetas = np.stack([I.mpc_initial_state(int(i), fam) for i in ids])
+    qps = [I.QP(fam.Q, fam.A, fam.b_for(t), fam.c) for t in thetas]
+    return thetas, qps
+
+
+def solve_family(fam, ids, settings: _pd.Settings, x0s=None, y0s=None, chunk=8192):
+    """Batched PDHCG solves of the family members `ids` (chunks of `chunk`);
+    returns (theta, x, y, results, seconds)."""
+    thetas, qps = family_qps(fam, ids)
+    xs, ys, rs = [], [], []
+    t0 = time.perf_counter()
+    for a in range(0, len(qps), chunk):
+        part = qps[a:a + chunk]
+        x0 = None if x0s is None else list(x0s[a:a + chunk])
+        y0 = None if y0s is None else list(y0s[a:a + chunk])
+        out = _pd.solve_batch(part, settings, x0s=x0, y0s=y0)
+        xs += [o[0] for o in out]
+        ys += [o[1] for o in out]
+        rs += [o[2] for o in out]
+    secs = time.perf_counter() - t0
+    return thetas, np.stack(xs), np.stack(ys), rs, secs
+
+
+@dataclasses.dataclass
+class Scaler:
+    mu: np.ndarray
+    sd: np.ndarray
+
+    @staticmethod
+    def fit(Z):
+        mu = Z.mean(axis=0)
+        sd = Z.std(axis=0)
+        return Scaler(mu, np.where(sd > 1e-9, sd, 1.0))
+
+    def fwd(self, Z):
+        return (Z - self.mu) / self.sd
+
+    def inv(self, Z):
+        return Z * self.sd + self.mu
+
+
+class WarmStarter:
+    """theta -> (x0, y0) through the trained network (y0 projected on y >= 0)."""
+
+    def __init__(self, net: _mlp.Network, sin: Scaler, sout: Scaler, n: int):
+        self.net, self.sin, self.sout, self.n = net, sin, sout, n
+
+    def predict(self, thetas):
+        import torch
+        out = []
+        B = self.net.max_batch
+        for a in range(0, len(thetas), B):
+            Xt = torch.tensor(self.sin.fwd(thetas[a:a + B]), dtype=torch.float32, device="cuda")
+            out.append(self.net.forward(Xt).cpu().numpy().astype(np.float64))
+        Z = self.sout.inv(np.concatenate(out))
+        x0 = Z[:, : self.n]
+        y0 = np.maximum(Z[:, self.n:], 0.0)
+        return x0, y0
+
+
+def train(theta, X, Y, hidden=512, epochs=20, batch=512, lr=1e-3, seed=0, log=None):
+    """Train the network on (theta -> [x, y]) with Adam on standardised data;
+    returns the WarmStarter and the per-epoch mean losses."""
+    import torch
+    n = X.shape[1]
+    Z = np.concatenate([X, Y], axis=1)
+    sin, sout = Scaler.fit(theta), Scaler.fit(Z)
+    Xt = torch.tensor(sin.fwd(theta), dtype=torch.float32, device="cuda")
+    Zt = torch.tensor(sout.fwd(Z), dtype=torch.float32, device="cuda")
+    net = _mlp.Network(theta.shape[1], hidden, Z.shape[1], max_batch=batch,
+                       params=_mlp.init_params(theta.shape[1], hidden, Z.shape[1], seed=seed))
+    rng = np.random.default_rng(seed)
+    N = len(theta)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(N), device="cuda")
+        tot, cnt = 0.0, 0
+        step_lr = lr * 0.5 * (1 + np.cos(np.pi * ep / epochs))   # cosine decay
+        for a in range(0, N - batch + 1, batch):
+            idx = perm[a:a + batch]
+            tot += net.train_step(Xt[idx], Zt[idx], lr=float(step_lr))
+            cnt += 1
+        losses.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep}: loss {losses[-1]:.4e}")
+    return WarmStarter(net, sin, sout, n), losses

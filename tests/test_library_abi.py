@@ -8,8 +8,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "pdhcg.h")).read()
+def declared_functions(header="pdhcg.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(pdhcg_[a-z_]+)\s*\(", src)))
 
@@ -26,6 +26,15 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(L, name), name
     assert set(declared_functions()) == set(pdhcg.EXPORTS)
+
+
+def test_library_exports_the_network_abi():
+    from paper_2405_16160_amd import mlp, pdhcg
+    L = pdhcg.lib()
+    names = declared_functions("pdhcg_mlp.h")
+    assert set(names) == set(mlp.MLP_EXPORTS)
+    for name in names:
+        assert hasattr(L, name), name
 
 
 def test_default_settings_match_the_paper_constants():
