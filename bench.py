@@ -42,6 +42,14 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip SpMV and CG-cap-1 side measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the FETCH/WRITE counters)")
+    ap.add_argument("--config", default="random1e5",
+                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned"],
+                    help="workload; the default is the benchmark line, the others are extra measurements")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--train", type=int, default=100_000)
+    ap.add_argument("--test", type=int, default=10_000)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--iters", type=int, default=300, help="fixed iterations for the power-law bandwidth run")
     return ap.parse_args()
 
 
@@ -87,6 +95,162 @@ def cpu_baseline(qp, tol):
             "seconds_per_solve": dt, "status": r.status}
 
 
+def spmv_rates(solver, qp, precisions=(0, 1), reps=50):
+    """Standalone product bandwidth: compulsory bytes / kernel time (HIP events)."""
+    import torch
+    rng = np.random.default_rng(0)
+    xn, xm = rng.standard_normal(qp.n), rng.standard_normal(qp.m)
+    out = {}
+    for which, name, nnz, nr, nc, v in ((0, "Q", qp.Q.nnz, qp.n, qp.n, xn), (1, "A", qp.A.nnz, qp.m, qp.n, xn),
+                                        (2, "At", qp.A.nnz, qp.n, qp.m, xm)):
+        for prec in precisions:
+            solver.spmv(which, v, precision=prec, repeats=3)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            solver.spmv(which, v, precision=prec, repeats=reps)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            sv = 4 if prec else 8
+            gbs = csr_bytes(nnz, nr, nc, sv, 8) / (us * 1e-6) / 1e9
+            out[f"spmv_{name}_{'fp32' if prec else 'fp64'}"] = {"us": us, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
+def bench_tiny(args):
+    """n = 1000, m = 500 FP64 random QP, 10 instances, tol 1e-4."""
+    import torch
+    from paper_2405_16160_amd import instances as I, pdhcg
+    times, iters = [], []
+    for inst in range(10):
+        qp = I.random_qp(family=1, instance=inst)
+        sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=args.tol, num_blocks=args.num_blocks))
+        sol.solve()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, r = sol.solve()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t) / args.steps)
+        iters.append(r["iters"])
+        plan = sol.plan_info()
+        sol.close()
+    g = float(np.exp(np.mean(np.log(times))))
+    return {"config": "tiny random QP n=1000 m=500 FP64, 10 instances, tol %g" % args.tol,
+            "geomean_ms": g * 1e3, "QPs/s": 1 / g, "iters": iters, "plan": plan}
+
+
+def bench_powerlaw(args):
+    """n = 2e6, m = 1e6 power-law QP: standalone products and a fixed number
+    of solve iterations (bandwidth of the phases; the family converges slowly
+    without preconditioning, so time-to-tolerance is not measured here)."""
+    import torch
+    from paper_2405_16160_amd import instances as I, pdhcg
+    t = time.perf_counter()
+    qp = I.powerlaw_qp(2_000_000, 1_000_000, family=3, instance=0)
+    gen_s = time.perf_counter() - t
+    lens = np.diff(qp.A.rowptr)
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-12, precision=args.precision, max_iters=args.iters,
+                                          num_blocks=args.num_blocks))
+    rates = spmv_rates(sol, qp)
+    sol.solve()
+    torch.cuda.synchronize()
+    _, _, r = sol.solve()
+    bytes_alg = solve_bytes(qp, r, args.precision)
+    ach = bytes_alg / r["kernel_s"] / 1e9
+    out = {"config": "power-law QP n=2e6 m=1e6 (A row lengths Pareto 1.5, mean 8, max 5000)",
+           "nnz_Q": qp.Q.nnz, "nnz_A": qp.A.nnz, "A_row_max": int(lens.max()), "gen_s": gen_s,
+           "plan": sol.plan_info(), "spmv": rates,
+           "solve_fixed_iters": {"iters": r["iters"], "cg_steps": r["cg_iters_total"], "kernel_ms": r["kernel_s"] * 1e3,
+                                 "us_per_iter": r["kernel_s"] * 1e6 / max(r["iters"], 1), "rel_kkt": r["rel_kkt"],
+                                 "GB/s": ach, "frac": ach / HBM_PEAK_GBS}}
+    sol.close()
+    return out
+
+
+def bench_batch(args):
+    """4096 portfolio QPs (n log-uniform in [50, 2000], dense Q = FF' + D) in one
+    batched solve, against one-by-one solves of a stratified sample."""
+    from paper_2405_16160_amd import instances as I, pdhcg
+    t = time.perf_counter()
+    qps = [I.portfolio_qp(i) for i in range(args.batch_count)]
+    gen_s = time.perf_counter() - t
+    s = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=200_000)
+    t = time.perf_counter()
+    out = pdhcg.solve_batch(qps, s)
+    wall = time.perf_counter() - t
+    rs = [o[2] for o in out]
+    ok = sum(r["status"] == 0 for r in rs)
+    kernel_s = rs[0]["kernel_s"]
+    setup_s = rs[0]["setup_s"]
+    # one-by-one baseline on a stratified sample: 2 instances per log-size bin
+    ns = np.array([q.n for q in qps])
+    edges = np.exp(np.linspace(np.log(50), np.log(2000), 17))
+    sample, weights = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        idx = np.nonzero((ns >= a) & (ns < b + 1e-9))[0]
+        if idx.size:
+            pick = idx[:2]
+            sample += list(pick)
+            weights += [idx.size / pick.size] * pick.size
+    single_s = 0.0
+    for i, w in zip(sample, weights):
+        sol = pdhcg.Solver(qps[i], s)
+        _, _, r = sol.solve()
+        single_s += w * r["solve_s"]
+        sol.close()
+    return {"config": f"batched portfolio QPs x{args.batch_count}, n log-uniform [50, 2000], dense Q, tol {args.tol:g}",
+            "solved": ok, "batch_kernel_s": kernel_s, "batch_wall_s": wall, "setup_s": setup_s,
+            "QPs/s_batched": args.batch_count / kernel_s, "gen_s": gen_s,
+            "iters_mean": float(np.mean([r["iters"] for r in rs])),
+            "one_by_one_estimated_s": single_s, "QPs/s_one_by_one": args.batch_count / single_s,
+            "one_by_one_sample": len(sample), "speedup": single_s / kernel_s}
+
+
+def bench_learned(args):
+    """Learned warm start on the MPC family: train on PDHCG solutions, then
+    batched cold vs warm solves of held-out members to tol."""
+    from paper_2405_16160_amd import instances as I, pdhcg, warmstart as W
+    fam = I.mpc_family()
+    plus, minus = W.pair_index(fam)
+    t = time.perf_counter()
+    th, X, Y, rs, gen_solve_s = W.solve_family(fam, range(args.train), pdhcg.Settings(tol_rel_kkt=1e-6))
+    Y = W.canonical_duals(Y, plus, minus)
+    t_train = time.perf_counter()
+    ws, losses = W.train(th, X, Y, epochs=args.epochs)
+    train_s = time.perf_counter() - t_train
+    ids = range(100_000, 100_000 + args.test)
+    th_t, _ = W.family_qps(fam, ids)
+    t = time.perf_counter()
+    x0, y0 = ws.predict(th_t)
+    infer_s = time.perf_counter() - t
+    s = pdhcg.Settings(tol_rel_kkt=args.tol)
+    _, _, _, rc, tc = W.solve_family(fam, ids, s)
+    _, _, _, rw, tw = W.solve_family(fam, ids, s, x0s=x0, y0s=y0)
+    s_nf = pdhcg.Settings(tol_rel_kkt=args.tol, warm_fallback=0)
+    _, _, _, rn, tn = W.solve_family(fam, ids, s_nf, x0s=x0, y0s=y0)
+    _, _, _, rx, tx = W.solve_family(fam, ids, s_nf, x0s=x0)
+    from oracle import oracle as O
+    _, qps_t = W.family_qps(fam, list(ids)[:200])
+    k_pred = [O.kkt(q, a, b)["rel_kkt"] for q, a, b in zip(qps_t, x0[:200], y0[:200])]
+    k_zero = [O.kkt(q, np.zeros(q.n), np.zeros(q.m))["rel_kkt"] for q in qps_t]
+    return {"config": f"learned warm start, MPC T=50 (n=1500, m=5000), train {args.train}, test {args.test}, tol {args.tol:g}",
+            "train_solves_s": gen_solve_s, "train_s": train_s, "loss_first_last": [losses[0], losses[-1]],
+            "infer_s": infer_s, "cold": {"kernel_s": tc, "QPs/s": args.test / tc,
+                                         "iters_mean": float(np.mean([r["iters"] for r in rc])),
+                                         "solved": sum(r["status"] == 0 for r in rc)},
+            "warm": {"kernel_s": tw, "QPs/s": args.test / tw, "iters_mean": float(np.mean([r["iters"] for r in rw])),
+                     "solved": sum(r["status"] == 0 for r in rw),
+                     "fallback_rate": float(np.mean([r["cold_fallback"] for r in rw]))},
+            "warm_no_fallback": {"kernel_s": tn, "iters_mean": float(np.mean([r["iters"] for r in rn])),
+                                 "solved": sum(r["status"] == 0 for r in rn)},
+            "warm_primal_only": {"kernel_s": tx, "iters_mean": float(np.mean([r["iters"] for r in rx])),
+                                 "solved": sum(r["status"] == 0 for r in rx)},
+            "relkkt_pred_median": float(np.median(k_pred)), "relkkt_zero_median": float(np.median(k_zero)),
+            "speedup_warm_vs_cold": tc / tw}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -107,6 +271,11 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": a.numel() * 8, "copies": 3}))
         return
 
+    if args.config != "random1e5":
+        line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch,
+                "learned": bench_learned}[args.config](args)
+        print(json.dumps(line), flush=True)
+        return
     qp = workload()
     settings = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, num_blocks=args.num_blocks)
     solver = pdhcg.Solver(qp, settings)

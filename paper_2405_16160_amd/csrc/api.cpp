@@ -243,6 +243,8 @@ struct pdhcg_handle {
   double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *ax = nullptr, *ax_avg = nullptr,
          *x_anc = nullptr, *y_anc = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   float *x32 = nullptr, *r32 = nullptr, *p32_0 = nullptr, *p32_1 = nullptr, *xs32 = nullptr;
+  double *r_alt = nullptr, *u0 = nullptr, *u1 = nullptr, *s0 = nullptr, *s1 = nullptr;
+  float *r32_alt = nullptr, *u32_0 = nullptr, *u32_1 = nullptr, *s32_0 = nullptr, *s32_1 = nullptr;
   double *part = nullptr, *tmp_x0 = nullptr, *tmp_y0 = nullptr, *scratch = nullptr;
   uint64_t* bar = nullptr;
   SolverState* st = nullptr;
@@ -335,6 +337,9 @@ int ensure_mixed(pdhcg_handle* h) {
   if ((rc = h->alloc(&h->p32_0, h->n))) return rc;
   if ((rc = h->alloc(&h->p32_1, h->n))) return rc;
   if ((rc = h->alloc(&h->xs32, std::max(h->n, h->m)))) return rc;
+  float** f32v[] = {&h->r32_alt, &h->u32_0, &h->u32_1, &h->s32_0, &h->s32_1};
+  for (float** v : f32v)
+    if ((rc = h->alloc(v, h->n))) return rc;
   HIPX(launch_to_f32(h->q_val, h->q_val32, h->nnzQ, h->stream));
   if (h->nnzA > 0) {
     HIPX(launch_to_f32(h->a_val, h->a_val32, h->nnzA, h->stream));
@@ -405,6 +410,8 @@ SolveParams make_params(pdhcg_handle* h) {
   p.x = h->x; p.y = h->y; p.xa = h->xa; p.ya = h->ya; p.ax = h->ax; p.ax_avg = h->ax_avg;
   p.x_anc = h->x_anc; p.y_anc = h->y_anc; p.r = h->r; p.p0 = h->p0; p.p1 = h->p1; p.q = h->q;
   p.x32 = h->x32; p.r32 = h->r32; p.p32_0 = h->p32_0; p.p32_1 = h->p32_1;
+  p.r_alt = h->r_alt; p.u0 = h->u0; p.u1 = h->u1; p.s0 = h->s0; p.s1 = h->s1;
+  p.r32_alt = h->r32_alt; p.u32_0 = h->u32_0; p.u32_1 = h->u32_1; p.s32_0 = h->s32_0; p.s32_1 = h->s32_1;
   p.part = h->part;
   p.bar = h->bar;
   p.st = h->st;
@@ -529,7 +536,8 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
   if ((rc = upload_csr(h, A, &h->a_rowptr, &h->a_col, &h->a_val))) return bail(rc);
   if ((rc = upload_csr(h, T, &h->t_rowptr, &h->t_col, &h->t_val))) return bail(rc);
   const int64_t n = h->n, m = h->m;
-  double** nvecs[] = {&h->c, &h->x, &h->xa, &h->x_anc, &h->r, &h->p0, &h->p1, &h->q, &h->tmp_x0};
+  double** nvecs[] = {&h->c, &h->x, &h->xa, &h->x_anc, &h->r, &h->p0, &h->p1, &h->q, &h->tmp_x0,
+                      &h->r_alt, &h->u0, &h->u1, &h->s0, &h->s1};
   for (double** v : nvecs)
     if ((rc = h->alloc(v, n))) return bail(rc);
   double** mvecs[] = {&h->b, &h->y, &h->ya, &h->ax, &h->ax_avg, &h->y_anc, &h->tmp_y0};

@@ -187,6 +187,8 @@ struct GatherDir {
 
 struct TileLds {
   double prod[kTileNnz];
+  double sum1[kTileRows];
+  double sum2[kTileRows];
   int32_t rp[kTileRows + 1];
   int32_t rp2[kTileRows + 1];
 };
@@ -235,8 +237,10 @@ __device__ __forceinline__ void stage_rowptr(const int32_t* rowptr, int ra, int 
   for (int i = threadIdx.x; i <= nr; i += kBlock) rp[i] = rowptr[ra + i] - z0;
 }
 
-// One tile of a single matrix: epi(row, sum) is called by lane 0 of the
-// row's G-lane group.
+// One tile of a single matrix.  Row sums are formed by G-lane groups from the
+// staged products and parked in LDS; then epi(row, sum) runs with one thread
+// per row, so the epilogue's own loads and stores for all rows of the tile
+// are in flight together.
 template <typename V, typename Gather, typename Epi>
 __device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* col, const V* val, const int32_t* t,
                                           int G, const Gather& g, Epi epi) {
@@ -253,8 +257,10 @@ __device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* 
     if (act)
       for (int k = L.rp[i] + lane; k < L.rp[i + 1]; k += G) s += L.prod[k];
     s = group_sum(s, G);
-    if (act && lane == 0) epi(ra + i, s);
+    if (act && lane == 0) L.sum1[i] = s;
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr; i += kBlock) epi(ra + i, L.sum1[i]);
   __syncthreads();
 }
 
@@ -289,8 +295,13 @@ __device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t
     }
     s1 = group_sum(s1, G);
     s2 = group_sum(s2, G);
-    if (act && lane == 0) epi(ra + i, s1, s2);
+    if (act && lane == 0) {
+      L.sum1[i] = s1;
+      L.sum2[i] = s2;
+    }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr; i += kBlock) epi(ra + i, L.sum1[i], L.sum2[i]);
   __syncthreads();
 }
 

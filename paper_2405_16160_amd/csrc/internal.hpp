@@ -47,7 +47,7 @@ struct Part {
 };
 
 constexpr int kTileNnz = 4096;    // staged products per tile (FP64 in LDS)
-constexpr int kTileRows = 2048;   // rows per tile
+constexpr int kTileRows = 1024;   // rows per tile
 
 // Partial-result slots.  Every workgroup writes one value per slot; after a
 // grid barrier every workgroup reduces all of them in the same fixed order,
@@ -110,8 +110,12 @@ struct SolveParams {
   double *x, *y, *xa, *ya, *ax, *ax_avg, *x_anc, *y_anc;
   // CG work vectors (FP64)
   double *r, *p0, *p1, *q;
+  // one-reduction CG (cooperative kernel): second r buffer, u = (Q + I/tau) r
+  // and s = (Q + I/tau) p, double-buffered (null in the batched kernel)
+  double *r_alt, *u0, *u1, *s0, *s1;
   // FP32 copies used by the mixed-precision products
   float *x32, *r32, *p32_0, *p32_1;
+  float *r32_alt, *u32_0, *u32_1, *s32_0, *s32_1;
   double* part;         // [NSLOT][nb]
   uint64_t* bar;        // grid barrier words (zeroed before each launch)
   SolverState* st;

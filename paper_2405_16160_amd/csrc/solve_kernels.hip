@@ -258,6 +258,95 @@ __device__ __attribute__((noinline)) void phase_cg_update(const SolveParams& P, 
   if (B.tid == 0) P.part[S_RR * B.nb + B.b] = s[0];
 }
 
+// One step of CG in the single-reduction form of Chronopoulos and Gear, as
+// one phase.  With u = (Q + I/tau) r and s = (Q + I/tau) p kept alongside
+// r and p, step l (l >= 1, given alpha = alpha_{l-1}, beta = beta_{l-1})
+// forms on the owned rows
+//   s_{l-1} = u_{l-1} + beta s_{l-2},  p_{l-1} = r_{l-1} + beta p_{l-2},
+//   x += alpha p_{l-1},  r_l = r_{l-1} - alpha s_{l-1},
+// and u_l = (Q + I/tau) r_l with r_l formed at gather time from r_{l-1},
+// u_{l-1}, s_{l-2} of the other rows; the partials gamma_l = r_l.r_l and
+// delta_l = r_l.u_l then give beta_l = gamma_l / gamma_{l-1} and
+// alpha_l = gamma_l / (delta_l - beta_l gamma_l / alpha_{l-1}).  In exact
+// arithmetic this is the same iteration as the textbook CG of the primal step
+// (same x, r, step lengths), with one grid barrier per step instead of two.
+// Step 0 only forms u_0 = (Q + I/tau) r_0 and delta_0.  With product = false
+// (the last allowed step) only x is advanced.
+template <typename T>
+struct GatherCG {
+  const T* r;
+  const T* u;
+  const T* s;
+  double alpha, beta;
+  int l;
+  __device__ __forceinline__ double operator()(int j) const {
+    if (l == 0) return (double)r[j];
+    const double sj = l == 1 ? (double)u[j] : (double)u[j] + beta * (double)s[j];
+    return (double)r[j] - alpha * sj;
+  }
+};
+
+struct CgBufs {
+  const double *r_prev, *u_prev, *s_prev2;
+  double *r_new, *u_new, *s_prev1;
+  const float *r32_prev, *u32_prev, *s32_prev2;
+  float *r32_new, *u32_new, *s32_prev1;
+};
+
+template <typename V, typename T>
+__device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, const Block& B, const V* qval, const T* rg,
+                                                     const T* ug, const T* sg, const CgBufs& cb, int l, double alpha,
+                                                     double beta, double inv_tau, int product, int mixed,
+                                                     double* lds) {
+  double s[2] = {0.0, 0.0};  // gamma_l, delta_l
+  auto own = [&](int i) -> double {  // owned-row updates; returns r_l[i]
+    if (l == 0) return cb.r_prev[i];
+    const double s1 = l == 1 ? cb.u_prev[i] : cb.u_prev[i] + beta * cb.s_prev2[i];
+    const double pi = l == 1 ? cb.r_prev[i] : cb.r_prev[i] + beta * P.p0[i];
+    P.p0[i] = pi;
+    const double xi = P.x[i] + alpha * pi;
+    P.x[i] = xi;
+    if (mixed) P.x32[i] = (float)xi;
+    if (!product) return 0.0;
+    cb.s_prev1[i] = s1;
+    if (mixed) cb.s32_prev1[i] = (float)s1;
+    const double ri = cb.r_prev[i] - alpha * s1;
+    cb.r_new[i] = ri;
+    if (mixed) cb.r32_new[i] = (float)ri;
+    return ri;
+  };
+  if (!product) {
+    const int r0 = P.pcg.bounds[B.b], r1 = P.pcg.bounds[B.b + 1];
+    for (int i = r0 + B.tid; i < r1; i += kBlock) own(i);
+    return;
+  }
+  auto epi = [&](int i, double qr) {
+    const double ri = own(i);
+    const double ui = qr + ri * inv_tau;
+    cb.u_new[i] = ui;
+    if (mixed) cb.u32_new[i] = (float)ui;
+    s[0] += ri * ri;
+    s[1] += ri * ui;
+  };
+  const Part& pt = P.pcg;
+  GatherCG<T> g{rg, ug, sg, alpha, beta, l};
+  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
+    tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tiles + 6 * t, pt.group, g, epi);
+  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+    const int i = pt.long_rows[t];
+    double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, g)};
+    double dummy[1] = {0.0};
+    block_reduce<1, 0>(v, dummy, lds);
+    if (B.tid == 0) epi(i, v[0]);
+  }
+  double dummy[1] = {0.0};
+  block_reduce<2, 0>(s, dummy, lds);
+  if (B.tid == 0) {
+    P.part[S_RR * B.nb + B.b] = s[0];
+    P.part[S_PQ * B.nb + B.b] = s[1];
+  }
+}
+
 // Dual step and averages (Alg. 1): u = A x^{k+1};
 // y <- max(0, y + sigma (2u - A x^k - b)); A x^k <- u; ya += w (y - ya);
 // xa += w (x - xa) on an n-slice; m-side partials of the new point.
@@ -528,7 +617,51 @@ __device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, Solver
     S.eps += P.eps_factor * kc.kkt;
     const double inv_tau = 1.0 / S.tau;
     int steps = 0;
-    if (rho > 0.0) {
+    if (rho > 0.0 && P.u0 != nullptr) {
+      // single-reduction CG: L steps take L + 1 grid barriers
+      double* rb[2] = {P.r, P.r_alt};
+      double* ub[2] = {P.u0, P.u1};
+      double* sb[2] = {P.s0, P.s1};
+      float* rb32[2] = {P.r32, P.r32_alt};
+      float* ub32[2] = {P.u32_0, P.u32_1};
+      float* sb32[2] = {P.s32_0, P.s32_1};
+      double gamma = rho, alpha = 0.0, beta = 0.0;
+      for (int l = 0; l <= P.max_cg; ++l) {
+        const int product = l < P.max_cg;
+        const int c = l & 1, o = c ^ 1;
+        CgBufs cb{rb[o], ub[o], sb[c], rb[c], ub[c], sb[o], rb32[o], ub32[o], sb32[c], rb32[c], ub32[c], sb32[o]};
+        if (l == 0) {  // step 0 reads r_0 from buffer 0 and writes u_0 to buffer 0
+          cb.r_prev = rb[0];
+          cb.u_new = ub[0];
+          cb.u32_new = ub32[0];
+        }
+        if (S.mixed)
+          phase_cgcg(P, B, P.Q.val32, (const float*)(l == 0 ? rb32[0] : rb32[o]), (const float*)ub32[o],
+                     (const float*)sb32[c], cb, l, alpha, beta, inv_tau, product, 1, lds);
+        else
+          phase_cgcg(P, B, P.Q.val, (const double*)(l == 0 ? rb[0] : rb[o]), (const double*)ub[o],
+                     (const double*)sb[c], cb, l, alpha, beta, inv_tau, product, 0, lds);
+        if (!(ok = gs.sync())) break;
+        if (l > 0) steps = l;
+        if (!product) break;
+        const int ss2[2] = {S_RR, S_PQ};
+        const int ms2[1] = {0};
+        double gd[2], m2[1];
+        reduce_partials<2, 0>(P.part, B.nb, ss2, ms2, gd, m2, lds);
+        if (l == 0) {
+          alpha = gamma / gd[1];
+          beta = 0.0;
+          continue;
+        }
+        const double gl = gd[0], dl = gd[1];
+        if (P.cg_rule == 0 && S.tau * sqrt(gl) <= S.eps) break;
+        if (!(gl > 0.0)) break;
+        beta = gl / gamma;
+        alpha = gl / (dl - beta * gl / alpha);
+        gamma = gl;
+      }
+      if (!ok) break;
+    } else if (rho > 0.0) {
       double beta = 0.0;
       int first = 1, cur = 0;
       for (int l = 1; l <= P.max_cg; ++l) {
@@ -573,7 +706,7 @@ __device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, Solver
   return ok;
 }
 
-__global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
+__global__ void __launch_bounds__(kBlock, 2) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
   const SolveParams& P = *Pg;
   const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
   __shared__ double lds[kWaves * 16];
@@ -680,7 +813,7 @@ __global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) {
 // nb = 1 (a grid barrier degenerates to a workgroup barrier), on its own slice
 // of the packed matrices and vectors; dense Q blocks use the streaming dense
 // product.  ||A|| comes from the same power iteration, per instance.
-__global__ void __launch_bounds__(kBlock) pdhcg_batch_kernel(BatchParams BP) {
+__global__ void __launch_bounds__(kBlock, 2) pdhcg_batch_kernel(BatchParams BP) {
   __shared__ double lds[kWaves * 16];
   __shared__ double svec[kDenseTile];
   const int idx = BP.order[blockIdx.x];

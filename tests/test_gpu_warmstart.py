@@ -21,21 +21,6 @@ def say(msg):
     print(msg, flush=True)
 
 
-def test_canonical_duals_keep_At_y_and_b_y():
-    fam = I.mpc_family()
-    plus, minus = W.pair_index(fam)
-    A = fam.A.to_scipy()
-    assert abs(A[plus] + A[minus]).max() == 0          # rows really are +/- pairs
-    rng = np.random.default_rng(0)
-    Y = np.abs(rng.standard_normal((3, fam.A.nrows)))
-    Yc = W.canonical_duals(Y, plus, minus)
-    b = fam.b_for(I.mpc_initial_state(0, fam))
-    for y, yc in zip(Y, Yc):
-        assert np.allclose(A.T @ y, A.T @ yc, atol=1e-12)
-        assert b @ y == pytest.approx(b @ yc, abs=1e-10)
-        assert np.all(np.minimum(yc[plus], yc[minus]) == 0)
-
-
 def test_learned_warm_start_gains_over_cold_start():
     fam = I.mpc_family()
     plus, minus = W.pair_index(fam)
