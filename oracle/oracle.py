@@ -94,13 +94,23 @@ def build(force: bool = False) -> str:
 
 
 _lib = None
+_lib_path = None
+
+
+def use_library(path=None):
+    """Load the oracle from another compiled copy of pdhcg_oracle.c (the
+    mutation tests build copies with a planted mistake); None restores the
+    default library."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        if _lib_path is None:
+            build()
+        L = C.CDLL(_lib_path or _LIB)
         P = C.c_void_p
         L.or_matvec.argtypes = [C.POINTER(_Csr), P, P]
         L.or_matvec_t.argtypes = [C.POINTER(_Csr), P, P]
