@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the FETCH/WRITE counters)")
     ap.add_argument("--config", default="random1e5",
-                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned"],
+                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "precision"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--train", type=int, default=100_000)
@@ -218,7 +218,7 @@ def bench_learned(args):
     th, X, Y, rs, gen_solve_s = W.solve_family(fam, range(args.train), pdhcg.Settings(tol_rel_kkt=1e-6))
     Y = W.canonical_duals(Y, plus, minus)
     t_train = time.perf_counter()
-    ws, losses = W.train(th, X, Y, epochs=args.epochs)
+    ws, losses = W.train(th, X, Y, W.DualCode(fam.A.nrows, plus, minus), epochs=args.epochs)
     train_s = time.perf_counter() - t_train
     ids = range(100_000, 100_000 + args.test)
     th_t, _ = W.family_qps(fam, ids)
@@ -251,6 +251,38 @@ def bench_learned(args):
             "speedup_warm_vs_cold": tc / tw}
 
 
+def bench_precision(args):
+    """Error of the FP64 and the FP32-product modes against the FP64 oracle
+    (run to relKKT 1e-9), both solved to relKKT 1e-6, for each workload family."""
+    from oracle import oracle as O
+    from paper_2405_16160_amd import instances as I, pdhcg
+    cases = [("tiny random n=1000", I.random_qp(family=1, instance=0), None),
+             ("random n=1e5 (benchmark instance)", workload(), None),
+             ("manufactured n=1e5 (exact optimum)", I.manufactured(100_000, 50_000, 2e-5, 2e-4, r_rows=50_000,
+                                                                   family=41), "exact"),
+             ("MPC n=1500 m=5000", I.mpc_qp(0), None),
+             ("portfolio n=355 (dense Q)", I.portfolio_qp(0, nmax=400), None)]
+    out = {}
+    for name, qp, kind in cases:
+        if kind == "exact":
+            xr, fr = qp.x_star, 0.5 * qp.x_star @ (qp.Q.to_scipy() @ qp.x_star) + qp.c @ qp.x_star
+        else:
+            ref = O.solve(qp, O.Settings(tol=1e-9, max_iters=1_000_000))
+            xr, fr = ref.x, ref.primal_obj
+        row = {}
+        for prec in (0, 1):
+            sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-6, precision=prec, max_iters=1_000_000))
+            x, y, r = sol.solve()
+            sol.close()
+            x = x.cpu().numpy()
+            k = O.kkt(qp, x, y.cpu().numpy())
+            row["fp64" if prec == 0 else "fp32_products"] = {
+                "rel_kkt_fp64_data": k["rel_kkt"], "x_rel_err": float(np.linalg.norm(x - xr) / np.linalg.norm(xr)),
+                "obj_rel_err": abs(k["primal_obj"] - fr) / (1 + abs(fr)), "iters": r["iters"]}
+        out[name] = row
+    return {"config": "precision modes vs the FP64 oracle at relKKT 1e-6", "cases": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -273,7 +305,7 @@ def main():
 
     if args.config != "random1e5":
         line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch,
-                "learned": bench_learned}[args.config](args)
+                "learned": bench_learned, "precision": bench_precision}[args.config](args)
         print(json.dumps(line), flush=True)
         return
     qp = workload()

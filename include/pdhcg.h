@@ -149,6 +149,15 @@ int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
 int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* x, double* y,
                int32_t repeats);
 
+/* Autotuner of the single-QP kernel: for each candidate grid size (64, 128,
+ * 256, 512 workgroups, within what fits on the device) and lane-group scaling
+ * (the planner's lane group per row halved, as planned, doubled) run `iters`
+ * iterations from (0, 0) and time the solve kernel (HIP events); keep the
+ * fastest per iteration and re-plan the row partitions for it.  The settings'
+ * num_blocks becomes the chosen grid size.  num_blocks and group_scale
+ * (log2 of the scaling) may be NULL. */
+int pdhcg_autotune(pdhcg_handle* h, int32_t iters, int32_t* num_blocks, int32_t* group_scale);
+
 /* Grid size and row-split parameters the planner chose (for reporting). */
 int pdhcg_plan_info(const pdhcg_handle* h, int32_t* num_blocks, int32_t* group_n, int32_t* group_q,
                     int32_t* group_m, int64_t* long_rows);

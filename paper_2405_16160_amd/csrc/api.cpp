@@ -158,7 +158,7 @@ int pow2_ceil(double v) {
 // kLongRow entries listed per workgroup; the other rows cut into tiles of at
 // most kTileNnz entries and kTileRows rows.  The lane group is the power of
 // two at or above the mean length of the short rows.
-HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp2) {
+HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp2, int gscale = 0) {
   HostPart P;
   auto len = [&](int64_t i) -> int64_t {
     return (rp1 ? rp1[i + 1] - rp1[i] : 0) + (rp2 ? rp2[i + 1] - rp2[i] : 0);
@@ -210,6 +210,8 @@ HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp
   }
   const double mean = short_rows ? (double)short_nnz / (double)short_rows : 1.0;
   P.group = pow2_ceil(mean);
+  for (int k = 0; k < gscale && P.group < 64; ++k) P.group <<= 1;
+  for (int k = 0; k > gscale && P.group > 1; --k) P.group >>= 1;
   return P;
 }
 
@@ -254,6 +256,9 @@ struct pdhcg_handle {
   DevPart sq, sa, st_;                     // parts for the standalone products
   std::vector<void*> allocs;
   std::vector<double> c_host;  // c, for relKKT(0, 0) when b changes
+  std::vector<int64_t> qrp_h, arp_h, trp_h;  // host row pointers, for re-planning
+  int gscale = 0;              // lane-group scaling (log2) chosen by the autotuner
+  int max_nb = 1;
 
   ~pdhcg_handle() {
     if (ev0) (void)hipEventDestroy(ev0);
@@ -364,6 +369,34 @@ int check_settings(const pdhcg_settings* s) {
   return 0;
 }
 
+void free_part(pdhcg_handle* h, DevPart& D) {
+  for (int32_t** p : {&D.bounds, &D.long_ptr, &D.long_rows, &D.tile_ptr, &D.tiles}) {
+    if (*p) {
+      (void)hipFree(*p);
+      h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), (void*)*p), h->allocs.end());
+      *p = nullptr;
+    }
+  }
+}
+
+// (Re)build the partitions of the persistent kernels for nb workgroups and
+// lane groups scaled by 2^gscale.
+int plan_grid(pdhcg_handle* h, int nb, int gscale) {
+  int rc;
+  nb = std::max(1, std::min(nb, h->max_nb));
+  h->nb = nb;
+  h->gscale = gscale;
+  const int64_t* qrp = h->qrp_h.data();
+  const int64_t* arp = h->m ? h->arp_h.data() : nullptr;
+  const int64_t* trp = h->m ? h->trp_h.data() : nullptr;
+  for (DevPart* d : {&h->pn1, &h->pcg, &h->pm, &h->pt}) free_part(h, *d);
+  if ((rc = upload_part(h, build_part(h->n, nb, qrp, trp, gscale), h->pn1))) return rc;
+  if ((rc = upload_part(h, build_part(h->n, nb, qrp, nullptr, gscale), h->pcg))) return rc;
+  if ((rc = upload_part(h, build_part(h->m, nb, arp, nullptr, gscale), h->pm))) return rc;
+  if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr, gscale), h->pt))) return rc;
+  return 0;
+}
+
 int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) {
   int rc;
   int dev = 0, cus = 0;
@@ -371,22 +404,22 @@ int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) 
   HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   int per_cu = 0;
   HIPX(solve_occupancy(&per_cu));
-  const int max_nb = std::max(1, std::min(cus * std::max(per_cu, 1), 1024));
+  h->max_nb = std::max(1, std::min(cus * std::max(per_cu, 1), 1024));
   int nb = h->s.num_blocks;
   if (nb == 0) {
     const double work = (double)h->nnzQ + 0.25 * (double)h->nnzA + (double)(h->n + h->m);
     nb = 8;
     while (nb < 256 && work / nb > 4096.0) nb <<= 1;
   }
-  nb = std::min(nb, max_nb);
-  h->nb = nb;
+  h->qrp_h = Q.rowptr;
+  if (A.nrows) {
+    h->arp_h = A.rowptr;
+    h->trp_h = T.rowptr;
+  }
   const int64_t* qrp = Q.rowptr.data();
   const int64_t* arp = A.nrows ? A.rowptr.data() : nullptr;
   const int64_t* trp = A.nrows ? T.rowptr.data() : nullptr;
-  if ((rc = upload_part(h, build_part(h->n, nb, qrp, trp), h->pn1))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nb, qrp, nullptr), h->pcg))) return rc;
-  if ((rc = upload_part(h, build_part(h->m, nb, arp, nullptr), h->pm))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr), h->pt))) return rc;
+  if ((rc = plan_grid(h, nb, 0))) return rc;
   // standalone products: enough workgroups to fill the chip
   int nbs = 64;
   const double w = (double)std::max<int64_t>(h->nnzQ, h->nnzA) + (double)std::max(h->n, h->m);
@@ -569,10 +602,10 @@ int pdhcg_set_settings(pdhcg_handle* h, const pdhcg_settings* s) {
   if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
   int rc;
   if ((rc = check_settings(s))) return rc;
-  const bool replan = s->num_blocks != h->s.num_blocks;
+  const bool replan = s->num_blocks != 0 && s->num_blocks != h->nb;
   const int32_t old_power = h->s.power_iters;
   h->s = *s;
-  if (replan) return fail(PDHCG_ERR_INVALID_ARGUMENT, "num_blocks cannot change after pdhcg_create");
+  if (replan && (rc = plan_grid(h, s->num_blocks, h->gscale))) return rc;
   if (s->precision == 1 && (rc = ensure_mixed(h))) return rc;
   if (s->power_iters != old_power && (rc = estimate_norm(h))) return rc;
   return 0;
@@ -685,6 +718,49 @@ int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* 
   for (int r = 0; r < std::max(repeats, 1); ++r)
     HIPX(launch_spmv(M, pt.view(), h->nb_spmv, precision, x, x32, y, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+int pdhcg_autotune(pdhcg_handle* h, int32_t iters, int32_t* num_blocks, int32_t* group_scale) {
+  if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
+  if (iters < 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "iters must be >= 1");
+  int rc;
+  double* xs = nullptr;
+  double* ys = nullptr;
+  if ((rc = h->alloc(&xs, h->n))) return rc;
+  if ((rc = h->alloc(&ys, std::max<int64_t>(h->m, 1)))) return rc;
+  const pdhcg_settings saved = h->s;
+  h->s.tol_rel_kkt = 0.0;
+  h->s.max_iters = iters;
+  h->s.time_limit_s = 0.0;
+  h->s.verbose = 0;
+  double best = 1e300;
+  int best_nb = h->nb, best_g = h->gscale;
+  for (int nb : {64, 128, 256, 512}) {
+    if (nb > h->max_nb) continue;
+    for (int g : {-1, 0, 1}) {
+      if ((rc = plan_grid(h, nb, g))) break;
+      pdhcg_result r;
+      if ((rc = pdhcg_solve(h, nullptr, nullptr, xs, ys, 1, &r))) break;
+      const double per = r.kernel_s / (double)std::max<int64_t>(r.iters, 1);
+      if (per < best) {
+        best = per;
+        best_nb = h->nb;
+        best_g = g;
+      }
+    }
+    if (rc) break;
+  }
+  h->s = saved;
+  for (double* p : {xs, ys}) {
+    (void)hipFree(p);
+    h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), (void*)p), h->allocs.end());
+  }
+  if (rc) return rc;
+  if ((rc = plan_grid(h, best_nb, best_g))) return rc;
+  h->s.num_blocks = best_nb;
+  if (num_blocks) *num_blocks = best_nb;
+  if (group_scale) *group_scale = best_g;
   return 0;
 }
 

@@ -199,42 +199,62 @@ __device__ __forceinline__ TileLds& tile_lds() {
   return L;
 }
 
-constexpr int kStageUnroll = 8;  // loads in flight per thread while staging
+constexpr int kStageUnroll = kTileNnz / kBlock;  // entries per thread: one burst per tile
+constexpr int kRowsPerThread = (kTileRows + 1 + kBlock - 1) / kBlock;
 
-// prod[base + k] = M[z0 + k] * g(col[z0 + k]) for k < nz: every thread issues
-// kStageUnroll index/value loads, then kStageUnroll gathers, then the stores.
-template <typename V, typename Gather>
-__device__ __forceinline__ void stage_products(const int32_t* col, const V* val, int z0, int nz, const Gather& g,
-                                               double* prod) {
-  for (int k0 = 0; k0 < nz; k0 += kBlock * kStageUnroll) {
-    int c[kStageUnroll];
-    double v[kStageUnroll];
+// Stage one tile in LDS with every load of the tile in flight at once:
+// row offsets of up to two matrices (rp1, rp2: rowptr[ra + i] - base), and the
+// entry list [M1 entries z0..z0+nz, M2 entries w0..w0+nw] as products
+// val * g(col) into prod[0 .. nz+nw).  Index, value and row-pointer loads are
+// issued first, then the gathers, then the LDS stores.
+template <typename V1, typename G1, typename V2, typename G2>
+__device__ __forceinline__ void stage_tile(const int32_t* rowptr1, const int32_t* col1, const V1* val1, const G1& g1,
+                                           int z0, int nz, const int32_t* rowptr2, const int32_t* col2,
+                                           const V2* val2, const G2& g2, int w0, int nw, int ra, int nr,
+                                           int32_t* rp1, int32_t* rp2, double* prod) {
+  const int tid = threadIdx.x;
+  int r1[kRowsPerThread], r2[kRowsPerThread];
 #pragma unroll
-    for (int u = 0; u < kStageUnroll; ++u) {
-      const int k = k0 + u * kBlock + (int)threadIdx.x;
-      c[u] = 0;
-      v[u] = 0.0;
-      if (k < nz) {
-        c[u] = col[z0 + k];
-        v[u] = ldv(val, z0 + k);
-      }
-    }
-    double gv[kStageUnroll];
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int i = u * kBlock + tid;
+    r1[u] = (rowptr1 && i <= nr) ? rowptr1[ra + i] : 0;
+    r2[u] = (rowptr2 && i <= nr) ? rowptr2[ra + i] : 0;
+  }
+  const int ntot = nz + nw;
+  int c[kStageUnroll];
+  double v[kStageUnroll];
 #pragma unroll
-    for (int u = 0; u < kStageUnroll; ++u) {
-      const int k = k0 + u * kBlock + (int)threadIdx.x;
-      gv[u] = k < nz ? g(c[u]) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < kStageUnroll; ++u) {
-      const int k = k0 + u * kBlock + (int)threadIdx.x;
-      if (k < nz) prod[k] = v[u] * gv[u];
+  for (int u = 0; u < kStageUnroll; ++u) {
+    const int k = u * kBlock + tid;
+    c[u] = 0;
+    v[u] = 0.0;
+    if (k < nz) {
+      c[u] = col1[z0 + k];
+      v[u] = ldv(val1, z0 + k);
+    } else if (k < ntot) {
+      c[u] = col2[w0 + k - nz];
+      v[u] = ldv(val2, w0 + k - nz);
     }
   }
-}
-
-__device__ __forceinline__ void stage_rowptr(const int32_t* rowptr, int ra, int nr, int z0, int32_t* rp) {
-  for (int i = threadIdx.x; i <= nr; i += kBlock) rp[i] = rowptr[ra + i] - z0;
+  double gv[kStageUnroll];
+#pragma unroll
+  for (int u = 0; u < kStageUnroll; ++u) {
+    const int k = u * kBlock + tid;
+    gv[u] = k < nz ? g1(c[u]) : (k < ntot ? g2(c[u]) : 0.0);
+  }
+#pragma unroll
+  for (int u = 0; u < kStageUnroll; ++u) {
+    const int k = u * kBlock + tid;
+    if (k < ntot) prod[k] = v[u] * gv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int i = u * kBlock + tid;
+    if (i <= nr) {
+      if (rowptr1) rp1[i] = r1[u] - z0;
+      if (rowptr2) rp2[i] = r2[u] - w0 + nz;
+    }
+  }
 }
 
 // One tile of a single matrix.  Row sums are formed by G-lane groups from the
@@ -246,8 +266,7 @@ __device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* 
                                           int G, const Gather& g, Epi epi) {
   TileLds& L = tile_lds();
   const int ra = t[0], nr = t[1] - t[0], z0 = t[2], nz = t[3] - t[2];
-  stage_rowptr(rowptr, ra, nr, z0, L.rp);
-  stage_products(col, val, z0, nz, g, L.prod);
+  stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, 0, 0, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
   const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
   for (int base = 0; base < nr; base += ng) {
@@ -272,15 +291,8 @@ __device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t
                                            const double* val2, const Gather2& g2, const int32_t* t, int G, Epi epi) {
   TileLds& L = tile_lds();
   const int ra = t[0], nr = t[1] - t[0];
-  const int z0 = t[2], nz = t[3] - t[2], w0 = t[4], nw = t[5] - t[4];
-  if (rowptr1) {
-    stage_rowptr(rowptr1, ra, nr, z0, L.rp);
-    stage_products(col1, val1, z0, nz, g1, L.prod);
-  }
-  if (rowptr2) {
-    stage_rowptr(rowptr2, ra, nr, w0 - nz, L.rp2);
-    stage_products(col2, val2, w0, nw, g2, L.prod + nz);
-  }
+  const int z0 = t[2], nz = rowptr1 ? t[3] - t[2] : 0, w0 = t[4], nw = rowptr2 ? t[5] - t[4] : 0;
+  stage_tile(rowptr1, col1, val1, g1, z0, nz, rowptr2, col2, val2, g2, w0, nw, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
   const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
   for (int base = 0; base < nr; base += ng) {

@@ -5,7 +5,7 @@
 
 namespace pdhcg {
 
-constexpr int kBlock = 256;       // threads per workgroup of every solver kernel
+constexpr int kBlock = 512;       // threads per workgroup of every solver kernel
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kWaves = kBlock / kWave;
 constexpr int kLongRow = 1024;    // rows longer than this are reduced by the whole workgroup

@@ -706,7 +706,7 @@ __device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, Solver
   return ok;
 }
 
-__global__ void __launch_bounds__(kBlock, 2) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
+__global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
   const SolveParams& P = *Pg;
   const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
   __shared__ double lds[kWaves * 16];
@@ -813,7 +813,7 @@ __global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) {
 // nb = 1 (a grid barrier degenerates to a workgroup barrier), on its own slice
 // of the packed matrices and vectors; dense Q blocks use the streaming dense
 // product.  ||A|| comes from the same power iteration, per instance.
-__global__ void __launch_bounds__(kBlock, 2) pdhcg_batch_kernel(BatchParams BP) {
+__global__ void __launch_bounds__(kBlock) pdhcg_batch_kernel(BatchParams BP) {
   __shared__ double lds[kWaves * 16];
   __shared__ double svec[kDenseTile];
   const int idx = BP.order[blockIdx.x];

@@ -45,8 +45,8 @@ class pdhcg_result(C.Structure):
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
 EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_spmv", "pdhcg_plan_info", "pdhcg_destroy", "pdhcg_error_string",
-           "pdhcg_last_error"]
+           "pdhcg_solve_batch", "pdhcg_spmv", "pdhcg_autotune", "pdhcg_plan_info", "pdhcg_destroy",
+           "pdhcg_error_string", "pdhcg_last_error"]
 
 
 class PdhcgError(RuntimeError):
@@ -77,6 +77,7 @@ def lib():
         L.pdhcg_solve_batch.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_spmv.argtypes = [P, C.c_int32, C.c_int32, P, P, C.c_int32]
         L.pdhcg_plan_info.argtypes = [P, P, P, P, P, P]
+        L.pdhcg_autotune.argtypes = [P, C.c_int32, P, P]
         L.pdhcg_destroy.argtypes = [P]
         L.pdhcg_destroy.restype = None
         L.pdhcg_error_string.argtypes = [C.c_int]
@@ -201,6 +202,12 @@ class Solver:
         y = out if out is not None else torch.empty(max(nrows, 1), dtype=torch.float64, device=self.dev)
         _check(lib().pdhcg_spmv(self.h, which, precision, xt.data_ptr(), y.data_ptr(), repeats))
         return y[:nrows]
+
+    def autotune(self, iters: int = 50) -> dict:
+        nb, g = C.c_int32(), C.c_int32()
+        _check(lib().pdhcg_autotune(self.h, iters, C.byref(nb), C.byref(g)))
+        self.settings.num_blocks = nb.value
+        return {"num_blocks": nb.value, "group_scale": g.value}
 
     def plan_info(self) -> dict:
         v = [C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()]

@@ -84,11 +84,40 @@ class Scaler:
         return Z * self.sd + self.mu
 
 
-class WarmStarter:
-    """theta -> (x0, y0) through the trained network (y0 projected on y >= 0)."""
+class DualCode:
+    """Network targets for the dual: the multiplier of each equality pair,
+    lam = y+ - y- (smooth in theta), and the other rows' duals as they are;
+    decoding puts y+ = max(lam, 0), y- = max(-lam, 0) and projects the rest on
+    y >= 0 (the canonical form of canonical_duals)."""
 
-    def __init__(self, net: _mlp.Network, sin: Scaler, sout: Scaler, n: int):
-        self.net, self.sin, self.sout, self.n = net, sin, sout, n
+    def __init__(self, m, plus, minus):
+        self.m, self.plus, self.minus = m, plus, minus
+        mask = np.ones(m, dtype=bool)
+        mask[plus] = False
+        mask[minus] = False
+        self.rest = np.nonzero(mask)[0]
+
+    @property
+    def width(self):
+        return len(self.plus) + len(self.rest)
+
+    def encode(self, Y):
+        return np.concatenate([Y[:, self.plus] - Y[:, self.minus], Y[:, self.rest]], axis=1)
+
+    def decode(self, Z):
+        k = len(self.plus)
+        Y = np.zeros((Z.shape[0], self.m))
+        Y[:, self.plus] = np.maximum(Z[:, :k], 0.0)
+        Y[:, self.minus] = np.maximum(-Z[:, :k], 0.0)
+        Y[:, self.rest] = np.maximum(Z[:, k:], 0.0)
+        return Y
+
+
+class WarmStarter:
+    """theta -> (x0, y0) through the trained network (y0 >= 0 by construction)."""
+
+    def __init__(self, net: _mlp.Network, sin: Scaler, sout: Scaler, n: int, code: DualCode):
+        self.net, self.sin, self.sout, self.n, self.code = net, sin, sout, n, code
 
     def predict(self, thetas):
         import torch
@@ -98,17 +127,16 @@ class WarmStarter:
             Xt = torch.tensor(self.sin.fwd(thetas[a:a + B]), dtype=torch.float32, device="cuda")
             out.append(self.net.forward(Xt).cpu().numpy().astype(np.float64))
         Z = self.sout.inv(np.concatenate(out))
-        x0 = Z[:, : self.n]
-        y0 = np.maximum(Z[:, self.n:], 0.0)
-        return x0, y0
+        return Z[:, : self.n], self.code.decode(Z[:, self.n:])
 
 
-def train(theta, X, Y, hidden=512, epochs=20, batch=512, lr=1e-3, seed=0, log=None):
-    """Train the network on (theta -> [x, y]) with Adam on standardised data;
-    returns the WarmStarter and the per-epoch mean losses."""
+def train(theta, X, Y, code: DualCode, hidden=512, epochs=20, batch=512, lr=1e-3, seed=0, log=None):
+    """Train the network on theta -> [x, encoded y] with Adam on standardised
+    data (cosine learning-rate decay); returns the WarmStarter and the
+    per-epoch mean losses."""
     import torch
     n = X.shape[1]
-    Z = np.concatenate([X, Y], axis=1)
+    Z = np.concatenate([X, code.encode(Y)], axis=1)
     sin, sout = Scaler.fit(theta), Scaler.fit(Z)
     Xt = torch.tensor(sin.fwd(theta), dtype=torch.float32, device="cuda")
     Zt = torch.tensor(sout.fwd(Z), dtype=torch.float32, device="cuda")
@@ -128,4 +156,4 @@ def train(theta, X, Y, hidden=512, epochs=20, batch=512, lr=1e-3, seed=0, log=No
         losses.append(tot / max(cnt, 1))
         if log:
             log(f"epoch {ep}: loss {losses[-1]:.4e}")
-    return WarmStarter(net, sin, sout, n), losses
+    return WarmStarter(net, sin, sout, n, code), losses

@@ -259,3 +259,18 @@ def test_powerlaw_parity_small():
     assert info["long_rows"] > 0
     assert r["status"] == 0
     assert O.kkt(qp, x, y)["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+
+
+def test_autotune_then_solve():
+    """The autotuner re-plans the partitions; the tuned solve still meets the contract."""
+    say("[autotune] random_qp n=1000 instance=3")
+    qp = I.random_qp(family=1, instance=3)
+    ref = oracle_ref(qp, ("rq1", 3))
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-6))
+    choice = sol.autotune(iters=20)
+    say(f"  chose {choice}")
+    assert choice["num_blocks"] in (64, 128, 256, 512) and choice["group_scale"] in (-1, 0, 1)
+    x, y, r = sol.solve()
+    assert r["status"] == 0
+    check_contract(qp, x.cpu().numpy(), y.cpu().numpy(), ref)
+    sol.close()

@@ -30,7 +30,7 @@ def test_learned_warm_start_gains_over_cold_start():
     assert all(r["status"] == 0 for r in rs)
     Y = W.canonical_duals(Y, plus, minus)
     say(f"  solved in {secs:.2f}s; training")
-    ws, losses = W.train(th, X, Y, epochs=30, batch=256, lr=2e-3, log=say)
+    ws, losses = W.train(th, X, Y, W.DualCode(fam.A.nrows, plus, minus), epochs=40, batch=256, lr=2e-3, log=say)
     assert losses[-1] < 0.5 * losses[0]
     test_ids = range(100_000, 100_200)
     th_t, qps = W.family_qps(fam, test_ids)

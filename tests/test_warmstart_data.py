@@ -21,3 +21,14 @@ def test_canonical_duals_keep_At_y_and_b_y():
         assert np.allclose(A.T @ y, A.T @ yc, atol=1e-12)
         assert b @ y == pytest.approx(b @ yc, abs=1e-10)
         assert np.all(np.minimum(yc[plus], yc[minus]) == 0)
+
+
+
+def test_dual_code_round_trip():
+    fam = I.mpc_family()
+    plus, minus = W.pair_index(fam)
+    code = W.DualCode(fam.A.nrows, plus, minus)
+    rng = np.random.default_rng(1)
+    Y = W.canonical_duals(np.abs(rng.standard_normal((4, fam.A.nrows))), plus, minus)
+    assert code.width == fam.A.nrows - len(plus)
+    assert np.allclose(code.decode(code.encode(Y)), Y, atol=0, rtol=0)
