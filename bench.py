@@ -46,9 +46,9 @@ def parse():
                     choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "precision"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--train", type=int, default=100_000)
-    ap.add_argument("--test", type=int, default=10_000)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--train", type=int, default=20_000)
+    ap.add_argument("--test", type=int, default=4_000)
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--iters", type=int, default=300, help="fixed iterations for the power-law bandwidth run")
     return ap.parse_args()
 
@@ -211,10 +211,10 @@ def bench_batch(args):
 def bench_learned(args):
     """Learned warm start on the MPC family: train on PDHCG solutions, then
     batched cold vs warm solves of held-out members to tol."""
+    import dataclasses
     from paper_2405_16160_amd import instances as I, pdhcg, warmstart as W
     fam = I.mpc_family()
     plus, minus = W.pair_index(fam)
-    t = time.perf_counter()
     th, X, Y, rs, gen_solve_s = W.solve_family(fam, range(args.train), pdhcg.Settings(tol_rel_kkt=1e-6))
     Y = W.canonical_duals(Y, plus, minus)
     t_train = time.perf_counter()
@@ -225,30 +225,29 @@ def bench_learned(args):
     t = time.perf_counter()
     x0, y0 = ws.predict(th_t)
     infer_s = time.perf_counter() - t
-    s = pdhcg.Settings(tol_rel_kkt=args.tol)
+    s = pdhcg.Settings(tol_rel_kkt=args.tol, warm_fallback=0)
     _, _, _, rc, tc = W.solve_family(fam, ids, s)
     _, _, _, rw, tw = W.solve_family(fam, ids, s, x0s=x0, y0s=y0)
-    s_nf = pdhcg.Settings(tol_rel_kkt=args.tol, warm_fallback=0)
-    _, _, _, rn, tn = W.solve_family(fam, ids, s_nf, x0s=x0, y0s=y0)
-    _, _, _, rx, tx = W.solve_family(fam, ids, s_nf, x0s=x0)
+    _, _, _, rf, tf = W.solve_family(fam, ids, dataclasses.replace(s, warm_fallback=1), x0s=x0, y0s=y0)
+    _, _, _, rx, tx = W.solve_family(fam, ids, s, x0s=x0)
     from oracle import oracle as O
     _, qps_t = W.family_qps(fam, list(ids)[:200])
     k_pred = [O.kkt(q, a, b)["rel_kkt"] for q, a, b in zip(qps_t, x0[:200], y0[:200])]
     k_zero = [O.kkt(q, np.zeros(q.n), np.zeros(q.m))["rel_kkt"] for q in qps_t]
-    return {"config": f"learned warm start, MPC T=50 (n=1500, m=5000), train {args.train}, test {args.test}, tol {args.tol:g}",
+
+    def row(r, secs):
+        return {"kernel_s": secs, "QPs/s": args.test / secs, "iters_mean": float(np.mean([x["iters"] for x in r])),
+                "solved": sum(x["status"] == 0 for x in r)}
+
+    fb = row(rf, tf)
+    fb["fallback_rate"] = float(np.mean([x["cold_fallback"] for x in rf]))
+    return {"config": f"learned warm start, MPC T=50 (n=1500, m=5000), train {args.train}, "
+                      f"epochs {args.epochs}, test {args.test}, tol {args.tol:g}",
             "train_solves_s": gen_solve_s, "train_s": train_s, "loss_first_last": [losses[0], losses[-1]],
-            "infer_s": infer_s, "cold": {"kernel_s": tc, "QPs/s": args.test / tc,
-                                         "iters_mean": float(np.mean([r["iters"] for r in rc])),
-                                         "solved": sum(r["status"] == 0 for r in rc)},
-            "warm": {"kernel_s": tw, "QPs/s": args.test / tw, "iters_mean": float(np.mean([r["iters"] for r in rw])),
-                     "solved": sum(r["status"] == 0 for r in rw),
-                     "fallback_rate": float(np.mean([r["cold_fallback"] for r in rw]))},
-            "warm_no_fallback": {"kernel_s": tn, "iters_mean": float(np.mean([r["iters"] for r in rn])),
-                                 "solved": sum(r["status"] == 0 for r in rn)},
-            "warm_primal_only": {"kernel_s": tx, "iters_mean": float(np.mean([r["iters"] for r in rx])),
-                                 "solved": sum(r["status"] == 0 for r in rx)},
+            "infer_s": infer_s, "cold": row(rc, tc), "warm": row(rw, tw),
+            "warm_per_instance_fallback": fb, "warm_primal_only": row(rx, tx),
             "relkkt_pred_median": float(np.median(k_pred)), "relkkt_zero_median": float(np.median(k_zero)),
-            "speedup_warm_vs_cold": tc / tw}
+            "speedup_warm_vs_cold": tc / tw, "speedup_warm_vs_cold_incl_inference": tc / (tw + infer_s)}
 
 
 def bench_precision(args):

@@ -273,7 +273,8 @@ struct pdhcg_handle {
     hipError_t e = hipMalloc((void**)p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      return fail(PDHCG_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      return fail(PDHCG_ERR_OUT_OF_MEMORY,
+                  "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
     }
     allocs.push_back(*p);
     return 0;
@@ -879,9 +880,11 @@ struct DevBuf {
   int alloc(T** p, int64_t count) {
     *p = nullptr;
     const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
-    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+    const hipError_t e = hipMalloc((void**)p, bytes);
+    if (e != hipSuccess) {
       (void)hipGetLastError();
-      return fail(PDHCG_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      return fail(PDHCG_ERR_OUT_OF_MEMORY,
+                  "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
     }
     ptrs.push_back(*p);
     return 0;

@@ -2,6 +2,8 @@
 // reductions, a grid barrier for cooperative launches, and the row-split CSR
 // row reduction used by every sparse product of the solver.
 #pragma once
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace pdhcg {
@@ -154,6 +156,19 @@ struct GridSync {
 template <typename V>
 __device__ __forceinline__ double ldv(const V* p, int k) { return (double)p[k]; }
 
+// Load through a global-address-space pointer (the solver's arrays all live
+// in device memory; a generic pointer would make the compiler emit flat loads,
+// which also count against the LDS counter and force wider waits).
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 // sum_k M[i,k] * g(col[k]) for the entries [beg, end) of one row, computed by
 // `width` lanes starting at lane `lane` (partial sums; reduce with group_sum)
 template <typename V, typename Gather>
@@ -167,7 +182,7 @@ __device__ __forceinline__ double row_partial(const int32_t* col, const V* val, 
 template <typename T>
 struct GatherVec {
   const T* v;
-  __device__ __forceinline__ double operator()(int j) const { return (double)v[j]; }
+  __device__ __forceinline__ double operator()(int j) const { return (double)gld(v + j); }
 };
 
 // p_j = r_j + beta p_prev_j, formed at gather time (the CG direction update is
@@ -178,8 +193,11 @@ struct GatherDir {
   const T* pp;
   double beta;
   int first;
+  // both loads are unconditional (pp is always a valid buffer; when first is
+  // set its contents are not used), so a tile's gathers issue together
   __device__ __forceinline__ double operator()(int j) const {
-    return first ? (double)r[j] : (double)r[j] + beta * (double)pp[j];
+    const double rj = (double)gld(r + j), pj = (double)gld(pp + j);
+    return first ? rj : rj + beta * pj;
   }
 };
 
@@ -205,47 +223,50 @@ constexpr int kRowsPerThread = (kTileRows + 1 + kBlock - 1) / kBlock;
 // Stage one tile in LDS with every load of the tile in flight at once:
 // row offsets of up to two matrices (rp1, rp2: rowptr[ra + i] - base), and the
 // entry list [M1 entries z0..z0+nz, M2 entries w0..w0+nw] as products
-// val * g(col) into prod[0 .. nz+nw).  Index, value and row-pointer loads are
-// issued first, then the gathers, then the LDS stores.
-template <typename V1, typename G1, typename V2, typename G2>
-__device__ __forceinline__ void stage_tile(const int32_t* rowptr1, const int32_t* col1, const V1* val1, const G1& g1,
+// val * g(col) into prod[0 .. nz+nw).  Every load is unconditional (indices
+// are clamped into the tile, surplus lanes repeat the last entry and store
+// nothing), so the index, value and row-pointer loads all issue before the
+// first wait, then all gathers before the next.
+template <typename V, typename G1, typename G2>
+__device__ __forceinline__ void stage_tile(const int32_t* rowptr1, const int32_t* col1, const V* val1, const G1& g1,
                                            int z0, int nz, const int32_t* rowptr2, const int32_t* col2,
-                                           const V2* val2, const G2& g2, int w0, int nw, int ra, int nr,
+                                           const V* val2, const G2& g2, int w0, int nw, int ra, int nr,
                                            int32_t* rp1, int32_t* rp2, double* prod) {
   const int tid = threadIdx.x;
   int r1[kRowsPerThread], r2[kRowsPerThread];
 #pragma unroll
   for (int u = 0; u < kRowsPerThread; ++u) {
-    const int i = u * kBlock + tid;
-    r1[u] = (rowptr1 && i <= nr) ? rowptr1[ra + i] : 0;
-    r2[u] = (rowptr2 && i <= nr) ? rowptr2[ra + i] : 0;
+    const int i = min(u * kBlock + tid, nr);
+    r1[u] = rowptr1 ? gld(rowptr1 + ra + i) : 0;
+    r2[u] = rowptr2 ? gld(rowptr2 + ra + i) : 0;
   }
   const int ntot = nz + nw;
-  int c[kStageUnroll];
-  double v[kStageUnroll];
+  if (ntot > 0) {
+    int c[kStageUnroll];
+    V v[kStageUnroll];
 #pragma unroll
-  for (int u = 0; u < kStageUnroll; ++u) {
-    const int k = u * kBlock + tid;
-    c[u] = 0;
-    v[u] = 0.0;
-    if (k < nz) {
-      c[u] = col1[z0 + k];
-      v[u] = ldv(val1, z0 + k);
-    } else if (k < ntot) {
-      c[u] = col2[w0 + k - nz];
-      v[u] = ldv(val2, w0 + k - nz);
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = min(u * kBlock + tid, ntot - 1);
+      const bool first = k < nz;
+      c[u] = gld(first ? col1 + z0 + k : col2 + w0 + (k - nz));
+      v[u] = gld(first ? val1 + z0 + k : val2 + w0 + (k - nz));
     }
-  }
-  double gv[kStageUnroll];
+    double gv[kStageUnroll];
 #pragma unroll
-  for (int u = 0; u < kStageUnroll; ++u) {
-    const int k = u * kBlock + tid;
-    gv[u] = k < nz ? g1(c[u]) : (k < ntot ? g2(c[u]) : 0.0);
-  }
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = min(u * kBlock + tid, ntot - 1);
+      if constexpr (std::is_same<G1, G2>::value) {
+        const G1 g = k < nz ? g1 : g2;
+        gv[u] = g(c[u]);
+      } else {
+        gv[u] = k < nz ? g1(c[u]) : g2(c[u]);
+      }
+    }
 #pragma unroll
-  for (int u = 0; u < kStageUnroll; ++u) {
-    const int k = u * kBlock + tid;
-    if (k < ntot) prod[k] = v[u] * gv[u];
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = u * kBlock + tid;
+      if (k < ntot) prod[k] = (double)v[u] * gv[u];
+    }
   }
 #pragma unroll
   for (int u = 0; u < kRowsPerThread; ++u) {
@@ -266,7 +287,7 @@ __device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* 
                                           int G, const Gather& g, Epi epi) {
   TileLds& L = tile_lds();
   const int ra = t[0], nr = t[1] - t[0], z0 = t[2], nz = t[3] - t[2];
-  stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, 0, 0, ra, nr, L.rp, L.rp2, L.prod);
+  stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, z0, 0, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
   const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
   for (int base = 0; base < nr; base += ng) {

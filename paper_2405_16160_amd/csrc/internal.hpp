@@ -49,6 +49,20 @@ struct Part {
 constexpr int kTileNnz = 4096;    // staged products per tile (FP64 in LDS)
 constexpr int kTileRows = 1024;   // rows per tile
 
+// One workgroup's share of a Part, cached in LDS when a solve kernel starts:
+// owned rows [r0, r1), tiles t0 .. t1-1 (the first kCacheTiles of them copied
+// into tl), long rows long_rows[l0 .. l1-1].
+constexpr int kCacheTiles = 16;
+struct WgPart {
+  int32_t r0, r1, t0, t1, l0, l1, group, pad;
+  const int32_t* tiles;
+  const int32_t* long_rows;
+  int32_t tl[6 * kCacheTiles];
+  __device__ __forceinline__ const int32_t* tile(int t) const {
+    return t - t0 < kCacheTiles ? tl + 6 * (t - t0) : tiles + 6 * t;
+  }
+};
+
 // Partial-result slots.  Every workgroup writes one value per slot; after a
 // grid barrier every workgroup reduces all of them in the same fixed order,
 // so every workgroup holds bit-identical scalars and takes the same decisions.
@@ -120,6 +134,9 @@ struct SolveParams {
   uint64_t* bar;        // grid barrier words (zeroed before each launch)
   SolverState* st;
   Part pn1, pcg, pm, pt;  // n-side pass, CG (rows of Q), A rows, A' rows
+  // the executing workgroup's share of pn1, pcg, pm (filled in its LDS copy of
+  // this block; unused in the copy in device memory)
+  WgPart w_n1, w_cg, w_m;
   double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf (enter every relKKT)
   double kkt_zero;        // relKKT(0, 0) when the warm-start fallback applies, else 0
   // start point of a batched solve (null: zero)

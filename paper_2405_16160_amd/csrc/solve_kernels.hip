@@ -77,7 +77,7 @@ __device__ __attribute__((noinline)) void dense_qx(const SolveParams& P, const d
 
 // CG product for a dense Q owned by one workgroup: stage p in LDS, stream Q
 template <typename V>
-__device__ __attribute__((noinline)) void dense_cg_spmv(const SolveParams& P, const Block& B, const V* qd,
+__device__ __attribute__((noinline)) void dense_cg_spmv(const SolveParams& P, Block B, const V* qd,
                                                         const double* pprev, double* pcur, double beta, int first,
                                                         double inv_tau, double* lds, double* svec) {
   double s[1] = {0.0}, dummy[1] = {0.0};
@@ -102,7 +102,7 @@ __device__ __attribute__((noinline)) void dense_cg_spmv(const SolveParams& P, co
 // workgroup's rows of the partition `pt`.  Writes r = -g (and its FP32 copy)
 // when r != null and stores the six n-side partials at slot0.
 template <bool DENSE>
-__device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, const Part& pt, const Block& B, const double* xv,
+__device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, const WgPart& pt, Block B, const double* xv,
                             const double* yv, double* r, float* r32, int slot0, double* lds, double* svec) {
   // dense Q (one workgroup per QP): Q xv first, into the free CG buffer q
   constexpr bool dense = DENSE;
@@ -125,10 +125,10 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
     mx[1] = maxp(mx[1], fabs(qx));
     mx[2] = maxp(mx[2], fabs(aty));
   };
-  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
+  for (int t = pt.t0; t < pt.t1; ++t)
     tile_rows2(dense ? nullptr : P.Q.rowptr, P.Q.col, P.Q.val, gx, P.m > 0 ? P.At.rowptr : nullptr, P.At.col,
-               P.At.val, gy, pt.tiles + 6 * t, G, [&](int i, double qx, double aty) { epi(i, dense ? P.q[i] : qx, aty); });
-  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+               P.At.val, gy, pt.tile(t), G, [&](int i, double qx, double aty) { epi(i, dense ? P.q[i] : qx, aty); });
+  for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[2] = {dense ? 0.0 : row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gx),
                    P.m > 0 ? row_partial(P.At.col, P.At.val, P.At.rowptr[i], P.At.rowptr[i + 1], B.tid, kBlock, gy)
@@ -152,13 +152,12 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
 // epilogue epi(i, u) that returns nothing and accumulates the three m-side
 // partials (max (u-b)^+, max |u|, sum b.y) through the references given.
 template <typename V, typename Tx, typename Epi>
-__device__ void mside_rows(const SolveParams& P, const Block& B, const V* aval, const Tx* xg, double* lds,
+__device__ void mside_rows(const SolveParams& P, Block B, const V* aval, const Tx* xg, double* lds,
                            Epi epi) {
-  const Part& pt = P.pm;
+  const WgPart& pt = P.w_m;
   GatherVec<Tx> gx{xg};
-  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
-    tile_rows(P.A.rowptr, P.A.col, aval, pt.tiles + 6 * t, pt.group, gx, epi);
-  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+  for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.A.rowptr, P.A.col, aval, pt.tile(t), pt.group, gx, epi);
+  for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.A.col, aval, P.A.rowptr[i], P.A.rowptr[i + 1], B.tid, kBlock, gx)};
     double dummy[1] = {0.0};
@@ -167,7 +166,7 @@ __device__ void mside_rows(const SolveParams& P, const Block& B, const V* aval, 
   }
 }
 
-__device__ void store_mside(const SolveParams& P, const Block& B, int slot0, double* s1, double* mx, double* lds) {
+__device__ void store_mside(const SolveParams& P, Block B, int slot0, double* s1, double* mx, double* lds) {
   block_reduce<1, 2>(s1, mx, lds);
   if (B.tid == 0) {
     P.part[(slot0 + S_MVIOL) * B.nb + B.b] = mx[0];
@@ -177,7 +176,7 @@ __device__ void store_mside(const SolveParams& P, const Block& B, int slot0, dou
 }
 
 // ax = A x and the m-side partials of the current point (start of a solve)
-__device__ __attribute__((noinline)) void phase_ax(const SolveParams& P, const Block& B, double* lds) {
+__device__ __attribute__((noinline)) void phase_ax(const SolveParams& P, Block B, double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(P, B, P.A.val, P.x, lds, [&](int i, double u) {
     P.ax[i] = u;
@@ -190,8 +189,8 @@ __device__ __attribute__((noinline)) void phase_ax(const SolveParams& P, const B
 
 // relKKT pieces of the average: n-side at (xa, ya), m-side u = A xa (kept in ax_avg)
 template <bool DENSE>
-__device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, const Block& B, double* lds, double* svec) {
-  phase_nside<DENSE>(P, P.pn1, B, P.xa, P.ya, nullptr, nullptr, S_AVG0, lds, svec);
+__device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, Block B, double* lds, double* svec) {
+  phase_nside<DENSE>(P, P.w_n1, B, P.xa, P.ya, nullptr, nullptr, S_AVG0, lds, svec);
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(P, B, P.A.val, P.xa, lds, [&](int i, double u) {
     P.ax_avg[i] = u;
@@ -205,14 +204,14 @@ __device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, c
 // CG product: p = r + beta p_prev on the owned rows (FP64, stored), and
 // q = (Q + I/tau) p with p gathered through GatherDir; partial p.q.
 template <bool DENSE, typename V, typename T>
-__device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, const Block& B, const V* qval, const T* rg, const T* ppg,
+__device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Block B, const V* qval, const T* rg, const T* ppg,
                               const double* pprev, double* pcur, float* pcur32, double beta, int first,
                               double inv_tau, double* lds, double* svec) {
   if constexpr (DENSE) {
     dense_cg_spmv(P, B, qval, pprev, pcur, beta, first, inv_tau, lds, svec);
     return;
   }
-  const Part& pt = P.pcg;
+  const WgPart& pt = P.w_cg;
   GatherDir<T> gp{rg, ppg, beta, first};
   double s[1] = {0.0};
   auto epi = [&](int i, double qp) {
@@ -223,9 +222,8 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, co
     P.q[i] = qi;
     s[0] += pi * qi;
   };
-  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
-    tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tiles + 6 * t, pt.group, gp, epi);
-  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+  for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, gp, epi);
+  for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gp)};
     double dummy[1] = {0.0};
@@ -238,9 +236,9 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, co
 }
 
 // CG update on the owned rows: x += alpha p, r -= alpha q; partial r.r
-__device__ __attribute__((noinline)) void phase_cg_update(const SolveParams& P, const Block& B, const double* pcur, double alpha, int mixed,
+__device__ __attribute__((noinline)) void phase_cg_update(const SolveParams& P, Block B, const double* pcur, double alpha, int mixed,
                                 double* lds) {
-  const int r0 = P.pcg.bounds[B.b], r1 = P.pcg.bounds[B.b + 1];
+  const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
   double s[1] = {0.0};
   for (int i = r0 + B.tid; i < r1; i += kBlock) {
     const double xi = P.x[i] + alpha * pcur[i];
@@ -279,60 +277,79 @@ struct GatherCG {
   const T* s;
   double alpha, beta;
   int l;
+  // unconditional loads (u and s are always valid buffers; values not used
+  // at the current step are discarded by the selects), so that a tile's
+  // gathers all issue before the first wait
   __device__ __forceinline__ double operator()(int j) const {
-    if (l == 0) return (double)r[j];
-    const double sj = l == 1 ? (double)u[j] : (double)u[j] + beta * (double)s[j];
-    return (double)r[j] - alpha * sj;
+    const double rj = (double)gld(r + j), uj = (double)gld(u + j), sj = (double)gld(s + j);
+    const double s1 = l == 1 ? uj : uj + beta * sj;
+    return l == 0 ? rj : rj - alpha * s1;
   }
 };
 
-struct CgBufs {
-  const double *r_prev, *u_prev, *s_prev2;
-  double *r_new, *u_new, *s_prev1;
-  const float *r32_prev, *u32_prev, *s32_prev2;
-  float *r32_new, *u32_new, *s32_prev1;
-};
-
 template <typename V, typename T>
-__device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, const Block& B, const V* qval, const T* rg,
-                                                     const T* ug, const T* sg, const CgBufs& cb, int l, double alpha,
-                                                     double beta, double inv_tau, int product, int mixed,
-                                                     double* lds) {
+__device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block B, const V* qval, int l,
+                                                     double alpha, double beta, double inv_tau, int product,
+                                                     int mixed, double* lds) {
+  // buffers of step l: r, u and s alternate between two copies (c = l mod 2
+  // receives r_l, u_l and s_{l-2}'s successor); step 0 reads r_0 from the first
+  const int c = l & 1, o = c ^ 1;
+  const bool r_alt = o == 1 && l != 0;
+  struct {
+    const double *r_prev, *u_prev, *s_prev2;
+    double *r_new, *u_new, *s_prev1;
+    float *r32_new, *u32_new, *s32_prev1;
+  } cb = {r_alt ? P.r_alt : P.r, o ? P.u1 : P.u0, c ? P.s1 : P.s0,
+          c ? P.r_alt : P.r, c ? P.u1 : P.u0, o ? P.s1 : P.s0,
+          c ? P.r32_alt : P.r32, c ? P.u32_1 : P.u32_0, o ? P.s32_1 : P.s32_0};
+  const T *rg, *ug, *sg;  // the vectors gathered by the product (FP32 copies in mixed precision)
+  if constexpr (std::is_same<T, float>::value) {
+    rg = r_alt ? P.r32_alt : P.r32;
+    ug = o ? P.u32_1 : P.u32_0;
+    sg = c ? P.s32_1 : P.s32_0;
+  } else {
+    rg = cb.r_prev;
+    ug = cb.u_prev;
+    sg = cb.s_prev2;
+  }
   double s[2] = {0.0, 0.0};  // gamma_l, delta_l
   auto own = [&](int i) -> double {  // owned-row updates; returns r_l[i]
-    if (l == 0) return cb.r_prev[i];
-    const double s1 = l == 1 ? cb.u_prev[i] : cb.u_prev[i] + beta * cb.s_prev2[i];
-    const double pi = l == 1 ? cb.r_prev[i] : cb.r_prev[i] + beta * P.p0[i];
-    P.p0[i] = pi;
-    const double xi = P.x[i] + alpha * pi;
-    P.x[i] = xi;
-    if (mixed) P.x32[i] = (float)xi;
+    // every input is loaded unconditionally (all buffers are valid; unused
+    // values are discarded by selects), so the loads issue together
+    const double rp = gld(cb.r_prev + i), up = gld(cb.u_prev + i), sp = gld(cb.s_prev2 + i);
+    const double pp = gld(P.p0 + i), xp = gld(P.x + i);
+    if (l == 0) return rp;
+    const double s1 = l == 1 ? up : up + beta * sp;
+    const double pi = l == 1 ? rp : rp + beta * pp;
+    gst(P.p0 + i, pi);
+    const double xi = xp + alpha * pi;
+    gst(P.x + i, xi);
+    if (mixed) gst(P.x32 + i, (float)xi);
     if (!product) return 0.0;
-    cb.s_prev1[i] = s1;
-    if (mixed) cb.s32_prev1[i] = (float)s1;
-    const double ri = cb.r_prev[i] - alpha * s1;
-    cb.r_new[i] = ri;
-    if (mixed) cb.r32_new[i] = (float)ri;
+    gst(cb.s_prev1 + i, s1);
+    if (mixed) gst(cb.s32_prev1 + i, (float)s1);
+    const double ri = rp - alpha * s1;
+    gst(cb.r_new + i, ri);
+    if (mixed) gst(cb.r32_new + i, (float)ri);
     return ri;
   };
   if (!product) {
-    const int r0 = P.pcg.bounds[B.b], r1 = P.pcg.bounds[B.b + 1];
+    const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
     for (int i = r0 + B.tid; i < r1; i += kBlock) own(i);
     return;
   }
   auto epi = [&](int i, double qr) {
     const double ri = own(i);
     const double ui = qr + ri * inv_tau;
-    cb.u_new[i] = ui;
-    if (mixed) cb.u32_new[i] = (float)ui;
+    gst(cb.u_new + i, ui);
+    if (mixed) gst(cb.u32_new + i, (float)ui);
     s[0] += ri * ri;
     s[1] += ri * ui;
   };
-  const Part& pt = P.pcg;
+  const WgPart& pt = P.w_cg;
   GatherCG<T> g{rg, ug, sg, alpha, beta, l};
-  for (int t = pt.tile_ptr[B.b]; t < pt.tile_ptr[B.b + 1]; ++t)
-    tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tiles + 6 * t, pt.group, g, epi);
-  for (int t = pt.long_ptr[B.b]; t < pt.long_ptr[B.b + 1]; ++t) {
+  for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, g, epi);
+  for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, g)};
     double dummy[1] = {0.0};
@@ -351,7 +368,7 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, const
 // y <- max(0, y + sigma (2u - A x^k - b)); A x^k <- u; ya += w (y - ya);
 // xa += w (x - xa) on an n-slice; m-side partials of the new point.
 template <typename V, typename Tx>
-__device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, const Block& B, const V* aval, const Tx* xg, double sigma, double w,
+__device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, Block B, const V* aval, const Tx* xg, double sigma, double w,
                            double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(P, B, aval, xg, lds, [&](int i, double u) {
@@ -365,7 +382,7 @@ __device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, const
     mx[1] = maxp(mx[1], fabs(u));
     s1[0] += bi * yn;
   });
-  const int r0 = P.pcg.bounds[B.b], r1 = P.pcg.bounds[B.b + 1];
+  const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
   for (int j = r0 + B.tid; j < r1; j += kBlock) P.xa[j] += w * (P.x[j] - P.xa[j]);
   store_mside(P, B, 0, s1, mx, lds);
 }
@@ -373,9 +390,9 @@ __device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, const
 // Restart: move to the candidate (average when use_avg), measure the
 // movement from the previous anchor, and make the candidate the new anchor
 // and the new (empty) average.
-__device__ __attribute__((noinline)) void phase_restart(const SolveParams& P, const Block& B, int use_avg, int mixed, double* lds) {
+__device__ __attribute__((noinline)) void phase_restart(const SolveParams& P, Block B, int use_avg, int mixed, double* lds) {
   double s[2] = {0.0, 0.0};
-  const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
+  const int n0 = P.w_cg.r0, n1 = P.w_cg.r1;
   for (int j = n0 + B.tid; j < n1; j += kBlock) {
     const double xc = use_avg ? P.xa[j] : P.x[j];
     const double d = xc - P.x_anc[j];
@@ -385,7 +402,7 @@ __device__ __attribute__((noinline)) void phase_restart(const SolveParams& P, co
     P.x_anc[j] = xc;
     P.xa[j] = xc;
   }
-  const int m0 = P.pm.bounds[B.b], m1 = P.pm.bounds[B.b + 1];
+  const int m0 = P.w_m.r0, m1 = P.w_m.r1;
   for (int i = m0 + B.tid; i < m1; i += kBlock) {
     const double yc = use_avg ? P.ya[i] : P.y[i];
     const double d = yc - P.y_anc[i];
@@ -410,23 +427,23 @@ __device__ __attribute__((noinline)) void phase_restart(const SolveParams& P, co
 
 // copy src -> dst on the workgroup's n- and m-slices (returning the average
 // or restoring the anchor at the end of a solve)
-__device__ __attribute__((noinline)) void phase_copy_point(const SolveParams& P, const Block& B, const double* xs, const double* ys) {
-  const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
+__device__ __attribute__((noinline)) void phase_copy_point(const SolveParams& P, Block B, const double* xs, const double* ys) {
+  const int n0 = P.w_cg.r0, n1 = P.w_cg.r1;
   for (int j = n0 + B.tid; j < n1; j += kBlock) P.x[j] = xs[j];
-  const int m0 = P.pm.bounds[B.b], m1 = P.pm.bounds[B.b + 1];
+  const int m0 = P.w_m.r0, m1 = P.w_m.r1;
   for (int i = m0 + B.tid; i < m1; i += kBlock) P.y[i] = ys[i];
 }
 
 // x, y, their averages and anchors, Ax and the FP32 copy of x set to zero
-__device__ __attribute__((noinline)) void phase_zero_point(const SolveParams& P, const Block& B) {
-  const int n0 = P.pcg.bounds[B.b], n1 = P.pcg.bounds[B.b + 1];
+__device__ __attribute__((noinline)) void phase_zero_point(const SolveParams& P, Block B) {
+  const int n0 = P.w_cg.r0, n1 = P.w_cg.r1;
   for (int j = n0 + B.tid; j < n1; j += kBlock) {
     P.x[j] = 0.0;
     P.xa[j] = 0.0;
     P.x_anc[j] = 0.0;
     if (P.x32) P.x32[j] = 0.0f;
   }
-  const int m0 = P.pm.bounds[B.b], m1 = P.pm.bounds[B.b + 1];
+  const int m0 = P.w_m.r0, m1 = P.w_m.r1;
   for (int i = m0 + B.tid; i < m1; i += kBlock) {
     P.y[i] = 0.0;
     P.ya[i] = 0.0;
@@ -452,7 +469,7 @@ __device__ Kkt kkt_from(const double* s, const double* mx, double nb_inf, double
   return k;
 }
 
-__device__ __attribute__((noinline)) Kkt reduce_kkt(const SolveParams& P, const Block& B, int slot0, double nb_inf, double nc_inf, double* gg,
+__device__ __attribute__((noinline)) Kkt reduce_kkt(const SolveParams& P, Block B, int slot0, double nb_inf, double nc_inf, double* gg,
                           double* flag, double* lds) {
   const int ss[4] = {slot0 + S_GG, slot0 + S_XQX, slot0 + S_CX, slot0 + S_BY};
   const int ms[6] = {slot0 + S_MG, slot0 + S_MQX, slot0 + S_MATY, slot0 + S_MVIOL, slot0 + S_MAX, S_FLAG};
@@ -466,7 +483,7 @@ __device__ __attribute__((noinline)) Kkt reduce_kkt(const SolveParams& P, const 
   return k;
 }
 
-__device__ __attribute__((noinline)) double reduce_one(const SolveParams& P, const Block& B, int slot, double* lds) {
+__device__ __attribute__((noinline)) double reduce_one(const SolveParams& P, Block B, int slot, double* lds) {
   const int ss[1] = {slot};
   const int ms[1] = {0};
   double s[1], mx[1];
@@ -484,7 +501,7 @@ __device__ __attribute__((noinline)) double reduce_one(const SolveParams& P, con
 // barrier is a workgroup barrier).  Runs at most `budget` iterations from
 // state S; returns false only if a grid barrier failed.
 template <bool DENSE>
-__device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, SolverState& S, double nb_inf,
+__device__ bool drive(const SolveParams& P, Block B, GridSync& gs, SolverState& S, double nb_inf,
                       double nc_inf, double* lds, double* svec, int64_t budget) {
   bool ok = true;
 
@@ -497,7 +514,7 @@ __device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, Solver
   bool have_avg = false;
   while (ok && !S.done && budget > 0) {
     // ---- n-side pass at z^{n,k}: r0 = -(Qx + A'y + c), relKKT(z^{n,k})
-    phase_nside<DENSE>(P, P.pn1, B, P.x, P.y, P.r, S.mixed ? P.r32 : nullptr, 0, lds, svec);
+    phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, S.mixed ? P.r32 : nullptr, 0, lds, svec);
     if (B.tid == 0) {
       double f = 0.0;
       if (B.b == 0 && P.time_limit_ticks && wall_clock64() - S.t_start > P.time_limit_ticks) f = 1.0;
@@ -619,28 +636,13 @@ __device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, Solver
     int steps = 0;
     if (rho > 0.0 && P.u0 != nullptr) {
       // single-reduction CG: L steps take L + 1 grid barriers
-      double* rb[2] = {P.r, P.r_alt};
-      double* ub[2] = {P.u0, P.u1};
-      double* sb[2] = {P.s0, P.s1};
-      float* rb32[2] = {P.r32, P.r32_alt};
-      float* ub32[2] = {P.u32_0, P.u32_1};
-      float* sb32[2] = {P.s32_0, P.s32_1};
       double gamma = rho, alpha = 0.0, beta = 0.0;
       for (int l = 0; l <= P.max_cg; ++l) {
         const int product = l < P.max_cg;
-        const int c = l & 1, o = c ^ 1;
-        CgBufs cb{rb[o], ub[o], sb[c], rb[c], ub[c], sb[o], rb32[o], ub32[o], sb32[c], rb32[c], ub32[c], sb32[o]};
-        if (l == 0) {  // step 0 reads r_0 from buffer 0 and writes u_0 to buffer 0
-          cb.r_prev = rb[0];
-          cb.u_new = ub[0];
-          cb.u32_new = ub32[0];
-        }
         if (S.mixed)
-          phase_cgcg(P, B, P.Q.val32, (const float*)(l == 0 ? rb32[0] : rb32[o]), (const float*)ub32[o],
-                     (const float*)sb32[c], cb, l, alpha, beta, inv_tau, product, 1, lds);
+          phase_cgcg<float, float>(P, B, P.Q.val32, l, alpha, beta, inv_tau, product, 1, lds);
         else
-          phase_cgcg(P, B, P.Q.val, (const double*)(l == 0 ? rb[0] : rb[o]), (const double*)ub[o],
-                     (const double*)sb[c], cb, l, alpha, beta, inv_tau, product, 0, lds);
+          phase_cgcg<double, double>(P, B, P.Q.val, l, alpha, beta, inv_tau, product, 0, lds);
         if (!(ok = gs.sync())) break;
         if (l > 0) steps = l;
         if (!product) break;
@@ -706,8 +708,45 @@ __device__ bool drive(const SolveParams& P, const Block& B, GridSync& gs, Solver
   return ok;
 }
 
+// The workgroup's share of a row partition, for its LDS copy of the
+// parameter block.
+__device__ void fill_wg_part(WgPart& w, const Part& p, int b) {
+  const int t0 = p.tile_ptr[b], t1 = p.tile_ptr[b + 1];
+  if (threadIdx.x == 0) {
+    w.r0 = p.bounds[b];
+    w.r1 = p.bounds[b + 1];
+    w.t0 = t0;
+    w.t1 = t1;
+    w.l0 = p.long_ptr[b];
+    w.l1 = p.long_ptr[b + 1];
+    w.group = p.group;
+    w.tiles = p.tiles;
+    w.long_rows = p.long_rows;
+  }
+  const int nt = t1 - t0 < kCacheTiles ? t1 - t0 : kCacheTiles;
+  for (int k = threadIdx.x; k < 6 * nt; k += kBlock) w.tl[k] = p.tiles[6 * t0 + k];
+}
+
+// Copy the parameter block into LDS and cache the workgroup's share of the
+// row partitions there: the phases then read pointers, sizes and tile
+// descriptors at LDS latency instead of through the L2 that every grid
+// barrier invalidates.
+__device__ void load_params(SolveParams& Ps, const SolveParams* Pg, int b) {
+  static_assert(sizeof(SolveParams) % 8 == 0, "parameter block copied in 8-byte words");
+  const uint64_t* src = (const uint64_t*)Pg;
+  uint64_t* dst = (uint64_t*)&Ps;
+  for (int k = threadIdx.x; k < (int)(sizeof(SolveParams) / 8); k += kBlock) dst[k] = src[k];
+  __syncthreads();
+  fill_wg_part(Ps.w_n1, Ps.pn1, b);
+  fill_wg_part(Ps.w_cg, Ps.pcg, b);
+  fill_wg_part(Ps.w_m, Ps.pm, b);
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
-  const SolveParams& P = *Pg;
+  __shared__ SolveParams Ps;
+  load_params(Ps, Pg, (int)blockIdx.x);
+  const SolveParams& P = Ps;
   const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
   __shared__ double lds[kWaves * 16];
   Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
@@ -732,7 +771,7 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* 
 // v, w (n) and u (m) are work vectors; pn partitions the rows of A', pm
 // those of A.  Returns false if a grid barrier failed.
 __device__ bool power_norm(const DevMat& A, const DevMat& At, double* v, double* w, double* u, double* part,
-                           const Part& pn, const Part& pm, int iters, const Block& B, GridSync& gs, double* lds,
+                           const Part& pn, const Part& pm, int iters, Block B, GridSync& gs, double* lds,
                            double* out) {
   const int n0 = pn.bounds[B.b], n1 = pn.bounds[B.b + 1];
   double s[1] = {0.0}, dummy[1] = {0.0};
@@ -817,7 +856,9 @@ __global__ void __launch_bounds__(kBlock) pdhcg_batch_kernel(BatchParams BP) {
   __shared__ double lds[kWaves * 16];
   __shared__ double svec[kDenseTile];
   const int idx = BP.order[blockIdx.x];
-  const SolveParams& P = BP.params[idx];
+  __shared__ SolveParams Ps;
+  load_params(Ps, BP.params + idx, 0);
+  const SolveParams& P = Ps;
   Block B{0, 1, (int)threadIdx.x};
   GridSync gs{nullptr, 1u, 0};
   // start point (x0 or 0; y0 projected onto y >= 0, or 0)

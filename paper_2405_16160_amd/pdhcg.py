@@ -65,6 +65,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(_build.LIB):
             _build.build()
+        # torch ships its own HIP runtime under a different file name; loading
+        # torch first makes the library bind to that same runtime (loading the
+        # library first would put a second HIP runtime in the process, and the
+        # two then fail each other's allocations)
+        import torch  # noqa: F401
         L = C.CDLL(_build.LIB)
         P = C.c_void_p
         L.pdhcg_default_settings.argtypes = [C.POINTER(pdhcg_settings)]

@@ -5,9 +5,16 @@ theta (here the initial state of a linear MPC problem), a network maps theta
 to a predicted primal-dual pair (x, y) that restarted PDHCG starts from.  The
 training targets are PDHCG's own solutions, computed by the batched solver;
 the network is trained by the library's bfloat16 kernels.  A prediction never
-costs accuracy: the solve that starts from it stops on the same relKKT test,
-and a start point whose relKKT exceeds that of (0, 0) is replaced by (0, 0)
-(the solver's warm_fallback setting).
+costs accuracy: the solve that starts from it stops on the same relKKT test.
+
+Whether predictions pay is decided per family on held-out members
+(`validate`), not per instance.  The solver's per-instance fallback
+(warm_fallback: a start point whose relKKT exceeds that of (0, 0) is replaced
+by (0, 0)) is a poor judge for families with c = 0 such as MPC: (0, 0) is then
+exactly dual feasible, so its relKKT is the primal residual alone, while any
+error in a predicted dual shows up undamped in the dual residual (whose
+denominator 1 + ||c|| is 1).  Predictions that start far closer to the optimum
+are then rejected, so the learned path solves with warm_fallback = 0.
 
 Data preparation on the host (numpy): the dual targets are made canonical on
 each row pair that encodes an equality (a'x <= u, -a'x <= -u admits
@@ -130,7 +137,23 @@ class WarmStarter:
         return Z[:, : self.n], self.code.decode(Z[:, self.n:])
 
 
-def train(theta, X, Y, code: DualCode, hidden=512, epochs=20, batch=512, lr=1e-3, seed=0, log=None):
+def validate(fam, ws: "WarmStarter", ids, settings: _pd.Settings):
+    """Cold and warm batched solves of held-out family members `ids` (warm:
+    the network's predictions, no per-instance fallback).  Returns a dict with
+    the mean iterations and kernel seconds of both and whether warm starts
+    paid (fewer mean iterations)."""
+    thetas, _ = family_qps(fam, ids)
+    x0, y0 = ws.predict(thetas)
+    s_nf = dataclasses.replace(settings, warm_fallback=0)
+    _, _, _, rc, tc = solve_family(fam, ids, s_nf)
+    _, _, _, rw, tw = solve_family(fam, ids, s_nf, x0s=x0, y0s=y0)
+    ic = float(np.mean([r["iters"] for r in rc]))
+    iw = float(np.mean([r["iters"] for r in rw]))
+    return {"cold_iters": ic, "warm_iters": iw, "cold_s": tc, "warm_s": tw, "pays": iw < ic,
+            "solved": sum(r["status"] == 0 for r in rc + rw), "count": 2 * len(rc)}
+
+
+def train(theta, X, Y, code: DualCode, hidden=512, epochs=300, batch=256, lr=1e-3, seed=0, log=None):
     """Train the network on theta -> [x, encoded y] with Adam on standardised
     data (cosine learning-rate decay); returns the WarmStarter and the
     per-epoch mean losses."""
