@@ -16,20 +16,51 @@ __device__ __forceinline__ double maxp(double a, double b) {
   return a > b ? a : b;
 }
 
-__device__ __forceinline__ double group_sum(double v, int width) {
-  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, width);
+// A value that every lane of the wave holds equal, marked as such for the
+// compiler (it then keeps it in scalar registers instead of 64 vector lanes,
+// which matters for the solver's scalar state that stays live across phases).
+__device__ __forceinline__ double uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Data-parallel-primitive (DPP) lane moves of a double: each half moves with
+// v_mov_b32_dpp inside the VALU, far cheaper than a shuffle through the LDS
+// crossbar.  Lanes whose source lies outside the row, or whose row is masked
+// off, read +0.0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Reduction over aligned groups of G lanes (G a power of two <= 64) with the
+// result in the group's last lane (lane G-1 of each group): row shifts by 1,
+// 2, 4, 8 make lane i hold the combination of lanes i-2^s+1 .. i of its row;
+// row_bcast15 / row_bcast31 then carry row totals across the rows of a wave.
+// op must have +0.0 as identity on its inputs (sums; maxima of values >= 0).
+template <typename Op>
+__device__ __forceinline__ double group_reduce_last(double v, int G, Op op) {
+  if (G >= 2) v = op(v, dpp<0x111>(v));       // row_shr:1
+  if (G >= 4) v = op(v, dpp<0x112>(v));       // row_shr:2
+  if (G >= 8) v = op(v, dpp<0x114>(v));       // row_shr:4
+  if (G >= 16) v = op(v, dpp<0x118>(v));      // row_shr:8
+  if (G >= 32) v = op(v, dpp<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+  if (G >= 64) v = op(v, dpp<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = kWave >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
+struct AddOp {
+  __device__ __forceinline__ double operator()(double a, double b) const { return a + b; }
+};
+struct MaxOp {
+  __device__ __forceinline__ double operator()(double a, double b) const { return maxp(a, b); }
+};
 
-__device__ __forceinline__ double wave_max(double v) {
-  for (int off = kWave >> 1; off > 0; off >>= 1) v = maxp(v, __shfl_xor(v, off, kWave));
-  return v;
-}
+// sum over the aligned group of G lanes, valid in the group's last lane
+__device__ __forceinline__ double group_sum_last(double v, int G) { return group_reduce_last(v, G, AddOp{}); }
 
 // Workgroup reduction of NS sums and NM maxima at once.  Every thread ends
 // with the results; the combination order is fixed, so equal inputs give
@@ -38,11 +69,11 @@ template <int NS, int NM>
 __device__ __forceinline__ void block_reduce(double* s, double* mx, double* lds) {
   constexpr int W = NS + NM;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) s[k] = wave_sum(s[k]);
+  for (int k = 0; k < NS; ++k) s[k] = group_reduce_last(s[k], kWave, AddOp{});
 #pragma unroll
-  for (int k = 0; k < NM; ++k) mx[k] = wave_max(mx[k]);
+  for (int k = 0; k < NM; ++k) mx[k] = group_reduce_last(mx[k], kWave, MaxOp{});
   const int w = threadIdx.x / kWave;
-  if ((threadIdx.x & (kWave - 1)) == 0) {
+  if ((threadIdx.x & (kWave - 1)) == kWave - 1) {
 #pragma unroll
     for (int k = 0; k < NS; ++k) lds[w * W + k] = s[k];
 #pragma unroll
@@ -53,13 +84,13 @@ __device__ __forceinline__ void block_reduce(double* s, double* mx, double* lds)
   for (int k = 0; k < NS; ++k) {
     double a = lds[k];
     for (int j = 1; j < kWaves; ++j) a += lds[j * W + k];
-    s[k] = a;
+    s[k] = uniform(a);
   }
 #pragma unroll
   for (int k = 0; k < NM; ++k) {
     double a = lds[NS + k];
     for (int j = 1; j < kWaves; ++j) a = maxp(a, lds[j * W + NS + k]);
-    mx[k] = a;
+    mx[k] = uniform(a);
   }
   __syncthreads();
 }
@@ -170,7 +201,7 @@ __device__ __forceinline__ void gst(T* p, T v) {
 }
 
 // sum_k M[i,k] * g(col[k]) for the entries [beg, end) of one row, computed by
-// `width` lanes starting at lane `lane` (partial sums; reduce with group_sum)
+// `width` lanes starting at lane `lane` (partial sums; reduced by the caller)
 template <typename V, typename Gather>
 __device__ __forceinline__ double row_partial(const int32_t* col, const V* val, int beg, int end, int lane,
                                               int width, const Gather& g) {
@@ -278,15 +309,30 @@ __device__ __forceinline__ void stage_tile(const int32_t* rowptr1, const int32_t
   }
 }
 
-// One tile of a single matrix.  Row sums are formed by G-lane groups from the
-// staged products and parked in LDS; then epi(row, sum) runs with one thread
-// per row, so the epilogue's own loads and stores for all rows of the tile
-// are in flight together.
-template <typename V, typename Gather, typename Epi>
-__device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* col, const V* val, const int32_t* t,
-                                          int G, const Gather& g, Epi epi) {
+constexpr int kEpiRows = kTileRows / kBlock;  // epilogue rows per thread in one tile
+static_assert(kTileRows % kBlock == 0, "tile rows split evenly over the threads");
+
+// The no-op prefetch of tile_rows / tile_rows2.
+struct NoPre {
+  __device__ __forceinline__ int operator()(int) const { return 0; }
+};
+
+// One tile of a single matrix.  pre(row) loads the row epilogue's own inputs
+// (rows of the tile, indices clamped into it) and is issued together with the
+// tile's staging loads, so those inputs cost no extra memory round trip.  Row
+// sums are formed by G-lane groups from the staged products and parked in LDS;
+// then epi(row, sum, pre(row)) runs with one thread per row.
+template <typename V, typename Gather, typename Pre, typename Epi>
+__device__ __forceinline__ void tile_rows_pf(const int32_t* rowptr, const int32_t* col, const V* val,
+                                             const int32_t* t, int G, const Gather& g, const Pre& pre, Epi epi) {
   TileLds& L = tile_lds();
   const int ra = t[0], nr = t[1] - t[0], z0 = t[2], nz = t[3] - t[2];
+  using PV = decltype(pre(0));
+  PV pv[kEpiRows];
+  if (nr > 0) {
+#pragma unroll
+    for (int u = 0; u < kEpiRows; ++u) pv[u] = pre(ra + min(u * kBlock + (int)threadIdx.x, nr - 1));
+  }
   stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, z0, 0, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
   const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
@@ -296,23 +342,40 @@ __device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* 
     double s = 0.0;
     if (act)
       for (int k = L.rp[i] + lane; k < L.rp[i + 1]; k += G) s += L.prod[k];
-    s = group_sum(s, G);
-    if (act && lane == 0) L.sum1[i] = s;
+    s = group_sum_last(s, G);
+    if (act && lane == G - 1) L.sum1[i] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nr; i += kBlock) epi(ra + i, L.sum1[i]);
+#pragma unroll
+  for (int u = 0; u < kEpiRows; ++u) {
+    const int i = u * kBlock + (int)threadIdx.x;
+    if (i < nr) epi(ra + i, L.sum1[i], pv[u]);
+  }
   __syncthreads();
 }
 
+template <typename V, typename Gather, typename Epi>
+__device__ __forceinline__ void tile_rows(const int32_t* rowptr, const int32_t* col, const V* val, const int32_t* t,
+                                          int G, const Gather& g, Epi epi) {
+  tile_rows_pf(rowptr, col, val, t, G, g, NoPre{}, [&](int i, double s, int) { epi(i, s); });
+}
+
 // One tile of two matrices over the same rows (the stacked [Q | A'] pass):
-// epi(row, sum1, sum2).  M2 may be absent (rowptr2 == nullptr: sum2 = 0).
-template <typename Gather1, typename Gather2, typename Epi>
+// epi(row, sum1, sum2, pre(row)).  M2 may be absent (rowptr2 == nullptr: sum2 = 0).
+template <typename Gather1, typename Gather2, typename Pre, typename Epi>
 __device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t* col1, const double* val1,
                                            const Gather1& g1, const int32_t* rowptr2, const int32_t* col2,
-                                           const double* val2, const Gather2& g2, const int32_t* t, int G, Epi epi) {
+                                           const double* val2, const Gather2& g2, const int32_t* t, int G,
+                                           const Pre& pre, Epi epi) {
   TileLds& L = tile_lds();
   const int ra = t[0], nr = t[1] - t[0];
   const int z0 = t[2], nz = rowptr1 ? t[3] - t[2] : 0, w0 = t[4], nw = rowptr2 ? t[5] - t[4] : 0;
+  using PV = decltype(pre(0));
+  PV pv[kEpiRows];
+  if (nr > 0) {
+#pragma unroll
+    for (int u = 0; u < kEpiRows; ++u) pv[u] = pre(ra + min(u * kBlock + (int)threadIdx.x, nr - 1));
+  }
   stage_tile(rowptr1, col1, val1, g1, z0, nz, rowptr2, col2, val2, g2, w0, nw, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
   const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
@@ -326,15 +389,19 @@ __device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t
       if (rowptr2)
         for (int k = L.rp2[i] + lane; k < L.rp2[i + 1]; k += G) s2 += L.prod[k];
     }
-    s1 = group_sum(s1, G);
-    s2 = group_sum(s2, G);
-    if (act && lane == 0) {
+    s1 = group_sum_last(s1, G);
+    s2 = group_sum_last(s2, G);
+    if (act && lane == G - 1) {
       L.sum1[i] = s1;
       L.sum2[i] = s2;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nr; i += kBlock) epi(ra + i, L.sum1[i], L.sum2[i]);
+#pragma unroll
+  for (int u = 0; u < kEpiRows; ++u) {
+    const int i = u * kBlock + (int)threadIdx.x;
+    if (i < nr) epi(ra + i, L.sum1[i], L.sum2[i], pv[u]);
+  }
   __syncthreads();
 }
 

@@ -111,23 +111,27 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
   double s[3] = {0.0, 0.0, 0.0};   // g.g, x.Qx, c.x
   double mx[3] = {0.0, 0.0, 0.0};  // |g|, |Qx|, |A'y|
   GatherVec<double> gx{xv}, gy{yv};
-  auto epi = [&](int i, double qx, double aty) {
-    const double ci = P.c[i];
-    const double g = qx + aty + ci;
+  struct Row {
+    double c, x, q;
+  };
+  auto pre = [&](int i) { return Row{gld(P.c + i), gld(xv + i), dense ? gld(P.q + i) : 0.0}; };
+  auto epi = [&](int i, double qx, double aty, const Row& rw) {
+    const double g = qx + aty + rw.c;
     if (r) {
-      r[i] = -g;
-      if (r32) r32[i] = (float)(-g);
+      gst(r + i, -g);
+      if (r32) gst(r32 + i, (float)(-g));
     }
     s[0] += g * g;
-    s[1] += xv[i] * qx;
-    s[2] += ci * xv[i];
+    s[1] += rw.x * qx;
+    s[2] += rw.c * rw.x;
     mx[0] = maxp(mx[0], fabs(g));
     mx[1] = maxp(mx[1], fabs(qx));
     mx[2] = maxp(mx[2], fabs(aty));
   };
   for (int t = pt.t0; t < pt.t1; ++t)
     tile_rows2(dense ? nullptr : P.Q.rowptr, P.Q.col, P.Q.val, gx, P.m > 0 ? P.At.rowptr : nullptr, P.At.col,
-               P.At.val, gy, pt.tile(t), G, [&](int i, double qx, double aty) { epi(i, dense ? P.q[i] : qx, aty); });
+               P.At.val, gy, pt.tile(t), G, pre,
+               [&](int i, double qx, double aty, const Row& rw) { epi(i, dense ? rw.q : qx, aty, rw); });
   for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[2] = {dense ? 0.0 : row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gx),
@@ -135,7 +139,10 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
                            : 0.0};
     double dummy[1] = {0.0};
     block_reduce<2, 0>(v, dummy, lds);
-    if (B.tid == 0) epi(i, dense ? P.q[i] : v[0], v[1]);
+    if (B.tid == 0) {
+      const Row rw = pre(i);
+      epi(i, dense ? rw.q : v[0], v[1], rw);
+    }
   }
   block_reduce<3, 3>(s, mx, lds);
   if (B.tid == 0) {
@@ -151,20 +158,25 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
 // m-side product u = A xg over the workgroup's rows of pm, with a per-row
 // epilogue epi(i, u) that returns nothing and accumulates the three m-side
 // partials (max (u-b)^+, max |u|, sum b.y) through the references given.
-template <typename V, typename Tx, typename Epi>
+template <typename V, typename Tx, typename Pre, typename Epi>
 __device__ void mside_rows(const SolveParams& P, Block B, const V* aval, const Tx* xg, double* lds,
-                           Epi epi) {
+                           const Pre& pre, Epi epi) {
   const WgPart& pt = P.w_m;
   GatherVec<Tx> gx{xg};
-  for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.A.rowptr, P.A.col, aval, pt.tile(t), pt.group, gx, epi);
+  for (int t = pt.t0; t < pt.t1; ++t) tile_rows_pf(P.A.rowptr, P.A.col, aval, pt.tile(t), pt.group, gx, pre, epi);
   for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.A.col, aval, P.A.rowptr[i], P.A.rowptr[i + 1], B.tid, kBlock, gx)};
     double dummy[1] = {0.0};
     block_reduce<1, 0>(v, dummy, lds);
-    if (B.tid == 0) epi(i, v[0]);
+    if (B.tid == 0) epi(i, v[0], pre(i));
   }
 }
+
+// per-row inputs of the m-side epilogues
+struct MRow {
+  double b, y, ax, ya;
+};
 
 __device__ void store_mside(const SolveParams& P, Block B, int slot0, double* s1, double* mx, double* lds) {
   block_reduce<1, 2>(s1, mx, lds);
@@ -178,12 +190,14 @@ __device__ void store_mside(const SolveParams& P, Block B, int slot0, double* s1
 // ax = A x and the m-side partials of the current point (start of a solve)
 __device__ __attribute__((noinline)) void phase_ax(const SolveParams& P, Block B, double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
-  mside_rows(P, B, P.A.val, P.x, lds, [&](int i, double u) {
-    P.ax[i] = u;
-    mx[0] = maxp(mx[0], pos_part(u - P.b[i]));
-    mx[1] = maxp(mx[1], fabs(u));
-    s1[0] += P.b[i] * P.y[i];
-  });
+  mside_rows(
+      P, B, P.A.val, P.x, lds, [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), 0.0, 0.0}; },
+      [&](int i, double u, const MRow& rw) {
+        gst(P.ax + i, u);
+        mx[0] = maxp(mx[0], pos_part(u - rw.b));
+        mx[1] = maxp(mx[1], fabs(u));
+        s1[0] += rw.b * rw.y;
+      });
   store_mside(P, B, 0, s1, mx, lds);
 }
 
@@ -192,12 +206,14 @@ template <bool DENSE>
 __device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, Block B, double* lds, double* svec) {
   phase_nside<DENSE>(P, P.w_n1, B, P.xa, P.ya, nullptr, nullptr, S_AVG0, lds, svec);
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
-  mside_rows(P, B, P.A.val, P.xa, lds, [&](int i, double u) {
-    P.ax_avg[i] = u;
-    mx[0] = maxp(mx[0], pos_part(u - P.b[i]));
-    mx[1] = maxp(mx[1], fabs(u));
-    s1[0] += P.b[i] * P.ya[i];
-  });
+  mside_rows(
+      P, B, P.A.val, P.xa, lds, [&](int i) { return MRow{gld(P.b + i), 0.0, 0.0, gld(P.ya + i)}; },
+      [&](int i, double u, const MRow& rw) {
+        gst(P.ax_avg + i, u);
+        mx[0] = maxp(mx[0], pos_part(u - rw.b));
+        mx[1] = maxp(mx[1], fabs(u));
+        s1[0] += rw.b * rw.ya;
+      });
   store_mside(P, B, S_AVG0, s1, mx, lds);
 }
 
@@ -313,11 +329,16 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
     sg = cb.s_prev2;
   }
   double s[2] = {0.0, 0.0};  // gamma_l, delta_l
-  auto own = [&](int i) -> double {  // owned-row updates; returns r_l[i]
-    // every input is loaded unconditionally (all buffers are valid; unused
-    // values are discarded by selects), so the loads issue together
-    const double rp = gld(cb.r_prev + i), up = gld(cb.u_prev + i), sp = gld(cb.s_prev2 + i);
-    const double pp = gld(P.p0 + i), xp = gld(P.x + i);
+  struct Row {
+    double rp, up, sp, pp, xp;
+  };
+  // the owned-row inputs, loaded unconditionally (all buffers are valid;
+  // values not used at this step are discarded by selects)
+  auto pre = [&](int i) {
+    return Row{gld(cb.r_prev + i), gld(cb.u_prev + i), gld(cb.s_prev2 + i), gld(P.p0 + i), gld(P.x + i)};
+  };
+  auto own = [&](int i, const Row& rw) -> double {  // owned-row updates; returns r_l[i]
+    const double rp = rw.rp, up = rw.up, sp = rw.sp, pp = rw.pp, xp = rw.xp;
     if (l == 0) return rp;
     const double s1 = l == 1 ? up : up + beta * sp;
     const double pi = l == 1 ? rp : rp + beta * pp;
@@ -335,11 +356,11 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
   };
   if (!product) {
     const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
-    for (int i = r0 + B.tid; i < r1; i += kBlock) own(i);
+    for (int i = r0 + B.tid; i < r1; i += kBlock) own(i, pre(i));
     return;
   }
-  auto epi = [&](int i, double qr) {
-    const double ri = own(i);
+  auto epi = [&](int i, double qr, const Row& rw) {
+    const double ri = own(i, rw);
     const double ui = qr + ri * inv_tau;
     gst(cb.u_new + i, ui);
     if (mixed) gst(cb.u32_new + i, (float)ui);
@@ -348,13 +369,13 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
   };
   const WgPart& pt = P.w_cg;
   GatherCG<T> g{rg, ug, sg, alpha, beta, l};
-  for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, g, epi);
+  for (int t = pt.t0; t < pt.t1; ++t) tile_rows_pf(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, g, pre, epi);
   for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, g)};
     double dummy[1] = {0.0};
     block_reduce<1, 0>(v, dummy, lds);
-    if (B.tid == 0) epi(i, v[0]);
+    if (B.tid == 0) epi(i, v[0], pre(i));
   }
   double dummy[1] = {0.0};
   block_reduce<2, 0>(s, dummy, lds);
@@ -371,19 +392,22 @@ template <typename V, typename Tx>
 __device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, Block B, const V* aval, const Tx* xg, double sigma, double w,
                            double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
-  mside_rows(P, B, aval, xg, lds, [&](int i, double u) {
-    const double bi = P.b[i];
-    double yn = P.y[i] + sigma * (2.0 * u - P.ax[i] - bi);
-    yn = pos_part(yn);
-    P.y[i] = yn;
-    P.ax[i] = u;
-    P.ya[i] += w * (yn - P.ya[i]);
-    mx[0] = maxp(mx[0], pos_part(u - bi));
-    mx[1] = maxp(mx[1], fabs(u));
-    s1[0] += bi * yn;
-  });
+  mside_rows(
+      P, B, aval, xg, lds, [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), gld(P.ax + i), gld(P.ya + i)}; },
+      [&](int i, double u, const MRow& rw) {
+        const double yn = pos_part(rw.y + sigma * (2.0 * u - rw.ax - rw.b));
+        gst(P.y + i, yn);
+        gst(P.ax + i, u);
+        gst(P.ya + i, rw.ya + w * (yn - rw.ya));
+        mx[0] = maxp(mx[0], pos_part(u - rw.b));
+        mx[1] = maxp(mx[1], fabs(u));
+        s1[0] += rw.b * yn;
+      });
   const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
-  for (int j = r0 + B.tid; j < r1; j += kBlock) P.xa[j] += w * (P.x[j] - P.xa[j]);
+  for (int j = r0 + B.tid; j < r1; j += kBlock) {
+    const double xaj = gld(P.xa + j), xj = gld(P.x + j);
+    gst(P.xa + j, xaj + w * (xj - xaj));
+  }
   store_mside(P, B, 0, s1, mx, lds);
 }
 
@@ -469,18 +493,23 @@ __device__ Kkt kkt_from(const double* s, const double* mx, double nb_inf, double
   return k;
 }
 
-__device__ __attribute__((noinline)) Kkt reduce_kkt(const SolveParams& P, Block B, int slot0, double nb_inf, double nc_inf, double* gg,
-                          double* flag, double* lds) {
+// relKKT pieces from the partials at slot0 (and, when gg / flag are given,
+// g.g and the time-limit flag); thread 0 writes them to *out, *gg, *flag (LDS)
+__device__ __attribute__((noinline)) void reduce_kkt(const SolveParams& P, Block B, int slot0, double nb_inf,
+                                                     double nc_inf, Kkt* out, double* gg, double* flag,
+                                                     double* lds) {
   const int ss[4] = {slot0 + S_GG, slot0 + S_XQX, slot0 + S_CX, slot0 + S_BY};
   const int ms[6] = {slot0 + S_MG, slot0 + S_MQX, slot0 + S_MATY, slot0 + S_MVIOL, slot0 + S_MAX, S_FLAG};
   double s[4], mx[6];
   reduce_partials<4, 6>(P.part, B.nb, ss, ms, s, mx, lds);
-  if (gg) *gg = s[0];
-  if (flag) *flag = mx[5];
-  Kkt k = kkt_from(s, mx, nb_inf, nc_inf);
-  // a NaN anywhere in g shows in g.g even where the max would not see it
-  if (!(s[0] == s[0])) k.kkt = s[0];
-  return k;
+  if (B.tid == 0) {
+    if (gg) *gg = s[0];
+    if (flag) *flag = mx[5];
+    Kkt k = kkt_from(s, mx, nb_inf, nc_inf);
+    // a NaN anywhere in g shows in g.g even where the max would not see it
+    if (!(s[0] == s[0])) k.kkt = s[0];
+    *out = k;
+  }
 }
 
 __device__ __attribute__((noinline)) double reduce_one(const SolveParams& P, Block B, int slot, double* lds) {
@@ -498,212 +527,420 @@ __device__ __attribute__((noinline)) double reduce_one(const SolveParams& P, Blo
 // The restarted PDHCG loop (Alg. 1 with the practical rules of Sec. 4),
 // shared by the cooperative single-QP kernel (many workgroups, grid
 // barriers) and the batched kernel (one workgroup per QP, nb = 1, where a
-// barrier is a workgroup barrier).  Runs at most `budget` iterations from
-// state S; returns false only if a grid barrier failed.
-template <bool DENSE>
-__device__ bool drive(const SolveParams& P, Block B, GridSync& gs, SolverState& S, double nb_inf,
-                      double nc_inf, double* lds, double* svec, int64_t budget) {
-  bool ok = true;
+// barrier is a workgroup barrier).
+//
+// Every thread of the workgroup runs the data-parallel phases and the
+// reductions of their partials; the scalar logic (relKKT tests, restart
+// rules, step sizes, CG coefficients) runs on one control thread that keeps
+// the solver state in LDS and writes the next phase and its arguments there.
+// The state thus occupies no vector registers across phases, and every
+// workgroup's control thread takes the same decisions from the same reduced
+// values.
 
-  if (S.K_anchor != S.K_anchor) {  // first launch of a solve: m-side of the start point
-    phase_ax(P, B, lds);
-    ok = gs.sync();
+// phases the control thread can schedule
+enum Op : int32_t {
+  OP_END = 0,
+  OP_AX_START,     // m-side of the start point (first launch of a solve)
+  OP_NSIDE,        // n-side pass at the current point, relKKT pieces
+  OP_ZERO,         // warm-start fallback: the start point is replaced by (0, 0)
+  OP_AX_ZERO,      // ... and its m-side recomputed
+  OP_CERTIFY,      // FP64 m-side of a point that passed with FP32 products
+  OP_EVAL,         // relKKT of the running average
+  OP_RESTART,      // restart to the candidate
+  OP_LIMIT_AX,     // exact m-side before reporting at a limit
+  OP_LIMIT_EVAL,   // average's relKKT before reporting at a limit
+  OP_CG,           // one step of single-reduction CG
+  OP_CG_SPMV,      // textbook CG: product
+  OP_CG_UPDATE,    // textbook CG: update
+  OP_DUAL,         // dual step and averages
+  OP_COPY_AVG,     // return the average (no barrier follows)
+  OP_COPY_ANCHOR,  // return the epoch's anchor (no barrier follows)
+};
+
+struct Ctl {
+  SolverState S;
+  Kkt kc, ka;         // relKKT pieces of the current point and of the average
+  Kkt rk;             // result of the reduction that followed the last phase
+  double ra, rb;      // (its scalar results)
+  double rho, tflag;  // r0.r0 of the primal step, time-limit flag
+  double Kc;          // candidate relKKT of the pending restart
+  double gamma, alpha, beta, inv_tau, w;
+  int64_t budget;     // iterations left in this launch
+  int32_t op, l, steps, have_avg, use_avg, first, cur;
+};
+
+__device__ void ctl_end_cg(Ctl& C) {
+  C.S.cg_total += C.steps;
+  C.w = 1.0 / (double)(C.S.k + 1);  // averages with weight 1/(k+1)
+  C.op = OP_DUAL;
+}
+
+// primal step: inexact CG on (Q + I/tau) x = x^k/tau - c - A'y^k (Alg. 1)
+__device__ void ctl_start_cg(const SolveParams& P, Ctl& C) {
+  C.S.eps += P.eps_factor * C.kc.kkt;
+  C.inv_tau = 1.0 / C.S.tau;
+  C.steps = 0;
+  if (C.rho > 0.0 && P.u0 != nullptr) {  // single-reduction CG: L steps take L + 1 grid barriers
+    C.gamma = C.rho;
+    C.alpha = 0.0;
+    C.beta = 0.0;
+    C.l = 0;
+    C.op = OP_CG;
+  } else if (C.rho > 0.0) {
+    C.beta = 0.0;
+    C.first = 1;
+    C.cur = 0;
+    C.l = 1;
+    C.op = OP_CG_SPMV;
+  } else {
+    ctl_end_cg(C);
   }
+}
 
-  Kkt kc{}, ka{};
-  bool have_avg = false;
-  while (ok && !S.done && budget > 0) {
-    // ---- n-side pass at z^{n,k}: r0 = -(Qx + A'y + c), relKKT(z^{n,k})
-    phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, S.mixed ? P.r32 : nullptr, 0, lds, svec);
-    if (B.tid == 0) {
-      double f = 0.0;
-      if (B.b == 0 && P.time_limit_ticks && wall_clock64() - S.t_start > P.time_limit_ticks) f = 1.0;
-      P.part[S_FLAG * B.nb + B.b] = f;
+__device__ void ctl_finish(Ctl& C, const Kkt& k, int status, int avg) {
+  C.S.done = 1;
+  C.S.status = status;
+  C.S.returned_average = avg;
+  C.S.r_p = k.rp;
+  C.S.r_d = k.rd;
+  C.S.r_g = k.rg;
+  C.S.kkt = k.kkt;
+  C.S.pobj = k.pobj;
+  C.S.dobj = k.dobj;
+}
+
+// at the iteration cap or the time limit: report the better of current and average
+__device__ void ctl_limit_report(const SolveParams& P, Ctl& C) {
+  const bool at_cap = C.S.k_total >= P.max_iters;
+  const bool avg = C.have_avg && C.ka.kkt < C.kc.kkt;
+  const Kkt& k = avg ? C.ka : C.kc;
+  ctl_finish(C, k, k.kkt <= P.tol ? 0 : (at_cap ? 1 : 2), avg ? 1 : 0);
+  C.op = avg ? OP_COPY_AVG : OP_END;
+}
+
+__device__ void ctl_limit_after_ax(const SolveParams& P, Ctl& C) {
+  if (C.S.k > 0 && !C.have_avg) {
+    C.op = OP_LIMIT_EVAL;
+    return;
+  }
+  ctl_limit_report(P, C);
+}
+
+__device__ void ctl_limits(const SolveParams& P, Ctl& C) {
+  const bool at_cap = C.S.k_total >= P.max_iters;
+  const bool at_time = C.tflag > 0.0;
+  if (at_cap || at_time) {
+    if (C.S.mixed) {  // exact FP64 m-side partials for the reported relKKT
+      C.op = OP_LIMIT_AX;
+      return;
     }
-    if (!(ok = gs.sync())) break;
-    double rho, tflag;
-    kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, &rho, &tflag, lds);
-    have_avg = false;
-    if (!S.start_checked) {
-      S.start_checked = 1;
-      if (P.kkt_zero > 0.0 && !(kc.kkt <= P.kkt_zero)) {
-        // the given start point is worse than (0, 0): start cold
-        phase_zero_point(P, B);
-        if (!(ok = gs.sync())) break;
-        phase_ax(P, B, lds);
-        if (!(ok = gs.sync())) break;
-        S.cold_fallback = 1;
-        continue;
-      }
+    ctl_limit_after_ax(P, C);
+    return;
+  }
+  ctl_start_cg(P, C);
+}
+
+// restart evaluation (Sec. 4, adaptive restart) once the average's relKKT is known
+__device__ void ctl_after_eval(const SolveParams& P, Ctl& C) {
+  C.have_avg = 1;
+  C.S.evals += 1;
+  if (C.ka.kkt <= P.tol) {
+    ctl_finish(C, C.ka, 0, 1);
+    C.op = OP_COPY_AVG;
+    return;
+  }
+  const int use_avg = (P.restart_to == 1) || (C.ka.kkt < C.kc.kkt);
+  const double Kc = use_avg ? C.ka.kkt : C.kc.kkt;
+  int why = 0;
+  if (Kc <= P.beta_suf * C.S.K_anchor) why = 1;
+  else if (Kc <= P.beta_nec * C.S.K_anchor && Kc > C.S.K_prev) why = 2;
+  else if ((double)C.S.k >= P.beta_art * (double)C.S.k_total) why = 3;
+  C.S.K_prev = Kc;
+  if (why) {
+    C.use_avg = use_avg;
+    C.Kc = Kc;
+    C.op = OP_RESTART;
+    return;
+  }
+  ctl_limits(P, C);
+}
+
+// after the current point's relKKT is final (certified when it came from FP32 products)
+__device__ void ctl_after_kkt(const SolveParams& P, Ctl& C) {
+  if (C.kc.kkt <= P.tol) {
+    ctl_finish(C, C.kc, 0, 0);
+    C.op = OP_END;
+    return;
+  }
+  if (C.S.k > 0 && C.S.k % P.eval_period == 0) {
+    C.op = OP_EVAL;
+    return;
+  }
+  ctl_limits(P, C);
+}
+
+__device__ void ctl_after_nside(const SolveParams& P, Ctl& C) {
+  C.have_avg = 0;
+  if (!C.S.start_checked) {
+    C.S.start_checked = 1;
+    if (P.kkt_zero > 0.0 && !(C.kc.kkt <= P.kkt_zero)) {  // the given start point is worse than (0, 0)
+      C.op = OP_ZERO;
+      return;
     }
-    if (S.K_anchor != S.K_anchor) {
-      S.K_anchor = kc.kkt;
-    }
-    if (!(kc.kkt == kc.kkt) || isinf(kc.kkt)) {  // NUMERICAL_ERROR: back to the anchor
-      S.done = 1;
-      S.status = 3;
-      phase_copy_point(P, B, P.x_anc, P.y_anc);
-      S.r_p = S.r_d = S.r_g = NAN;
-      S.kkt = kc.kkt;
-      S.pobj = S.dobj = NAN;
+  }
+  if (C.S.K_anchor != C.S.K_anchor) C.S.K_anchor = C.kc.kkt;
+  if (!(C.kc.kkt == C.kc.kkt) || isinf(C.kc.kkt)) {  // NUMERICAL_ERROR: back to the anchor
+    C.S.done = 1;
+    C.S.status = 3;
+    C.S.r_p = C.S.r_d = C.S.r_g = NAN;
+    C.S.kkt = C.kc.kkt;
+    C.S.pobj = C.S.dobj = NAN;
+    C.op = OP_COPY_ANCHOR;
+    return;
+  }
+  if (C.kc.kkt <= P.tol && C.S.mixed) {  // the m-side partials came from FP32 products
+    C.op = OP_CERTIFY;
+    return;
+  }
+  ctl_after_kkt(P, C);
+}
+
+// the control step after phase `op` and its reduction (C.rk, C.ra, C.rb)
+__device__ void control(const SolveParams& P, Ctl& C, int op) {
+  const Ctl& r = C;
+  switch (op) {
+    case OP_AX_START:
+      C.op = OP_NSIDE;
+      break;
+    case OP_NSIDE:
+      C.kc = r.rk;
+      C.rho = r.ra;
+      C.tflag = r.rb;
+      ctl_after_nside(P, C);
+      break;
+    case OP_ZERO:
+      C.op = OP_AX_ZERO;
+      break;
+    case OP_AX_ZERO:
+      C.S.cold_fallback = 1;
+      C.op = OP_NSIDE;
+      break;
+    case OP_CERTIFY:
+      C.kc = r.rk;
+      if (C.kc.kkt > P.tol) C.S.mixed = 0;  // the certificate failed: finish in FP64
+      ctl_after_kkt(P, C);
+      break;
+    case OP_EVAL:
+      C.ka = r.rk;
+      ctl_after_eval(P, C);
+      break;
+    case OP_RESTART: {
+      const double dx = sqrt(r.ra), dy = sqrt(r.rb);
+      if (P.theta > 0.0 && dx > 1e-10 && dy > 1e-10)
+        C.S.omega = exp(P.theta * log(dy / dx) + (1.0 - P.theta) * log(C.S.omega));
+      C.S.tau = C.S.eta / C.S.omega;
+      C.S.sigma = C.S.eta * C.S.omega;
+      C.S.K_anchor = C.Kc;
+      C.S.K_prev = INFINITY;
+      C.S.k = 0;
+      C.S.eps = 0.0;
+      C.S.restarts += 1;
+      C.have_avg = 0;
+      if (C.use_avg)
+        C.op = OP_NSIDE;  // the point moved: redo the n-side pass there
+      else
+        ctl_limits(P, C);
       break;
     }
-    if (kc.kkt <= P.tol && S.mixed) {
-      // the m-side partials came from FP32 products: certify r_primal with
-      // an FP64 product, and finish in FP64 if the certificate fails
-      phase_ax(P, B, lds);
-      if (!(ok = gs.sync())) break;
-      kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, nullptr, nullptr, lds);
-      if (kc.kkt > P.tol) S.mixed = 0;
-    }
-    if (kc.kkt <= P.tol) {
-      S.done = 1;
-      S.status = 0;
-      S.returned_average = 0;
-      S.r_p = kc.rp; S.r_d = kc.rd; S.r_g = kc.rg; S.kkt = kc.kkt; S.pobj = kc.pobj; S.dobj = kc.dobj;
+    case OP_LIMIT_AX:
+      C.kc = r.rk;
+      ctl_limit_after_ax(P, C);
       break;
-    }
-    // ---- restart evaluation (Sec. 4, adaptive restart)
-    if (S.k > 0 && S.k % P.eval_period == 0) {
-      phase_eval_avg<DENSE>(P, B, lds, svec);
-      if (!(ok = gs.sync())) break;
-      ka = reduce_kkt(P, B, S_AVG0, nb_inf, nc_inf, nullptr, nullptr, lds);
-      have_avg = true;
-      S.evals += 1;
-      if (ka.kkt <= P.tol) {
-        S.done = 1;
-        S.status = 0;
-        S.returned_average = 1;
-        S.r_p = ka.rp; S.r_d = ka.rd; S.r_g = ka.rg; S.kkt = ka.kkt; S.pobj = ka.pobj; S.dobj = ka.dobj;
-        phase_copy_point(P, B, P.xa, P.ya);
+    case OP_LIMIT_EVAL:
+      C.ka = r.rk;
+      C.have_avg = 1;
+      ctl_limit_report(P, C);
+      break;
+    case OP_CG: {
+      const int l = C.l;
+      if (l > 0) C.steps = l;
+      if (l >= P.max_cg) {  // the last allowed step only advanced x
+        ctl_end_cg(C);
         break;
       }
-      const int use_avg = (P.restart_to == 1) || (ka.kkt < kc.kkt);
-      const double Kc = use_avg ? ka.kkt : kc.kkt;
-      int why = 0;
-      if (Kc <= P.beta_suf * S.K_anchor) why = 1;
-      else if (Kc <= P.beta_nec * S.K_anchor && Kc > S.K_prev) why = 2;
-      else if ((double)S.k >= P.beta_art * (double)S.k_total) why = 3;
-      S.K_prev = Kc;
-      if (why) {
-        phase_restart(P, B, use_avg, S.mixed, lds);
-        if (!(ok = gs.sync())) break;
+      if (l == 0) {
+        C.alpha = C.gamma / r.rb;
+        C.beta = 0.0;
+        C.l = 1;
+        break;
+      }
+      const double gl = r.ra, dl = r.rb;
+      if ((P.cg_rule == 0 && C.S.tau * sqrt(gl) <= C.S.eps) || !(gl > 0.0)) {
+        ctl_end_cg(C);
+        break;
+      }
+      C.beta = gl / C.gamma;
+      C.alpha = gl / (dl - C.beta * gl / C.alpha);
+      C.gamma = gl;
+      C.l = l + 1;
+      break;
+    }
+    case OP_CG_SPMV:
+      C.alpha = C.rho / r.ra;
+      C.op = OP_CG_UPDATE;
+      break;
+    case OP_CG_UPDATE: {
+      const double rho_new = r.ra;
+      C.steps = C.l;
+      if (C.l == P.max_cg || (P.cg_rule == 0 && C.S.tau * sqrt(rho_new) <= C.S.eps) || !(rho_new > 0.0)) {
+        ctl_end_cg(C);
+        break;
+      }
+      C.beta = rho_new / C.rho;
+      C.rho = rho_new;
+      C.first = 0;
+      C.cur ^= 1;
+      C.l += 1;
+      C.op = OP_CG_SPMV;
+      break;
+    }
+    case OP_DUAL:
+      C.S.k += 1;
+      C.S.k_total += 1;
+      C.budget -= 1;
+      C.op = C.budget > 0 ? OP_NSIDE : OP_END;
+      break;
+    default:
+      C.op = OP_END;
+  }
+}
+
+// Runs at most `budget` iterations from the state C.S (set by thread 0 before
+// the call, updated in place); returns false only if a grid barrier failed.
+template <bool DENSE>
+__device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, double nb_inf, double nc_inf,
+                      double* lds, double* svec, int64_t budget) {
+  if (B.tid == 0) {
+    C.budget = budget;
+    C.have_avg = 0;
+    C.op = C.S.done || budget <= 0 ? OP_END : (C.S.K_anchor != C.S.K_anchor ? OP_AX_START : OP_NSIDE);
+  }
+  __syncthreads();
+  bool ok = true;
+  for (;;) {
+    const int op = C.op;
+    if (op == OP_END) break;
+    const int mixed = C.S.mixed;
+    switch (op) {
+      case OP_AX_START:
+      case OP_AX_ZERO:
+      case OP_CERTIFY:
+      case OP_LIMIT_AX:
+        phase_ax(P, B, lds);
+        break;
+      case OP_NSIDE:
+        phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? P.r32 : nullptr, 0, lds, svec);
+        if (B.tid == 0) {
+          double f = 0.0;
+          if (B.b == 0 && P.time_limit_ticks && wall_clock64() - C.S.t_start > P.time_limit_ticks) f = 1.0;
+          P.part[S_FLAG * B.nb + B.b] = f;
+        }
+        break;
+      case OP_ZERO:
+        phase_zero_point(P, B);
+        break;
+      case OP_EVAL:
+      case OP_LIMIT_EVAL:
+        phase_eval_avg<DENSE>(P, B, lds, svec);
+        break;
+      case OP_RESTART:
+        phase_restart(P, B, C.use_avg, mixed, lds);
+        break;
+      case OP_CG:
+        if (mixed)
+          phase_cgcg<float, float>(P, B, P.Q.val32, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 1, lds);
+        else
+          phase_cgcg<double, double>(P, B, P.Q.val, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 0, lds);
+        break;
+      case OP_CG_SPMV: {
+        const int cur = C.cur;
+        double* pc = cur ? P.p1 : P.p0;
+        const double* pp = cur ? P.p0 : P.p1;
+        if (mixed)
+          phase_cg_spmv<DENSE>(P, B, P.Q.val32, (const float*)P.r32, (const float*)(cur ? P.p32_0 : P.p32_1), pp,
+                               pc, cur ? P.p32_1 : P.p32_0, C.beta, C.first, C.inv_tau, lds, svec);
+        else
+          phase_cg_spmv<DENSE>(P, B, P.Q.val, (const double*)P.r, pp, pp, pc, nullptr, C.beta, C.first, C.inv_tau,
+                               lds, svec);
+        break;
+      }
+      case OP_CG_UPDATE:
+        phase_cg_update(P, B, C.cur ? P.p1 : P.p0, C.alpha, mixed, lds);
+        break;
+      case OP_DUAL:
+        if (mixed)
+          phase_dual(P, B, P.A.val32, (const float*)P.x32, C.S.sigma, C.w, lds);
+        else
+          phase_dual(P, B, P.A.val, (const double*)P.x, C.S.sigma, C.w, lds);
+        break;
+      case OP_COPY_AVG:
+        phase_copy_point(P, B, P.xa, P.ya);
+        break;
+      case OP_COPY_ANCHOR:
+        phase_copy_point(P, B, P.x_anc, P.y_anc);
+        break;
+    }
+    if (op == OP_COPY_AVG || op == OP_COPY_ANCHOR) break;  // the solve ends with this copy
+    if (!(ok = gs.sync())) break;
+    double a = 0.0, b = 0.0;
+    switch (op) {
+      case OP_NSIDE:
+        reduce_kkt(P, B, 0, nb_inf, nc_inf, &C.rk, &C.ra, &C.rb, lds);
+        break;
+      case OP_CERTIFY:
+      case OP_LIMIT_AX:
+        reduce_kkt(P, B, 0, nb_inf, nc_inf, &C.rk, nullptr, nullptr, lds);
+        break;
+      case OP_EVAL:
+      case OP_LIMIT_EVAL:
+        reduce_kkt(P, B, S_AVG0, nb_inf, nc_inf, &C.rk, nullptr, nullptr, lds);
+        break;
+      case OP_RESTART: {
         const int ss[2] = {S_DX, S_DY};
         const int ms[1] = {0};
         double s2[2], m0[1];
         reduce_partials<2, 0>(P.part, B.nb, ss, ms, s2, m0, lds);
-        const double dx = sqrt(s2[0]), dy = sqrt(s2[1]);
-        if (P.theta > 0.0 && dx > 1e-10 && dy > 1e-10)
-          S.omega = exp(P.theta * log(dy / dx) + (1.0 - P.theta) * log(S.omega));
-        S.tau = S.eta / S.omega;
-        S.sigma = S.eta * S.omega;
-        S.K_anchor = Kc;
-        S.K_prev = INFINITY;
-        S.k = 0;
-        S.eps = 0.0;
-        S.restarts += 1;
-        have_avg = false;
-        if (use_avg) continue;  // the point moved: redo the n-side pass there
+        a = s2[0];
+        b = s2[1];
+        break;
       }
-    }
-    // ---- limits
-    const bool at_cap = S.k_total >= P.max_iters;
-    const bool at_time = tflag > 0.0;
-    if (at_cap || at_time) {
-      if (S.mixed) {  // exact FP64 m-side partials for the reported relKKT
-        phase_ax(P, B, lds);
-        if (!(ok = gs.sync())) break;
-        kc = reduce_kkt(P, B, 0, nb_inf, nc_inf, nullptr, nullptr, lds);
-      }
-      if (S.k > 0 && !have_avg) {
-        phase_eval_avg<DENSE>(P, B, lds, svec);
-        if (!(ok = gs.sync())) break;
-        ka = reduce_kkt(P, B, S_AVG0, nb_inf, nc_inf, nullptr, nullptr, lds);
-        have_avg = true;
-      }
-      S.done = 1;
-      const bool avg = have_avg && ka.kkt < kc.kkt;
-      const Kkt& k = avg ? ka : kc;
-      S.status = k.kkt <= P.tol ? 0 : (at_cap ? 1 : 2);
-      S.returned_average = avg ? 1 : 0;
-      S.r_p = k.rp; S.r_d = k.rd; S.r_g = k.rg; S.kkt = k.kkt; S.pobj = k.pobj; S.dobj = k.dobj;
-      if (avg) phase_copy_point(P, B, P.xa, P.ya);
-      break;
-    }
-    // ---- primal step: inexact CG on (Q + I/tau) x = x^k/tau - c - A'y^k (Alg. 1)
-    S.eps += P.eps_factor * kc.kkt;
-    const double inv_tau = 1.0 / S.tau;
-    int steps = 0;
-    if (rho > 0.0 && P.u0 != nullptr) {
-      // single-reduction CG: L steps take L + 1 grid barriers
-      double gamma = rho, alpha = 0.0, beta = 0.0;
-      for (int l = 0; l <= P.max_cg; ++l) {
-        const int product = l < P.max_cg;
-        if (S.mixed)
-          phase_cgcg<float, float>(P, B, P.Q.val32, l, alpha, beta, inv_tau, product, 1, lds);
-        else
-          phase_cgcg<double, double>(P, B, P.Q.val, l, alpha, beta, inv_tau, product, 0, lds);
-        if (!(ok = gs.sync())) break;
-        if (l > 0) steps = l;
-        if (!product) break;
-        const int ss2[2] = {S_RR, S_PQ};
-        const int ms2[1] = {0};
-        double gd[2], m2[1];
-        reduce_partials<2, 0>(P.part, B.nb, ss2, ms2, gd, m2, lds);
-        if (l == 0) {
-          alpha = gamma / gd[1];
-          beta = 0.0;
-          continue;
+      case OP_CG:
+        if (C.l < P.max_cg) {
+          const int ss[2] = {S_RR, S_PQ};
+          const int ms[1] = {0};
+          double gd[2], m0[1];
+          reduce_partials<2, 0>(P.part, B.nb, ss, ms, gd, m0, lds);
+          a = gd[0];
+          b = gd[1];
         }
-        const double gl = gd[0], dl = gd[1];
-        if (P.cg_rule == 0 && S.tau * sqrt(gl) <= S.eps) break;
-        if (!(gl > 0.0)) break;
-        beta = gl / gamma;
-        alpha = gl / (dl - beta * gl / alpha);
-        gamma = gl;
-      }
-      if (!ok) break;
-    } else if (rho > 0.0) {
-      double beta = 0.0;
-      int first = 1, cur = 0;
-      for (int l = 1; l <= P.max_cg; ++l) {
-        double* pc = cur ? P.p1 : P.p0;
-        const double* pp = cur ? P.p0 : P.p1;
-        if (S.mixed) {
-          float* pc32 = cur ? P.p32_1 : P.p32_0;
-          const float* pp32 = cur ? P.p32_0 : P.p32_1;
-          phase_cg_spmv<DENSE>(P, B, P.Q.val32, (const float*)P.r32, pp32, pp, pc, pc32, beta, first, inv_tau, lds, svec);
-        } else {
-          phase_cg_spmv<DENSE>(P, B, P.Q.val, (const double*)P.r, pp, pp, pc, nullptr, beta, first, inv_tau, lds, svec);
-        }
-        if (!(ok = gs.sync())) break;
-        const double pq = reduce_one(P, B, S_PQ, lds);
-        const double alpha = rho / pq;
-        phase_cg_update(P, B, pc, alpha, S.mixed, lds);
-        if (!(ok = gs.sync())) break;
-        const double rho_new = reduce_one(P, B, S_RR, lds);
-        steps = l;
-        if (l == P.max_cg) break;
-        if (P.cg_rule == 0 && S.tau * sqrt(rho_new) <= S.eps) break;
-        if (!(rho_new > 0.0)) break;
-        beta = rho_new / rho;
-        rho = rho_new;
-        first = 0;
-        cur ^= 1;
-      }
-      if (!ok) break;
+        break;
+      case OP_CG_SPMV:
+        a = reduce_one(P, B, S_PQ, lds);
+        break;
+      case OP_CG_UPDATE:
+        a = reduce_one(P, B, S_RR, lds);
+        break;
+      default:
+        break;
     }
-    S.cg_total += steps;
-    // ---- dual step at 2x^{k+1} - x^k and averages with weight 1/(k+1)
-    const double w = 1.0 / (double)(S.k + 1);
-    if (S.mixed)
-      phase_dual(P, B, P.A.val32, (const float*)P.x32, S.sigma, w, lds);
-    else
-      phase_dual(P, B, P.A.val, (const double*)P.x, S.sigma, w, lds);
-    if (!(ok = gs.sync())) break;
-    S.k += 1;
-    S.k_total += 1;
-    budget -= 1;
+    if (B.tid == 0) {
+      if (op != OP_NSIDE) {  // (the n-side reduction wrote its own scalars)
+        C.ra = a;
+        C.rb = b;
+      }
+      control(P, C, op);
+    }
+    __syncthreads();
   }
   return ok;
 }
@@ -751,14 +988,16 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* 
   __shared__ double lds[kWaves * 16];
   Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
   GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
-  SolverState S = *P.st;
-  if (S.done) return;
-  const bool ok = drive<false>(P, B, gs, S, nb_inf, nc_inf, lds, nullptr, P.iters_this_launch);
+  __shared__ Ctl C;
+  if (B.tid == 0) C.S = *P.st;
+  __syncthreads();
+  if (C.S.done) return;
+  const bool ok = drive<false>(P, B, gs, C, nb_inf, nc_inf, lds, nullptr, P.iters_this_launch);
   if (B.b == 0 && B.tid == 0) {
     if (!ok)
       P.st->done = -1;  // barrier failure: reported as a HIP error
     else
-      *P.st = S;
+      *P.st = C.S;
   }
 }
 
@@ -878,21 +1117,26 @@ __global__ void __launch_bounds__(kBlock) pdhcg_batch_kernel(BatchParams BP) {
   __syncthreads();
   double nrm = 0.0;
   if (P.m > 0) power_norm(P.A, P.At, P.p0, P.p1, P.ax_avg, P.part, P.pt, P.pm, BP.power_iters, B, gs, lds, &nrm);
-  SolverState S{};
-  S.K_anchor = NAN;
-  S.K_prev = INFINITY;
-  S.omega = BP.pw_init;
-  S.eta = BP.eta_factor / (nrm > 0.0 ? nrm : 1.0);
-  S.tau = S.eta / S.omega;
-  S.sigma = S.eta * S.omega;
-  S.mixed = BP.mixed;
-  S.t_start = *BP.t0;
-  S.norm_A = nrm;
+  __shared__ Ctl C;
+  if (B.tid == 0) {
+    SolverState& S = C.S;
+    S = SolverState{};
+    S.K_anchor = NAN;
+    S.K_prev = INFINITY;
+    S.omega = BP.pw_init;
+    S.eta = BP.eta_factor / (nrm > 0.0 ? nrm : 1.0);
+    S.tau = S.eta / S.omega;
+    S.sigma = S.eta * S.omega;
+    S.mixed = BP.mixed;
+    S.t_start = *BP.t0;
+    S.norm_A = nrm;
+  }
+  __syncthreads();
   if (P.Q.dense)
-    drive<true>(P, B, gs, S, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
+    drive<true>(P, B, gs, C, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
   else
-    drive<false>(P, B, gs, S, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
-  if (B.tid == 0) BP.st[idx] = S;
+    drive<false>(P, B, gs, C, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
+  if (B.tid == 0) BP.st[idx] = C.S;
 }
 
 __global__ void batch_clock_kernel(uint64_t* t0) {
