@@ -28,6 +28,70 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "pdhcg_solve_kernel_random_qp_1e5_counters.md")
+CALIBRATION_BYTES = 1 << 30   # the --calibrate-copy kernel reads and writes 1 GiB
+
+
+def kernel_source_hash():
+    """SHA-256 over the library's device and host sources: the counter summary
+    is used only while it was measured on the same code."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2405_16160_amd", "csrc", "*"))
+                   + glob.glob(os.path.join(ROOT, "include", "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_counter_csv(d):
+    """Per-dispatch counter values (KiB) from a rocprofv3 --pmc CSV run:
+    [(kernel_name, counter, value)]."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r.get("Kernel_Name", ""), r.get("Counter_Name", ""), float(r.get("Counter_Value", 0))))
+    return rows
+
+
+def summarize_counters(d, algorithmic_bytes):
+    """Scale the solve kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
+    what the same counters read for a plain 1 GiB device copy."""
+    out = {}
+    for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        solve = [v for k, c, v in read_counter_csv(os.path.join(d, sub))
+                 if c == counter and "pdhcg_solve_kernel" in k]
+        copy = [v for k, c, v in read_counter_csv(os.path.join(d, "copy_" + sub)) if c == counter]
+        if not solve or not copy:
+            raise SystemExit(f"no {counter} rows under {d}/{sub} or {d}/copy_{sub}")
+        factor = max(copy) * 1024.0 / CALIBRATION_BYTES   # counter bytes per copied byte
+        out[counter] = {"solve_kib_per_dispatch": float(np.mean(solve)), "dispatches": len(solve),
+                        "copy_kib": max(copy), "factor": factor,
+                        "bytes_per_launch": float(np.mean(solve)) * 1024.0 / factor}
+    traffic = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
+    return {"source_sha256": kernel_source_hash(), "traffic_bytes_per_launch": traffic,
+            "algorithmic_bytes_per_launch": algorithmic_bytes, "traffic_over_algorithmic": traffic / algorithmic_bytes,
+            "counters": out}
+
+
+def measured_traffic():
+    """Bytes per launch of the solve kernel from the committed counter summary,
+    or None when there is none or the sources changed since it was taken."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None, None
+    for line in open(COUNTERS_FILE):
+        if line.startswith("counters-json: "):
+            d = json.loads(line[len("counters-json: "):])
+            if d.get("source_sha256") == kernel_source_hash():
+                return d["traffic_bytes_per_launch"], d
+            return None, None
+    return None, None
 
 
 def parse():
@@ -42,6 +106,10 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip SpMV and CG-cap-1 side measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the FETCH/WRITE counters)")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="turn rocprofv3 --pmc CSV runs under DIR/{fetch,write,copy_fetch,copy_write} into "
+                         "the counter summary line (prints it; needs the solve's algorithmic bytes, so it "
+                         "also runs one solve)")
     ap.add_argument("--config", default="random1e5",
                     choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "precision"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
@@ -327,6 +395,7 @@ def main():
     launches = 1   # one solve-kernel launch per solve at this size (5000-iteration chunks)
     bytes_alg = solve_bytes(qp, r, args.precision)
     achieved = bytes_alg / kernel_s / 1e9
+    traffic, _ = measured_traffic()
     line = {
         "metric": "time & QPs/s to rel. KKT<=1e-4 (batched/warm-start vs plain); SpMV HBM GB/s",
         "value": args.steps / dt,
@@ -349,9 +418,14 @@ def main():
                   "kkt_evals": r["kkt_evals"], "rel_kkt": r["rel_kkt"], "setup_s": r["setup_s"],
                   "kernel_ms": kernel_s * 1e3, "launches_per_solve": launches},
         "roofline": {"kernel": "pdhcg_solve_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_alg / launches},
     }
+    if args.summarize_counters:
+        print("counters-json: " + json.dumps(summarize_counters(args.summarize_counters, bytes_alg / launches)))
+        return
+    if traffic is not None:
+        line["roofline"]["traffic_over_algorithmic"] = traffic / (bytes_alg / launches)
     if not args.no_extras:
         extras = {}
         rng = np.random.default_rng(0)

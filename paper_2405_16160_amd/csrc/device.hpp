@@ -309,6 +309,28 @@ __device__ __forceinline__ void stage_tile(const int32_t* rowptr1, const int32_t
   }
 }
 
+// Lanes per row for a tile's row sums: the partition's group size G, made
+// smaller when the tile has many rows, so that all of its rows are summed in
+// one pass of the workgroup (two when it has more rows than threads); each
+// lane then adds a longer stretch of the row.
+__device__ __forceinline__ int tile_group(int G, int nr) {
+  const int fit = nr > 0 ? kBlock / nr : kBlock;
+  const int g = fit >= 1 ? 1 << (31 - __clz(fit)) : 1;
+  return g < G ? g : G;
+}
+
+// sum of prod[k] for k = beg + lane, beg + lane + G, ... < end (two chains)
+__device__ __forceinline__ double lane_row_sum(const double* prod, int beg, int end, int lane, int G) {
+  double a0 = 0.0, a1 = 0.0;
+  int k = beg + lane;
+  for (; k + G < end; k += 2 * G) {
+    a0 += prod[k];
+    a1 += prod[k + G];
+  }
+  if (k < end) a0 += prod[k];
+  return a0 + a1;
+}
+
 constexpr int kEpiRows = kTileRows / kBlock;  // epilogue rows per thread in one tile
 static_assert(kTileRows % kBlock == 0, "tile rows split evenly over the threads");
 
@@ -335,15 +357,15 @@ __device__ __forceinline__ void tile_rows_pf(const int32_t* rowptr, const int32_
   }
   stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, z0, 0, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
-  const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
+  const int Gt = tile_group(G, nr);
+  const int lane = threadIdx.x & (Gt - 1), ng = kBlock / Gt;
   for (int base = 0; base < nr; base += ng) {
-    const int i = base + (int)threadIdx.x / G;
+    const int i = base + (int)threadIdx.x / Gt;
     const bool act = i < nr;
     double s = 0.0;
-    if (act)
-      for (int k = L.rp[i] + lane; k < L.rp[i + 1]; k += G) s += L.prod[k];
-    s = group_sum_last(s, G);
-    if (act && lane == G - 1) L.sum1[i] = s;
+    if (act) s = lane_row_sum(L.prod, L.rp[i], L.rp[i + 1], lane, Gt);
+    s = group_sum_last(s, Gt);
+    if (act && lane == Gt - 1) L.sum1[i] = s;
   }
   __syncthreads();
 #pragma unroll
@@ -378,20 +400,19 @@ __device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t
   }
   stage_tile(rowptr1, col1, val1, g1, z0, nz, rowptr2, col2, val2, g2, w0, nw, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
-  const int lane = threadIdx.x & (G - 1), ng = kBlock / G;
+  const int Gt = tile_group(G, nr);
+  const int lane = threadIdx.x & (Gt - 1), ng = kBlock / Gt;
   for (int base = 0; base < nr; base += ng) {
-    const int i = base + (int)threadIdx.x / G;
+    const int i = base + (int)threadIdx.x / Gt;
     const bool act = i < nr;
     double s1 = 0.0, s2 = 0.0;
     if (act) {
-      if (rowptr1)
-        for (int k = L.rp[i] + lane; k < L.rp[i + 1]; k += G) s1 += L.prod[k];
-      if (rowptr2)
-        for (int k = L.rp2[i] + lane; k < L.rp2[i + 1]; k += G) s2 += L.prod[k];
+      if (rowptr1) s1 = lane_row_sum(L.prod, L.rp[i], L.rp[i + 1], lane, Gt);
+      if (rowptr2) s2 = lane_row_sum(L.prod, L.rp2[i], L.rp2[i + 1], lane, Gt);
     }
-    s1 = group_sum_last(s1, G);
-    s2 = group_sum_last(s2, G);
-    if (act && lane == G - 1) {
+    s1 = group_sum_last(s1, Gt);
+    s2 = group_sum_last(s2, Gt);
+    if (act && lane == Gt - 1) {
       L.sum1[i] = s1;
       L.sum2[i] = s2;
     }
