@@ -108,8 +108,10 @@ def parse():
                     help="only run a 1 GiB device copy (for scaling the FETCH/WRITE counters)")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="turn rocprofv3 --pmc CSV runs under DIR/{fetch,write,copy_fetch,copy_write} into "
-                         "the counter summary line (prints it; needs the solve's algorithmic bytes, so it "
-                         "also runs one solve)")
+                         "the counter summary line (prints it; runs on the CPU)")
+    ap.add_argument("--bench-line", metavar="FILE",
+                    help="with --summarize-counters: a file holding the bench line of the profiled run "
+                         "(its algorithmic bytes per launch)")
     ap.add_argument("--config", default="random1e5",
                     choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "precision"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
@@ -356,6 +358,11 @@ def main():
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
               "the solver does not shard a QP across GPUs.", file=sys.stderr)
         sys.exit(2)
+    if args.summarize_counters:
+        line = [json.loads(x) for x in open(args.bench_line) if x.startswith('{"metric"')][-1]
+        alg = line["roofline"]["algorithmic_bytes_per_launch"]
+        print("counters-json: " + json.dumps(summarize_counters(args.summarize_counters, alg)))
+        return
     import torch
     from paper_2405_16160_amd import pdhcg
     torch.cuda.set_device(0)
@@ -421,9 +428,6 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_alg / launches},
     }
-    if args.summarize_counters:
-        print("counters-json: " + json.dumps(summarize_counters(args.summarize_counters, bytes_alg / launches)))
-        return
     if traffic is not None:
         line["roofline"]["traffic_over_algorithmic"] = traffic / (bytes_alg / launches)
     if not args.no_extras:
