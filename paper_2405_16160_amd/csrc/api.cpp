@@ -158,6 +158,27 @@ int pow2_ceil(double v) {
 // kLongRow entries listed per workgroup; the other rows cut into tiles of at
 // most kTileNnz entries and kTileRows rows.  The lane group is the power of
 // two at or above the mean length of the short rows.
+// Tiles of the standalone product: runs of whole rows with at most
+// spmv_stream_tile_nnz() entries and spmv_stream_tile_rows() rows; a row
+// longer than that forms a tile of its own.  4 ints per tile: first row, end
+// row, first entry, end entry.
+std::vector<int32_t> stream_tiles(int64_t nrows, const int64_t* rp) {
+  const int64_t cap = spmv_stream_tile_nnz(), rcap = spmv_stream_tile_rows();
+  std::vector<int32_t> t;
+  int64_t i = 0;
+  while (i < nrows) {
+    const int64_t start = i;
+    if (rp[i + 1] - rp[i] > cap) {
+      ++i;
+    } else {
+      while (i < nrows && i - start < rcap && rp[i + 1] - rp[start] <= cap) ++i;
+    }
+    const int32_t q[4] = {(int32_t)start, (int32_t)i, (int32_t)rp[start], (int32_t)rp[i]};
+    t.insert(t.end(), q, q + 4);
+  }
+  return t;
+}
+
 HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp2, int gscale = 0) {
   HostPart P;
   auto len = [&](int64_t i) -> int64_t {
@@ -234,7 +255,6 @@ struct pdhcg_handle {
   hipStream_t stream = nullptr;
   pdhcg_settings s{};
   int nb = 0;                 // workgroups of the persistent kernels
-  int nb_spmv = 0;            // workgroups of the standalone product kernels
   double norm_A = 0.0, nb_inf = 0.0, nc_inf = 0.0, setup_s = 0.0, kkt_zero = 0.0;
   // device data
   int32_t *q_rowptr = nullptr, *q_col = nullptr, *a_rowptr = nullptr, *a_col = nullptr, *t_rowptr = nullptr,
@@ -253,7 +273,8 @@ struct pdhcg_handle {
   SolveParams* d_params = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   DevPart pn1, pcg, pm, pt;                // parts for the persistent kernels
-  DevPart sq, sa, st_;                     // parts for the standalone products
+  int32_t* stiles[3] = {nullptr, nullptr, nullptr};  // tiles of the standalone products (Q, A, A')
+  int32_t nstiles[3] = {0, 0, 0};
   std::vector<void*> allocs;
   std::vector<double> c_host;  // c, for relKKT(0, 0) when b changes
   std::vector<int64_t> qrp_h, arp_h, trp_h;  // host row pointers, for re-planning
@@ -421,14 +442,17 @@ int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) 
   const int64_t* arp = A.nrows ? A.rowptr.data() : nullptr;
   const int64_t* trp = A.nrows ? T.rowptr.data() : nullptr;
   if ((rc = plan_grid(h, nb, 0))) return rc;
-  // standalone products: enough workgroups to fill the chip
-  int nbs = 64;
-  const double w = (double)std::max<int64_t>(h->nnzQ, h->nnzA) + (double)std::max(h->n, h->m);
-  while (nbs < 8192 && w / nbs > 2048.0) nbs <<= 1;
-  h->nb_spmv = nbs;
-  if ((rc = upload_part(h, build_part(h->n, nbs, qrp, nullptr), h->sq))) return rc;
-  if ((rc = upload_part(h, build_part(h->m, nbs, arp, nullptr), h->sa))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nbs, trp, nullptr), h->st_))) return rc;
+  // standalone products: one short tile per workgroup
+  const int64_t* rps[3] = {qrp, arp, trp};
+  const int64_t nrs[3] = {h->n, h->m, h->n};
+  for (int k = 0; k < 3; ++k) {
+    if (!rps[k] || nrs[k] == 0) continue;
+    const std::vector<int32_t> t = stream_tiles(nrs[k], rps[k]);
+    h->nstiles[k] = (int32_t)(t.size() / 4);
+    if ((rc = h->alloc(&h->stiles[k], (int64_t)t.size()))) return rc;
+    HIPX(hipMemcpyAsync(h->stiles[k], t.data(), sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, h->stream));
+  }
+  HIPX(hipStreamSynchronize(h->stream));
   return 0;
 }
 
@@ -710,14 +734,14 @@ int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* 
   if (precision == 1 && (rc = ensure_mixed(h))) return rc;
   const DevMat M = h->mat(which);
   if (M.nrows == 0) return 0;
-  const DevPart& pt = which == 0 ? h->sq : (which == 1 ? h->sa : h->st_);
   float* x32 = nullptr;
   if (precision == 1) {
     x32 = h->xs32;  // scratch FP32 copy of x
     HIPX(launch_to_f32(x, x32, M.ncols, h->stream));
   }
   for (int r = 0; r < std::max(repeats, 1); ++r)
-    HIPX(launch_spmv(M, pt.view(), h->nb_spmv, precision, x, x32, y, h->stream));
+    HIPX(launch_spmv_stream(M.rowptr, M.col, M.val, M.val32, precision, x, x32, y, h->stiles[which],
+                            h->nstiles[which], h->stream));
   HIPX(hipStreamSynchronize(h->stream));
   return 0;
 }

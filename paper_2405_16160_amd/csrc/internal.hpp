@@ -184,8 +184,12 @@ hipError_t launch_batch(const BatchParams& p, int count, hipStream_t s);
 hipError_t launch_solve(const SolveParams* p_dev, int nb, hipStream_t s);
 hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s);
 hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hipStream_t s);
-hipError_t launch_spmv(const DevMat& M, const Part& pt, int nb, int precision, const double* x, float* x32,
-                       double* y, hipStream_t s);
+// standalone product y = M x over host-cut tiles (spmv_kernels.hip)
+hipError_t launch_spmv_stream(const int32_t* rowptr, const int32_t* col, const double* val, const float* val32,
+                              int precision, const double* x, const float* x32, double* y, const int32_t* tiles,
+                              int ntiles, hipStream_t s);
+int spmv_stream_tile_nnz();
+int spmv_stream_tile_rows();
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 // workgroups per CU that the persistent kernels can keep resident (the
 // smaller of the solve and power kernels)

@@ -1167,22 +1167,6 @@ __global__ void init_point_kernel(const SolveParams* __restrict__ Pg) {
   if (blockIdx.x == 0 && threadIdx.x == 0) P.st->t_start = wall_clock64();
 }
 
-template <typename V, typename T>
-__global__ void __launch_bounds__(kBlock) spmv_kernel(DevMat M, Part pt, const V* val, const T* x, double* y) {
-  __shared__ double lds[kWaves * 4];
-  const int b = blockIdx.x, tid = threadIdx.x;
-  GatherVec<T> gx{x};
-  for (int t = pt.tile_ptr[b]; t < pt.tile_ptr[b + 1]; ++t)
-    tile_rows(M.rowptr, M.col, val, pt.tiles + 6 * t, pt.group, gx, [&](int i, double v) { y[i] = v; });
-  for (int t = pt.long_ptr[b]; t < pt.long_ptr[b + 1]; ++t) {
-    const int i = pt.long_rows[t];
-    double v[1] = {row_partial(M.col, val, M.rowptr[i], M.rowptr[i + 1], tid, kBlock, gx)};
-    double dummy[1] = {0.0};
-    block_reduce<1, 0>(v, dummy, lds);
-    if (tid == 0) y[i] = v[0];
-  }
-}
-
 __global__ void to_f32_kernel(const double* in, float* out, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride) out[j] = (float)in[j];
@@ -1214,17 +1198,6 @@ hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hip
   if (grid < 1) grid = 1;
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(init_point_kernel, dim3(grid), dim3(kBlock), 0, s, p_dev);
-  return hipGetLastError();
-}
-
-hipError_t launch_spmv(const DevMat& M, const Part& pt, int nb, int precision, const double* x, float* x32,
-                       double* y, hipStream_t s) {
-  if (precision == 1) {
-    hipLaunchKernelGGL((spmv_kernel<float, float>), dim3(nb), dim3(kBlock), 0, s, M, pt, M.val32,
-                       (const float*)x32, y);
-  } else {
-    hipLaunchKernelGGL((spmv_kernel<double, double>), dim3(nb), dim3(kBlock), 0, s, M, pt, M.val, x, y);
-  }
   return hipGetLastError();
 }
 
