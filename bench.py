@@ -128,10 +128,10 @@ def workload():
     return I.random_qp(100_000, 50_000, 50_000, 2e-5, 2e-4, family=2, instance=0)
 
 
-def csr_bytes(nnz, nrows, ncols, sv, sx):
+def csr_bytes(nnz, nrows, ncols, sv, sx, sy=None):
     """Compulsory bytes of y = M x: matrix once (values + int32 columns +
-    int32 row pointers), x once, y once."""
-    return nnz * (sv + 4) + 4 * (nrows + 1) + ncols * sx + nrows * sx
+    int32 row pointers), x once (sx bytes per entry), y once (sy, default sx)."""
+    return nnz * (sv + 4) + 4 * (nrows + 1) + ncols * sx + nrows * (sx if sy is None else sy)
 
 
 def solve_bytes(qp, r, precision):
@@ -182,8 +182,8 @@ def spmv_rates(solver, qp, precisions=(0, 1), reps=50):
             e1.record()
             torch.cuda.synchronize()
             us = e0.elapsed_time(e1) * 1e3 / reps
-            sv = 4 if prec else 8
-            gbs = csr_bytes(nnz, nr, nc, sv, 8) / (us * 1e-6) / 1e9
+            sv = 4 if prec else 8   # FP32 mode gathers an FP32 copy of x; y is FP64 either way
+            gbs = csr_bytes(nnz, nr, nc, sv, sv, 8) / (us * 1e-6) / 1e9
             out[f"spmv_{name}_{'fp32' if prec else 'fp64'}"] = {"us": us, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
     return out
 
@@ -211,6 +211,27 @@ def bench_tiny(args):
             "geomean_ms": g * 1e3, "QPs/s": 1 / g, "iters": iters, "plan": plan}
 
 
+def local_columns_rates(qp):
+    """The power-law A with the same row lengths but each row's columns a
+    contiguous block near its diagonal position (gathers coalesce and x stays
+    in cache): separates the product's streaming rate from the cost of the
+    random gathers of the benchmark matrix."""
+    from paper_2405_16160_amd import instances as I, pdhcg
+    m, n = qp.A.nrows, qp.A.ncols
+    lens = np.diff(qp.A.rowptr)
+    centre = (np.arange(m, dtype=np.int64) * n) // m
+    start = np.clip(centre - lens // 2, 0, n - lens)
+    rowptr = qp.A.rowptr.astype(np.int64)
+    col = (np.repeat(start, lens) + (np.arange(rowptr[-1]) - np.repeat(rowptr[:-1], lens))).astype(np.int32)
+    A = I.CSR(m, n, rowptr, col, qp.A.val.copy())
+    Qd = I.CSR(n, n, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), np.ones(n))
+    loc = I.QP(Qd, A, qp.b, qp.c)
+    sol = pdhcg.Solver(loc, pdhcg.Settings(precision=1))
+    r = spmv_rates(sol, loc)
+    sol.close()
+    return {k: v for k, v in r.items() if not k.startswith("spmv_Q")}
+
+
 def bench_powerlaw(args):
     """n = 2e6, m = 1e6 power-law QP: standalone products and a fixed number
     of solve iterations (bandwidth of the phases; the family converges slowly
@@ -224,6 +245,7 @@ def bench_powerlaw(args):
     sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-12, precision=args.precision, max_iters=args.iters,
                                           num_blocks=args.num_blocks))
     rates = spmv_rates(sol, qp)
+    local = local_columns_rates(qp)
     sol.solve()
     torch.cuda.synchronize()
     _, _, r = sol.solve()
@@ -231,7 +253,7 @@ def bench_powerlaw(args):
     ach = bytes_alg / r["kernel_s"] / 1e9
     out = {"config": "power-law QP n=2e6 m=1e6 (A row lengths Pareto 1.5, mean 8, max 5000)",
            "nnz_Q": qp.Q.nnz, "nnz_A": qp.A.nnz, "A_row_max": int(lens.max()), "gen_s": gen_s,
-           "plan": sol.plan_info(), "spmv": rates,
+           "plan": sol.plan_info(), "spmv": rates, "spmv_local_columns": local,
            "solve_fixed_iters": {"iters": r["iters"], "cg_steps": r["cg_iters_total"], "kernel_ms": r["kernel_s"] * 1e3,
                                  "us_per_iter": r["kernel_s"] * 1e6 / max(r["iters"], 1), "rel_kkt": r["rel_kkt"],
                                  "GB/s": ach, "frac": ach / HBM_PEAK_GBS}}
@@ -431,25 +453,7 @@ def main():
     if traffic is not None:
         line["roofline"]["traffic_over_algorithmic"] = traffic / (bytes_alg / launches)
     if not args.no_extras:
-        extras = {}
-        rng = np.random.default_rng(0)
-        xn, xm = rng.standard_normal(qp.n), rng.standard_normal(qp.m)
-        for which, name, nnz, nr, nc, v in ((0, "Q", qp.Q.nnz, qp.n, qp.n, xn), (1, "A", qp.A.nnz, qp.m, qp.n, xn),
-                                            (2, "At", qp.A.nnz, qp.n, qp.m, xm)):
-            for prec in (0, 1):
-                reps = 200
-                solver.spmv(which, v, precision=prec, repeats=5)
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                solver.spmv(which, v, precision=prec, repeats=reps)
-                e1.record()
-                torch.cuda.synchronize()
-                us = e0.elapsed_time(e1) * 1e3 / reps
-                sv = sx = 4 if prec else 8
-                gbs = csr_bytes(nnz, nr, nc, sv, 8) / (us * 1e-6) / 1e9
-                extras[f"spmv_{name}_{'fp32' if prec else 'fp64'}"] = {"us": us, "GB/s": gbs,
-                                                                        "frac": gbs / HBM_PEAK_GBS}
+        extras = spmv_rates(solver, qp, reps=200)
         # in-run comparison: CG capped at one step (linearised primal step)
         s1 = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, num_blocks=args.num_blocks,
                             max_cg_iters=1, cg_rule=1, max_iters=200_000)

@@ -266,7 +266,7 @@ struct pdhcg_handle {
          *x_anc = nullptr, *y_anc = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   float *x32 = nullptr, *r32 = nullptr, *p32_0 = nullptr, *p32_1 = nullptr, *xs32 = nullptr;
   double *r_alt = nullptr, *u0 = nullptr, *u1 = nullptr, *s0 = nullptr, *s1 = nullptr;
-  float *r32_alt = nullptr, *u32_0 = nullptr, *u32_1 = nullptr, *s32_0 = nullptr, *s32_1 = nullptr;
+  float4 *v32_0 = nullptr, *v32_1 = nullptr;   // interleaved FP32 (r, u, s) of the one-reduction CG
   double *part = nullptr, *tmp_x0 = nullptr, *tmp_y0 = nullptr, *scratch = nullptr;
   uint64_t* bar = nullptr;
   SolverState* st = nullptr;
@@ -364,9 +364,8 @@ int ensure_mixed(pdhcg_handle* h) {
   if ((rc = h->alloc(&h->p32_0, h->n))) return rc;
   if ((rc = h->alloc(&h->p32_1, h->n))) return rc;
   if ((rc = h->alloc(&h->xs32, std::max(h->n, h->m)))) return rc;
-  float** f32v[] = {&h->r32_alt, &h->u32_0, &h->u32_1, &h->s32_0, &h->s32_1};
-  for (float** v : f32v)
-    if ((rc = h->alloc(v, h->n))) return rc;
+  if ((rc = h->alloc(&h->v32_0, h->n))) return rc;
+  if ((rc = h->alloc(&h->v32_1, h->n))) return rc;
   HIPX(launch_to_f32(h->q_val, h->q_val32, h->nnzQ, h->stream));
   if (h->nnzA > 0) {
     HIPX(launch_to_f32(h->a_val, h->a_val32, h->nnzA, h->stream));
@@ -469,7 +468,7 @@ SolveParams make_params(pdhcg_handle* h) {
   p.x_anc = h->x_anc; p.y_anc = h->y_anc; p.r = h->r; p.p0 = h->p0; p.p1 = h->p1; p.q = h->q;
   p.x32 = h->x32; p.r32 = h->r32; p.p32_0 = h->p32_0; p.p32_1 = h->p32_1;
   p.r_alt = h->r_alt; p.u0 = h->u0; p.u1 = h->u1; p.s0 = h->s0; p.s1 = h->s1;
-  p.r32_alt = h->r32_alt; p.u32_0 = h->u32_0; p.u32_1 = h->u32_1; p.s32_0 = h->s32_0; p.s32_1 = h->s32_1;
+  p.v32_0 = h->v32_0; p.v32_1 = h->v32_1;
   p.part = h->part;
   p.bar = h->bar;
   p.st = h->st;

@@ -200,6 +200,26 @@ __device__ __forceinline__ void gst(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// float4 rows move as one 16-byte access (through the clang vector type: the
+// HIP vector class has no constructors for address-space-qualified operands)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <>
+__device__ __forceinline__ float4 gld<float4>(const float4* p) {
+  const f32x4 v = *(const __attribute__((address_space(1))) f32x4*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <>
+__device__ __forceinline__ void gst<float4>(float4* p, float4 v) {
+  f32x4 w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  *(__attribute__((address_space(1))) f32x4*)p = w;
+}
+
 // sum_k M[i,k] * g(col[k]) for the entries [beg, end) of one row, computed by
 // `width` lanes starting at lane `lane` (partial sums; reduced by the caller)
 template <typename V, typename Gather>
@@ -240,6 +260,8 @@ struct TileLds {
   double sum2[kTileRows];
   int32_t rp[kTileRows + 1];
   int32_t rp2[kTileRows + 1];
+  int32_t wide[kTileRows];  // rows of the tile summed by a whole wave
+  int32_t nwide;
 };
 
 // the workgroup's single LDS staging area for tiles
@@ -319,6 +341,11 @@ __device__ __forceinline__ int tile_group(int G, int nr) {
   return g < G ? g : G;
 }
 
+// A row longer than this many entries per lane of its group is summed by a
+// whole wave instead (skewed tiles: one long row among many short ones)
+constexpr int kLaneEntries = 8;
+__device__ __forceinline__ int wide_row_len(int G) { return kLaneEntries * G > kWave ? kLaneEntries * G : kWave; }
+
 // sum of prod[k] for k = beg + lane, beg + lane + G, ... < end (two chains)
 __device__ __forceinline__ double lane_row_sum(const double* prod, int beg, int end, int lane, int G) {
   double a0 = 0.0, a1 = 0.0;
@@ -355,19 +382,33 @@ __device__ __forceinline__ void tile_rows_pf(const int32_t* rowptr, const int32_
 #pragma unroll
     for (int u = 0; u < kEpiRows; ++u) pv[u] = pre(ra + min(u * kBlock + (int)threadIdx.x, nr - 1));
   }
+  if (threadIdx.x == 0) L.nwide = 0;
   stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, z0, 0, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
   const int Gt = tile_group(G, nr);
-  const int lane = threadIdx.x & (Gt - 1), ng = kBlock / Gt;
+  const int lane = threadIdx.x & (Gt - 1), ng = kBlock / Gt, wlen = wide_row_len(Gt);
   for (int base = 0; base < nr; base += ng) {
     const int i = base + (int)threadIdx.x / Gt;
     const bool act = i < nr;
+    const bool wide = act && L.rp[i + 1] - L.rp[i] > wlen;
     double s = 0.0;
-    if (act) s = lane_row_sum(L.prod, L.rp[i], L.rp[i + 1], lane, Gt);
+    if (act && !wide) s = lane_row_sum(L.prod, L.rp[i], L.rp[i + 1], lane, Gt);
     s = group_sum_last(s, Gt);
-    if (act && lane == Gt - 1) L.sum1[i] = s;
+    if (act && !wide && lane == Gt - 1) L.sum1[i] = s;
+    if (wide && lane == 0) L.wide[atomicAdd(&L.nwide, 1)] = i;
   }
   __syncthreads();
+  const int nw = L.nwide;
+  if (nw > 0) {  // wide rows: one wave each
+    const int ln = threadIdx.x & (kWave - 1);
+    for (int j = (int)threadIdx.x / kWave; j < nw; j += kWaves) {
+      const int i = L.wide[j];
+      double s = lane_row_sum(L.prod, L.rp[i], L.rp[i + 1], ln, kWave);
+      s = group_sum_last(s, kWave);
+      if (ln == kWave - 1) L.sum1[i] = s;
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int u = 0; u < kEpiRows; ++u) {
     const int i = u * kBlock + (int)threadIdx.x;
@@ -398,26 +439,48 @@ __device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t
 #pragma unroll
     for (int u = 0; u < kEpiRows; ++u) pv[u] = pre(ra + min(u * kBlock + (int)threadIdx.x, nr - 1));
   }
+  if (threadIdx.x == 0) L.nwide = 0;
   stage_tile(rowptr1, col1, val1, g1, z0, nz, rowptr2, col2, val2, g2, w0, nw, ra, nr, L.rp, L.rp2, L.prod);
   __syncthreads();
   const int Gt = tile_group(G, nr);
-  const int lane = threadIdx.x & (Gt - 1), ng = kBlock / Gt;
+  const int lane = threadIdx.x & (Gt - 1), ng = kBlock / Gt, wlen = wide_row_len(Gt);
+  auto len1 = [&](int i) { return rowptr1 ? L.rp[i + 1] - L.rp[i] : 0; };
+  auto len2 = [&](int i) { return rowptr2 ? L.rp2[i + 1] - L.rp2[i] : 0; };
   for (int base = 0; base < nr; base += ng) {
     const int i = base + (int)threadIdx.x / Gt;
     const bool act = i < nr;
+    const bool wide = act && (len1(i) > wlen || len2(i) > wlen);
     double s1 = 0.0, s2 = 0.0;
-    if (act) {
+    if (act && !wide) {
       if (rowptr1) s1 = lane_row_sum(L.prod, L.rp[i], L.rp[i + 1], lane, Gt);
       if (rowptr2) s2 = lane_row_sum(L.prod, L.rp2[i], L.rp2[i + 1], lane, Gt);
     }
     s1 = group_sum_last(s1, Gt);
     s2 = group_sum_last(s2, Gt);
-    if (act && lane == Gt - 1) {
+    if (act && !wide && lane == Gt - 1) {
       L.sum1[i] = s1;
       L.sum2[i] = s2;
     }
+    if (wide && lane == 0) L.wide[atomicAdd(&L.nwide, 1)] = i;
   }
   __syncthreads();
+  const int nwr = L.nwide;
+  if (nwr > 0) {  // wide rows: one wave each
+    const int ln = threadIdx.x & (kWave - 1);
+    for (int j = (int)threadIdx.x / kWave; j < nwr; j += kWaves) {
+      const int i = L.wide[j];
+      double s1 = 0.0, s2 = 0.0;
+      if (rowptr1) s1 = lane_row_sum(L.prod, L.rp[i], L.rp[i + 1], ln, kWave);
+      if (rowptr2) s2 = lane_row_sum(L.prod, L.rp2[i], L.rp2[i + 1], ln, kWave);
+      s1 = group_sum_last(s1, kWave);
+      s2 = group_sum_last(s2, kWave);
+      if (ln == kWave - 1) {
+        L.sum1[i] = s1;
+        L.sum2[i] = s2;
+      }
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int u = 0; u < kEpiRows; ++u) {
     const int i = u * kBlock + (int)threadIdx.x;

@@ -127,9 +127,11 @@ struct SolveParams {
   // one-reduction CG (cooperative kernel): second r buffer, u = (Q + I/tau) r
   // and s = (Q + I/tau) p, double-buffered (null in the batched kernel)
   double *r_alt, *u0, *u1, *s0, *s1;
-  // FP32 copies used by the mixed-precision products
+  // FP32 copies used by the mixed-precision products; v32_0 / v32_1 hold
+  // (r, u, s) of the one-reduction CG interleaved per row (null in the
+  // batched kernel)
   float *x32, *r32, *p32_0, *p32_1;
-  float *r32_alt, *u32_0, *u32_1, *s32_0, *s32_1;
+  float4 *v32_0, *v32_1;
   double* part;         // [NSLOT][nb]
   uint64_t* bar;        // grid barrier words (zeroed before each launch)
   SolverState* st;

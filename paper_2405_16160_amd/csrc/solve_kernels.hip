@@ -103,7 +103,8 @@ __device__ __attribute__((noinline)) void dense_cg_spmv(const SolveParams& P, Bl
 // when r != null and stores the six n-side partials at slot0.
 template <bool DENSE>
 __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, const WgPart& pt, Block B, const double* xv,
-                            const double* yv, double* r, float* r32, int slot0, double* lds, double* svec) {
+                            const double* yv, double* r, float* r32, int r32_stride, int slot0, double* lds,
+                            double* svec) {
   // dense Q (one workgroup per QP): Q xv first, into the free CG buffer q
   constexpr bool dense = DENSE;
   if (dense) dense_qx(P, xv, svec);
@@ -119,7 +120,7 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
     const double g = qx + aty + rw.c;
     if (r) {
       gst(r + i, -g);
-      if (r32) gst(r32 + i, (float)(-g));
+      if (r32) gst(r32 + (int64_t)r32_stride * i, (float)(-g));
     }
     s[0] += g * g;
     s[1] += rw.x * qx;
@@ -204,7 +205,7 @@ __device__ __attribute__((noinline)) void phase_ax(const SolveParams& P, Block B
 // relKKT pieces of the average: n-side at (xa, ya), m-side u = A xa (kept in ax_avg)
 template <bool DENSE>
 __device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, Block B, double* lds, double* svec) {
-  phase_nside<DENSE>(P, P.w_n1, B, P.xa, P.ya, nullptr, nullptr, S_AVG0, lds, svec);
+  phase_nside<DENSE>(P, P.w_n1, B, P.xa, P.ya, nullptr, nullptr, 1, S_AVG0, lds, svec);
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(
       P, B, P.A.val, P.xa, lds, [&](int i) { return MRow{gld(P.b + i), 0.0, 0.0, gld(P.ya + i)}; },
@@ -303,31 +304,39 @@ struct GatherCG {
   }
 };
 
+// the same with the FP32 copies of (r, u, s) interleaved per row: one
+// 16-byte load per gathered column instead of three loads on three lines
+struct GatherCG4 {
+  const float4* v;
+  double alpha, beta;
+  int l;
+  __device__ __forceinline__ double operator()(int j) const {
+    const float4 q = gld(v + j);
+    const double rj = q.x, uj = q.y, sj = q.z;
+    const double s1 = l == 1 ? uj : uj + beta * sj;
+    return l == 0 ? rj : rj - alpha * s1;
+  }
+};
+
+// Buffers: r, u, s (FP64, and in mixed precision their FP32 copies
+// interleaved as float4 rows) alternate between two copies.  Step l reads
+// copy rd = (l == 0 ? 0 : 1 - l mod 2) and writes copy c = l mod 2: r_l and
+// u_l, and s_{l-1}, which step l + 1 reads as its s_{l-2}.  The n-side pass
+// leaves r_0 in copy 0; step 0 reads it there and adds u_0 (no step reads a
+// field another workgroup is writing in the same phase).
 template <typename V, typename T>
 __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block B, const V* qval, int l,
                                                      double alpha, double beta, double inv_tau, int product,
                                                      int mixed, double* lds) {
-  // buffers of step l: r, u and s alternate between two copies (c = l mod 2
-  // receives r_l, u_l and s_{l-2}'s successor); step 0 reads r_0 from the first
-  const int c = l & 1, o = c ^ 1;
-  const bool r_alt = o == 1 && l != 0;
-  struct {
-    const double *r_prev, *u_prev, *s_prev2;
-    double *r_new, *u_new, *s_prev1;
-    float *r32_new, *u32_new, *s32_prev1;
-  } cb = {r_alt ? P.r_alt : P.r, o ? P.u1 : P.u0, c ? P.s1 : P.s0,
-          c ? P.r_alt : P.r, c ? P.u1 : P.u0, o ? P.s1 : P.s0,
-          c ? P.r32_alt : P.r32, c ? P.u32_1 : P.u32_0, o ? P.s32_1 : P.s32_0};
-  const T *rg, *ug, *sg;  // the vectors gathered by the product (FP32 copies in mixed precision)
-  if constexpr (std::is_same<T, float>::value) {
-    rg = r_alt ? P.r32_alt : P.r32;
-    ug = o ? P.u32_1 : P.u32_0;
-    sg = c ? P.s32_1 : P.s32_0;
-  } else {
-    rg = cb.r_prev;
-    ug = cb.u_prev;
-    sg = cb.s_prev2;
-  }
+  const int c = l & 1;
+  const int rd = l == 0 ? 0 : c ^ 1;
+  const double* r_prev = rd ? P.r_alt : P.r;
+  const double* u_prev = rd ? P.u1 : P.u0;
+  const double* s_prev2 = rd ? P.s1 : P.s0;
+  double* r_new = c ? P.r_alt : P.r;
+  double* u_new = c ? P.u1 : P.u0;
+  double* s_prev1 = c ? P.s1 : P.s0;
+  float4* v_new = c ? P.v32_1 : P.v32_0;
   double s[2] = {0.0, 0.0};  // gamma_l, delta_l
   struct Row {
     double rp, up, sp, pp, xp;
@@ -335,24 +344,25 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
   // the owned-row inputs, loaded unconditionally (all buffers are valid;
   // values not used at this step are discarded by selects)
   auto pre = [&](int i) {
-    return Row{gld(cb.r_prev + i), gld(cb.u_prev + i), gld(cb.s_prev2 + i), gld(P.p0 + i), gld(P.x + i)};
+    return Row{gld(r_prev + i), gld(u_prev + i), gld(s_prev2 + i), gld(P.p0 + i), gld(P.x + i)};
   };
-  auto own = [&](int i, const Row& rw) -> double {  // owned-row updates; returns r_l[i]
+  struct Own {
+    double r, s;  // r_l[i] and s_{l-1}[i]
+  };
+  auto own = [&](int i, const Row& rw) -> Own {  // owned-row updates
     const double rp = rw.rp, up = rw.up, sp = rw.sp, pp = rw.pp, xp = rw.xp;
-    if (l == 0) return rp;
+    if (l == 0) return Own{rp, 0.0};
     const double s1 = l == 1 ? up : up + beta * sp;
     const double pi = l == 1 ? rp : rp + beta * pp;
     gst(P.p0 + i, pi);
     const double xi = xp + alpha * pi;
     gst(P.x + i, xi);
     if (mixed) gst(P.x32 + i, (float)xi);
-    if (!product) return 0.0;
-    gst(cb.s_prev1 + i, s1);
-    if (mixed) gst(cb.s32_prev1 + i, (float)s1);
+    if (!product) return Own{0.0, 0.0};
+    gst(s_prev1 + i, s1);
     const double ri = rp - alpha * s1;
-    gst(cb.r_new + i, ri);
-    if (mixed) gst(cb.r32_new + i, (float)ri);
-    return ri;
+    gst(r_new + i, ri);
+    return Own{ri, s1};
   };
   if (!product) {
     const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
@@ -360,23 +370,28 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
     return;
   }
   auto epi = [&](int i, double qr, const Row& rw) {
-    const double ri = own(i, rw);
-    const double ui = qr + ri * inv_tau;
-    gst(cb.u_new + i, ui);
-    if (mixed) gst(cb.u32_new + i, (float)ui);
-    s[0] += ri * ri;
-    s[1] += ri * ui;
+    const Own ow = own(i, rw);
+    const double ui = qr + ow.r * inv_tau;
+    gst(u_new + i, ui);
+    if (mixed) gst(v_new + i, make_float4((float)ow.r, (float)ui, (float)ow.s, 0.0f));
+    s[0] += ow.r * ow.r;
+    s[1] += ow.r * ui;
   };
   const WgPart& pt = P.w_cg;
-  GatherCG<T> g{rg, ug, sg, alpha, beta, l};
-  for (int t = pt.t0; t < pt.t1; ++t) tile_rows_pf(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, g, pre, epi);
-  for (int t = pt.l0; t < pt.l1; ++t) {
-    const int i = pt.long_rows[t];
-    double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, g)};
-    double dummy[1] = {0.0};
-    block_reduce<1, 0>(v, dummy, lds);
-    if (B.tid == 0) epi(i, v[0], pre(i));
-  }
+  auto run = [&](const auto& g) {
+    for (int t = pt.t0; t < pt.t1; ++t) tile_rows_pf(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, g, pre, epi);
+    for (int t = pt.l0; t < pt.l1; ++t) {
+      const int i = pt.long_rows[t];
+      double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, g)};
+      double dummy[1] = {0.0};
+      block_reduce<1, 0>(v, dummy, lds);
+      if (B.tid == 0) epi(i, v[0], pre(i));
+    }
+  };
+  if constexpr (std::is_same<T, float>::value)
+    run(GatherCG4{rd ? P.v32_1 : P.v32_0, alpha, beta, l});
+  else
+    run(GatherCG<double>{r_prev, u_prev, s_prev2, alpha, beta, l});
   double dummy[1] = {0.0};
   block_reduce<2, 0>(s, dummy, lds);
   if (B.tid == 0) {
@@ -839,7 +854,12 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         phase_ax(P, B, lds);
         break;
       case OP_NSIDE:
-        phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? P.r32 : nullptr, 0, lds, svec);
+        // r_0 in FP32 goes where the next product gathers it: the interleaved
+        // (r, u, s) rows of the single-reduction CG, or the plain copy
+        if (P.v32_0)
+          phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? (float*)P.v32_0 : nullptr, 4, 0, lds, svec);
+        else
+          phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? P.r32 : nullptr, 1, 0, lds, svec);
         if (B.tid == 0) {
           double f = 0.0;
           if (B.b == 0 && P.time_limit_ticks && wall_clock64() - C.S.t_start > P.time_limit_ticks) f = 1.0;

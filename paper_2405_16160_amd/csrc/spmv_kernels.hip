@@ -8,7 +8,8 @@
 // end entry.  A regular tile stages val * x[col] for all its entries in LDS
 // with one burst of loads (unconditional, indices clamped into the tile),
 // then sums each row with a group of lanes sized to the tile's row count
-// (data-parallel-primitive lane moves, no LDS shuffles).  A long tile is
+// (data-parallel-primitive lane moves, no LDS shuffles; a row far longer
+// than its group is summed by a whole wave instead).  A long tile is
 // summed by the whole workgroup in chunks.  Every row's sum is formed in a
 // fixed order, so results are bit-reproducible.
 #include "device.hpp"
@@ -43,6 +44,8 @@ __global__ void __launch_bounds__(kStreamBlock) spmv_stream_kernel(const int32_t
   __shared__ double prod[kStreamNnz];
   __shared__ int32_t rp[kStreamRows + 1];
   __shared__ double wsum[kStreamWaves];
+  __shared__ int32_t wide[kStreamRows];  // rows summed by a whole wave
+  __shared__ int32_t nwide;
   const int tid = threadIdx.x;
   const int32_t* t = tiles + 4 * blockIdx.x;
   const int r0 = t[0], nr = t[1] - t[0], e0 = t[2], ne = t[3] - t[2];
@@ -71,6 +74,7 @@ __global__ void __launch_bounds__(kStreamBlock) spmv_stream_kernel(const int32_t
     return;
   }
   // regular tile: row offsets and entries in one burst, then the gathers
+  if (tid == 0) nwide = 0;
   int rv[kStreamRowLoads];
 #pragma unroll
   for (int u = 0; u < kStreamRowLoads; ++u) rv[u] = gld(rowptr + r0 + min(u * kStreamBlock + tid, nr));
@@ -99,14 +103,25 @@ __global__ void __launch_bounds__(kStreamBlock) spmv_stream_kernel(const int32_t
   }
   __syncthreads();
   const int G = stream_group(nr > 0 ? (ne + nr - 1) / nr : 1, nr);
-  const int lane = tid & (G - 1), ng = kStreamBlock / G;
+  const int lane = tid & (G - 1), ng = kStreamBlock / G, wlen = wide_row_len(G);
   for (int base = 0; base < nr; base += ng) {
     const int i = base + tid / G;
     const bool act = i < nr;
+    const bool w = act && rp[i + 1] - rp[i] > wlen;
     double s = 0.0;
-    if (act) s = lane_row_sum(prod, rp[i], rp[i + 1], lane, G);
+    if (act && !w) s = lane_row_sum(prod, rp[i], rp[i + 1], lane, G);
     s = group_sum_last(s, G);
-    if (act && lane == G - 1) gst(y + r0 + i, s);
+    if (act && !w && lane == G - 1) gst(y + r0 + i, s);
+    if (w && lane == 0) wide[atomicAdd(&nwide, 1)] = i;
+  }
+  __syncthreads();
+  const int nw = nwide;
+  const int ln = tid & (kWave - 1);
+  for (int j = tid / kWave; j < nw; j += kStreamWaves) {  // wide rows: one wave each
+    const int i = wide[j];
+    double s = lane_row_sum(prod, rp[i], rp[i + 1], ln, kWave);
+    s = group_sum_last(s, kWave);
+    if (ln == kWave - 1) gst(y + r0 + i, s);
   }
 }
 
