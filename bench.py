@@ -261,17 +261,40 @@ def bench_powerlaw(args):
     return out
 
 
+def progress(msg):
+    """A progress line on stderr (long modes), so a watcher sees the run advance."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
 def bench_batch(args):
     """4096 portfolio QPs (n log-uniform in [50, 2000], dense Q = FF' + D) in one
     batched solve, against one-by-one solves of a stratified sample."""
+    import threading
     from paper_2405_16160_amd import instances as I, pdhcg
     t = time.perf_counter()
-    qps = [I.portfolio_qp(i) for i in range(args.batch_count)]
+    qps = []
+    for i in range(args.batch_count):
+        qps.append(I.portfolio_qp(i))
+        if (i + 1) % 256 == 0:
+            progress(f"generated {i + 1} portfolio QPs")
     gen_s = time.perf_counter() - t
     s = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=200_000)
     t = time.perf_counter()
-    out = pdhcg.solve_batch(qps, s)
+    done = threading.Event()
+
+    def ticker():   # the batched solve is one call; report that it is still running
+        while not done.wait(30.0):
+            progress(f"batched solve running ({time.perf_counter() - t:.0f} s)")
+
+    th = threading.Thread(target=ticker, daemon=True)
+    th.start()
+    try:
+        out = pdhcg.solve_batch(qps, s)
+    finally:
+        done.set()
+        th.join()
     wall = time.perf_counter() - t
+    progress(f"batched solve done in {wall:.1f} s; one-by-one sample")
     rs = [o[2] for o in out]
     ok = sum(r["status"] == 0 for r in rs)
     kernel_s = rs[0]["kernel_s"]
@@ -292,6 +315,7 @@ def bench_batch(args):
         _, _, r = sol.solve()
         single_s += w * r["solve_s"]
         sol.close()
+        progress(f"one-by-one instance {i} (n={qps[i].n}): {r['solve_s']:.3f} s")
     return {"config": f"batched portfolio QPs x{args.batch_count}, n log-uniform [50, 2000], dense Q, tol {args.tol:g}",
             "solved": ok, "batch_kernel_s": kernel_s, "batch_wall_s": wall, "setup_s": setup_s,
             "QPs/s_batched": args.batch_count / kernel_s, "gen_s": gen_s,
@@ -307,10 +331,13 @@ def bench_learned(args):
     from paper_2405_16160_amd import instances as I, pdhcg, warmstart as W
     fam = I.mpc_family()
     plus, minus = W.pair_index(fam)
+    progress(f"solving {args.train} training QPs")
     th, X, Y, rs, gen_solve_s = W.solve_family(fam, range(args.train), pdhcg.Settings(tol_rel_kkt=1e-6))
     Y = W.canonical_duals(Y, plus, minus)
     t_train = time.perf_counter()
-    ws, losses = W.train(th, X, Y, W.DualCode(fam.A.nrows, plus, minus), epochs=args.epochs)
+    progress("training")
+    ws, losses = W.train(th, X, Y, W.DualCode(fam.A.nrows, plus, minus), epochs=args.epochs,
+                         log=lambda m: progress(m) if int(m.split()[1].rstrip(":")) % 50 == 0 else None)
     train_s = time.perf_counter() - t_train
     ids = range(100_000, 100_000 + args.test)
     th_t, _ = W.family_qps(fam, ids)
