@@ -273,6 +273,8 @@ struct pdhcg_handle {
   SolveParams* d_params = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   DevPart pn1, pcg, pm, pt;                // parts for the persistent kernels
+  std::vector<int32_t> cg_bounds, m_bounds;          // host copies of the pcg / pm row ranges
+  int res_bytes = 0;                                 // dynamic LDS of the last solve launch
   int32_t* stiles[3] = {nullptr, nullptr, nullptr};  // tiles of the standalone products (Q, A, A')
   int32_t nstiles[3] = {0, 0, 0};
   std::vector<void*> allocs;
@@ -412,8 +414,12 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
   const int64_t* trp = h->m ? h->trp_h.data() : nullptr;
   for (DevPart* d : {&h->pn1, &h->pcg, &h->pm, &h->pt}) free_part(h, *d);
   if ((rc = upload_part(h, build_part(h->n, nb, qrp, trp, gscale), h->pn1))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nb, qrp, nullptr, gscale), h->pcg))) return rc;
-  if ((rc = upload_part(h, build_part(h->m, nb, arp, nullptr, gscale), h->pm))) return rc;
+  const HostPart pcg = build_part(h->n, nb, qrp, nullptr, gscale);
+  const HostPart pm = build_part(h->m, nb, arp, nullptr, gscale);
+  h->cg_bounds = pcg.bounds;
+  h->m_bounds = pm.bounds;
+  if ((rc = upload_part(h, pcg, h->pcg))) return rc;
+  if ((rc = upload_part(h, pm, h->pm))) return rc;
   if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr, gscale), h->pt))) return rc;
   return 0;
 }
@@ -452,6 +458,51 @@ int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) 
     HIPX(hipMemcpyAsync(h->stiles[k], t.data(), sizeof(int32_t) * t.size(), hipMemcpyHostToDevice, h->stream));
   }
   HIPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+// LDS residency of the CG rows of Q and the dual rows of A for this launch:
+// each is held when the largest workgroup block fits the LDS a workgroup can
+// have beside the kernel's static LDS with nb workgroups co-resident.
+int plan_residency(pdhcg_handle* h, SolveParams& p) {
+  p.res_cg = p.res_m = 0;
+  p.res_vbytes = h->s.precision == 1 ? 4 : 8;
+  p.res_m_off = 0;
+  h->res_bytes = 0;
+  int dev = 0, cus = 0, lds_cu = 0, stat = 0;
+  HIPX(hipGetDevice(&dev));
+  HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPX(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+  HIPX(solve_kernel_lds(&stat));
+  const int per_cu = (h->nb + cus - 1) / std::max(cus, 1);
+  const int64_t budget = (int64_t)lds_cu / std::max(per_cu, 1) - stat - 256;
+  auto block = [&](const std::vector<int32_t>& bnd, const std::vector<int64_t>& rp) {
+    int64_t best = 0;
+    for (size_t b = 0; b + 1 < bnd.size(); ++b)
+      best = std::max(best, res_block_bytes(bnd[b + 1] - bnd[b], rp[bnd[b + 1]] - rp[bnd[b]], p.res_vbytes));
+    return best;
+  };
+  const int64_t bq = block(h->cg_bounds, h->qrp_h);
+  const int64_t ba = h->m ? block(h->m_bounds, h->arp_h) : 0;
+  int64_t total = 0;
+  if (bq <= budget) {
+    p.res_cg = 1;
+    total = bq;
+  }
+  if (h->m && total + ba <= budget) {
+    p.res_m = 1;
+    p.res_m_off = (int32_t)total;
+    total += ba;
+  }
+  if (total > 0) {
+    int occ = 0;
+    HIPX(solve_occupancy_dyn((int)total, &occ));
+    if (occ * cus < h->nb) {  // would break co-residency: keep everything in device memory
+      p.res_cg = p.res_m = 0;
+      total = 0;
+    }
+  }
+  h->res_bytes = (int)total;
   return 0;
 }
 
@@ -667,6 +718,7 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
     dy0 = h->tmp_y0;
   }
   SolveParams p = make_params(h);
+  if ((rc = plan_residency(h, p))) return rc;
   p.x0 = dx0;
   p.y0 = dy0;
   p.kkt_zero = (h->s.warm_fallback && (dx0 || dy0)) ? h->kkt_zero : 0.0;
@@ -686,7 +738,7 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
   for (;;) {
     HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * 512, h->stream));
     HIPX(hipEventRecord(h->ev0, h->stream));
-    HIPX(launch_solve(h->d_params, h->nb, h->stream));
+    HIPX(launch_solve(h->d_params, h->nb, h->res_bytes, h->stream));
     HIPX(hipEventRecord(h->ev1, h->stream));
     HIPX(hipMemcpyAsync(&st, h->st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
     HIPX(hipStreamSynchronize(h->stream));

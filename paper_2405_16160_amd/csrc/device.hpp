@@ -366,14 +366,54 @@ struct NoPre {
   __device__ __forceinline__ int operator()(int) const { return 0; }
 };
 
+// Load through a pointer known to address LDS (ds_read rather than a flat load)
+template <typename T>
+__device__ __forceinline__ T lld(const T* p) {
+  return *(const __attribute__((address_space(3))) T*)p;
+}
+
+// Stage one tile of a single matrix whose rows of the workgroup are held in
+// LDS (lrp[j] = rowptr[roff + j]; lcol / lval hold the entries from eoff):
+// the same products as stage_tile, with only the gathers going to memory.
+template <typename V, typename G1>
+__device__ __forceinline__ void stage_tile_lds(const int32_t* lrp, int roff, const int32_t* lcol, const V* lval,
+                                               int eoff, const G1& g, int z0, int nz, int ra, int nr, int32_t* rp1,
+                                               double* prod) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int i = u * kBlock + tid;
+    if (i <= nr) rp1[i] = lld(lrp + ra + i - roff) - z0;
+  }
+  if (nz > 0) {
+    int c[kStageUnroll];
+    V v[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = z0 - eoff + min(u * kBlock + tid, nz - 1);
+      c[u] = lld(lcol + k);
+      v[u] = lld(lval + k);
+    }
+    double gv[kStageUnroll];
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) gv[u] = g(c[u]);
+#pragma unroll
+    for (int u = 0; u < kStageUnroll; ++u) {
+      const int k = u * kBlock + tid;
+      if (k < nz) prod[k] = (double)v[u] * gv[u];
+    }
+  }
+}
+
 // One tile of a single matrix.  pre(row) loads the row epilogue's own inputs
 // (rows of the tile, indices clamped into it) and is issued together with the
 // tile's staging loads, so those inputs cost no extra memory round trip.  Row
 // sums are formed by G-lane groups from the staged products and parked in LDS;
 // then epi(row, sum, pre(row)) runs with one thread per row.
-template <typename V, typename Gather, typename Pre, typename Epi>
-__device__ __forceinline__ void tile_rows_pf(const int32_t* rowptr, const int32_t* col, const V* val,
-                                             const int32_t* t, int G, const Gather& g, const Pre& pre, Epi epi) {
+// stage(L, ra, nr, z0, nz) fills L.rp and L.prod for the tile
+template <typename Stage, typename Pre, typename Epi>
+__device__ __forceinline__ void tile_rows_impl(const int32_t* t, int G, const Stage& stage, const Pre& pre,
+                                               Epi epi) {
   TileLds& L = tile_lds();
   const int ra = t[0], nr = t[1] - t[0], z0 = t[2], nz = t[3] - t[2];
   using PV = decltype(pre(0));
@@ -383,7 +423,7 @@ __device__ __forceinline__ void tile_rows_pf(const int32_t* rowptr, const int32_
     for (int u = 0; u < kEpiRows; ++u) pv[u] = pre(ra + min(u * kBlock + (int)threadIdx.x, nr - 1));
   }
   if (threadIdx.x == 0) L.nwide = 0;
-  stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, z0, 0, ra, nr, L.rp, L.rp2, L.prod);
+  stage(L, ra, nr, z0, nz);
   __syncthreads();
   const int Gt = tile_group(G, nr);
   const int lane = threadIdx.x & (Gt - 1), ng = kBlock / Gt, wlen = wide_row_len(Gt);
@@ -415,6 +455,31 @@ __device__ __forceinline__ void tile_rows_pf(const int32_t* rowptr, const int32_
     if (i < nr) epi(ra + i, L.sum1[i], pv[u]);
   }
   __syncthreads();
+}
+
+template <typename V, typename Gather, typename Pre, typename Epi>
+__device__ __forceinline__ void tile_rows_pf(const int32_t* rowptr, const int32_t* col, const V* val,
+                                             const int32_t* t, int G, const Gather& g, const Pre& pre, Epi epi) {
+  tile_rows_impl(
+      t, G,
+      [&](TileLds& L, int ra, int nr, int z0, int nz) {
+        stage_tile(rowptr, col, val, g, z0, nz, (const int32_t*)nullptr, col, val, g, z0, 0, ra, nr, L.rp, L.rp2,
+                   L.prod);
+      },
+      pre, epi);
+}
+
+// the same over the workgroup's rows held in LDS (see stage_tile_lds)
+template <typename V, typename Gather, typename Pre, typename Epi>
+__device__ __forceinline__ void tile_rows_res(const int32_t* lrp, int roff, const int32_t* lcol, const V* lval,
+                                              int eoff, const int32_t* t, int G, const Gather& g, const Pre& pre,
+                                              Epi epi) {
+  tile_rows_impl(
+      t, G,
+      [&](TileLds& L, int ra, int nr, int z0, int nz) {
+        stage_tile_lds(lrp, roff, lcol, lval, eoff, g, z0, nz, ra, nr, L.rp, L.prod);
+      },
+      pre, epi);
 }
 
 template <typename V, typename Gather, typename Epi>

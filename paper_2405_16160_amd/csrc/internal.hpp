@@ -46,6 +46,12 @@ struct Part {
   int32_t group;
 };
 
+// bytes of a workgroup's resident block: row pointers, columns, values (each 16-byte aligned)
+__host__ __device__ inline int64_t align16(int64_t b) { return (b + 15) & ~(int64_t)15; }
+__host__ __device__ inline int64_t res_block_bytes(int64_t nrows, int64_t ne, int vbytes) {
+  return align16(4 * (nrows + 1)) + align16(4 * ne) + align16((int64_t)vbytes * ne);
+}
+
 constexpr int kTileNnz = 4096;    // staged products per tile (FP64 in LDS)
 constexpr int kTileRows = 1024;   // rows per tile
 
@@ -54,9 +60,15 @@ constexpr int kTileRows = 1024;   // rows per tile
 // into tl), long rows long_rows[l0 .. l1-1].
 constexpr int kCacheTiles = 16;
 struct WgPart {
-  int32_t r0, r1, t0, t1, l0, l1, group, pad;
+  int32_t r0, r1, t0, t1, l0, l1, group;
+  int32_t e0;               // first entry of row r0 (resident block)
   const int32_t* tiles;
   const int32_t* long_rows;
+  // the workgroup's rows of the matrix held in LDS for the whole launch (null
+  // when not held): lrp[j] = rowptr[r0 + j], lcol / lval = entries from e0
+  const int32_t* lrp;
+  const int32_t* lcol;
+  const void* lval;
   int32_t tl[6 * kCacheTiles];
   __device__ __forceinline__ const int32_t* tile(int t) const {
     return t - t0 < kCacheTiles ? tl + 6 * (t - t0) : tiles + 6 * t;
@@ -139,6 +151,10 @@ struct SolveParams {
   // the executing workgroup's share of pn1, pcg, pm (filled in its LDS copy of
   // this block; unused in the copy in device memory)
   WgPart w_n1, w_cg, w_m;
+  // LDS residency of Q (CG product rows) and A (dual product rows) in the
+  // cooperative kernel: flags, value bytes (4: FP32 copies, 8: FP64), byte
+  // offset of the A block in dynamic LDS
+  int32_t res_cg, res_m, res_vbytes, res_m_off;
   double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf (enter every relKKT)
   double kkt_zero;        // relKKT(0, 0) when the warm-start fallback applies, else 0
   // start point of a batched solve (null: zero)
@@ -183,7 +199,11 @@ struct BatchParams {
 int set_error(int code, const char* msg);
 
 hipError_t launch_batch(const BatchParams& p, int count, hipStream_t s);
-hipError_t launch_solve(const SolveParams* p_dev, int nb, hipStream_t s);
+hipError_t launch_solve(const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s);
+// static LDS bytes of the solve kernel, and the co-resident workgroups per CU
+// it reaches with dyn_lds bytes of dynamic LDS
+hipError_t solve_kernel_lds(int* static_bytes);
+hipError_t solve_occupancy_dyn(int dyn_lds, int* per_cu);
 hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s);
 hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hipStream_t s);
 // standalone product y = M x over host-cut tiles (spmv_kernels.hip)

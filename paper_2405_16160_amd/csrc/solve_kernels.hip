@@ -164,7 +164,13 @@ __device__ void mside_rows(const SolveParams& P, Block B, const V* aval, const T
                            const Pre& pre, Epi epi) {
   const WgPart& pt = P.w_m;
   GatherVec<Tx> gx{xg};
-  for (int t = pt.t0; t < pt.t1; ++t) tile_rows_pf(P.A.rowptr, P.A.col, aval, pt.tile(t), pt.group, gx, pre, epi);
+  const bool res = pt.lcol != nullptr && (int)sizeof(V) == P.res_vbytes;  // rows of A held in LDS
+  for (int t = pt.t0; t < pt.t1; ++t) {
+    if (res)
+      tile_rows_res(pt.lrp, pt.r0, pt.lcol, (const V*)pt.lval, pt.e0, pt.tile(t), pt.group, gx, pre, epi);
+    else
+      tile_rows_pf(P.A.rowptr, P.A.col, aval, pt.tile(t), pt.group, gx, pre, epi);
+  }
   for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[1] = {row_partial(P.A.col, aval, P.A.rowptr[i], P.A.rowptr[i + 1], B.tid, kBlock, gx)};
@@ -378,8 +384,14 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
     s[1] += ow.r * ui;
   };
   const WgPart& pt = P.w_cg;
+  const bool res = pt.lcol != nullptr && (int)sizeof(V) == P.res_vbytes;  // rows of Q held in LDS
   auto run = [&](const auto& g) {
-    for (int t = pt.t0; t < pt.t1; ++t) tile_rows_pf(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, g, pre, epi);
+    for (int t = pt.t0; t < pt.t1; ++t) {
+      if (res)
+        tile_rows_res(pt.lrp, pt.r0, pt.lcol, (const V*)pt.lval, pt.e0, pt.tile(t), pt.group, g, pre, epi);
+      else
+        tile_rows_pf(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, g, pre, epi);
+    }
     for (int t = pt.l0; t < pt.l1; ++t) {
       const int i = pt.long_rows[t];
       double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, g)};
@@ -979,6 +991,10 @@ __device__ void fill_wg_part(WgPart& w, const Part& p, int b) {
     w.group = p.group;
     w.tiles = p.tiles;
     w.long_rows = p.long_rows;
+    w.e0 = 0;
+    w.lrp = nullptr;
+    w.lcol = nullptr;
+    w.lval = nullptr;
   }
   const int nt = t1 - t0 < kCacheTiles ? t1 - t0 : kCacheTiles;
   for (int k = threadIdx.x; k < 6 * nt; k += kBlock) w.tl[k] = p.tiles[6 * t0 + k];
@@ -1000,9 +1016,35 @@ __device__ void load_params(SolveParams& Ps, const SolveParams* Pg, int b) {
   __syncthreads();
 }
 
+// Copy the workgroup's rows of M (row pointers, columns, values of vbytes)
+// into its resident block at base and record the block in w.
+__device__ void place_resident(WgPart& w, const DevMat& M, char* base, int vbytes) {
+  const int nr = w.r1 - w.r0;
+  const int e0 = M.rowptr[w.r0], ne = M.rowptr[w.r1] - e0;
+  int32_t* lrp = (int32_t*)base;
+  int32_t* lcol = (int32_t*)(base + align16(4 * (int64_t)(nr + 1)));
+  char* lval = (char*)lcol + align16(4 * (int64_t)ne);
+  for (int j = threadIdx.x; j <= nr; j += kBlock) lrp[j] = gld(M.rowptr + w.r0 + j);
+  for (int k = threadIdx.x; k < ne; k += kBlock) lcol[k] = gld(M.col + e0 + k);
+  if (vbytes == 4)
+    for (int k = threadIdx.x; k < ne; k += kBlock) ((float*)lval)[k] = gld(M.val32 + e0 + k);
+  else
+    for (int k = threadIdx.x; k < ne; k += kBlock) ((double*)lval)[k] = gld(M.val + e0 + k);
+  if (threadIdx.x == 0) {
+    w.e0 = e0;
+    w.lrp = lrp;
+    w.lcol = lcol;
+    w.lval = lval;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
   __shared__ SolveParams Ps;
+  extern __shared__ __align__(16) char dyn_lds[];
   load_params(Ps, Pg, (int)blockIdx.x);
+  if (Ps.res_cg) place_resident(Ps.w_cg, Ps.Q, dyn_lds, Ps.res_vbytes);
+  if (Ps.res_m) place_resident(Ps.w_m, Ps.A, dyn_lds + Ps.res_m_off, Ps.res_vbytes);
+  __syncthreads();
   const SolveParams& P = Ps;
   const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
   __shared__ double lds[kWaves * 16];
@@ -1194,10 +1236,33 @@ __global__ void to_f32_kernel(const double* in, float* out, int64_t n) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_solve(const SolveParams* p_dev, int nb, hipStream_t s) {
+hipError_t launch_solve(const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s) {
   const SolveParams* pc = p_dev;
   void* args[] = {&pc};
-  return hipLaunchCooperativeKernel((const void*)pdhcg_solve_kernel, dim3(nb), dim3(kBlock), args, 0, s);
+  if (dyn_lds > 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)pdhcg_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       dyn_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipLaunchCooperativeKernel((const void*)pdhcg_solve_kernel, dim3(nb), dim3(kBlock), args,
+                                    (unsigned)dyn_lds, s);
+}
+
+hipError_t solve_kernel_lds(int* static_bytes) {
+  hipFuncAttributes a;
+  hipError_t e = hipFuncGetAttributes(&a, (const void*)pdhcg_solve_kernel);
+  if (e != hipSuccess) return e;
+  *static_bytes = (int)a.sharedSizeBytes;
+  return hipSuccess;
+}
+
+hipError_t solve_occupancy_dyn(int dyn_lds, int* per_cu) {
+  if (dyn_lds > 0) {
+    hipError_t e = hipFuncSetAttribute((const void*)pdhcg_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       dyn_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)pdhcg_solve_kernel, kBlock, dyn_lds);
 }
 
 hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s) {
