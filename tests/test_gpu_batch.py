@@ -98,3 +98,27 @@ def test_batch_mixed_precision_and_per_instance_status():
             continue
         assert r["status"] == 0
         assert O.kkt(qp, x, y)["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+
+
+def test_batch_portfolio_maximum_size():
+    """A batch holding the largest portfolio size of the configuration (n = 2000,
+    a 4e6-entry dense Q) beside small ones: each instance meets the relKKT test
+    recomputed in FP64 by the oracle, y >= 0, and the batched solve of the
+    largest instance agrees with its single-QP solve."""
+    say("[batch max] n = 2000 with 3 small instances")
+    qps = [I.portfolio_qp(900, n=2000)] + [I.portfolio_qp(i, nmax=120) for i in range(3)]
+    s = pdhcg.Settings(tol_rel_kkt=1e-5, precision=1, max_iters=200_000)
+    out = pdhcg.solve_batch(qps, s)
+    for qp, (x, y, r) in zip(qps, out):
+        assert r["status"] == 0, r
+        k = O.kkt(qp, x, y)
+        assert k["rel_kkt"] <= 1e-5 * (1 + 1e-6), k
+        assert np.all(y >= 0)
+    sol = pdhcg.Solver(qps[0], s)
+    xs, ys, rs = sol.solve()
+    sol.close()
+    xb = out[0][0]
+    xs = xs.cpu().numpy()
+    say(f"  n=2000: batch {out[0][2]['iters']} iters, single {rs['iters']} iters, "
+        f"|x_b - x_s|/|x_s| = {np.linalg.norm(xb - xs) / np.linalg.norm(xs):.2e}")
+    assert np.linalg.norm(xb - xs) / np.linalg.norm(xs) <= 5e-3   # both within relKKT 1e-5 of x*

@@ -274,3 +274,38 @@ def test_autotune_then_solve():
     assert r["status"] == 0
     check_contract(qp, x.cpu().numpy(), y.cpu().numpy(), ref)
     sol.close()
+
+
+# ----------------------------------------------- full-size power-law (2e6 x 1e6)
+
+def test_powerlaw_full_size_products_and_solve_properties():
+    """The power-law configuration at its full size, in the launch configuration
+    the benchmark uses (default plan, FP32 products): every product against the
+    oracle's FP64 matvec, element by element; a fixed-iteration solve (the
+    oracle cannot finish one at this size) checked by properties that hold at
+    any size: the reported relKKT equals the oracle's FP64 recomputation at
+    the returned point, y >= 0, and a second run is bit-identical."""
+    say("[powerlaw full] n=2e6 m=1e6")
+    qp = I.powerlaw_qp(2_000_000, 1_000_000, family=3, instance=0)
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-12, precision=1, max_iters=40))
+    rng = np.random.default_rng(11)
+    xn, xm = rng.standard_normal(qp.n), rng.standard_normal(qp.m)
+    At = I.CSR.from_scipy(qp.A.to_scipy().T)
+    for which, M, v in ((0, qp.Q, xn), (1, qp.A, xn), (2, At, xm)):
+        ref = O.matvec(M, v)
+        scale = O.matvec(I.CSR(M.nrows, M.ncols, M.rowptr, M.col, np.abs(M.val)), np.abs(v)) + 1e-300
+        err = np.max(np.abs(sol.spmv(which, v).cpu().numpy() - ref) / scale)
+        err32 = np.max(np.abs(sol.spmv(which, v, precision=1).cpu().numpy() - ref) / scale)
+        say(f"  which={which} fp64 {err:.2e} fp32 {err32:.2e}")
+        assert err <= 1e-14
+        assert err32 <= 2 * 2.0 ** -24 * 1.01
+    x1, y1, r1 = sol.solve()
+    x1, y1 = x1.cpu().numpy(), y1.cpu().numpy()
+    say(f"  40 iterations: relKKT {r1['rel_kkt']:.4e} status {r1['status']}")
+    assert r1["status"] == 1 and r1["iters"] == 40
+    k = O.kkt(qp, x1, y1)
+    assert np.all(y1 >= 0)
+    assert abs(k["rel_kkt"] - r1["rel_kkt"]) <= 1e-9 * max(k["rel_kkt"], 1e-300), (k["rel_kkt"], r1["rel_kkt"])
+    x2, y2, r2 = sol.solve()
+    assert np.array_equal(x1, x2.cpu().numpy()) and np.array_equal(y1, y2.cpu().numpy())
+    sol.close()
