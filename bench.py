@@ -134,7 +134,7 @@ def csr_bytes(nnz, nrows, ncols, sv, sx, sy=None):
     return nnz * (sv + 4) + 4 * (nrows + 1) + ncols * sx + nrows * (sx if sy is None else sy)
 
 
-def solve_bytes(qp, r, precision):
+def solve_bytes(qp, r, precision, dense_q=False):
     """Algorithmic HBM bytes of one solve, from the counts the solver reports.
     Per iteration: the n-side pass [Q|A'][x;y] in FP64 (r0 and relKKT), the
     dual step y = proj(y + sigma(A(2x+ - x) - b)) with its vectors, and the
@@ -144,6 +144,13 @@ def solve_bytes(qp, r, precision):
     n, m = qp.n, qp.m
     nq, na = qp.Q.nnz, qp.A.nnz
     sv = sx = 4 if precision == 1 else 8
+    if dense_q:   # a dense Q is stored as n x n values without indices: count it as such
+        nq_b64, nq_bv = n * n * 8, n * n * sv
+        a1 = nq_b64 + na * 12 + 4 * (n + 1) + (n + m) * 8 + 2 * n * 8
+        cg = nq_bv + 11 * n * sx
+        ev = nq_b64 + na * 12 + 4 * (n + 1) + (n + m) * 8 + n * 8 + csr_bytes(na, m, n, 8, 8) + 2 * m * 8
+        dual = csr_bytes(na, m, n, sv, sx) - m * sx + 7 * m * 8 + 3 * n * 8
+        return r["iters"] * (a1 + dual) + r["cg_iters_total"] * cg + r["kkt_evals"] * ev
     a1 = (nq + na) * 12 + 8 * (n + 1) + (n + m) * 8 + 2 * n * 8           # matrices, x, y, c, r
     dual = csr_bytes(na, m, n, sv, sx) - m * sx + 7 * m * 8 + 3 * n * 8   # + y, ax, b, ya (r/w); xa update
     cg = nq * (sv + 4) + 4 * (n + 1) + 11 * n * sx
@@ -316,8 +323,12 @@ def bench_batch(args):
         single_s += w * r["solve_s"]
         sol.close()
         progress(f"one-by-one instance {i} (n={qps[i].n}): {r['solve_s']:.3f} s")
+    alg = sum(solve_bytes(q, r, args.precision, dense_q=True) for q, r in zip(qps, rs))
     return {"config": f"batched portfolio QPs x{args.batch_count}, n log-uniform [50, 2000], dense Q, tol {args.tol:g}",
             "solved": ok, "batch_kernel_s": kernel_s, "batch_wall_s": wall, "setup_s": setup_s,
+            "roofline": {"kernel": "pdhcg_batch_kernel", "bound": "hbm", "algorithmic_bytes": alg,
+                         "achieved": alg / kernel_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / kernel_s / 1e9 / HBM_PEAK_GBS},
             "QPs/s_batched": args.batch_count / kernel_s, "gen_s": gen_s,
             "iters_mean": float(np.mean([r["iters"] for r in rs])),
             "one_by_one_estimated_s": single_s, "QPs/s_one_by_one": args.batch_count / single_s,

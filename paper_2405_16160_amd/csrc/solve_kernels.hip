@@ -29,42 +29,60 @@ __device__ __forceinline__ double pos_part(double v) { return v > 0.0 ? v : (v =
 // M[i0.., j]) with unit stride across threads, and v_j is broadcast from an
 // LDS tile.  No cross-lane reduction is needed.  gen(j) produces v_j (FP64)
 // and is called once per j per row pass; epi(i, sum) receives each row.
+// One pass of a dense product over rows i0 + tid + k * kBlock, k < K (rows
+// clamped into range: surplus rows are computed and dropped, so every load
+// is unconditional and kJ * K of them are in flight per thread).
+template <int K, typename V, typename Gen>
+__device__ __forceinline__ void dense_pass(const V* M, int n, int i0, double* svec, Gen& gen, double* acc) {
+  constexpr int kJ = 8;  // columns per unrolled step
+  int ic[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc[k] = 0.0;
+    ic[k] = min(i0 + (int)threadIdx.x + k * kBlock, n - 1);
+  }
+  for (int j0 = 0; j0 < n; j0 += kDenseTile) {
+    const int jt = n - j0 < kDenseTile ? n - j0 : kDenseTile;
+    __syncthreads();
+    for (int j = threadIdx.x; j < jt; j += kBlock) svec[j] = gen(j0 + j, i0 == 0);
+    __syncthreads();
+    const V* base = M + (int64_t)j0 * n;
+    int j = 0;
+    for (; j + kJ <= jt; j += kJ) {
+      V v[kJ][K];
+#pragma unroll
+      for (int jj = 0; jj < kJ; ++jj)
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[jj][k] = gld(base + (int64_t)(j + jj) * n + ic[k]);
+#pragma unroll
+      for (int jj = 0; jj < kJ; ++jj) {
+        const double sj = svec[j + jj];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += (double)v[jj][k] * sj;
+      }
+    }
+    for (; j < jt; ++j) {
+      const double sj = svec[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[k] += (double)gld(base + (int64_t)j * n + ic[k]) * sj;
+    }
+  }
+}
+
 template <typename V, typename Gen, typename Epi>
 __device__ void dense_rows(const V* M, int n, double* svec, Gen gen, Epi epi) {
   for (int i0 = 0; i0 < n; i0 += kBlock * kDenseRows) {
     double acc[kDenseRows];
-#pragma unroll
-    for (int k = 0; k < kDenseRows; ++k) acc[k] = 0.0;
-    for (int j0 = 0; j0 < n; j0 += kDenseTile) {
-      const int jt = n - j0 < kDenseTile ? n - j0 : kDenseTile;
-      __syncthreads();
-      for (int j = threadIdx.x; j < jt; j += kBlock) svec[j] = gen(j0 + j, i0 == 0);
-      __syncthreads();
-      const V* row = M + (int64_t)j0 * n + i0 + threadIdx.x;
-      int j = 0;
-      for (; j + 4 <= jt; j += 4, row += 4 * (int64_t)n) {
-#pragma unroll
-        for (int k = 0; k < kDenseRows; ++k) {
-          const int i = i0 + threadIdx.x + k * kBlock;
-          if (i < n) {
-            acc[k] += ldv(row, k * kBlock) * svec[j] + ldv(row + n, k * kBlock) * svec[j + 1] +
-                      ldv(row + 2 * (int64_t)n, k * kBlock) * svec[j + 2] +
-                      ldv(row + 3 * (int64_t)n, k * kBlock) * svec[j + 3];
-          }
-        }
-      }
-      for (; j < jt; ++j, row += n) {
-#pragma unroll
-        for (int k = 0; k < kDenseRows; ++k) {
-          const int i = i0 + threadIdx.x + k * kBlock;
-          if (i < n) acc[k] += ldv(row, k * kBlock) * svec[j];
-        }
-      }
-    }
+    const int rows = n - i0;
+    const int K = rows > 3 * kBlock ? 4 : (rows > 2 * kBlock ? 3 : (rows > kBlock ? 2 : 1));  // uniform
+    if (K == 4) dense_pass<4>(M, n, i0, svec, gen, acc);
+    else if (K == 3) dense_pass<3>(M, n, i0, svec, gen, acc);
+    else if (K == 2) dense_pass<2>(M, n, i0, svec, gen, acc);
+    else dense_pass<1>(M, n, i0, svec, gen, acc);
 #pragma unroll
     for (int k = 0; k < kDenseRows; ++k) {
-      const int i = i0 + threadIdx.x + k * kBlock;
-      if (i < n) epi(i, acc[k]);
+      const int i = i0 + (int)threadIdx.x + k * kBlock;
+      if (k < K && i < n) epi(i, acc[k]);
     }
   }
   __syncthreads();
