@@ -222,11 +222,30 @@ __device__ __forceinline__ void gst<float4>(float4* p, float4 v) {
 
 // sum_k M[i,k] * g(col[k]) for the entries [beg, end) of one row, computed by
 // `width` lanes starting at lane `lane` (partial sums; reduced by the caller)
+// Loads go in batches of 8 per lane, unconditional (indices clamped into the
+// row): 8 index/value loads, then 8 gathers, instead of one dependent pair at
+// a time.
 template <typename V, typename Gather>
 __device__ __forceinline__ double row_partial(const int32_t* col, const V* val, int beg, int end, int lane,
                                               int width, const Gather& g) {
+  constexpr int U = 8;
   double s = 0.0;
-  for (int k = beg + lane; k < end; k += width) s += ldv(val, k) * g(col[k]);
+  for (int base = beg + lane; base < end; base += U * width) {
+    int c[U];
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = min(base + u * width, end - 1);
+      c[u] = gld(col + k);
+      v[u] = gld(val + k);
+    }
+    double gv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) gv[u] = g(c[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (base + u * width < end) s += (double)v[u] * gv[u];
+  }
   return s;
 }
 
