@@ -343,7 +343,8 @@ def bench_learned(args):
     fam = I.mpc_family()
     plus, minus = W.pair_index(fam)
     progress(f"solving {args.train} training QPs")
-    th, X, Y, rs, gen_solve_s = W.solve_family(fam, range(args.train), pdhcg.Settings(tol_rel_kkt=1e-6))
+    th, X, Y, rs, gen_solve_s = W.solve_family(fam, range(args.train), pdhcg.Settings(tol_rel_kkt=1e-6),
+                                               log=progress)
     Y = W.canonical_duals(Y, plus, minus)
     t_train = time.perf_counter()
     progress("training")

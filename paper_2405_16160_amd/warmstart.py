@@ -54,10 +54,11 @@ def family_qps(fam: I.MPCFamily, ids):
     return thetas, qps
 
 
-def solve_family(fam, ids, settings: _pd.Settings, x0s=None, y0s=None, chunk=8192):
+def solve_family(fam, ids, settings: _pd.Settings, x0s=None, y0s=None, chunk=8192, log=None):
     """Batched PDHCG solves of the family members `ids` (chunks of `chunk`);
     returns (theta, x, y, results, seconds) where seconds is the device time
-    of the batched solve kernels (HIP events), packing excluded."""
+    of the batched solve kernels (HIP events), packing excluded.  log(msg), if
+    given, is called after each chunk."""
     thetas, qps = family_qps(fam, ids)
     xs, ys, rs = [], [], []
     secs = 0.0
@@ -70,6 +71,8 @@ def solve_family(fam, ids, settings: _pd.Settings, x0s=None, y0s=None, chunk=819
         ys += [o[1] for o in out]
         rs += [o[2] for o in out]
         secs += out[0][2]["kernel_s"]
+        if log:
+            log(f"solved {a + len(part)} of {len(qps)}")
     return thetas, np.stack(xs), np.stack(ys), rs, secs
 
 
