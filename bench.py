@@ -176,7 +176,9 @@ def spmv_rates(solver, qp, precisions=(0, 1), reps=50):
     """Standalone product bandwidth: compulsory bytes / kernel time (HIP events)."""
     import torch
     rng = np.random.default_rng(0)
-    xn, xm = rng.standard_normal(qp.n), rng.standard_normal(qp.m)
+    # x resident on the device before the timed region (no host copy inside it)
+    xn = torch.as_tensor(rng.standard_normal(qp.n), device="cuda")
+    xm = torch.as_tensor(rng.standard_normal(qp.m), device="cuda")
     out = {}
     for which, name, nnz, nr, nc, v in ((0, "Q", qp.Q.nnz, qp.n, qp.n, xn), (1, "A", qp.A.nnz, qp.m, qp.n, xn),
                                         (2, "At", qp.A.nnz, qp.n, qp.m, xm)):
@@ -193,6 +195,69 @@ def spmv_rates(solver, qp, precisions=(0, 1), reps=50):
             gbs = csr_bytes(nnz, nr, nc, sv, sv, 8) / (us * 1e-6) / 1e9
             out[f"spmv_{name}_{'fp32' if prec else 'fp64'}"] = {"us": us, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
     return out
+
+
+def spmv_cold_rates(solver, qp, reps=10):
+    """Single products with the 256 MB last-level cache (MALL) flushed
+    before each: a 1 GiB buffer is written, then one product is timed with
+    HIP events (median of reps).  The fill keeps the stream busy long enough
+    that the product is queued before its start event is reached.  FP32 times
+    include the conversion of x to FP32 (a small extra kernel)."""
+    import torch
+    rng = np.random.default_rng(0)
+    xn = torch.as_tensor(rng.standard_normal(qp.n), device="cuda")
+    xm = torch.as_tensor(rng.standard_normal(qp.m), device="cuda")
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    out = {}
+    for which, name, nnz, nr, nc, v in ((0, "Q", qp.Q.nnz, qp.n, qp.n, xn), (1, "A", qp.A.nnz, qp.m, qp.n, xn),
+                                        (2, "At", qp.A.nnz, qp.n, qp.m, xm)):
+        for prec in (0, 1):
+            solver.spmv(which, v, precision=prec, repeats=1)
+            ts = []
+            for k in range(reps):
+                flush.fill_(float(k))
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                solver.spmv(which, v, precision=prec, repeats=1)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e3)
+            us = float(np.median(ts))
+            sv = 4 if prec else 8
+            gbs = csr_bytes(nnz, nr, nc, sv, sv, 8) / (us * 1e-6) / 1e9
+            out[f"spmv_{name}_{'fp32' if prec else 'fp64'}"] = {"us": us, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    del flush
+    return out
+
+
+def instances_geomean(args, count=10):
+    """Time to tolerance on instances 0..count-1 of the benchmark family:
+    one warm-up and args.steps timed solves each (median), geometric mean
+    over the instances."""
+    import torch
+    from paper_2405_16160_amd import instances as I, pdhcg
+    times, iters, cg = [], [], []
+    for inst in range(count):
+        qp = I.random_qp(100_000, 50_000, 50_000, 2e-5, 2e-4, family=2, instance=inst)
+        sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision,
+                                              num_blocks=args.num_blocks))
+        sol.solve()
+        ts = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, _, r = sol.solve()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            assert r["status"] == 0, r["status_name"]
+        times.append(float(np.median(ts)))
+        iters.append(r["iters"])
+        cg.append(r["cg_iters_total"])
+        sol.close()
+        progress(f"instance {inst}: {times[-1] * 1e3:.1f} ms, {iters[-1]} iterations")
+    g = float(np.exp(np.mean(np.log(times))))
+    return {"instances": count, "geomean_ms": g * 1e3, "QPs/s": 1.0 / g,
+            "ms": [t * 1e3 for t in times], "iters": iters, "cg_steps": cg}
 
 
 def bench_tiny(args):
@@ -252,6 +317,7 @@ def bench_powerlaw(args):
     sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-12, precision=args.precision, max_iters=args.iters,
                                           num_blocks=args.num_blocks))
     rates = spmv_rates(sol, qp)
+    cold = spmv_cold_rates(sol, qp)
     local = local_columns_rates(qp)
     sol.solve()
     torch.cuda.synchronize()
@@ -260,7 +326,7 @@ def bench_powerlaw(args):
     ach = bytes_alg / r["kernel_s"] / 1e9
     out = {"config": "power-law QP n=2e6 m=1e6 (A row lengths Pareto 1.5, mean 8, max 5000)",
            "nnz_Q": qp.Q.nnz, "nnz_A": qp.A.nnz, "A_row_max": int(lens.max()), "gen_s": gen_s,
-           "plan": sol.plan_info(), "spmv": rates, "spmv_local_columns": local,
+           "plan": sol.plan_info(), "spmv": rates, "spmv_cold": cold, "spmv_local_columns": local,
            "solve_fixed_iters": {"iters": r["iters"], "cg_steps": r["cg_iters_total"], "kernel_ms": r["kernel_s"] * 1e3,
                                  "us_per_iter": r["kernel_s"] * 1e6 / max(r["iters"], 1), "rel_kkt": r["rel_kkt"],
                                  "GB/s": ach, "frac": ach / HBM_PEAK_GBS}}
@@ -503,6 +569,8 @@ def main():
         extras["cg_cap_1"] = {"seconds": time.perf_counter() - t, "iters": r1["iters"], "status": r1["status_name"],
                               "speedup_of_pdhcg": (time.perf_counter() - t) / (dt / args.steps)}
         solver.set_settings(settings)
+        extras["spmv_cold"] = spmv_cold_rates(solver, qp)
+        extras["instances_0_9"] = instances_geomean(args)
         line["extras"] = extras
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(qp, args.tol)

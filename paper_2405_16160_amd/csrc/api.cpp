@@ -461,13 +461,17 @@ int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) 
   return 0;
 }
 
-// LDS residency of the CG rows of Q and the dual rows of A for this launch:
-// each is held when the largest workgroup block fits the LDS a workgroup can
-// have beside the kernel's static LDS with nb workgroups co-resident.
+// LDS use of the solve kernel for this launch, in this order while it fits
+// the LDS a workgroup can have beside the kernel's static LDS with nb
+// workgroups co-resident: the CG state of the workgroup's CG rows (five FP64
+// values per row), the CG rows of Q, the dual rows of A (each sized by the
+// largest workgroup block).
 int plan_residency(pdhcg_handle* h, SolveParams& p) {
   p.res_cg = p.res_m = 0;
   p.res_vbytes = h->s.precision == 1 ? 4 : 8;
   p.res_m_off = 0;
+  p.own_cg = p.own_off = 0;
+  p.cg_own = nullptr;
   h->res_bytes = 0;
   int dev = 0, cus = 0, lds_cu = 0, stat = 0;
   HIPX(hipGetDevice(&dev));
@@ -482,23 +486,33 @@ int plan_residency(pdhcg_handle* h, SolveParams& p) {
       best = std::max(best, res_block_bytes(bnd[b + 1] - bnd[b], rp[bnd[b + 1]] - rp[bnd[b]], p.res_vbytes));
     return best;
   };
+  int64_t bo = 0;
+  for (size_t b = 0; b + 1 < h->cg_bounds.size(); ++b)
+    bo = std::max(bo, align16(5 * 8 * (int64_t)(h->cg_bounds[b + 1] - h->cg_bounds[b])));
   const int64_t bq = block(h->cg_bounds, h->qrp_h);
   const int64_t ba = h->m ? block(h->m_bounds, h->arp_h) : 0;
   int64_t total = 0;
-  if (bq <= budget) {
+  if (p.u0 && bo > 0 && bo <= budget) {
+    p.own_cg = 1;
+    total = bo;
+  }
+  if (total + bq <= budget) {
     p.res_cg = 1;
-    total = bq;
+    total += bq;
   }
   if (h->m && total + ba <= budget) {
     p.res_m = 1;
-    p.res_m_off = (int32_t)total;
     total += ba;
   }
+  // layout: Q block at 0, then the A block, then the CG state
+  const int64_t q_end = p.res_cg ? bq : 0;
+  p.res_m_off = (int32_t)q_end;
+  p.own_off = (int32_t)(q_end + (p.res_m ? ba : 0));
   if (total > 0) {
     int occ = 0;
     HIPX(solve_occupancy_dyn((int)total, &occ));
     if (occ * cus < h->nb) {  // would break co-residency: keep everything in device memory
-      p.res_cg = p.res_m = 0;
+      p.res_cg = p.res_m = p.own_cg = 0;
       total = 0;
     }
   }

@@ -391,6 +391,12 @@ __device__ __forceinline__ T lld(const T* p) {
   return *(const __attribute__((address_space(3))) T*)p;
 }
 
+// store through a generic pointer known to point into LDS
+template <typename T>
+__device__ __forceinline__ void lst(T* p, T v) {
+  *(__attribute__((address_space(3))) T*)p = v;
+}
+
 // Stage one tile of a single matrix whose rows of the workgroup are held in
 // LDS (lrp[j] = rowptr[roff + j]; lcol / lval hold the entries from eoff):
 // the same products as stage_tile, with only the gathers going to memory.

@@ -155,6 +155,12 @@ struct SolveParams {
   // cooperative kernel: flags, value bytes (4: FP32 copies, 8: FP64), byte
   // offset of the A block in dynamic LDS
   int32_t res_cg, res_m, res_vbytes, res_m_off;
+  // the single-reduction CG's state on the workgroup's CG rows (x, p, r, u,
+  // s in FP64, five arrays of r1 - r0 values) held in LDS across the steps of
+  // a primal step: flag, byte offset in dynamic LDS, and the block of the
+  // executing workgroup (set in its LDS copy of this block; null otherwise)
+  int32_t own_cg, own_off;
+  double* cg_own;
   double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf (enter every relKKT)
   double kkt_zero;        // relKKT(0, 0) when the warm-start fallback applies, else 0
   // start point of a batched solve (null: zero)

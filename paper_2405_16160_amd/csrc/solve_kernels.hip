@@ -348,7 +348,14 @@ struct GatherCG4 {
 // u_l, and s_{l-1}, which step l + 1 reads as its s_{l-2}.  The n-side pass
 // leaves r_0 in copy 0; step 0 reads it there and adds u_0 (no step reads a
 // field another workgroup is writing in the same phase).
-template <typename V, typename T>
+//
+// When the launch holds the CG state of the workgroup's rows in LDS
+// (P.cg_own), x, p, r, u and s of the owned rows live there from step 0 to the
+// dual step; device memory then receives only what other workgroups read
+// during the primal step: the FP32 x (for the dual product) and the
+// interleaved (r, u, s) rows in mixed precision, or x, r, u, s in FP64.  The
+// FP64 x of mixed precision is written back by the dual step (phase_dual).
+template <typename V, typename T, bool OWN>
 __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block B, const V* qval, int l,
                                                      double alpha, double beta, double inv_tau, int product,
                                                      int mixed, double* lds) {
@@ -362,41 +369,74 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
   double* s_prev1 = c ? P.s1 : P.s0;
   float4* v_new = c ? P.v32_1 : P.v32_0;
   double s[2] = {0.0, 0.0};  // gamma_l, delta_l
+  // owned-row state in LDS (OWN): x, p, r, u, s at ob + {0, 1, 2, 3, 4} * no
+  double* const ob = P.cg_own;
+  const int ro0 = P.w_cg.r0, no = P.w_cg.r1 - P.w_cg.r0;
+  const bool pub = !OWN || !mixed;  // FP64 r, u, s, x go to device memory
   struct Row {
     double rp, up, sp, pp, xp;
   };
   // the owned-row inputs, loaded unconditionally (all buffers are valid;
   // values not used at this step are discarded by selects)
+  // (with the state in LDS only step 0 prefetches: r_0 and x from device
+  // memory; later steps read LDS in the epilogue)
   auto pre = [&](int i) {
-    return Row{gld(r_prev + i), gld(u_prev + i), gld(s_prev2 + i), gld(P.p0 + i), gld(P.x + i)};
+    if (!OWN) return Row{gld(r_prev + i), gld(u_prev + i), gld(s_prev2 + i), gld(P.p0 + i), gld(P.x + i)};
+    if (l == 0) return Row{gld(r_prev + i), 0.0, 0.0, 0.0, gld(P.x + i)};
+    return Row{0.0, 0.0, 0.0, 0.0, 0.0};
   };
   struct Own {
     double r, s;  // r_l[i] and s_{l-1}[i]
   };
   auto own = [&](int i, const Row& rw) -> Own {  // owned-row updates
-    const double rp = rw.rp, up = rw.up, sp = rw.sp, pp = rw.pp, xp = rw.xp;
-    if (l == 0) return Own{rp, 0.0};
+    double rp = rw.rp, up = rw.up, sp = rw.sp, pp = rw.pp, xp = rw.xp;
+    double* const o = ob + (i - ro0);
+    if (OWN && l > 0) {
+      xp = lld(o);
+      pp = lld(o + no);
+      rp = lld(o + 2 * no);
+      up = lld(o + 3 * no);
+      sp = lld(o + 4 * no);
+    }
+    if (l == 0) {
+      if (OWN) {
+        lst(o, xp);
+        lst(o + 2 * no, rp);
+      }
+      return Own{rp, 0.0};
+    }
     const double s1 = l == 1 ? up : up + beta * sp;
     const double pi = l == 1 ? rp : rp + beta * pp;
-    gst(P.p0 + i, pi);
     const double xi = xp + alpha * pi;
-    gst(P.x + i, xi);
+    if (OWN) {
+      lst(o + no, pi);
+      lst(o, xi);
+    } else {
+      gst(P.p0 + i, pi);
+    }
+    if (pub) gst(P.x + i, xi);
     if (mixed) gst(P.x32 + i, (float)xi);
     if (!product) return Own{0.0, 0.0};
-    gst(s_prev1 + i, s1);
     const double ri = rp - alpha * s1;
-    gst(r_new + i, ri);
+    if (OWN) {
+      lst(o + 4 * no, s1);
+      lst(o + 2 * no, ri);
+    }
+    if (pub) {
+      gst(s_prev1 + i, s1);
+      gst(r_new + i, ri);
+    }
     return Own{ri, s1};
   };
   if (!product) {
-    const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
-    for (int i = r0 + B.tid; i < r1; i += kBlock) own(i, pre(i));
+    for (int i = ro0 + B.tid; i < ro0 + no; i += kBlock) own(i, pre(i));
     return;
   }
   auto epi = [&](int i, double qr, const Row& rw) {
     const Own ow = own(i, rw);
     const double ui = qr + ow.r * inv_tau;
-    gst(u_new + i, ui);
+    if (OWN) lst(ob + (i - ro0) + 3 * no, ui);
+    if (pub) gst(u_new + i, ui);
     if (mixed) gst(v_new + i, make_float4((float)ow.r, (float)ui, (float)ow.s, 0.0f));
     s[0] += ow.r * ow.r;
     s[1] += ow.r * ui;
@@ -433,9 +473,11 @@ __device__ __attribute__((noinline)) void phase_cgcg(const SolveParams& P, Block
 // Dual step and averages (Alg. 1): u = A x^{k+1};
 // y <- max(0, y + sigma (2u - A x^k - b)); A x^k <- u; ya += w (y - ya);
 // xa += w (x - xa) on an n-slice; m-side partials of the new point.
+// xo: the LDS x of the CG rows when the primal step kept it there (null:
+// device memory holds x); in mixed precision it is written back here.
 template <typename V, typename Tx>
-__device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, Block B, const V* aval, const Tx* xg, double sigma, double w,
-                           double* lds) {
+__device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, Block B, const V* aval, const Tx* xg,
+                                                     double sigma, double w, const double* xo, double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(
       P, B, aval, xg, lds, [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), gld(P.ax + i), gld(P.ya + i)}; },
@@ -450,7 +492,14 @@ __device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, Block
       });
   const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
   for (int j = r0 + B.tid; j < r1; j += kBlock) {
-    const double xaj = gld(P.xa + j), xj = gld(P.x + j);
+    const double xaj = gld(P.xa + j);
+    double xj;
+    if (xo) {
+      xj = lld(xo + (j - r0));
+      if (sizeof(Tx) == 4) gst(P.x + j, xj);  // (in FP64 the primal step already wrote it)
+    } else {
+      xj = gld(P.x + j);
+    }
     gst(P.xa + j, xaj + w * (xj - xaj));
   }
   store_mside(P, B, 0, s1, mx, lds);
@@ -612,6 +661,7 @@ struct Ctl {
   double gamma, alpha, beta, inv_tau, w;
   int64_t budget;     // iterations left in this launch
   int32_t op, l, steps, have_avg, use_avg, first, cur;
+  int32_t xlds;       // the primal step left x of the CG rows in LDS (P.cg_own)
 };
 
 __device__ void ctl_end_cg(Ctl& C) {
@@ -625,7 +675,9 @@ __device__ void ctl_start_cg(const SolveParams& P, Ctl& C) {
   C.S.eps += P.eps_factor * C.kc.kkt;
   C.inv_tau = 1.0 / C.S.tau;
   C.steps = 0;
+  C.xlds = 0;
   if (C.rho > 0.0 && P.u0 != nullptr) {  // single-reduction CG: L steps take L + 1 grid barriers
+    C.xlds = P.cg_own != nullptr;
     C.gamma = C.rho;
     C.alpha = 0.0;
     C.beta = 0.0;
@@ -907,10 +959,14 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         phase_restart(P, B, C.use_avg, mixed, lds);
         break;
       case OP_CG:
-        if (mixed)
-          phase_cgcg<float, float>(P, B, P.Q.val32, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 1, lds);
+        if (mixed && P.cg_own)
+          phase_cgcg<float, float, true>(P, B, P.Q.val32, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 1, lds);
+        else if (mixed)
+          phase_cgcg<float, float, false>(P, B, P.Q.val32, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 1, lds);
+        else if (P.cg_own)
+          phase_cgcg<double, double, true>(P, B, P.Q.val, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 0, lds);
         else
-          phase_cgcg<double, double>(P, B, P.Q.val, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 0, lds);
+          phase_cgcg<double, double, false>(P, B, P.Q.val, C.l, C.alpha, C.beta, C.inv_tau, C.l < P.max_cg, 0, lds);
         break;
       case OP_CG_SPMV: {
         const int cur = C.cur;
@@ -929,9 +985,9 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         break;
       case OP_DUAL:
         if (mixed)
-          phase_dual(P, B, P.A.val32, (const float*)P.x32, C.S.sigma, C.w, lds);
+          phase_dual(P, B, P.A.val32, (const float*)P.x32, C.S.sigma, C.w, C.xlds ? P.cg_own : nullptr, lds);
         else
-          phase_dual(P, B, P.A.val, (const double*)P.x, C.S.sigma, C.w, lds);
+          phase_dual(P, B, P.A.val, (const double*)P.x, C.S.sigma, C.w, C.xlds ? P.cg_own : nullptr, lds);
         break;
       case OP_COPY_AVG:
         phase_copy_point(P, B, P.xa, P.ya);
@@ -1062,6 +1118,7 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* 
   load_params(Ps, Pg, (int)blockIdx.x);
   if (Ps.res_cg) place_resident(Ps.w_cg, Ps.Q, dyn_lds, Ps.res_vbytes);
   if (Ps.res_m) place_resident(Ps.w_m, Ps.A, dyn_lds + Ps.res_m_off, Ps.res_vbytes);
+  if (threadIdx.x == 0) Ps.cg_own = Ps.own_cg ? (double*)(dyn_lds + Ps.own_off) : nullptr;
   __syncthreads();
   const SolveParams& P = Ps;
   const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
