@@ -578,11 +578,14 @@ int estimate_norm(pdhcg_handle* h) {
   pp.pn = h->pt.view();
   pp.pm = h->pm.view();
   pp.iters = h->s.power_iters;
-  HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * 512, h->stream));
+  HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * kBarWords, h->stream));
   HIPX(launch_power(pp, h->nb, h->stream));
   double v = 0.0;
+  uint64_t abort_word = 0;
   HIPX(hipMemcpyAsync(&v, h->scratch, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPX(hipMemcpyAsync(&abort_word, h->bar + kBarAbortWord, sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
+  if (abort_word != 0) return fail(PDHCG_ERR_HIP, "grid barrier of the power iteration timed out");
   h->norm_A = v;
   return 0;
 }
@@ -667,7 +670,7 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
     if ((rc = h->alloc(v, m))) return bail(rc);
   if ((rc = h->alloc(&h->scratch, 16))) return bail(rc);
   if ((rc = h->alloc(&h->part, (int64_t)NSLOT * 4096))) return bail(rc);
-  if ((rc = h->alloc(&h->bar, 512))) return bail(rc);
+  if ((rc = h->alloc(&h->bar, kBarWords))) return bail(rc);
   if ((rc = h->alloc(&h->st, 1))) return bail(rc);
   if ((rc = h->alloc(&h->d_params, 1))) return bail(rc);
   if ((rc = upload(h, h->b, hb.data(), m))) return bail(rc);
@@ -750,7 +753,7 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
   HIPX(launch_init_point(h->d_params, h->n, h->m, h->stream));
   double kernel_ms = 0.0;
   for (;;) {
-    HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * 512, h->stream));
+    HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * kBarWords, h->stream));
     HIPX(hipEventRecord(h->ev0, h->stream));
     HIPX(launch_solve(h->d_params, h->nb, h->res_bytes, h->stream));
     HIPX(hipEventRecord(h->ev1, h->stream));

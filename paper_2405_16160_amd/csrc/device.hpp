@@ -116,61 +116,117 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nb, cons
 
 // ------------------------------------------------------------ grid barrier
 //
-// Hierarchical arrival counters: workgroup w arrives on group counter w % 8
-// (one per XCD under the round-robin dispatch of workgroups), the last arrival
-// of a group arrives on the global counter, and the last group publishes the
-// new generation.  Waiters poll the generation with relaxed loads and take one
-// acquire fence at the end; arrivals take one release fence.  Counters grow
-// monotonically within a launch (64-bit), so no reset race exists.  Every wait
-// is bounded by a wall-clock limit: on expiry the workgroup raises the abort
-// word and returns false, and every other waiter then returns false too.
+// Arrival is counted per XCD, in that XCD's L2: the CUs of one XCD share its
+// L2, so a counter there needs no device-scope traffic.  Before arriving,
+// every wave of the workgroup waits until its stores are complete (written to
+// the L2); the last workgroup of an XCD to arrive then writes that L2 back to
+// memory once, for the whole XCD, and arrives on the device-scope counter; the
+// last XCD publishes the new generation.  Waiters poll the generation with
+// relaxed device-scope loads and take one acquire fence (invalidating their
+// L1 and the XCD's L2).  The XCD of a workgroup is read from the hardware
+// register that names it, and the number of the grid's workgroups on each XCD
+// is counted once per launch (init), so the barrier holds for any placement of
+// workgroups on XCDs.  Counters grow monotonically within a launch (64-bit),
+// so no reset race exists.  Every wait is bounded by a wall-clock limit: on
+// expiry the workgroup raises the abort word and returns false, and every
+// other waiter then returns false too.
 namespace bar {
-constexpr int kCount = 0, kGen = 32, kAbort = 64, kGroup = 96;  // word offsets (256-byte apart)
-constexpr int kWords = kGroup + 8 * 32;
+constexpr int kMaxXcd = 16;
+constexpr int kCount = 0, kGen = 32, kAbort = kBarAbortWord, kSetup = 96;  // word offsets (256 bytes apart)
+constexpr int kXcdArrive = 128;                     // + 32 x: arrivals of XCD x (in its L2)
+constexpr int kXcdCount = kXcdArrive + 32 * kMaxXcd;  // + 32 x: workgroups on XCD x
+constexpr int kWords = kXcdCount + 32 * kMaxXcd;
+static_assert(kWords <= kBarWords, "barrier words");
 }  // namespace bar
 
 #define PDHCG_LD(p) __hip_atomic_load((p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
 #define PDHCG_ST(p, v) __hip_atomic_store((p), (v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
 #define PDHCG_ADD(p, v) __hip_atomic_fetch_add((p), (v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
 
+// the XCD (accelerator complex die) this wave runs on
+__device__ __forceinline__ uint32_t xcd_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v & (uint32_t)(bar::kMaxXcd - 1);
+}
+
+// wait until this wave's outstanding memory operations are complete (stores
+// written to the L2)
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 struct GridSync {
   uint64_t* w;
   uint32_t nb;
   uint64_t epoch;
+  uint32_t xcd = 0, xsize = 1, nxcd = 1;  // this workgroup's XCD, workgroups on it, XCDs in use
   static constexpr uint64_t kTimeoutTicks = 500000000ull;  // 5 s of the 100 MHz wall clock
+
+  __device__ bool wait_word(int k, uint64_t target, int& ok) {
+    const uint64_t t0 = wall_clock64();
+    while (PDHCG_LD(&w[k]) < target) {
+      if (PDHCG_LD(&w[bar::kAbort]) != 0ull) { ok = 0; return false; }
+      if (wall_clock64() - t0 > kTimeoutTicks) {
+        PDHCG_ST(&w[bar::kAbort], 1ull);
+        ok = 0;
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+  }
+
+  // Once per launch, before the first sync: count the workgroups per XCD.
+  __device__ bool init() {
+    __shared__ uint32_t sx[3];
+    __shared__ int ok_s;
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      sx[0] = 0;
+      sx[1] = 1;
+      sx[2] = 1;
+      if (nb > 1) {
+        const uint32_t x = xcd_id();
+        PDHCG_ADD(&w[bar::kXcdCount + 32 * x], 1ull);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        PDHCG_ADD(&w[bar::kSetup], 1ull);
+        if (wait_word(bar::kSetup, nb, ok)) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          uint32_t used = 0;
+          for (int j = 0; j < bar::kMaxXcd; ++j) used += PDHCG_LD(&w[bar::kXcdCount + 32 * j]) > 0ull;
+          sx[0] = x;
+          sx[1] = (uint32_t)PDHCG_LD(&w[bar::kXcdCount + 32 * x]);
+          sx[2] = used;
+        }
+      }
+      ok_s = ok;
+    }
+    __syncthreads();
+    xcd = sx[0];
+    xsize = sx[1];
+    nxcd = sx[2];
+    return ok_s != 0;
+  }
 
   __device__ bool sync() {
     __shared__ int ok_s;
+    if (nb > 1) wait_stores();
     __syncthreads();
     ++epoch;
     if (threadIdx.x == 0) {
       int ok = 1;
       if (nb > 1) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t g = blockIdx.x & 7u;
-        const uint32_t ngroups = nb < 8u ? nb : 8u;
-        const uint64_t gsize = (nb - g + 7u) / 8u;
-        const uint64_t a = PDHCG_ADD(&w[bar::kGroup + 32 * g], 1ull);
-        if (a == gsize * epoch - 1) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const uint64_t a = __hip_atomic_fetch_add(&w[bar::kXcdArrive + 32 * xcd], 1ull, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (a == (uint64_t)xsize * epoch - 1) {  // last of its XCD: write the XCD's L2 back once
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           const uint64_t t = PDHCG_ADD(&w[bar::kCount], 1ull);
-          if (t == ngroups * epoch - 1) {
+          if (t == (uint64_t)nxcd * epoch - 1) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             PDHCG_ST(&w[bar::kGen], epoch);
           }
         }
-        const uint64_t t0 = wall_clock64();
-        while (PDHCG_LD(&w[bar::kGen]) < epoch) {
-          if (PDHCG_LD(&w[bar::kAbort]) != 0ull) { ok = 0; break; }
-          if (wall_clock64() - t0 > kTimeoutTicks) {
-            PDHCG_ST(&w[bar::kAbort], 1ull);
-            ok = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+        wait_word(bar::kGen, epoch, ok);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       ok_s = ok;

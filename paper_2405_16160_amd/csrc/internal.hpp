@@ -6,6 +6,8 @@
 namespace pdhcg {
 
 constexpr int kBlock = 512;       // threads per workgroup of every solver kernel
+constexpr int kBarWords = 2048;   // grid-barrier words (uint64) per handle, zeroed before each launch
+constexpr int kBarAbortWord = 64; // the barrier word raised when a wait timed out
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kWaves = kBlock / kWave;
 constexpr int kLongRow = 1024;    // rows longer than this are reduced by the whole workgroup

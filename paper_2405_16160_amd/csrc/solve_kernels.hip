@@ -1125,6 +1125,10 @@ __global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* 
   __shared__ double lds[kWaves * 16];
   Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
   GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  if (!gs.init()) {
+    if (B.b == 0 && B.tid == 0) P.st->done = -1;  // barrier failure: reported as a HIP error
+    return;
+  }
   __shared__ Ctl C;
   if (B.tid == 0) C.S = *P.st;
   __syncthreads();
@@ -1214,6 +1218,7 @@ __global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) {
   __shared__ double lds[kWaves * 8];
   Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
   GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  if (!gs.init()) return;  // (the host finds the abort word raised)
   double nrm = 0.0;
   if (power_norm(P.A, P.At, P.v, P.w, P.u, P.part, P.pn, P.pm, P.iters, B, gs, lds, &nrm) && B.b == 0 &&
       B.tid == 0)
