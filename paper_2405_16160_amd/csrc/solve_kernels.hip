@@ -912,6 +912,124 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
   }
 }
 
+// The primal step's CG run as one chain, for a workgroup whose CG rows form
+// one tile, whose rows of Q and CG state are held in LDS, with FP32 products:
+// the same product phase per step as phase_cgcg, one grid barrier per step,
+// the same reduction and control step.  What differs is the order after each
+// barrier: the gathers of the next step's product (the interleaved (r, u, s)
+// rows of the tile's columns, which need none of the scalars being reduced)
+// are issued together with the loads of the step's partials, so one memory
+// round trip serves both, and the next product is formed from those
+// registers once the control step has set alpha and beta.  Entered at a
+// product step (C.l < max_cg) after its control step; returns after the
+// control step that ends the chain (C.op then names the next phase, which the
+// caller runs), with the barrier's epoch and ok = 0 if a barrier failed.
+struct ChainEnd {
+  uint64_t epoch;
+  int ok;
+};
+
+__device__ __forceinline__ ChainEnd cg_chain(const SolveParams& P, Block B, GridSync gs, Ctl& C,
+                                                       double* lds) {
+  const WgPart& pt = P.w_cg;
+  const int32_t* t = pt.tile(pt.t0);
+  const int nz = t[3] - t[2];
+  const int zoff = t[2] - pt.e0;  // first entry of the tile in the LDS block
+  const float* lval = (const float*)pt.lval;
+  double* const ob = P.cg_own;
+  const int ro0 = pt.r0, no = pt.r1 - pt.r0;
+  const double inv_tau = C.inv_tau;  // fixed within a primal step
+  float4 q[kStageUnroll];
+  auto gather = [&](const float4* v) {  // raw rows of the tile's columns (no wait)
+    if (nz > 0) {
+      int c[kStageUnroll];
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; ++u) c[u] = lld(pt.lcol + zoff + min(u * kBlock + B.tid, nz - 1));
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; ++u) q[u] = gld(v + c[u]);
+    }
+  };
+  {
+    const int l = C.l;
+    gather((l == 0 ? 0 : (l & 1) ^ 1) ? P.v32_1 : P.v32_0);
+  }
+  for (;;) {
+    const int l = C.l;
+    const double alpha = C.alpha, beta = C.beta;
+    float4* v_new = (l & 1) ? P.v32_1 : P.v32_0;
+    auto stage = [&](TileLds& L, int ra, int nr, int z0, int nzt) {
+#pragma unroll
+      for (int u = 0; u < kRowsPerThread; ++u) {
+        const int i = u * kBlock + B.tid;
+        if (i <= nr) L.rp[i] = lld(pt.lrp + ra + i - ro0) - z0;
+      }
+#pragma unroll
+      for (int u = 0; u < kStageUnroll; ++u) {
+        const int k = u * kBlock + B.tid;
+        if (k < nzt) {
+          const double rj = q[u].x, uj = q[u].y, sj = q[u].z;
+          const double s1 = l == 1 ? uj : uj + beta * sj;
+          const double g = l == 0 ? rj : rj - alpha * s1;
+          L.prod[k] = (double)lld(lval + zoff + k) * g;
+        }
+      }
+    };
+    struct Row {
+      double rp, xp;
+    };
+    auto pre = [&](int i) {  // step 0 starts from r_0 and x in device memory
+      if (l == 0) return Row{gld(P.r + i), gld(P.x + i)};
+      return Row{0.0, 0.0};
+    };
+    double s2[2] = {0.0, 0.0};  // gamma_l, delta_l
+    auto epi = [&](int i, double qr, const Row& rw) {
+      double* const o = ob + (i - ro0);
+      double ri, s1 = 0.0;
+      if (l == 0) {
+        lst(o, rw.xp);
+        ri = rw.rp;
+      } else {
+        const double xp = lld(o), pp = lld(o + no), rp = lld(o + 2 * no), up = lld(o + 3 * no),
+                     sp = lld(o + 4 * no);
+        s1 = l == 1 ? up : up + beta * sp;
+        const double pi = l == 1 ? rp : rp + beta * pp;
+        const double xi = xp + alpha * pi;
+        lst(o + no, pi);
+        lst(o, xi);
+        gst(P.x32 + i, (float)xi);
+        ri = rp - alpha * s1;
+        lst(o + 4 * no, s1);
+      }
+      lst(o + 2 * no, ri);
+      const double ui = qr + ri * inv_tau;
+      lst(o + 3 * no, ui);
+      gst(v_new + i, make_float4((float)ri, (float)ui, (float)s1, 0.0f));
+      s2[0] += ri * ri;
+      s2[1] += ri * ui;
+    };
+    tile_rows_impl(t, pt.group, stage, pre, epi);
+    double dummy[1] = {0.0};
+    block_reduce<2, 0>(s2, dummy, lds);
+    if (B.tid == 0) {
+      P.part[S_RR * B.nb + B.b] = s2[0];
+      P.part[S_PQ * B.nb + B.b] = s2[1];
+    }
+    if (!gs.sync()) return ChainEnd{gs.epoch, 0};
+    gather(v_new);  // the next step reads the copy this step wrote
+    const int ss[2] = {S_RR, S_PQ};
+    const int ms[1] = {0};
+    double gd[2], m0[1];
+    reduce_partials<2, 0>(P.part, B.nb, ss, ms, gd, m0, lds);
+    if (B.tid == 0) {
+      C.ra = gd[0];
+      C.rb = gd[1];
+      control(P, C, OP_CG);
+    }
+    __syncthreads();
+    if (!(C.op == OP_CG && C.l < P.max_cg)) return ChainEnd{gs.epoch, 1};
+  }
+}
+
 // Runs at most `budget` iterations from the state C.S (set by thread 0 before
 // the call, updated in place); returns false only if a grid barrier failed.
 template <bool DENSE>
@@ -924,10 +1042,19 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
   }
   __syncthreads();
   bool ok = true;
+  const WgPart& pc = P.w_cg;
+  const bool chain_ok = !DENSE && P.cg_own != nullptr && pc.lcol != nullptr && P.res_vbytes == 4 &&
+                        pc.t1 - pc.t0 == 1 && pc.l1 == pc.l0;
   for (;;) {
     const int op = C.op;
     if (op == OP_END) break;
     const int mixed = C.S.mixed;
+    if (op == OP_CG && mixed && chain_ok && C.l < P.max_cg) {
+      const ChainEnd e = cg_chain(P, B, gs, C, lds);
+      gs.epoch = e.epoch;
+      if (!(ok = e.ok != 0)) break;
+      continue;
+    }
     switch (op) {
       case OP_AX_START:
       case OP_AX_ZERO:
