@@ -274,6 +274,7 @@ struct pdhcg_handle {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   DevPart pn1, pcg, pm, pt;                // parts for the persistent kernels
   std::vector<int32_t> cg_bounds, m_bounds;          // host copies of the pcg / pm row ranges
+  int cg_one_tile = 0;  // every workgroup's CG rows form one tile with no long row
   int res_bytes = 0;                                 // dynamic LDS of the last solve launch
   int32_t* stiles[3] = {nullptr, nullptr, nullptr};  // tiles of the standalone products (Q, A, A')
   int32_t nstiles[3] = {0, 0, 0};
@@ -418,6 +419,9 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
   const HostPart pm = build_part(h->m, nb, arp, nullptr, gscale);
   h->cg_bounds = pcg.bounds;
   h->m_bounds = pm.bounds;
+  h->cg_one_tile = 1;
+  for (int b = 0; b < nb; ++b)
+    if (pcg.tile_ptr[b + 1] - pcg.tile_ptr[b] != 1 || pcg.long_ptr[b + 1] != pcg.long_ptr[b]) h->cg_one_tile = 0;
   if ((rc = upload_part(h, pcg, h->pcg))) return rc;
   if ((rc = upload_part(h, pm, h->pm))) return rc;
   if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr, gscale), h->pt))) return rc;
@@ -470,7 +474,7 @@ int plan_residency(pdhcg_handle* h, SolveParams& p) {
   p.res_cg = p.res_m = 0;
   p.res_vbytes = h->s.precision == 1 ? 4 : 8;
   p.res_m_off = 0;
-  p.own_cg = p.own_off = 0;
+  p.own_cg = p.own_off = p.cg_chain = 0;
   p.cg_own = nullptr;
   h->res_bytes = 0;
   int dev = 0, cus = 0, lds_cu = 0, stat = 0;
@@ -516,6 +520,9 @@ int plan_residency(pdhcg_handle* h, SolveParams& p) {
       total = 0;
     }
   }
+  // the chained CG steps (every workgroup or none: they take the CG decisions
+  // themselves, so all must run the same code)
+  p.cg_chain = p.own_cg && p.res_cg && p.res_vbytes == 4 && h->cg_one_tile;
   h->res_bytes = (int)total;
   return 0;
 }

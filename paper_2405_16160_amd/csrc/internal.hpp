@@ -163,6 +163,9 @@ struct SolveParams {
   // executing workgroup (set in its LDS copy of this block; null otherwise)
   int32_t own_cg, own_off;
   double* cg_own;
+  // FP32 products, Q rows and CG state in LDS and one CG tile per workgroup in
+  // every workgroup: the CG steps run chained (cg_chain)
+  int32_t cg_chain;
   double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf (enter every relKKT)
   double kkt_zero;        // relKKT(0, 0) when the warm-start fallback applies, else 0
   // start point of a batched solve (null: zero)

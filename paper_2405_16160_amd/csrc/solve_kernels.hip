@@ -949,13 +949,14 @@ __device__ __forceinline__ ChainEnd cg_chain(const SolveParams& P, Block B, Grid
       for (int u = 0; u < kStageUnroll; ++u) q[u] = gld(v + c[u]);
     }
   };
-  {
-    const int l = C.l;
-    gather((l == 0 ? 0 : (l & 1) ^ 1) ? P.v32_1 : P.v32_0);
-  }
+  // the CG coefficients and counters, kept uniform in registers during the
+  // chain (every workgroup runs this code on the same reduced values) and
+  // written back before the control step that ends it
+  int l = C.l, steps = C.steps;
+  double alpha = C.alpha, beta = C.beta, gamma = C.gamma;
+  const double tau = C.S.tau, eps = C.S.eps;
+  gather((l == 0 ? 0 : (l & 1) ^ 1) ? P.v32_1 : P.v32_0);
   for (;;) {
-    const int l = C.l;
-    const double alpha = C.alpha, beta = C.beta;
     float4* v_new = (l & 1) ? P.v32_1 : P.v32_0;
     auto stage = [&](TileLds& L, int ra, int nr, int z0, int nzt) {
 #pragma unroll
@@ -1020,13 +1021,37 @@ __device__ __forceinline__ ChainEnd cg_chain(const SolveParams& P, Block B, Grid
     const int ms[1] = {0};
     double gd[2], m0[1];
     reduce_partials<2, 0>(P.part, B.nb, ss, ms, gd, m0, lds);
+    // the control step of a CG phase (control(), OP_CG) while the chain goes on
+    const double gl = uniform(gd[0]), dl = uniform(gd[1]);
+    const bool stop = l > 0 && ((P.cg_rule == 0 && tau * sqrt(gl) <= eps) || !(gl > 0.0));
+    const int l_next = l + 1;
+    if (!stop && l_next < P.max_cg) {
+      if (l == 0) {
+        alpha = gamma / dl;
+        beta = 0.0;
+      } else {
+        steps = l;
+        beta = gl / gamma;
+        alpha = gl / (dl - beta * gl / alpha);
+        gamma = gl;
+      }
+      l = l_next;
+      continue;
+    }
+    // the chain ends here: the control step proper decides from the state
+    // before this reduction (the end of the primal step, or its last step)
     if (B.tid == 0) {
+      C.l = l;
+      C.steps = steps;
+      C.alpha = alpha;
+      C.beta = beta;
+      C.gamma = gamma;
       C.ra = gd[0];
       C.rb = gd[1];
       control(P, C, OP_CG);
     }
     __syncthreads();
-    if (!(C.op == OP_CG && C.l < P.max_cg)) return ChainEnd{gs.epoch, 1};
+    return ChainEnd{gs.epoch, 1};
   }
 }
 
@@ -1043,8 +1068,7 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
   __syncthreads();
   bool ok = true;
   const WgPart& pc = P.w_cg;
-  const bool chain_ok = !DENSE && P.cg_own != nullptr && pc.lcol != nullptr && P.res_vbytes == 4 &&
-                        pc.t1 - pc.t0 == 1 && pc.l1 == pc.l0;
+  const bool chain_ok = !DENSE && P.cg_chain && P.cg_own != nullptr && pc.lcol != nullptr;
   for (;;) {
     const int op = C.op;
     if (op == OP_END) break;
