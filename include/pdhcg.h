@@ -87,6 +87,13 @@ typedef struct {
     int32_t warm_fallback;           /* 1: if relKKT at a given (x0, y0) exceeds relKKT at (0, 0),
                                         start from (0, 0) instead (a cold start) */
     int32_t verbose;                 /* 0 = silent */
+    int32_t cg_form;                 /* form of the CG steps in the single-QP solve (same iterates
+                                        in exact arithmetic): 0 = planner's choice (1 while the
+                                        interleaved FP32 (r, u, s) vector, 16 n bytes, fits the L2
+                                        of one XCD, else 2), 1 = one reduction and one grid barrier
+                                        per step with (r, u, s) gathered (Chronopoulos-Gear),
+                                        2 = textbook CG, two barriers per step with only the
+                                        direction gathered */
 } pdhcg_settings;
 
 typedef struct {

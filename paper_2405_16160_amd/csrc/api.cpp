@@ -275,6 +275,7 @@ struct pdhcg_handle {
   DevPart pn1, pcg, pm, pt;                // parts for the persistent kernels
   std::vector<int32_t> cg_bounds, m_bounds;          // host copies of the pcg / pm row ranges
   int cg_one_tile = 0;  // every workgroup's CG rows form one tile with no long row
+  int64_t l2_bytes = 4 << 20;  // L2 of one XCD (device attribute at create)
   int res_bytes = 0;                                 // dynamic LDS of the last solve launch
   int32_t* stiles[3] = {nullptr, nullptr, nullptr};  // tiles of the standalone products (Q, A, A')
   int32_t nstiles[3] = {0, 0, 0};
@@ -390,6 +391,7 @@ int check_settings(const pdhcg_settings* s) {
   if (s->power_iters < 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "power_iters must be >= 1");
   if (s->precision != 0 && s->precision != 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "precision must be 0 or 1");
   if (s->num_blocks < 0 || s->num_blocks > 4096) return fail(PDHCG_ERR_INVALID_ARGUMENT, "num_blocks out of range");
+  if (s->cg_form < 0 || s->cg_form > 2) return fail(PDHCG_ERR_INVALID_ARGUMENT, "cg_form must be 0, 1 or 2");
   return 0;
 }
 
@@ -433,6 +435,9 @@ int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) 
   int dev = 0, cus = 0;
   HIPX(hipGetDevice(&dev));
   HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int l2 = 0;
+  HIPX(hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, dev));
+  if (l2 > 0) h->l2_bytes = l2;
   int per_cu = 0;
   HIPX(solve_occupancy(&per_cu));
   h->max_nb = std::max(1, std::min(cus * std::max(per_cu, 1), 1024));
@@ -541,6 +546,15 @@ SolveParams make_params(pdhcg_handle* h) {
   p.x32 = h->x32; p.r32 = h->r32; p.p32_0 = h->p32_0; p.p32_1 = h->p32_1;
   p.r_alt = h->r_alt; p.u0 = h->u0; p.u1 = h->u1; p.s0 = h->s0; p.s1 = h->s1;
   p.v32_0 = h->v32_0; p.v32_1 = h->v32_1;
+  // CG form: the single-reduction steps gather 16 bytes per column (FP32 r, u,
+  // s), the textbook steps 4 (the direction) at one more grid barrier per step;
+  // the first wins while the gathered vector stays in an XCD's L2, the second
+  // once the gathers stream from the last-level cache
+  const bool single = h->s.cg_form == 1 || (h->s.cg_form == 0 && 16 * h->n <= h->l2_bytes);
+  if (!single) {
+    p.u0 = nullptr;
+    p.v32_0 = p.v32_1 = nullptr;
+  }
   p.part = h->part;
   p.bar = h->bar;
   p.st = h->st;
@@ -623,6 +637,7 @@ void pdhcg_default_settings(pdhcg_settings* s) {
   s->num_blocks = 0;
   s->warm_fallback = 1;
   s->verbose = 0;
+  s->cg_form = 0;
 }
 
 int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, const double* b, const double* c,

@@ -31,7 +31,7 @@ class pdhcg_settings(C.Structure):
                 ("eval_period", C.c_int32), ("primal_weight_theta", C.c_double),
                 ("primal_weight_init", C.c_double), ("step_eta_factor", C.c_double), ("power_iters", C.c_int32),
                 ("precision", C.c_int32), ("time_limit_s", C.c_double), ("num_blocks", C.c_int32),
-                ("warm_fallback", C.c_int32), ("verbose", C.c_int32)]
+                ("warm_fallback", C.c_int32), ("verbose", C.c_int32), ("cg_form", C.c_int32)]
 
 
 class pdhcg_result(C.Structure):
@@ -120,6 +120,7 @@ class Settings:
     num_blocks: int = 0
     warm_fallback: int = 1
     verbose: int = 0
+    cg_form: int = 0
 
     def c(self) -> pdhcg_settings:
         s = pdhcg_settings()

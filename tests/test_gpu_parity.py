@@ -251,6 +251,39 @@ def test_cg_cap_one_step():
     assert r2["iters"] < r["iters"]
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("form", [1, 2])
+def test_cg_forms(form, precision):
+    """Both forms of the CG steps (one reduction per step with (r, u, s)
+    gathered, and the textbook form with two) on the same instance and, in
+    FP32 products with one tile per workgroup, the chained steps of the first."""
+    say(f"[solve] random_qp n=1000 instance=2 cg_form={form} precision={precision}")
+    qp = I.random_qp(family=1, instance=2)
+    ref = oracle_ref(qp, ("rq1", 2))
+    x, y, r, info = gpu_solve(qp, tol_rel_kkt=1e-6, precision=precision, cg_form=form)
+    say(f"  status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} plan={info}")
+    assert r["status"] == 0
+    check_contract(qp, x, y, ref)
+
+
+def test_cg_forms_same_iterates_medium():
+    """At n = 2e4 (several workgroups, one CG tile each) the two forms take
+    the same iterations up to rounding: equal iteration counts within a few
+    and points within the parity bar of each other."""
+    say("[solve] random_qp n=20000 m=10000 both CG forms")
+    qp = I.random_qp(20_000, 10_000, 10_000, 1e-4, 1e-3, family=2, instance=7)
+    out = {}
+    for form in (1, 2):
+        x, y, r, info = gpu_solve(qp, tol_rel_kkt=1e-6, precision=1, cg_form=form)
+        say(f"  form={form} status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} plan={info}")
+        assert r["status"] == 0
+        assert O.kkt(qp, x, y)["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+        out[form] = (x, r)
+    (x1, r1), (x2, r2) = out[1], out[2]
+    assert abs(r1["iters"] - r2["iters"]) <= max(5, r1["iters"] // 20)
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x2) <= 1e-4
+
+
 def test_powerlaw_parity_small():
     say("[solve] power-law QP n=60000 m=30000 (long rows)")
     qp = I.powerlaw_qp(60_000, 30_000, family=3, instance=1)
