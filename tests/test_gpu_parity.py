@@ -213,28 +213,44 @@ def test_failure_modes_and_limits():
         pdhcg.Solver(I.QP(qp.Q, unsorted, qp.b, qp.c))
 
 
-def test_warm_start_resume_negative_y0_and_determinism():
-    say("[solve] warm start / resume / determinism")
+@pytest.mark.parametrize("precision", [0, 1])
+def test_warm_start_resume_negative_y0_and_determinism(precision):
+    say(f"[solve] warm start / resume / determinism precision={precision}")
     qp = I.random_qp(family=1, instance=2)
     ref = oracle_ref(qp, ("rq1", 2))
-    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-6, max_iters=200))
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-6, max_iters=200, precision=precision))
     x1, y1, r1 = sol.solve()
     assert r1["status"] == 1
-    sol.set_settings(pdhcg.Settings(tol_rel_kkt=1e-6))
+    sol.set_settings(pdhcg.Settings(tol_rel_kkt=1e-6, precision=precision))
     x2, y2, r2 = sol.solve(x0=x1, y0=y1)
     assert r2["status"] == 0
     check_contract(qp, x2.cpu().numpy(), y2.cpu().numpy(), ref)
     # negative y0 is projected: same first iterate as y0 = 0
-    sol.set_settings(pdhcg.Settings(tol_rel_kkt=1e-14, max_iters=1))
+    sol.set_settings(pdhcg.Settings(tol_rel_kkt=1e-14, max_iters=1, precision=precision))
     xa, _, _ = sol.solve(y0=-np.ones(qp.m))
     xb, _, _ = sol.solve(y0=np.zeros(qp.m))
     assert torch.equal(xa, xb)
     # fixed-order reductions: repeated solves are bit-identical
-    sol.set_settings(pdhcg.Settings(tol_rel_kkt=1e-6))
+    sol.set_settings(pdhcg.Settings(tol_rel_kkt=1e-6, precision=precision))
     xa, ya, ra = sol.solve()
     xb, yb, rb = sol.solve()
     assert torch.equal(xa, xb) and torch.equal(ya, yb) and ra["iters"] == rb["iters"]
     sol.close()
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_fixed_cg_steps_accounting(form):
+    """With a fixed number N of CG steps per iteration (cg_rule 1) every
+    iteration takes exactly N steps, whichever code path runs them (in FP32
+    products the chained steps hand the last one to the control step)."""
+    qp = I.random_qp(family=1, instance=3)
+    for n_cg in (2, 3, 7):
+        say(f"[solve] random_qp n=1000 instance=3 cg_rule=1 N={n_cg} cg_form={form}")
+        x, y, r, _ = gpu_solve(qp, tol_rel_kkt=1e-6, precision=1, cg_rule=1, max_cg_iters=n_cg,
+                               max_iters=200_000, cg_form=form)
+        assert r["status"] == 0
+        assert r["cg_iters_total"] == n_cg * r["iters"]
+        assert O.kkt(qp, x, y)["rel_kkt"] <= 1e-6 * (1 + 1e-6)
 
 
 def test_cg_cap_one_step():
