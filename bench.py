@@ -498,10 +498,16 @@ def main():
         b = torch.empty_like(a)
         a.fill_(1.0)
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(3):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": a.numel() * 8, "copies": 3}))
+        ms = e0.elapsed_time(e1) / 3
+        # a copy moves its size twice (read + write): the device's practical streaming rate
+        print(json.dumps({"calibrate_copy_bytes": a.numel() * 8, "copies": 3, "ms_per_copy": ms,
+                          "copy_GB/s_read_plus_write": 2 * a.numel() * 8 / (ms * 1e-3) / 1e9}))
         return
 
     if args.config != "random1e5":
