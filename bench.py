@@ -158,9 +158,39 @@ def solve_bytes(qp, r, precision, dense_q=False):
     return r["iters"] * (a1 + dual) + r["cg_iters_total"] * cg + r["kkt_evals"] * ev
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_one_core(tol):
+    """The same oracle solve on one core: a child process with one OpenMP
+    thread (the thread count of a running OpenMP runtime is fixed)."""
+    import subprocess
+    code = ("import sys, time, json; sys.path.insert(0, %r); "
+            "from oracle import oracle as O; from bench import workload; qp = workload(); "
+            "t = time.perf_counter(); r = O.solve(qp, O.Settings(tol=%r)); "
+            "print(json.dumps({'seconds': time.perf_counter() - t, 'iters': r.iters, "
+            "'threads': O.num_threads(), 'status': r.status}))") % (os.path.dirname(os.path.abspath(__file__)), tol)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    progress("oracle solve on one core")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        return {"error": out.stderr[-500:]}
+    d = json.loads(out.stdout.strip().splitlines()[-1])
+    d["QPs/s"] = 1.0 / d["seconds"]
+    return d
+
+
 def cpu_baseline(qp, tol):
     """FP64 CPU oracle on this host: one full solve of the same instance to
-    the same tolerance (about 5-15 s of CPU work)."""
+    the same tolerance (about 3-15 s of CPU work on all cores), and the same
+    solve on one core beside it."""
     from oracle import oracle as O
     O.build()
     t = time.perf_counter()
@@ -169,7 +199,8 @@ def cpu_baseline(qp, tol):
     return {"value": 1.0 / dt, "unit": "QPs/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"one full FP64 solve of the benchmark instance to relKKT <= {tol:g} "
                       f"({r.iters} iterations, {r.cg_steps} CG steps, {dt:.2f} s)",
-            "seconds_per_solve": dt, "status": r.status}
+            "seconds_per_solve": dt, "status": r.status, "cpu_model": cpu_model(),
+            "one_core": cpu_one_core(tol)}
 
 
 def spmv_rates(solver, qp, precisions=(0, 1), reps=50):
