@@ -458,6 +458,25 @@ def bench_learned(args):
     _, _, _, rw, tw = W.solve_family(fam, ids, s, x0s=x0, y0s=y0)
     _, _, _, rf, tf = W.solve_family(fam, ids, dataclasses.replace(s, warm_fallback=1), x0s=x0, y0s=y0)
     _, _, _, rx, tx = W.solve_family(fam, ids, s, x0s=x0)
+    # single-QP mode on a sample: one handle for the family (Q, A, c shared), b
+    # replaced per member, cold and warm solves with the cooperative kernel
+    n_single = min(200, args.test)
+    _, qps_s = W.family_qps(fam, list(ids)[:n_single])
+    sol = pdhcg.Solver(qps_s[0], s)
+    single = {"cold": [0.0, 0], "warm": [0.0, 0]}
+    progress(f"single-QP solves of {n_single} held-out members, cold and warm")
+    for k, q in enumerate(qps_s):
+        sol.set_b(q.b)
+        for mode, start in (("cold", (None, None)), ("warm", (x0[k], y0[k]))):
+            _, _, r = sol.solve(x0=start[0], y0=start[1])
+            assert r["status"] == 0, r["status_name"]
+            single[mode][0] += r["kernel_s"]
+            single[mode][1] += r["iters"]
+    sol.close()
+    single_row = {m: {"kernel_s": v[0], "QPs/s": n_single / v[0], "iters_mean": v[1] / n_single}
+                  for m, v in single.items()}
+    single_row["speedup_warm_vs_cold"] = single["cold"][0] / single["warm"][0]
+    single_row["sample"] = n_single
     from oracle import oracle as O
     _, qps_t = W.family_qps(fam, list(ids)[:200])
     k_pred = [O.kkt(q, a, b)["rel_kkt"] for q, a, b in zip(qps_t, x0[:200], y0[:200])]
@@ -473,7 +492,7 @@ def bench_learned(args):
                       f"epochs {args.epochs}, test {args.test}, tol {args.tol:g}",
             "train_solves_s": gen_solve_s, "train_s": train_s, "loss_first_last": [losses[0], losses[-1]],
             "infer_s": infer_s, "cold": row(rc, tc), "warm": row(rw, tw),
-            "warm_per_instance_fallback": fb, "warm_primal_only": row(rx, tx),
+            "warm_per_instance_fallback": fb, "warm_primal_only": row(rx, tx), "single_qp": single_row,
             "relkkt_pred_median": float(np.median(k_pred)), "relkkt_zero_median": float(np.median(k_zero)),
             "speedup_warm_vs_cold": tc / tw, "speedup_warm_vs_cold_incl_inference": tc / (tw + infer_s)}
 
