@@ -148,6 +148,17 @@ int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
                       double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
                       const pdhcg_settings* s, void* hip_stream);
 
+/* Solve `count` QPs that share Q, A and c and differ only in b (one family
+ * with many right-hand sides, e.g. the training data of a learned warm
+ * start): B holds b_i at B + i*m (m x count, column i = instance i), X0/Y0
+ * (may be NULL) hold the start points the same way (n x count, m x count), and
+ * X/Y receive the returned points (n x count, m x count).  All host arrays.
+ * The same batched kernel as pdhcg_solve_batch, with Q and A uploaded once;
+ * rs[i] is instance i's result.  Errors as pdhcg_solve_batch. */
+int pdhcg_solve_multi_rhs(int32_t count, const pdhcg_csr* Q, const pdhcg_csr* A, const double* B,
+                          const double* c, const double* X0, const double* Y0, double* X, double* Y,
+                          pdhcg_result* rs, const pdhcg_settings* s, void* hip_stream);
+
 /* y = M x with the library's SpMV kernel on the handle's device copy of
  * M = Q (which = 0), A (1) or A' (2), in FP64 (precision 0) or with FP32
  * values and an FP32 copy of x (precision 1, FP64 accumulation).  x and y are

@@ -1293,3 +1293,29 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
   }
   return 0;
 }
+
+// One family, many right-hand sides: the batch entry point with the shared
+// arrays passed for every instance (the packer stores a matrix given by the
+// same host pointers once).
+extern "C" int pdhcg_solve_multi_rhs(int32_t count, const pdhcg_csr* Q, const pdhcg_csr* A, const double* B,
+                                     const double* c, const double* X0, const double* Y0, double* X, double* Y,
+                                     pdhcg_result* rs, const pdhcg_settings* s, void* hip_stream) {
+  if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
+  if (count == 0) return 0;
+  if (!Q || !A || !c || !X || (A->nrows > 0 && (!B || !Y)))
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "null argument");
+  const int64_t n = Q->nrows, m = A->nrows;
+  std::vector<pdhcg_csr> Qs(count, *Q), As(count, *A);
+  std::vector<const double*> bs(count), cs(count, c), x0s(count), y0s(count);
+  std::vector<double*> xs(count), ys(count);
+  static double no_rows = 0.0;  // b and y of an instance without rows are never read
+  for (int32_t i = 0; i < count; ++i) {
+    bs[i] = m > 0 ? B + (int64_t)i * m : &no_rows;
+    x0s[i] = X0 ? X0 + (int64_t)i * n : nullptr;
+    y0s[i] = Y0 ? Y0 + (int64_t)i * m : nullptr;
+    xs[i] = X + (int64_t)i * n;
+    ys[i] = m > 0 ? Y + (int64_t)i * m : &no_rows;
+  }
+  return pdhcg_solve_batch(count, Qs.data(), As.data(), bs.data(), cs.data(), X0 ? x0s.data() : nullptr,
+                           Y0 ? y0s.data() : nullptr, xs.data(), ys.data(), rs, s, hip_stream);
+}

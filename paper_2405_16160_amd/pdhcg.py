@@ -45,8 +45,8 @@ class pdhcg_result(C.Structure):
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
 EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_spmv", "pdhcg_autotune", "pdhcg_plan_info", "pdhcg_destroy",
-           "pdhcg_error_string", "pdhcg_last_error"]
+           "pdhcg_solve_batch", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_autotune", "pdhcg_plan_info",
+           "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error"]
 
 
 class PdhcgError(RuntimeError):
@@ -80,6 +80,8 @@ def lib():
         L.pdhcg_set_b.argtypes = [P, P, C.c_int32]
         L.pdhcg_solve.argtypes = [P, P, P, P, P, C.c_int32, C.POINTER(pdhcg_result)]
         L.pdhcg_solve_batch.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
+        L.pdhcg_solve_multi_rhs.argtypes = [C.c_int32, C.POINTER(pdhcg_csr), C.POINTER(pdhcg_csr), P, P, P, P, P, P,
+                                            P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_spmv.argtypes = [P, C.c_int32, C.c_int32, P, P, C.c_int32]
         L.pdhcg_plan_info.argtypes = [P, P, P, P, P, P]
         L.pdhcg_autotune.argtypes = [P, C.c_int32, P, P]
@@ -274,3 +276,36 @@ def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None):
     _check(lib().pdhcg_solve_batch(cnt, Qs, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()),
                                    _stream_ptr()))
     return [(outs[i][0], outs[i][1][: qps[i].A.nrows], _result_dict(rs[i])) for i in range(cnt)]
+
+
+def solve_multi_rhs(Q, A, c, B, settings: Settings | None = None, X0=None, Y0=None):
+    """Solve the QPs (Q, A, B[i], c) for the rows B[i] of B (count x m) with
+    pdhcg_solve_multi_rhs (host arrays).  X0 / Y0: count x n / count x m start
+    points or None.  Returns (X, Y, results) with X count x n, Y count x m."""
+    settings = settings or Settings()
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    cnt, n, m = B.shape[0], Q.nrows, A.nrows
+    keep = []
+
+    def csr(M):
+        rp, col, val = (np.ascontiguousarray(M.rowptr, np.int64), np.ascontiguousarray(M.col, np.int32),
+                        np.ascontiguousarray(M.val, np.float64))
+        keep.extend((rp, col, val))
+        return pdhcg_csr(M.nrows, M.ncols, int(M.rowptr[-1]), rp.ctypes.data, col.ctypes.data, val.ctypes.data, 0)
+
+    def opt(a, shape):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64).reshape(shape)
+        keep.append(a)
+        return a.ctypes.data
+
+    cv = np.ascontiguousarray(c, dtype=np.float64)
+    X = np.zeros((cnt, n))
+    Y = np.zeros((cnt, max(m, 1)))
+    rs = (pdhcg_result * cnt)()
+    Qc, Ac = csr(Q), csr(A)
+    _check(lib().pdhcg_solve_multi_rhs(cnt, C.byref(Qc), C.byref(Ac), B.ctypes.data, cv.ctypes.data,
+                                       opt(X0, (cnt, n)), opt(Y0, (cnt, m)), X.ctypes.data, Y.ctypes.data, rs,
+                                       C.byref(settings.c()), _stream_ptr()))
+    return X, Y[:, :m], [_result_dict(rs[i]) for i in range(cnt)]

@@ -122,3 +122,29 @@ def test_batch_portfolio_maximum_size():
     say(f"  n=2000: batch {out[0][2]['iters']} iters, single {rs['iters']} iters, "
         f"|x_b - x_s|/|x_s| = {np.linalg.norm(xb - xs) / np.linalg.norm(xs):.2e}")
     assert np.linalg.norm(xb - xs) / np.linalg.norm(xs) <= 5e-3   # both within relKKT 1e-5 of x*
+
+
+def test_multi_rhs_matches_batch_and_oracle():
+    """One MPC family (shared Q, A, c), six right-hand sides: the multi-RHS
+    entry point returns the batch entry point's points bit for bit, each
+    meeting the relKKT test recomputed by the oracle, with and without
+    start points."""
+    from paper_2405_16160_amd import warmstart as W
+    say("[multi-rhs] MPC family, 6 members")
+    fam = I.mpc_family()
+    _, qps = W.family_qps(fam, range(6))
+    B = np.stack([q.b for q in qps])
+    s = pdhcg.Settings(tol_rel_kkt=1e-6)
+    X, Y, rs = pdhcg.solve_multi_rhs(fam.Q, fam.A, fam.c, B, s)
+    out = pdhcg.solve_batch(qps, s)
+    for i, (q, (x, y, r)) in enumerate(zip(qps, out)):
+        assert rs[i]["status"] == 0 and r["status"] == 0
+        assert np.array_equal(X[i], x) and np.array_equal(Y[i], y)
+        assert rs[i]["iters"] == r["iters"]
+        assert O.kkt(q, X[i], Y[i])["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+    # warm starts from the solutions: far fewer iterations
+    X2, Y2, rs2 = pdhcg.solve_multi_rhs(fam.Q, fam.A, fam.c, B, s, X0=X, Y0=Y)
+    for i, q in enumerate(qps):
+        assert rs2[i]["status"] == 0
+        assert rs2[i]["iters"] < rs[i]["iters"]
+        assert O.kkt(q, X2[i], Y2[i])["rel_kkt"] <= 1e-6 * (1 + 1e-6)
