@@ -134,7 +134,7 @@ def csr_bytes(nnz, nrows, ncols, sv, sx, sy=None):
     return nnz * (sv + 4) + 4 * (nrows + 1) + ncols * sx + nrows * (sx if sy is None else sy)
 
 
-def solve_bytes(qp, r, precision, dense_q=False):
+def solve_bytes(qp, r, precision, dense_q=False, rank=0):
     """Algorithmic HBM bytes of one solve, from the counts the solver reports.
     Per iteration: the n-side pass [Q|A'][x;y] in FP64 (r0 and relKKT), the
     dual step y = proj(y + sigma(A(2x+ - x) - b)) with its vectors, and the
@@ -146,6 +146,8 @@ def solve_bytes(qp, r, precision, dense_q=False):
     sv = sx = 4 if precision == 1 else 8
     if dense_q:   # a dense Q is stored as n x n values without indices: count it as such
         nq_b64, nq_bv = n * n * 8, n * n * sv
+        if rank:  # Q = F F' + diag(d) from its factor: F and F' streamed, d read
+            nq_b64, nq_bv = (2 * n * rank + n) * 8, (2 * n * rank + n) * sv
         a1 = nq_b64 + na * 12 + 4 * (n + 1) + (n + m) * 8 + 2 * n * 8
         cg = nq_bv + 11 * n * sx
         ev = nq_b64 + na * 12 + 4 * (n + 1) + (n + m) * 8 + n * 8 + csr_bytes(na, m, n, 8, 8) + 2 * m * 8
@@ -421,7 +423,25 @@ def bench_batch(args):
         sol.close()
         progress(f"one-by-one instance {i} (n={qps[i].n}): {r['solve_s']:.3f} s")
     alg = sum(solve_bytes(q, r, args.precision, dense_q=True) for q, r in zip(qps, rs))
+    # the same QPs with Q given by its factor (Q = F F' + diag(d), k = ceil(n/10))
+    progress("factored form: generating the factors")
+    fac = [I.portfolio_factor(i) for i in range(args.batch_count)]
+    t = time.perf_counter()
+    out_lr = pdhcg.solve_batch(qps, s, lowrank=fac)
+    wall_lr = time.perf_counter() - t
+    rs_lr = [o[2] for o in out_lr]
+    kernel_lr = rs_lr[0]["kernel_s"]
+    alg_lr = sum(solve_bytes(q, r, args.precision, dense_q=True, rank=f[0].shape[1])
+                 for q, r, f in zip(qps, rs_lr, fac))
+    progress(f"factored batch done in {wall_lr:.1f} s")
+    lowrank = {"solved": sum(r["status"] == 0 for r in rs_lr), "batch_kernel_s": kernel_lr, "batch_wall_s": wall_lr,
+               "QPs/s_batched": args.batch_count / kernel_lr, "iters_mean": float(np.mean([r["iters"] for r in rs_lr])),
+               "roofline": {"kernel": "pdhcg_batch_kernel", "bound": "hbm", "algorithmic_bytes": alg_lr,
+                            "achieved": alg_lr / kernel_lr / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": alg_lr / kernel_lr / 1e9 / HBM_PEAK_GBS},
+               "speedup_vs_dense_batch": kernel_s / kernel_lr, "speedup_vs_one_by_one": single_s / kernel_lr}
     return {"config": f"batched portfolio QPs x{args.batch_count}, n log-uniform [50, 2000], dense Q, tol {args.tol:g}",
+            "lowrank": lowrank,
             "solved": ok, "batch_kernel_s": kernel_s, "batch_wall_s": wall, "setup_s": setup_s,
             "roofline": {"kernel": "pdhcg_batch_kernel", "bound": "hbm", "algorithmic_bytes": alg,
                          "achieved": alg / kernel_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -148,6 +148,25 @@ int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
                       double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
                       const pdhcg_settings* s, void* hip_stream);
 
+/* A dense Q given by its factor: Q = F F' + diag(d), F n x k (row-major,
+ * k <= n), d (n); host arrays.  The portfolio model's form (Sec. 5): the
+ * batched products then read 2 n k values per product instead of n^2. */
+typedef struct {
+    int64_t n, k;
+    const double* F;
+    const double* d;
+} pdhcg_lowrank;
+
+/* pdhcg_solve_batch with every Q given by its factor (Qs[i]); A, b, c, start
+ * points, outputs, results and errors as there.  The products apply
+ * t = F' v, then F t + d v (two streamed passes over F and its transpose,
+ * which the library stores beside it). */
+int pdhcg_solve_batch_lowrank(int32_t count, const pdhcg_lowrank* Qs, const pdhcg_csr* As,
+                              const double* const* bs, const double* const* cs,
+                              const double* const* x0s, const double* const* y0s,
+                              double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                              const pdhcg_settings* s, void* hip_stream);
+
 /* Solve `count` QPs that share Q, A and c and differ only in b (one family
  * with many right-hand sides, e.g. the training data of a learned warm
  * start): B holds b_i at B + i*m (m x count, column i = instance i), X0/Y0

@@ -917,6 +917,7 @@ namespace {
 struct BatchInst {
   int32_t n = 0, m = 0;
   int32_t dense = 0;
+  int32_t q_rank = 0;  // k of a factored Q (dense = 2)
   int32_t g_n1 = 1, g_cg = 1, g_m = 1, g_t = 1;
   int32_t x0_given = 0, y0_given = 0;
   int64_t q_rp = 0, q_nz = 0, a_rp = 0, a_nz = 0, t_rp = 0, t_nz = 0;
@@ -1007,16 +1008,18 @@ struct DevBuf {
 
 }  // namespace
 
-extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As, const double* const* bs,
-                                 const double* const* cs, const double* const* x0s, const double* const* y0s,
-                                 double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
-                                 const pdhcg_settings* s, void* hip_stream) {
+// The batched solve; Q of instance i is Qs[i] (CSR, dense detected) or, when
+// Ls is given instead, the factor Ls[i] of Q = F F' + diag(d).
+int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls, const pdhcg_csr* As,
+                     const double* const* bs, const double* const* cs, const double* const* x0s,
+                     const double* const* y0s, double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                     const pdhcg_settings* s, void* hip_stream) {
   const double t0 = now_s();
   int rc;
   if ((rc = check_settings(s))) return rc;
   if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
   if (count == 0) return 0;
-  if (!Qs || !As || !bs || !cs || !x_outs || !y_outs)
+  if ((!Qs && !Ls) || !As || !bs || !cs || !x_outs || !y_outs)
     return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
   hipStream_t stream = (hipStream_t)hip_stream;
   const bool mixed = s->precision == 1;
@@ -1033,7 +1036,21 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
   std::vector<int> q_first(count, -1), a_first(count, -1);
   int64_t rp_tot = 0, nz_tot = 0, vn_tot = 0, vm_tot = 0;
   for (int i = 0; i < count; ++i) {
-    const pdhcg_csr& Q = Qs[i];
+    // a factored Q stands in as a dense n x n CSR header for the shape checks
+    pdhcg_csr Qf{};
+    if (Ls) {
+      const pdhcg_lowrank& L = Ls[i];
+      const std::string tag = "instance " + std::to_string(i);
+      if (L.n < 1 || L.k < 1 || L.k > L.n || L.n >= (1 << 30) || L.n * L.k >= (1ll << 31))
+        return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": factor sizes must satisfy 1 <= k <= n < 2^30");
+      if (!L.F || !L.d) return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": null factor array");
+      Qf.nrows = Qf.ncols = L.n;
+      Qf.nnz = 2 * L.n * L.k + L.n;  // stored values: F, F', d
+      Qf.rowptr = reinterpret_cast<const int64_t*>(L.F);  // (identity of the factor for sharing; not read)
+      Qf.col = reinterpret_cast<const int32_t*>(L.d);
+      Qf.val = L.F;
+    }
+    const pdhcg_csr& Q = Ls ? Qf : Qs[i];
     const pdhcg_csr& A = As[i];
     const std::string tag = "instance " + std::to_string(i);
     if (Q.on_device || A.on_device) return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": batch inputs must be host arrays");
@@ -1049,7 +1066,15 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     I.m = (int32_t)A.nrows;
     const Key qk{Q.rowptr, Q.col, Q.val}, ak{A.rowptr, A.col, A.val};
     auto qit = q_seen.find(qk);
-    if (qit == q_seen.end()) {
+    if (qit == q_seen.end() && Ls) {
+      I.dense = 2;
+      I.q_rank = (int32_t)Ls[i].k;
+      I.q_rp = 0;
+      I.q_nz = nz_tot;
+      nz_tot += Q.nnz;
+      q_seen[qk] = i;
+      q_first[i] = i;
+    } else if (qit == q_seen.end()) {
       if ((rc = check_structure(Q.rowptr, Q.col, Q.nrows, Q.ncols, Q.nnz, tag + " Q"))) return rc;
       const bool dense = is_dense(Q.rowptr, Q.nrows);
       if (!symmetric_ptrs(Q.rowptr, Q.col, Q.val, Q.nrows, dense))
@@ -1063,7 +1088,7 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
       q_first[i] = i;
     } else {
       const BatchInst& F = inst[qit->second];
-      I.dense = F.dense; I.q_rp = F.q_rp; I.q_nz = F.q_nz;
+      I.dense = F.dense; I.q_rank = F.q_rank; I.q_rp = F.q_rp; I.q_nz = F.q_nz;
       q_first[i] = qit->second;
     }
     auto ait = a_seen.find(ak);
@@ -1105,15 +1130,16 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     Ah.rowptr.assign(As[i].rowptr, As[i].rowptr + As[i].nrows + 1);
     I.part_off = (int64_t)parts.size();
     int32_t g[4];
-    batch_parts(Qs[q_first[i]].rowptr, I.dense != 0, I.n, Ah, T, parts, g, I.sub_off);
+    batch_parts(Ls ? nullptr : Qs[q_first[i]].rowptr, I.dense != 0, I.n, Ah, T, parts, g, I.sub_off);
     I.g_n1 = g[0]; I.g_cg = g[1]; I.g_m = g[2]; I.g_t = g[3];
   }
   // largest first: estimated work ~ entries of Q plus twice those of A
   std::vector<int32_t> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const double wa = (double)Qs[a].nnz + 2.0 * (double)As[a].nnz + inst[a].n;
-    const double wb = (double)Qs[b].nnz + 2.0 * (double)As[b].nnz + inst[b].n;
+    auto qnz = [&](int i) { return Ls ? 2.0 * (double)Ls[i].n * (double)Ls[i].k : (double)Qs[i].nnz; };
+    const double wa = qnz(a) + 2.0 * (double)As[a].nnz + inst[a].n;
+    const double wb = qnz(b) + 2.0 * (double)As[b].nnz + inst[b].n;
     return wa > wb;
   });
 
@@ -1141,7 +1167,7 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
   if ((rc = D.alloc(&d_c, vn_tot))) return rc;
   if ((rc = D.alloc(&d_part, (int64_t)count * NSLOT))) return rc;
   if ((rc = D.alloc(&d_order, count))) return rc;
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < (Ls ? 8 : 7); ++k)  // (+ F' v of a factored Q, k <= n entries)
     if ((rc = D.alloc(&nv[k], vn_tot))) return rc;
   for (int k = 0; k < 5; ++k)
     if ((rc = D.alloc(&mv[k], vm_tot))) return rc;
@@ -1162,9 +1188,20 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     return 0;
   };
   std::vector<std::vector<int32_t>> rp_keep;
+  std::vector<std::vector<double>> val_keep;  // factor blocks, alive until the uploads complete
   for (int i = 0; i < count; ++i) {
     const BatchInst& I = inst[i];
-    if (q_first[i] == i) {
+    if (q_first[i] == i && Ls) {  // block [F (n x k) | F' (k x n) | d (n)], row-major
+      const pdhcg_lowrank& L = Ls[i];
+      const int64_t n = L.n, k = L.k;
+      std::vector<double> blk((size_t)(2 * n * k + n));
+      memcpy(blk.data(), L.F, sizeof(double) * (size_t)(n * k));
+      for (int64_t r = 0; r < n; ++r)
+        for (int64_t c = 0; c < k; ++c) blk[(size_t)(n * k + c * n + r)] = L.F[r * k + c];
+      memcpy(blk.data() + 2 * n * k, L.d, sizeof(double) * (size_t)n);
+      val_keep.push_back(std::move(blk));
+      if ((rc = up(d_val + I.q_nz, val_keep.back().data(), sizeof(double) * val_keep.back().size()))) return rc;
+    } else if (q_first[i] == i) {
       const pdhcg_csr& Q = Qs[i];
       if (!I.dense) {
         rp_keep.emplace_back(Q.rowptr, Q.rowptr + Q.nrows + 1);
@@ -1196,7 +1233,8 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     const BatchInst& I = inst[i];
     SolveParams& P = hp[i];
     P.Q = DevMat{I.n, I.n, I.dense ? nullptr : d_rp + I.q_rp, I.dense ? nullptr : d_col + I.q_nz, d_val + I.q_nz,
-                 d_val32 ? d_val32 + I.q_nz : nullptr, I.dense};
+                 d_val32 ? d_val32 + I.q_nz : nullptr, I.dense, I.q_rank};
+    P.lr_t = Ls ? nv[7] + I.voff_n : nullptr;
     P.A = DevMat{I.m, I.n, d_rp + I.a_rp, d_col + I.a_nz, d_val + I.a_nz, d_val32 ? d_val32 + I.a_nz : nullptr, 0};
     P.At = DevMat{I.n, I.m, d_rp + I.t_rp, d_col + I.t_nz, d_val + I.t_nz, d_val32 ? d_val32 + I.t_nz : nullptr, 0};
     P.n = I.n;
@@ -1292,6 +1330,23 @@ extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg
     }
   }
   return 0;
+}
+
+extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As, const double* const* bs,
+                                 const double* const* cs, const double* const* x0s, const double* const* y0s,
+                                 double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                                 const pdhcg_settings* s, void* hip_stream) {
+  if (!Qs) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
+  return solve_batch_impl(count, Qs, nullptr, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream);
+}
+
+extern "C" int pdhcg_solve_batch_lowrank(int32_t count, const pdhcg_lowrank* Qs, const pdhcg_csr* As,
+                                         const double* const* bs, const double* const* cs,
+                                         const double* const* x0s, const double* const* y0s,
+                                         double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                                         const pdhcg_settings* s, void* hip_stream) {
+  if (!Qs) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
+  return solve_batch_impl(count, nullptr, Qs, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream);
 }
 
 // One family, many right-hand sides: the batch entry point with the shared

@@ -21,7 +21,8 @@ struct DevMat {
   const int32_t* col;
   const double* val;
   const float* val32;
-  int32_t dense;
+  int32_t dense;     // 0 CSR; 1 dense n x n rows; 2 Q = F F' + diag(d) from its factor (batch only)
+  int32_t rank;      // k of the factor when dense = 2 (0 otherwise)
 };
 
 constexpr int kDenseTile = 2048;  // doubles of the LDS tile that stages the vector of a dense product
@@ -146,6 +147,7 @@ struct SolveParams {
   // batched kernel)
   float *x32, *r32, *p32_0, *p32_1;
   float4 *v32_0, *v32_1;
+  double* lr_t;  // k-vector F' v of a factored dense Q (batch only)
   double* part;         // [NSLOT][nb]
   uint64_t* bar;        // grid barrier words (zeroed before each launch)
   SolverState* st;

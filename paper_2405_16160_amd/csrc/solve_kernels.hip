@@ -32,28 +32,32 @@ __device__ __forceinline__ double pos_part(double v) { return v > 0.0 ? v : (v =
 // One pass of a dense product over rows i0 + tid + k * kBlock, k < K (rows
 // clamped into range: surplus rows are computed and dropped, so every load
 // is unconditional and kJ * K of them are in flight per thread).
+// The pass is written for a rectangular M (nr rows streamed, nc columns
+// owned, row-major): out_c = sum_j M[j, c] v_j, which for a symmetric square M
+// is the product M v and for a tall factor F gives F' v.
 template <int K, typename V, typename Gen>
-__device__ __forceinline__ void dense_pass(const V* M, int n, int i0, double* svec, Gen& gen, double* acc) {
-  constexpr int kJ = 8;  // columns per unrolled step
+__device__ __forceinline__ void dense_pass(const V* M, int nr, int nc, int i0, double* svec, Gen& gen,
+                                           double* acc) {
+  constexpr int kJ = 8;  // rows per unrolled step
   int ic[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     acc[k] = 0.0;
-    ic[k] = min(i0 + (int)threadIdx.x + k * kBlock, n - 1);
+    ic[k] = min(i0 + (int)threadIdx.x + k * kBlock, nc - 1);
   }
-  for (int j0 = 0; j0 < n; j0 += kDenseTile) {
-    const int jt = n - j0 < kDenseTile ? n - j0 : kDenseTile;
+  for (int j0 = 0; j0 < nr; j0 += kDenseTile) {
+    const int jt = nr - j0 < kDenseTile ? nr - j0 : kDenseTile;
     __syncthreads();
     for (int j = threadIdx.x; j < jt; j += kBlock) svec[j] = gen(j0 + j, i0 == 0);
     __syncthreads();
-    const V* base = M + (int64_t)j0 * n;
+    const V* base = M + (int64_t)j0 * nc;
     int j = 0;
     for (; j + kJ <= jt; j += kJ) {
       V v[kJ][K];
 #pragma unroll
       for (int jj = 0; jj < kJ; ++jj)
 #pragma unroll
-        for (int k = 0; k < K; ++k) v[jj][k] = gld(base + (int64_t)(j + jj) * n + ic[k]);
+        for (int k = 0; k < K; ++k) v[jj][k] = gld(base + (int64_t)(j + jj) * nc + ic[k]);
 #pragma unroll
       for (int jj = 0; jj < kJ; ++jj) {
         const double sj = svec[j + jj];
@@ -64,33 +68,56 @@ __device__ __forceinline__ void dense_pass(const V* M, int n, int i0, double* sv
     for (; j < jt; ++j) {
       const double sj = svec[j];
 #pragma unroll
-      for (int k = 0; k < K; ++k) acc[k] += (double)gld(base + (int64_t)j * n + ic[k]) * sj;
+      for (int k = 0; k < K; ++k) acc[k] += (double)gld(base + (int64_t)j * nc + ic[k]) * sj;
     }
   }
 }
 
+// out_c = sum_j M[j, c] v_j for all c < nc, v_j = gen(j, first) (first: the
+// first column pass, where gen may store what it forms), epi(c, out_c)
 template <typename V, typename Gen, typename Epi>
-__device__ void dense_rows(const V* M, int n, double* svec, Gen gen, Epi epi) {
-  for (int i0 = 0; i0 < n; i0 += kBlock * kDenseRows) {
+__device__ void rect_rows(const V* M, int nr, int nc, double* svec, Gen& gen, Epi& epi) {
+  for (int i0 = 0; i0 < nc; i0 += kBlock * kDenseRows) {
     double acc[kDenseRows];
-    const int rows = n - i0;
-    const int K = rows > 3 * kBlock ? 4 : (rows > 2 * kBlock ? 3 : (rows > kBlock ? 2 : 1));  // uniform
-    if (K == 4) dense_pass<4>(M, n, i0, svec, gen, acc);
-    else if (K == 3) dense_pass<3>(M, n, i0, svec, gen, acc);
-    else if (K == 2) dense_pass<2>(M, n, i0, svec, gen, acc);
-    else dense_pass<1>(M, n, i0, svec, gen, acc);
+    const int cols = nc - i0;
+    const int K = cols > 3 * kBlock ? 4 : (cols > 2 * kBlock ? 3 : (cols > kBlock ? 2 : 1));  // uniform
+    if (K == 4) dense_pass<4>(M, nr, nc, i0, svec, gen, acc);
+    else if (K == 3) dense_pass<3>(M, nr, nc, i0, svec, gen, acc);
+    else if (K == 2) dense_pass<2>(M, nr, nc, i0, svec, gen, acc);
+    else dense_pass<1>(M, nr, nc, i0, svec, gen, acc);
 #pragma unroll
     for (int k = 0; k < kDenseRows; ++k) {
       const int i = i0 + (int)threadIdx.x + k * kBlock;
-      if (k < K && i < n) epi(i, acc[k]);
+      if (k < K && i < nc) epi(i, acc[k]);
     }
   }
   __syncthreads();
 }
 
+// Q v for a dense Q of one workgroup: full n x n rows (Q.dense = 1), or Q =
+// F F' + diag(d) from its factor (Q.dense = 2; Q.rank = k; the block holds F
+// (n x k), F' (k x n) and d, row-major, at M): t = F' v into tscr (k), then
+// F t + d v, 2 n k values read instead of n^2.
+template <typename V, typename Gen, typename Epi>
+__device__ void dense_rows(const V* M, const DevMat& Q, double* svec, double* tscr, Gen gen, Epi epi) {
+  const int n = Q.nrows;
+  if (Q.dense != 2) {
+    rect_rows(M, n, n, svec, gen, epi);
+    return;
+  }
+  const int k = Q.rank;
+  const V* Ft = M + (int64_t)n * k;
+  const V* d = Ft + (int64_t)k * n;
+  auto put_t = [&](int c, double s) { tscr[c] = s; };
+  rect_rows(M, n, k, svec, gen, put_t);  // (ends with a workgroup barrier: tscr visible)
+  auto get_t = [&](int c, bool) { return tscr[c]; };
+  auto fin = [&](int i, double s) { epi(i, s + (double)d[i] * gen(i, false)); };
+  rect_rows(Ft, k, n, svec, get_t, fin);
+}
+
 // q = Q xv for a dense Q owned by one workgroup
 __device__ __attribute__((noinline)) void dense_qx(const SolveParams& P, const double* xv, double* svec) {
-  dense_rows(P.Q.val, P.n, svec, [&](int j, bool) { return xv[j]; }, [&](int i, double v) { P.q[i] = v; });
+  dense_rows(P.Q.val, P.Q, svec, P.lr_t, [&](int j, bool) { return xv[j]; }, [&](int i, double v) { P.q[i] = v; });
 }
 
 // CG product for a dense Q owned by one workgroup: stage p in LDS, stream Q
@@ -100,7 +127,7 @@ __device__ __attribute__((noinline)) void dense_cg_spmv(const SolveParams& P, Bl
                                                         double inv_tau, double* lds, double* svec) {
   double s[1] = {0.0}, dummy[1] = {0.0};
   dense_rows(
-      qd, P.n, svec,
+      qd, P.Q, svec, P.lr_t,
       [&](int j, bool first_pass) {
         const double pj = first ? P.r[j] : P.r[j] + beta * pprev[j];
         if (first_pass) pcur[j] = pj;

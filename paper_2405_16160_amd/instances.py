@@ -181,17 +181,28 @@ def powerlaw_qp(n=2_000_000, m=1_000_000, a_mean=8.0, q_pairs_per_row=2, family=
     return QP(CSR.from_scipy(Q), CSR.from_scipy(A), b, c, name=f"powerlaw_qp(n={n},m={m},seed={family}/{instance})")
 
 
-def portfolio_qp(instance=0, n=None, family=4, nmin=50, nmax=2000) -> QP:
-    """Portfolio QP in direct form: Q = F F' + diag(d) (dense), F n x ceil(n/10)
-    with N(0, 1/n) entries, d ~ U[0.01, 0.1], c = -mu with mu ~ N(0.05, 0.02^2);
-    rows 1'x <= 1, -1'x <= -1 (the budget equality as a +/- pair) and -x <= 0.
-    n is log-uniform in [nmin, nmax] unless given."""
+def _portfolio_factor(instance, n, family, nmin, nmax):
     rng = _rng(family, instance)
     if n is None:
         n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
     k = int(math.ceil(n / 10))
     F = rng.standard_normal((n, k)) / math.sqrt(n)
     d = rng.uniform(0.01, 0.1, n)
+    return n, F, d, rng
+
+
+def portfolio_factor(instance=0, n=None, family=4, nmin=50, nmax=2000):
+    """(F, d) of portfolio_qp's Q = F F' + diag(d) for the same arguments."""
+    _, F, d, _ = _portfolio_factor(instance, n, family, nmin, nmax)
+    return F, d
+
+
+def portfolio_qp(instance=0, n=None, family=4, nmin=50, nmax=2000) -> QP:
+    """Portfolio QP in direct form: Q = F F' + diag(d) (dense), F n x ceil(n/10)
+    with N(0, 1/n) entries, d ~ U[0.01, 0.1], c = -mu with mu ~ N(0.05, 0.02^2);
+    rows 1'x <= 1, -1'x <= -1 (the budget equality as a +/- pair) and -x <= 0.
+    n is log-uniform in [nmin, nmax] unless given."""
+    n, F, d, rng = _portfolio_factor(instance, n, family, nmin, nmax)
     Qd = F @ F.T
     Qd = 0.5 * (Qd + Qd.T)
     Qd[np.diag_indices(n)] += d

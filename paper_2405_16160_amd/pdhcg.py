@@ -34,6 +34,10 @@ class pdhcg_settings(C.Structure):
                 ("warm_fallback", C.c_int32), ("verbose", C.c_int32), ("cg_form", C.c_int32)]
 
 
+class pdhcg_lowrank(C.Structure):
+    _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("F", C.c_void_p), ("d", C.c_void_p)]
+
+
 class pdhcg_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("returned_average", C.c_int32), ("rel_primal", C.c_double),
                 ("rel_dual", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double),
@@ -45,7 +49,7 @@ class pdhcg_result(C.Structure):
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
 EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_autotune", "pdhcg_plan_info",
+           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_autotune", "pdhcg_plan_info",
            "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error"]
 
 
@@ -80,6 +84,7 @@ def lib():
         L.pdhcg_set_b.argtypes = [P, P, C.c_int32]
         L.pdhcg_solve.argtypes = [P, P, P, P, P, C.c_int32, C.POINTER(pdhcg_result)]
         L.pdhcg_solve_batch.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
+        L.pdhcg_solve_batch_lowrank.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_solve_multi_rhs.argtypes = [C.c_int32, C.POINTER(pdhcg_csr), C.POINTER(pdhcg_csr), P, P, P, P, P, P,
                                             P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_spmv.argtypes = [P, C.c_int32, C.c_int32, P, P, C.c_int32]
@@ -235,13 +240,16 @@ class Solver:
             pass
 
 
-def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None):
+def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None, lowrank=None):
     """Solve a list of QPs with pdhcg_solve_batch (host arrays in and out).
-    Returns a list of (x, y, result) with numpy arrays."""
+    lowrank: optional list of (F, d) with Q_i = F F' + diag(d) (then
+    pdhcg_solve_batch_lowrank; qps[i].Q is not read).  Returns a list of
+    (x, y, result) with numpy arrays."""
     settings = settings or Settings()
     cnt = len(qps)
     keep = []
     Qs = (pdhcg_csr * cnt)()
+    Ls = (pdhcg_lowrank * cnt)() if lowrank is not None else None
     As = (pdhcg_csr * cnt)()
     bs = (C.c_void_p * cnt)()
     cs = (C.c_void_p * cnt)()
@@ -257,7 +265,10 @@ def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None):
         return a
 
     for i, qp in enumerate(qps):
-        for M, dst in ((qp.Q, Qs), (qp.A, As)):
+        if Ls is not None:
+            F, d = arr(lowrank[i][0], np.float64), arr(lowrank[i][1], np.float64)
+            Ls[i] = pdhcg_lowrank(F.shape[0], F.shape[1], F.ctypes.data, d.ctypes.data)
+        for M, dst in (((qp.A, As),) if Ls is not None else ((qp.Q, Qs), (qp.A, As))):
             rp, col, val = arr(M.rowptr, np.int64), arr(M.col, np.int32), arr(M.val, np.float64)
             dst[i] = pdhcg_csr(M.nrows, M.ncols, int(M.rowptr[-1]), rp.ctypes.data, col.ctypes.data,
                                val.ctypes.data, 0)
@@ -273,8 +284,12 @@ def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None):
         if y0 is not None and y0s[i] is not None:
             y0[i] = arr(y0s[i], np.float64).ctypes.data
     rs = (pdhcg_result * cnt)()
-    _check(lib().pdhcg_solve_batch(cnt, Qs, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()),
-                                   _stream_ptr()))
+    if Ls is not None:
+        _check(lib().pdhcg_solve_batch_lowrank(cnt, Ls, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()),
+                                               _stream_ptr()))
+    else:
+        _check(lib().pdhcg_solve_batch(cnt, Qs, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()),
+                                       _stream_ptr()))
     return [(outs[i][0], outs[i][1][: qps[i].A.nrows], _result_dict(rs[i])) for i in range(cnt)]
 
 

@@ -148,3 +148,25 @@ def test_multi_rhs_matches_batch_and_oracle():
         assert rs2[i]["status"] == 0
         assert rs2[i]["iters"] < rs[i]["iters"]
         assert O.kkt(q, X2[i], Y2[i])["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_lowrank_portfolio(precision):
+    """Portfolio Q given by its factor (Q = F F' + diag(d), F n x ceil(n/10)):
+    the same QPs as the dense form, so the same contract against the oracle
+    run on the dense Q; and beside them the largest size (n = 2000)."""
+    say(f"[batch lowrank] 6 portfolio QPs n <= 400 + n = 2000, precision={precision}")
+    ids = list(range(6))
+    qps = [I.portfolio_qp(i, nmax=400) for i in ids] + [I.portfolio_qp(900, n=2000)]
+    fac = [I.portfolio_factor(i, nmax=400) for i in ids] + [I.portfolio_factor(900, n=2000)]
+    tol = 1e-7 if precision == 0 else 1e-5
+    out = pdhcg.solve_batch(qps, pdhcg.Settings(tol_rel_kkt=tol, precision=precision, max_iters=400_000),
+                            lowrank=fac)
+    for j, (qp, (x, y, r)) in enumerate(zip(qps, out)):
+        say(f"  n={qp.n} status={r['status_name']} iters={r['iters']}")
+        assert r["status"] == 0, r
+        assert O.kkt(qp, x, y)["rel_kkt"] <= tol * (1 + 1e-6)
+        assert np.all(y >= 0)
+        if precision == 0 and qp.n <= 400:
+            ref = O.solve(qp, O.Settings(tol=1e-9, max_iters=1_000_000))
+            contract(qp, x, y, ref, 1e-6)
