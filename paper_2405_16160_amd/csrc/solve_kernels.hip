@@ -94,6 +94,52 @@ __device__ void rect_rows(const V* M, int nr, int nc, double* svec, Gen& gen, Ep
   __syncthreads();
 }
 
+// t = F' v for a factor with k <= 256 columns and n <= kDenseTile rows, v
+// already in svec: wave w takes rows w, w + kWaves, ... and its lanes the
+// columns lane + 64 q (all waves busy, where one thread per column would
+// leave most of them idle); the waves' partial sums are added in LDS in a
+// fixed order.  red holds kWaves * 256 doubles.
+template <int Q4, typename V>
+__device__ void factor_tv(const V* F, int n, int k, const double* svec, double* red, double* t) {
+  constexpr int kJ = 8;  // rows per unrolled step (per wave)
+  const int tid = (int)threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  double acc[Q4];
+  int cc[Q4];
+#pragma unroll
+  for (int q = 0; q < Q4; ++q) {
+    acc[q] = 0.0;
+    cc[q] = min(lane + kWave * q, k - 1);
+  }
+  for (int j = w; j < n; j += kWaves * kJ) {
+    V u[kJ][Q4];
+#pragma unroll
+    for (int jj = 0; jj < kJ; ++jj) {
+      const int row = min(j + kWaves * jj, n - 1);
+#pragma unroll
+      for (int q = 0; q < Q4; ++q) u[jj][q] = gld(F + (int64_t)row * k + cc[q]);
+    }
+#pragma unroll
+    for (int jj = 0; jj < kJ; ++jj) {
+      const int row = j + kWaves * jj;
+      const double vj = row < n ? svec[row] : 0.0;
+#pragma unroll
+      for (int q = 0; q < Q4; ++q) acc[q] += (double)u[jj][q] * vj;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q4; ++q) {
+    const int c = lane + kWave * q;
+    if (c < k) red[w * 256 + c] = acc[q];
+  }
+  __syncthreads();
+  for (int c = tid; c < k; c += kBlock) {
+    double sum = red[c];
+    for (int ww = 1; ww < kWaves; ++ww) sum += red[ww * 256 + c];
+    t[c] = sum;
+  }
+  __syncthreads();
+}
+
 // Q v for a dense Q of one workgroup: full n x n rows (Q.dense = 1), or Q =
 // F F' + diag(d) from its factor (Q.dense = 2; Q.rank = k; the block holds F
 // (n x k), F' (k x n) and d, row-major, at M): t = F' v into tscr (k), then
@@ -108,8 +154,19 @@ __device__ void dense_rows(const V* M, const DevMat& Q, double* svec, double* ts
   const int k = Q.rank;
   const V* Ft = M + (int64_t)n * k;
   const V* d = Ft + (int64_t)k * n;
-  auto put_t = [&](int c, double s) { tscr[c] = s; };
-  rect_rows(M, n, k, svec, gen, put_t);  // (ends with a workgroup barrier: tscr visible)
+  if (n <= kDenseTile && k <= 256) {
+    __syncthreads();
+    for (int j = (int)threadIdx.x; j < n; j += kBlock) svec[j] = gen(j, true);
+    __syncthreads();
+    double* red = tile_lds().prod;  // no tile is staged during a dense product
+    if (k <= 64) factor_tv<1>(M, n, k, svec, red, tscr);
+    else if (k <= 128) factor_tv<2>(M, n, k, svec, red, tscr);
+    else if (k <= 192) factor_tv<3>(M, n, k, svec, red, tscr);
+    else factor_tv<4>(M, n, k, svec, red, tscr);
+  } else {
+    auto put_t = [&](int c, double s) { tscr[c] = s; };
+    rect_rows(M, n, k, svec, gen, put_t);  // (ends with a workgroup barrier: tscr visible)
+  }
   auto get_t = [&](int c, bool) { return tscr[c]; };
   auto fin = [&](int i, double s) { epi(i, s + (double)d[i] * gen(i, false)); };
   rect_rows(Ft, k, n, svec, get_t, fin);
