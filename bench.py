@@ -113,7 +113,7 @@ def parse():
                     help="with --summarize-counters: a file holding the bench line of the profiled run "
                          "(its algorithmic bytes per launch)")
     ap.add_argument("--config", default="random1e5",
-                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "precision"],
+                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "precision", "kappa"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--train", type=int, default=20_000)
@@ -452,6 +452,33 @@ def bench_batch(args):
             "one_by_one_sample": len(sample), "speedup": single_s / kernel_s}
 
 
+def bench_kappa(args):
+    """Condition sweep (the shape of Table 2): n = m = 5e4, A at density 1e-3,
+    Q with condition number kappa in 1 .. 1e5 (kappa_qp).  PDHCG (adaptive CG)
+    against CG capped at one step (the linearised primal step), each to tol,
+    the capped runs bounded by a 20 s time limit."""
+    import torch
+    from paper_2405_16160_amd import instances as I, pdhcg
+    rows = []
+    for kappa in (1.0, 1e1, 1e2, 1e3, 1e4, 1e5):
+        qp = I.kappa_qp(kappa)
+        row = {"kappa": kappa}
+        for name, extra in (("pdhcg", {}), ("cg_cap_1", {"max_cg_iters": 1, "cg_rule": 1})):
+            st = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=1_000_000,
+                                time_limit_s=20.0, **extra)
+            sol = pdhcg.Solver(qp, st)
+            _, _, r = sol.solve()
+            torch.cuda.synchronize()
+            sol.close()
+            row[name] = {"status": r["status_name"], "iters": r["iters"], "cg_steps": r["cg_iters_total"],
+                         "kernel_ms": r["kernel_s"] * 1e3, "rel_kkt": r["rel_kkt"]}
+            progress(f"kappa {kappa:g} {name}: {r['status_name']} {r['iters']} iterations, "
+                     f"{r['cg_iters_total']} CG steps, {r['kernel_s'] * 1e3:.1f} ms")
+        rows.append(row)
+    return {"config": f"condition sweep, kappa_qp n=m=5e4, A density 1e-3, tol {args.tol:g}, "
+                      f"precision {args.precision}", "rows": rows}
+
+
 def bench_learned(args):
     """Learned warm start on the MPC family: train on PDHCG solutions, then
     batched cold vs warm solves of held-out members to tol."""
@@ -581,7 +608,7 @@ def main():
         return
 
     if args.config != "random1e5":
-        line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch,
+        line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch, "kappa": bench_kappa,
                 "learned": bench_learned, "precision": bench_precision}[args.config](args)
         print(json.dumps(line), flush=True)
         return

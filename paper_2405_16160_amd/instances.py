@@ -191,6 +191,37 @@ def _portfolio_factor(instance, n, family, nmin, nmax):
     return n, F, d, rng
 
 
+def kappa_qp(kappa, n=50_000, m=50_000, a_density=1e-3, block=8, family=6, instance=0) -> QP:
+    """Random QP whose Q has condition number exactly kappa (the condition
+    sweep of Table 2's shape): Q = P B diag(lam) B' P' with lam log-spaced in
+    [1/kappa, 1], B block diagonal with random orthogonal block x block blocks
+    (QR of Gaussian blocks) and P a random permutation (block nonzeros per
+    row); A (m x n) Bernoulli(a_density) Gaussian, c ~ N(0,1),
+    b = A x0 + U[0,1] with x0 ~ N(0,1)."""
+    rng = _rng(family, instance)
+    nb = n // block
+    assert nb * block == n, "n must be a multiple of block"
+    lam = np.logspace(-math.log10(kappa), 0.0, n) if kappa > 1 else np.ones(n)
+    lam = lam[rng.permutation(n)]
+    rows, cols, vals = [], [], []
+    for b0 in range(nb):
+        G = rng.standard_normal((block, block))
+        U, _ = np.linalg.qr(G)
+        Bq = U @ np.diag(lam[b0 * block:(b0 + 1) * block]) @ U.T
+        ii, jj = np.meshgrid(np.arange(block), np.arange(block), indexing="ij")
+        rows.append((b0 * block + ii).ravel())
+        cols.append((b0 * block + jj).ravel())
+        vals.append(Bq.ravel())
+    perm = rng.permutation(n)
+    Q = sp.csr_matrix((np.concatenate(vals), (perm[np.concatenate(rows)], perm[np.concatenate(cols)])), shape=(n, n))
+    Q = _symmetrize(Q)
+    A = _sparse_gaussian(rng, m, n, a_density)
+    c = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    b = A @ x0 + rng.uniform(0.0, 1.0, m)
+    return QP(CSR.from_scipy(Q), CSR.from_scipy(A), b, c, name=f"kappa_qp(kappa={kappa:g},n={n},m={m})")
+
+
 def portfolio_factor(instance=0, n=None, family=4, nmin=50, nmax=2000):
     """(F, d) of portfolio_qp's Q = F F' + diag(d) for the same arguments."""
     _, F, d, _ = _portfolio_factor(instance, n, family, nmin, nmax)
