@@ -10,7 +10,7 @@ costs accuracy: the solve that starts from it stops on the same relKKT test.
 Whether predictions pay is decided per family on held-out members
 (`validate`), not per instance.  The solver's per-instance fallback
 (warm_fallback: a start point whose relKKT exceeds that of (0, 0) is replaced
-by (0, 0)) is a poor judge for families with c = 0 such as MPC: (0, 0) is then
+by (0, 0)) is a poor guide for families with c = 0 such as MPC: (0, 0) is then
 exactly dual feasible, so its relKKT is the primal residual alone, while any
 error in a predicted dual shows up undamped in the dual residual (whose
 denominator 1 + ||c|| is 1).  Predictions that start far closer to the optimum
