@@ -443,9 +443,12 @@ int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) 
   h->max_nb = std::max(1, std::min(cus * std::max(per_cu, 1), 1024));
   int nb = h->s.num_blocks;
   if (nb == 0) {
+    // about a thousand work units per workgroup: below that the grid barrier
+    // outweighs the work it spreads (n = 1000 random QP: 64 workgroups
+    // 65 ms, 16 70 ms, 128 69 ms per solve)
     const double work = (double)h->nnzQ + 0.25 * (double)h->nnzA + (double)(h->n + h->m);
     nb = 8;
-    while (nb < 256 && work / nb > 4096.0) nb <<= 1;
+    while (nb < 256 && work / nb > 1024.0) nb <<= 1;
   }
   h->qrp_h = Q.rowptr;
   if (A.nrows) {
