@@ -121,9 +121,9 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nb, cons
 // every wave of the workgroup waits until its stores are complete (written to
 // the L2); the last workgroup of an XCD to arrive then writes that L2 back to
 // memory once, for the whole XCD, and arrives on the device-scope counter; the
-// last XCD publishes the new generation.  Waiters poll the generation with
-// relaxed device-scope loads and take one acquire fence (invalidating their
-// L1 and the XCD's L2).  The XCD of a workgroup is read from the hardware
+// last XCD publishes the new generation, one copy per XCD on a line of its own.
+// Waiters poll their XCD's copy with relaxed device-scope loads and take one
+// acquire fence (invalidating their L1 and the XCD's L2).  The XCD of a workgroup is read from the hardware
 // register that names it, and the number of the grid's workgroups on each XCD
 // is counted once per launch (init), so the barrier holds for any placement of
 // workgroups on XCDs.  Counters grow monotonically within a launch (64-bit),
@@ -132,10 +132,11 @@ __device__ __forceinline__ void reduce_partials(const double* part, int nb, cons
 // other waiter then returns false too.
 namespace bar {
 constexpr int kMaxXcd = 16;
-constexpr int kCount = 0, kGen = 32, kAbort = kBarAbortWord, kSetup = 96;  // word offsets (256 bytes apart)
+constexpr int kCount = 0, kAbort = kBarAbortWord, kSetup = 96;  // word offsets (256 bytes apart)
 constexpr int kXcdArrive = 128;                     // + 32 x: arrivals of XCD x (in its L2)
 constexpr int kXcdCount = kXcdArrive + 32 * kMaxXcd;  // + 32 x: workgroups on XCD x
-constexpr int kWords = kXcdCount + 32 * kMaxXcd;
+constexpr int kXcdGen = kXcdCount + 32 * kMaxXcd;     // + 32 x: the generation, one copy per XCD
+constexpr int kWords = kXcdGen + 32 * kMaxXcd;
 static_assert(kWords <= kBarWords, "barrier words");
 }  // namespace bar
 
@@ -220,13 +221,13 @@ struct GridSync {
         if (a == (uint64_t)xsize * epoch - 1) {  // last of its XCD: write the XCD's L2 back once
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           const uint64_t t = PDHCG_ADD(&w[bar::kCount], 1ull);
-          if (t == (uint64_t)nxcd * epoch - 1) {
+          if (t == (uint64_t)nxcd * epoch - 1) {  // publish to every XCD's own line
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            PDHCG_ST(&w[bar::kGen], epoch);
+            for (int x = 0; x < bar::kMaxXcd; ++x) PDHCG_ST(&w[bar::kXcdGen + 32 * x], epoch);
           }
         }
-        wait_word(bar::kGen, epoch, ok);
+        wait_word(bar::kXcdGen + 32 * xcd, epoch, ok);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       ok_s = ok;
