@@ -1,0 +1,94 @@
+"""Pins of the oracle's diagonal preconditioning (Ruiz + Pock-Chambolle on
+K = [[Q, A'], [A, 0]], Section 5) against hand-derived closed forms, the
+defining property of Ruiz equilibration and the invariance of the solution
+under the rescaling.  CPU only."""
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+from oracle import oracle as O
+from oracle import precondition as P
+from paper_2405_16160_amd import instances as I
+
+
+def _qp(Q, A, b, c):
+    return I.QP(I.CSR.from_scipy(sp.csr_matrix(np.atleast_2d(np.asarray(Q, float)))),
+                I.CSR.from_scipy(sp.csr_matrix(np.atleast_2d(np.asarray(A, float)))),
+                np.asarray(b, float), np.asarray(c, float))
+
+
+def test_one_by_one_closed_form():
+    # K = [[4, 1], [1, 0]].  Ruiz step 1 divides index 0 by sqrt(4) and leaves
+    # index 1 (row max 1): K -> [[1, 1/2], [1/2, 0]].  From then on the row max
+    # of index 0 stays 1 and the off-diagonal a_k obeys a_{k+1} = sqrt(a_k), so
+    # after 10 steps a = 2^(-2^-9), d2 = 1/2, d1 = 2^(1 - 2^-9).  The
+    # Pock-Chambolle step then divides index 0 by sqrt(1 + a) and index 1 by
+    # sqrt(a).
+    qp = _qp([[4.0]], [[1.0]], [1.0], [1.0])
+    d1, d2 = P.scaling(qp.Q, qp.A, ruiz_iters=10, pock_chambolle=False)
+    assert math.isclose(d2[0], 0.5, rel_tol=1e-15)
+    assert math.isclose(d1[0], 2.0 ** (1 - 2.0 ** -9), rel_tol=1e-14)
+    a = 2.0 ** (-2.0 ** -9)
+    d1, d2 = P.scaling(qp.Q, qp.A, ruiz_iters=10, pock_chambolle=True)
+    assert math.isclose(d2[0], 0.5 / math.sqrt(1.0 + a), rel_tol=1e-14)
+    assert math.isclose(d1[0], 2.0 ** (1 - 2.0 ** -9) / math.sqrt(a), rel_tol=1e-14)
+
+
+def test_pock_chambolle_alone_closed_form():
+    # Q = I3, A = [[1, 1, 0], [0, 1, -1]]: every entry has magnitude 1, so the
+    # 1-norms are the entry counts: variables 2, 3, 2 (Q's diagonal plus A's
+    # column), constraints 2, 2.
+    qp = _qp(np.eye(3), [[1.0, 1.0, 0.0], [0.0, 1.0, -1.0]], [1.0, 1.0], [0.0, 0.0, 0.0])
+    d1, d2 = P.scaling(qp.Q, qp.A, ruiz_iters=0, pock_chambolle=True)
+    np.testing.assert_allclose(d2, [1 / math.sqrt(2), 1 / math.sqrt(3), 1 / math.sqrt(2)], rtol=1e-15)
+    np.testing.assert_allclose(d1, [1 / math.sqrt(2), 1 / math.sqrt(2)], rtol=1e-15)
+    # no step at all leaves the identity
+    d1, d2 = P.scaling(qp.Q, qp.A, ruiz_iters=0, pock_chambolle=False)
+    assert np.all(d1 == 1.0) and np.all(d2 == 1.0)
+
+
+def test_ruiz_equilibrates_every_row_and_column_of_the_scaled_blocks():
+    # Ruiz equilibration converges to a matrix whose rows and columns all have
+    # largest magnitude 1.  Checked on the blocks of the scaled problem (Q~ and
+    # A~ from scale_qp, not the K the factors were computed on), so a wrong
+    # orientation of A or of a factor fails here.
+    qp = I.random_qp(n=300, m=120, r_rows=150, q_density=0.03, a_density=0.05, family=1, instance=3)
+    qp.A.val[:] *= np.exp(np.random.default_rng(7).uniform(-4, 4, qp.A.nnz))  # badly scaled rows
+    d1, d2 = P.scaling(qp.Q, qp.A, ruiz_iters=60, pock_chambolle=False)
+    s = P.scale_qp(qp, d1, d2)
+    Qh, Ah = abs(s.Q.to_scipy()), abs(s.A.to_scipy())
+    var_max = np.maximum(Qh.max(axis=1).toarray().ravel(), Ah.max(axis=0).toarray().ravel())
+    con_max = Ah.max(axis=1).toarray().ravel()
+    np.testing.assert_allclose(var_max, 1.0, rtol=1e-9)
+    np.testing.assert_allclose(con_max, 1.0, rtol=1e-9)
+    # the scaled Q stays exactly symmetric (each entry times d_i d_j)
+    Qd = s.Q.to_scipy()
+    assert (Qd != Qd.T).nnz == 0
+
+
+def test_empty_rows_and_columns_keep_factor_one():
+    # variable 2 appears nowhere (zero column of Q and A); constraint 1 is an
+    # all-zero row
+    Q = np.diag([2.0, 3.0, 0.0])
+    A = np.array([[1.0, -2.0, 0.0], [0.0, 0.0, 0.0]])
+    qp = _qp(Q, A, [1.0, 1.0], [1.0, -1.0, 0.0])
+    d1, d2 = P.scaling(qp.Q, qp.A)
+    assert d2[2] == 1.0 and d1[1] == 1.0
+    assert np.all(np.isfinite(d1)) and np.all(np.isfinite(d2)) and np.all(d1 > 0) and np.all(d2 > 0)
+
+
+def test_solution_maps_back_to_the_unscaled_optimum():
+    # The rescaling is a change of variables: x = D2 x~, y = D1 y~ solves the
+    # original problem.  A wrong direction of b~, c~, x or y fails here.
+    for qp in (I.tiny_qp(6, 10, instance=4), I.random_qp(n=200, m=80, r_rows=100, q_density=0.05,
+                                                         a_density=0.05, family=1, instance=5)):
+        ref = O.solve(qp, O.Settings(tol=1e-10, max_iters=400_000))
+        x, y, r, d1, d2 = P.solve(qp, O.Settings(tol=1e-10, max_iters=400_000))
+        assert ref.status == O.OPTIMAL and r.status == O.OPTIMAL
+        assert np.linalg.norm(x - ref.x) <= 1e-6 * max(1.0, np.linalg.norm(ref.x))
+        k = O.kkt(qp, x, y)
+        assert k["rel_kkt"] <= 1e-7
+        assert abs(k["primal_obj"] - ref.primal_obj) <= 1e-8 * (1 + abs(ref.primal_obj))
+        # the scaled objective equals the original one at corresponding points
+        assert math.isclose(r.primal_obj, ref.primal_obj, rel_tol=1e-7, abs_tol=1e-9)
