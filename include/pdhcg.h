@@ -94,6 +94,16 @@ typedef struct {
                                         per step with (r, u, s) gathered (Chronopoulos-Gear),
                                         2 = textbook CG, two barriers per step with only the
                                         direction gathered */
+    int32_t ruiz_iters;              /* 0 (off); diagonal preconditioning of the single-QP handle
+                                        (Sec. 5, preprocessing): Ruiz equilibration steps on
+                                        K = [[Q, A'], [A, 0]], the paper runs 10.  The solver then
+                                        works on D2 Q D2, D1 A D2, D1 b, D2 c; relKKT, the
+                                        residuals and the termination refer to that scaled problem,
+                                        the objective values are those of the original one, and
+                                        x = D2 x~, y = D1 y~ are returned.  Fixed at pdhcg_create;
+                                        the batched entry points reject a nonzero value */
+    int32_t pock_chambolle;          /* 0 (off); 1: one Pock-Chambolle step (alpha = 1) after the
+                                        Ruiz steps; same rules as ruiz_iters */
 } pdhcg_settings;
 
 typedef struct {
@@ -178,11 +188,19 @@ int pdhcg_solve_multi_rhs(int32_t count, const pdhcg_csr* Q, const pdhcg_csr* A,
                           const double* c, const double* X0, const double* Y0, double* X, double* Y,
                           pdhcg_result* rs, const pdhcg_settings* s, void* hip_stream);
 
+/* The diagonals of the preconditioning of a handle (Sec. 5, preprocessing):
+ * d1_out[m] = D1 (constraint rows), d2_out[n] = D2 (variables); all ones when
+ * ruiz_iters = 0 and pock_chambolle = 0 at pdhcg_create.  Outputs are device
+ * pointers when vec_on_device = 1, else host pointers; d1_out may be NULL when
+ * m = 0.  Returns INVALID_ARGUMENT for a null handle or output. */
+int pdhcg_get_scaling(const pdhcg_handle* h, double* d1_out, double* d2_out, int32_t vec_on_device);
+
 /* y = M x with the library's SpMV kernel on the handle's device copy of
  * M = Q (which = 0), A (1) or A' (2), in FP64 (precision 0) or with FP32
  * values and an FP32 copy of x (precision 1, FP64 accumulation).  x and y are
  * FP64 device pointers.  repeats > 1 launches the same product back to back
- * (for timing).  Test and measurement entry point. */
+ * (for timing).  With preconditioning on, M is the scaled matrix.  Test and
+ * measurement entry point. */
 int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* x, double* y,
                int32_t repeats);
 

@@ -268,6 +268,8 @@ struct pdhcg_handle {
   double *r_alt = nullptr, *u0 = nullptr, *u1 = nullptr, *s0 = nullptr, *s1 = nullptr;
   float4 *v32_0 = nullptr, *v32_1 = nullptr;   // interleaved FP32 (r, u, s) of the one-reduction CG
   double *part = nullptr, *tmp_x0 = nullptr, *tmp_y0 = nullptr, *scratch = nullptr;
+  double* dscale = nullptr;  // D2 (n) then D1 (m) of the preconditioning; ones when off
+  bool scaled = false;       // the device data are the preconditioned problem
   uint64_t* bar = nullptr;
   SolverState* st = nullptr;
   SolveParams* d_params = nullptr;
@@ -392,6 +394,9 @@ int check_settings(const pdhcg_settings* s) {
   if (s->precision != 0 && s->precision != 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "precision must be 0 or 1");
   if (s->num_blocks < 0 || s->num_blocks > 4096) return fail(PDHCG_ERR_INVALID_ARGUMENT, "num_blocks out of range");
   if (s->cg_form < 0 || s->cg_form > 2) return fail(PDHCG_ERR_INVALID_ARGUMENT, "cg_form must be 0, 1 or 2");
+  if (s->ruiz_iters < 0 || s->ruiz_iters > 100) return fail(PDHCG_ERR_INVALID_ARGUMENT, "ruiz_iters must be in [0, 100]");
+  if (s->pock_chambolle != 0 && s->pock_chambolle != 1)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "pock_chambolle must be 0 or 1");
   return 0;
 }
 
@@ -641,6 +646,8 @@ void pdhcg_default_settings(pdhcg_settings* s) {
   s->warm_fallback = 1;
   s->verbose = 0;
   s->cg_form = 0;
+  s->ruiz_iters = 0;
+  s->pock_chambolle = 0;
 }
 
 int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, const double* b, const double* c,
@@ -700,6 +707,32 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
   if ((rc = h->alloc(&h->d_params, 1))) return bail(rc);
   if ((rc = upload(h, h->b, hb.data(), m))) return bail(rc);
   if ((rc = upload(h, h->c, hc.data(), n))) return bail(rc);
+  if ((rc = h->alloc(&h->dscale, n + m))) return bail(rc);
+  {
+    const std::vector<double> ones(n + m, 1.0);
+    if ((rc = upload(h, h->dscale, ones.data(), n + m))) return bail(rc);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(PDHCG_ERR_HIP, "stream sync failed"));
+  }
+  if (s->ruiz_iters > 0 || s->pock_chambolle) {
+    // preconditioning (Sec. 5): scale Q, A, A', b, c on the device, then take
+    // the norms that relKKT uses from the scaled b and c
+    double* f = nullptr;
+    if ((rc = h->alloc(&f, n + m))) return bail(rc);
+    if (launch_precondition(h->mat(0), h->mat(1), h->mat(2), s->ruiz_iters, s->pock_chambolle, f, h->dscale,
+                            h->stream) != hipSuccess ||
+        launch_diag(h->b, h->dscale + n, m, 0, h->b, h->stream) != hipSuccess ||
+        launch_diag(h->c, h->dscale, n, 0, h->c, h->stream) != hipSuccess)
+      return bail(fail(PDHCG_ERR_HIP, "preconditioning kernels failed to launch"));
+    if ((m > 0 && hipMemcpyAsync(hb.data(), h->b, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess) ||
+        hipMemcpyAsync(hc.data(), h->c, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return bail(fail(PDHCG_ERR_HIP, "preconditioning failed"));
+    h->nb_inf = max_abs_nan(hb.data(), m);
+    h->nc_inf = max_abs_nan(hc.data(), n);
+    h->kkt_zero = kkt_at_zero(hb.data(), m, hc.data(), n);
+    h->c_host = hc;
+    h->scaled = true;
+  }
   if ((rc = plan(h, Q, A, T))) return bail(rc);
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
     return bail(fail(PDHCG_ERR_HIP, "hipEventCreate failed"));
@@ -719,6 +752,8 @@ int pdhcg_set_settings(pdhcg_handle* h, const pdhcg_settings* s) {
   if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
   int rc;
   if ((rc = check_settings(s))) return rc;
+  if (s->ruiz_iters != h->s.ruiz_iters || s->pock_chambolle != h->s.pock_chambolle)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "ruiz_iters and pock_chambolle are fixed at pdhcg_create");
   const bool replan = s->num_blocks != 0 && s->num_blocks != h->nb;
   const int32_t old_power = h->s.power_iters;
   h->s = *s;
@@ -734,6 +769,10 @@ int pdhcg_set_b(pdhcg_handle* h, const double* b, int32_t vec_on_device) {
   if (h->m > 0) {
     HIPX(hipMemcpy(hb.data(), b, sizeof(double) * h->m, vec_on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
     HIPX(hipMemcpyAsync(h->b, hb.data(), sizeof(double) * h->m, hipMemcpyHostToDevice, h->stream));
+    if (h->scaled) {  // b~ = D1 b
+      HIPX(launch_diag(h->b, h->dscale + h->n, h->m, 0, h->b, h->stream));
+      HIPX(hipMemcpyAsync(hb.data(), h->b, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->stream));
+    }
     HIPX(hipStreamSynchronize(h->stream));
   }
   h->nb_inf = max_abs_nan(hb.data(), h->m);
@@ -753,10 +792,12 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
   hipMemcpyKind in_kind = vec_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (x0) {
     HIPX(hipMemcpyAsync(h->tmp_x0, x0, sizeof(double) * h->n, in_kind, h->stream));
+    if (h->scaled) HIPX(launch_diag(h->tmp_x0, h->dscale, h->n, 1, h->tmp_x0, h->stream));  // x~ = x / D2
     dx0 = h->tmp_x0;
   }
   if (y0 && h->m > 0) {
     HIPX(hipMemcpyAsync(h->tmp_y0, y0, sizeof(double) * h->m, in_kind, h->stream));
+    if (h->scaled) HIPX(launch_diag(h->tmp_y0, h->dscale + h->n, h->m, 1, h->tmp_y0, h->stream));  // y~ = y / D1
     dy0 = h->tmp_y0;
   }
   SolveParams p = make_params(h);
@@ -794,8 +835,16 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
   }
   if (st.done < 0) return fail(PDHCG_ERR_HIP, "grid barrier timed out in the solve kernel");
   hipMemcpyKind out_kind = vec_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  HIPX(hipMemcpyAsync(x_out, h->x, sizeof(double) * h->n, out_kind, h->stream));
-  if (h->m > 0) HIPX(hipMemcpyAsync(y_out, h->y, sizeof(double) * h->m, out_kind, h->stream));
+  const double* xr = h->x;
+  const double* yr = h->y;
+  if (h->scaled) {  // x = D2 x~, y = D1 y~ (the start-point buffers are free again)
+    HIPX(launch_diag(h->x, h->dscale, h->n, 0, h->tmp_x0, h->stream));
+    HIPX(launch_diag(h->y, h->dscale + h->n, h->m, 0, h->tmp_y0, h->stream));
+    xr = h->tmp_x0;
+    yr = h->tmp_y0;
+  }
+  HIPX(hipMemcpyAsync(x_out, xr, sizeof(double) * h->n, out_kind, h->stream));
+  if (h->m > 0) HIPX(hipMemcpyAsync(y_out, yr, sizeof(double) * h->m, out_kind, h->stream));
   HIPX(hipStreamSynchronize(h->stream));
   if (res) {
     res->status = st.status;
@@ -816,6 +865,15 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
     res->kkt_evals = st.evals;
     res->cold_fallback = st.cold_fallback;
   }
+  return 0;
+}
+
+int pdhcg_get_scaling(const pdhcg_handle* h, double* d1_out, double* d2_out, int32_t vec_on_device) {
+  if (!h || !d2_out || (h->m > 0 && !d1_out)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle or output");
+  const hipMemcpyKind kind = vec_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPX(hipMemcpyAsync(d2_out, h->dscale, sizeof(double) * h->n, kind, h->stream));
+  if (h->m > 0) HIPX(hipMemcpyAsync(d1_out, h->dscale + h->n, sizeof(double) * h->m, kind, h->stream));
+  HIPX(hipStreamSynchronize(h->stream));
   return 0;
 }
 
@@ -1020,6 +1078,8 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
   const double t0 = now_s();
   int rc;
   if ((rc = check_settings(s))) return rc;
+  if (s->ruiz_iters != 0 || s->pock_chambolle != 0)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "preconditioning is available on single-QP handles only");
   if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
   if (count == 0) return 0;
   if ((!Qs && !Ls) || !As || !bs || !cs || !x_outs || !y_outs)

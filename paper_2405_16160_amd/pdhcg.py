@@ -31,7 +31,8 @@ class pdhcg_settings(C.Structure):
                 ("eval_period", C.c_int32), ("primal_weight_theta", C.c_double),
                 ("primal_weight_init", C.c_double), ("step_eta_factor", C.c_double), ("power_iters", C.c_int32),
                 ("precision", C.c_int32), ("time_limit_s", C.c_double), ("num_blocks", C.c_int32),
-                ("warm_fallback", C.c_int32), ("verbose", C.c_int32), ("cg_form", C.c_int32)]
+                ("warm_fallback", C.c_int32), ("verbose", C.c_int32), ("cg_form", C.c_int32),
+                ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32)]
 
 
 class pdhcg_lowrank(C.Structure):
@@ -49,7 +50,7 @@ class pdhcg_result(C.Structure):
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
 EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_autotune", "pdhcg_plan_info",
+           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_get_scaling", "pdhcg_autotune", "pdhcg_plan_info",
            "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error"]
 
 
@@ -89,6 +90,7 @@ def lib():
                                             P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_spmv.argtypes = [P, C.c_int32, C.c_int32, P, P, C.c_int32]
         L.pdhcg_plan_info.argtypes = [P, P, P, P, P, P]
+        L.pdhcg_get_scaling.argtypes = [P, P, P, C.c_int32]
         L.pdhcg_autotune.argtypes = [P, C.c_int32, P, P]
         L.pdhcg_destroy.argtypes = [P]
         L.pdhcg_destroy.restype = None
@@ -128,6 +130,8 @@ class Settings:
     warm_fallback: int = 1
     verbose: int = 0
     cg_form: int = 0
+    ruiz_iters: int = 0
+    pock_chambolle: int = 0
 
     def c(self) -> pdhcg_settings:
         s = pdhcg_settings()
@@ -215,6 +219,15 @@ class Solver:
         y = out if out is not None else torch.empty(max(nrows, 1), dtype=torch.float64, device=self.dev)
         _check(lib().pdhcg_spmv(self.h, which, precision, xt.data_ptr(), y.data_ptr(), repeats))
         return y[:nrows]
+
+    def scaling(self):
+        """(d1, d2): the diagonals D1 (m) and D2 (n) of the preconditioning, as
+        float64 device tensors (ones when it is off)."""
+        import torch
+        d1 = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.dev)
+        d2 = torch.empty(self.n, dtype=torch.float64, device=self.dev)
+        _check(lib().pdhcg_get_scaling(self.h, d1.data_ptr(), d2.data_ptr(), 1))
+        return d1[: self.m], d2
 
     def autotune(self, iters: int = 50) -> dict:
         nb, g = C.c_int32(), C.c_int32()
