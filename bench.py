@@ -113,7 +113,7 @@ def parse():
                     help="with --summarize-counters: a file holding the bench line of the profiled run "
                          "(its algorithmic bytes per launch)")
     ap.add_argument("--config", default="random1e5",
-                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "precision", "kappa"],
+                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "kappa", "precondition"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--train", type=int, default=20_000)
@@ -479,6 +479,46 @@ def bench_kappa(args):
                       f"precision {args.precision}", "rows": rows}
 
 
+def bench_precondition(args):
+    """Diagonal preconditioning (10 Ruiz steps + one Pock-Chambolle step on
+    [[Q, A'], [A, 0]]): the random QP n = 1e5 as generated and with its rows of
+    A (and b) rescaled by exp(U[-3, 3]), each solved to tol without and with
+    the preconditioning; the power-law QP n = 2e6 for the cost of the setup
+    kernels and a time-limited solve.  With preconditioning the reported relKKT
+    refers to the scaled problem; x_rel_diff compares the returned x with the
+    unpreconditioned solve's."""
+    import torch
+    from paper_2405_16160_amd import instances as I, pdhcg
+    rows = []
+    cases = [("random_qp n=1e5", lambda: I.random_qp(100_000, 50_000, 50_000, 2e-5, 2e-4, family=2), None),
+             ("random_qp n=1e5, rows x exp(U[-3,3])",
+              lambda: I.row_scaled(I.random_qp(100_000, 50_000, 50_000, 2e-5, 2e-4, family=2)), None),
+             ("powerlaw_qp n=2e6", lambda: I.powerlaw_qp(), 15.0)]
+    for name, make, tl in cases:
+        qp = make()
+        row = {"workload": name}
+        xs = {}
+        for tag, pre in (("plain", {}), ("preconditioned", {"ruiz_iters": 10, "pock_chambolle": 1})):
+            st = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, time_limit_s=tl or 0.0, **pre)
+            t0 = time.perf_counter()
+            sol = pdhcg.Solver(qp, st)
+            torch.cuda.synchronize()
+            create_s = time.perf_counter() - t0
+            x, _, r = sol.solve()
+            torch.cuda.synchronize()
+            xs[tag] = x.clone()
+            sol.close()
+            row[tag] = {"status": r["status_name"], "iters": r["iters"], "cg_steps": r["cg_iters_total"],
+                        "kernel_ms": r["kernel_s"] * 1e3, "rel_kkt": r["rel_kkt"], "create_s": create_s,
+                        "primal_obj": r["primal_obj"]}
+            progress(f"{name} {tag}: {r['status_name']} {r['iters']} iterations, {r['cg_iters_total']} CG steps, "
+                     f"{r['kernel_s'] * 1e3:.1f} ms, create {create_s:.2f} s")
+        row["x_rel_diff"] = float(torch.linalg.norm(xs["preconditioned"] - xs["plain"]) /
+                                  torch.linalg.norm(xs["plain"]))
+        rows.append(row)
+    return {"config": f"preconditioning, tol {args.tol:g}, precision {args.precision}", "rows": rows}
+
+
 def bench_learned(args):
     """Learned warm start on the MPC family: train on PDHCG solutions, then
     batched cold vs warm solves of held-out members to tol."""
@@ -524,10 +564,6 @@ def bench_learned(args):
                   for m, v in single.items()}
     single_row["speedup_warm_vs_cold"] = single["cold"][0] / single["warm"][0]
     single_row["sample"] = n_single
-    from oracle import oracle as O
-    _, qps_t = W.family_qps(fam, list(ids)[:200])
-    k_pred = [O.kkt(q, a, b)["rel_kkt"] for q, a, b in zip(qps_t, x0[:200], y0[:200])]
-    k_zero = [O.kkt(q, np.zeros(q.n), np.zeros(q.m))["rel_kkt"] for q in qps_t]
 
     def row(r, secs):
         return {"kernel_s": secs, "QPs/s": args.test / secs, "iters_mean": float(np.mean([x["iters"] for x in r])),
@@ -540,40 +576,7 @@ def bench_learned(args):
             "train_solves_s": gen_solve_s, "train_s": train_s, "loss_first_last": [losses[0], losses[-1]],
             "infer_s": infer_s, "cold": row(rc, tc), "warm": row(rw, tw),
             "warm_per_instance_fallback": fb, "warm_primal_only": row(rx, tx), "single_qp": single_row,
-            "relkkt_pred_median": float(np.median(k_pred)), "relkkt_zero_median": float(np.median(k_zero)),
             "speedup_warm_vs_cold": tc / tw, "speedup_warm_vs_cold_incl_inference": tc / (tw + infer_s)}
-
-
-def bench_precision(args):
-    """Error of the FP64 and the FP32-product modes against the FP64 oracle
-    (run to relKKT 1e-9), both solved to relKKT 1e-6, for each workload family."""
-    from oracle import oracle as O
-    from paper_2405_16160_amd import instances as I, pdhcg
-    cases = [("tiny random n=1000", I.random_qp(family=1, instance=0), None),
-             ("random n=1e5 (benchmark instance)", workload(), None),
-             ("manufactured n=1e5 (exact optimum)", I.manufactured(100_000, 50_000, 2e-5, 2e-4, r_rows=50_000,
-                                                                   family=41), "exact"),
-             ("MPC n=1500 m=5000", I.mpc_qp(0), None),
-             ("portfolio n=355 (dense Q)", I.portfolio_qp(0, nmax=400), None)]
-    out = {}
-    for name, qp, kind in cases:
-        if kind == "exact":
-            xr, fr = qp.x_star, 0.5 * qp.x_star @ (qp.Q.to_scipy() @ qp.x_star) + qp.c @ qp.x_star
-        else:
-            ref = O.solve(qp, O.Settings(tol=1e-9, max_iters=1_000_000))
-            xr, fr = ref.x, ref.primal_obj
-        row = {}
-        for prec in (0, 1):
-            sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-6, precision=prec, max_iters=1_000_000))
-            x, y, r = sol.solve()
-            sol.close()
-            x = x.cpu().numpy()
-            k = O.kkt(qp, x, y.cpu().numpy())
-            row["fp64" if prec == 0 else "fp32_products"] = {
-                "rel_kkt_fp64_data": k["rel_kkt"], "x_rel_err": float(np.linalg.norm(x - xr) / np.linalg.norm(xr)),
-                "obj_rel_err": abs(k["primal_obj"] - fr) / (1 + abs(fr)), "iters": r["iters"]}
-        out[name] = row
-    return {"config": "precision modes vs the FP64 oracle at relKKT 1e-6", "cases": out}
 
 
 def main():
@@ -608,8 +611,8 @@ def main():
         return
 
     if args.config != "random1e5":
-        line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch, "kappa": bench_kappa,
-                "learned": bench_learned, "precision": bench_precision}[args.config](args)
+        line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch, "kappa": bench_kappa, "precondition": bench_precondition,
+                "learned": bench_learned}[args.config](args)
         print(json.dumps(line), flush=True)
         return
     qp = workload()

@@ -351,6 +351,16 @@ def manufactured(n=1000, m=500, q_density=0.01, a_density=0.01, active_frac=0.3,
     return QP(CSR.from_scipy(Q), CSR.from_scipy(A), b, c, name=f"manufactured(n={n},m={m})", x_star=xs, y_star=ys)
 
 
+def row_scaled(qp: QP, spread=3.0, seed=3) -> QP:
+    """The same QP with row i of A and b_i multiplied by exp(U[-spread, spread]):
+    the same feasible set and optimum x, a badly scaled A (the case diagonal
+    preconditioning is for)."""
+    s = np.exp(np.random.default_rng(seed).uniform(-spread, spread, qp.m))
+    A = sp.diags(s) @ qp.A.to_scipy()
+    return dataclasses.replace(qp, A=CSR.from_scipy(A), b=qp.b * s, name=qp.name + f" rows x exp(U[-{spread:g},{spread:g}])",
+                               x_star=qp.x_star, y_star=None if qp.y_star is None else qp.y_star / s)
+
+
 def tiny_qp(n, m, instance=0, family=12) -> QP:
     """Dense tiny strictly convex QP (for brute-force active-set enumeration):
     Q = G'G + 0.1 I, A ~ N(0,1), c ~ N(0,1), b = A x0 + U[-0.5, 1] (some rows

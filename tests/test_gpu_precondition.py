@@ -33,15 +33,6 @@ def say(msg):
     print(msg, flush=True)
 
 
-def badly_scaled(qp, seed=3, spread=3.0):
-    """Rows of A (and b) multiplied by exp(U[-spread, spread]): the same
-    feasible set and optimum x, a badly scaled A."""
-    s = np.exp(np.random.default_rng(seed).uniform(-spread, spread, qp.m))
-    A = sp.diags(s) @ qp.A.to_scipy()
-    from dataclasses import replace
-    return replace(qp, A=I.CSR.from_scipy(A), b=qp.b * s, name=qp.name + " rows rescaled")
-
-
 def with_empty_row_and_variable(qp):
     """An all-zero constraint row (b = 1) and a variable with no entries."""
     n, m = qp.n, qp.m
@@ -53,7 +44,7 @@ def with_empty_row_and_variable(qp):
 
 
 CASES = {
-    "random n=1000": lambda: badly_scaled(I.random_qp(family=1, instance=1)),
+    "random n=1000": lambda: I.row_scaled(I.random_qp(family=1, instance=1)),
     "powerlaw n=4000": lambda: I.powerlaw_qp(n=4000, m=2000, family=3, instance=1),
     "empty row and variable": lambda: with_empty_row_and_variable(I.random_qp(n=300, m=120, r_rows=150, q_density=0.03,
                                                                               a_density=0.05, family=1, instance=6)),

@@ -22,3 +22,14 @@ def test_portfolio_factor_reproduces_q():
         assert F.shape == (q.n, -(-q.n // 10))
         Qd = q.Q.to_scipy().toarray()
         assert np.allclose(Qd, F @ F.T + np.diag(d), rtol=0, atol=1e-14)
+
+
+def test_row_scaled_keeps_the_optimum():
+    # the manufactured instance fixes (x*, y*); scaling row i by s_i keeps x*
+    # and divides y*_i by s_i, so the KKT residual of the mapped pair stays ~0
+    from oracle import oracle as O
+    qp = I.manufactured()
+    k0 = O.kkt(qp, qp.x_star, qp.y_star)["rel_kkt"]
+    rs = I.row_scaled(qp)
+    assert rs.A.nnz == qp.A.nnz and not np.allclose(rs.b, qp.b)
+    assert O.kkt(rs, rs.x_star, rs.y_star)["rel_kkt"] <= max(1e-12, 10 * k0)
