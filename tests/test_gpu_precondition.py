@@ -127,3 +127,20 @@ def test_batch_rejects_preconditioning_and_settings_are_fixed():
     x, y, r = sol.solve()
     assert r["status"] == 0
     sol.close()
+
+
+def test_unconstrained_preconditioned():
+    """m = 0: D1 is empty, D2 scales Q alone; the solve reaches x* = -Q^-1 c."""
+    say("[precondition] unconstrained n=150 (m = 0)")
+    qp = I.unconstrained(150)
+    e1, e2 = P.scaling(qp.Q, qp.A, 10, True)
+    assert e1.size == 0
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-10, **PRE))
+    d1, d2 = sol.scaling()
+    assert d1.numel() == 0
+    np.testing.assert_allclose(d2.cpu().numpy(), e2, rtol=1e-13, atol=0)
+    x, _, r = sol.solve()
+    assert r["status"] == 0
+    xs = -np.linalg.solve(qp.Q.to_scipy().toarray(), qp.c)
+    assert np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs) < 1e-7
+    sol.close()
