@@ -144,3 +144,27 @@ def test_unconstrained_preconditioned():
     xs = -np.linalg.solve(qp.Q.to_scipy().toarray(), qp.c)
     assert np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs) < 1e-7
     sol.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_preconditioned_powerlaw_solve_matches_oracle(precision):
+    """Power-law rows (the family the preprocessing is for): the preconditioned
+    solve against the oracle's preconditioned solve at 1e-9."""
+    say(f"[precondition] solve, powerlaw n=4000 m=2000, precision={precision}")
+    qp = CASES["powerlaw n=4000"]()
+    if "pl" not in _REF:
+        _REF["pl"] = P.solve(qp, O.Settings(tol=1e-9, max_iters=400_000))
+    xr, yr, rr, e1, e2 = _REF["pl"]
+    assert rr.status == O.OPTIMAL
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-6, precision=precision, **PRE))
+    x, y, r = sol.solve()
+    sol.close()
+    say(f"  status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} kkt={r['rel_kkt']:.2e}")
+    assert r["status"] == 0
+    x, y = x.cpu().numpy(), y.cpu().numpy()
+    assert np.all(y >= 0.0)
+    k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
+    assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+    assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-3
+    assert abs(O.kkt(qp, x, y)["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-5
