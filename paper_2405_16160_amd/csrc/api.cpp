@@ -718,8 +718,8 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
     // the norms that relKKT uses from the scaled b and c
     double* f = nullptr;
     if ((rc = h->alloc(&f, n + m))) return bail(rc);
-    if (launch_precondition(h->mat(0), h->mat(1), h->mat(2), s->ruiz_iters, s->pock_chambolle, f, h->dscale,
-                            h->stream) != hipSuccess ||
+    if (launch_precondition(h->mat(0), h->mat(1), h->mat(2), h->nnzQ, h->nnzA, s->ruiz_iters, s->pock_chambolle, f,
+                            h->dscale, h->stream) != hipSuccess ||
         launch_diag(h->b, h->dscale + n, m, 0, h->b, h->stream) != hipSuccess ||
         launch_diag(h->c, h->dscale, n, 0, h->c, h->stream) != hipSuccess)
       return bail(fail(PDHCG_ERR_HIP, "preconditioning kernels failed to launch"));

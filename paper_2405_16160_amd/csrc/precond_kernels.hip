@@ -11,16 +11,23 @@
 // the exact transpose of A).  The accumulated diagonal d holds D2 in d[0, n)
 // and D1 in d[n, n + m).
 //
-// A one-time setup pass: one thread per row, rows in a grid-stride loop.
+// A one-time setup pass.  Each row is walked by a group of g lanes (a power
+// of two up to 64, sized by the host to the mean row length) reading
+// consecutive entries, so the loads of a group are coalesced and a long row
+// costs len/g steps; the group combines its partial maxima or sums with lane
+// exchanges.  Rows are taken in a grid-stride loop; all lanes of a group see
+// the same row, so the exchanges only read active lanes.
 #include "device.hpp"
 
 namespace pdhcg {
 
 namespace {
 
-__device__ __forceinline__ double row_stat(const int32_t* rp, const double* v, int64_t i, int mode, double acc) {
+// this lane's share (entries lane, lane + g, ...) of row i's max or 1-norm
+__device__ __forceinline__ double row_stat(const int32_t* rp, const double* v, int64_t i, int mode, int lane, int g,
+                                           double acc) {
   const int32_t e = rp[i + 1];
-  for (int32_t k = rp[i]; k < e; ++k) {
+  for (int32_t k = rp[i] + lane; k < e; k += g) {
     const double a = fabs(v[k]);
     acc = mode == 0 ? fmax(acc, a) : acc + a;
   }
@@ -30,31 +37,41 @@ __device__ __forceinline__ double row_stat(const int32_t* rp, const double* v, i
 // f[i] = 1 / sqrt(stat of row i of K) (1 for a zero row), d[i] *= f[i];
 // mode 0: largest magnitude, mode 1: 1-norm
 __global__ void scale_factor_kernel(int64_t n, int64_t m, const int32_t* qrp, const double* qv, const int32_t* trp,
-                                    const double* tv, const int32_t* arp, const double* av, int mode, double* f,
-                                    double* d) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + m; i += stride) {
+                                    const double* tv, const int32_t* arp, const double* av, int mode, int g,
+                                    double* f, double* d) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = (int)(t & (g - 1));
+  const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / g;
+  for (int64_t i = t / g; i < n + m; i += stride) {
     double s;
     if (i < n) {
-      s = row_stat(qrp, qv, i, mode, 0.0);
-      if (m > 0) s = row_stat(trp, tv, i, mode, s);
+      s = row_stat(qrp, qv, i, mode, lane, g, 0.0);
+      if (m > 0) s = row_stat(trp, tv, i, mode, lane, g, s);
     } else {
-      s = row_stat(arp, av, i - n, mode, 0.0);
+      s = row_stat(arp, av, i - n, mode, lane, g, 0.0);
     }
-    const double fi = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
-    f[i] = fi;
-    d[i] *= fi;
+    for (int off = g >> 1; off > 0; off >>= 1) {
+      const double o = __shfl_xor(s, off, g);
+      s = mode == 0 ? fmax(s, o) : s + o;
+    }
+    if (lane == 0) {
+      const double fi = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+      f[i] = fi;
+      d[i] *= fi;
+    }
   }
 }
 
 // val of row i, column j times fr[i] * fc[j]
 __global__ void scale_apply_kernel(int64_t nrows, const int32_t* rp, const int32_t* col, double* val,
-                                   const double* fr, const double* fc) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows; i += stride) {
+                                   const double* fr, const double* fc, int g) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = (int)(t & (g - 1));
+  const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / g;
+  for (int64_t i = t / g; i < nrows; i += stride) {
     const double a = fr[i];
     const int32_t e = rp[i + 1];
-    for (int32_t k = rp[i]; k < e; ++k) val[k] *= a * fc[col[k]];
+    for (int32_t k = rp[i] + lane; k < e; k += g) val[k] *= a * fc[col[k]];
   }
 }
 
@@ -70,31 +87,49 @@ int grid_for(int64_t n) {
   return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
 }
 
-hipError_t apply(const DevMat& M, const double* fr, const double* fc, hipStream_t s) {
-  if (M.nrows == 0) return hipSuccess;
-  hipLaunchKernelGGL(scale_apply_kernel, dim3(grid_for(M.nrows)), dim3(kBlock), 0, s, (int64_t)M.nrows, M.rowptr,
-                     M.col, const_cast<double*>(M.val), fr, fc);
+// lanes per row: the power of two nearest above the mean row length, 1..64
+int lanes_for(int64_t nnz, int64_t nrows) {
+  const double mean = nrows > 0 ? (double)nnz / (double)nrows : 1.0;
+  int g = 1;
+  while (g < 64 && g < mean) g <<= 1;
+  return g;
+}
+
+struct Groups {
+  int q, a, t, k;  // lanes per row of Q, A, A' and of the rows of K
+};
+
+hipError_t apply(const DevMat& M, int64_t nnz, const double* fr, const double* fc, int g, hipStream_t s) {
+  if (M.nrows == 0 || nnz == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_apply_kernel, dim3(grid_for((int64_t)M.nrows * g)), dim3(kBlock), 0, s, (int64_t)M.nrows,
+                     M.rowptr, M.col, const_cast<double*>(M.val), fr, fc, g);
   return hipGetLastError();
 }
 
-hipError_t step(const DevMat& Q, const DevMat& A, const DevMat& T, int mode, double* f, double* d, hipStream_t s) {
+hipError_t step(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq, int64_t nnza, const Groups& G,
+                int mode, double* f, double* d, hipStream_t s) {
   const int64_t n = Q.nrows, m = A.nrows;
-  hipLaunchKernelGGL(scale_factor_kernel, dim3(grid_for(n + m)), dim3(kBlock), 0, s, n, m, Q.rowptr, Q.val,
-                     T.rowptr, T.val, A.rowptr, A.val, mode, f, d);
+  hipLaunchKernelGGL(scale_factor_kernel, dim3(grid_for((n + m) * G.k)), dim3(kBlock), 0, s, n, m, Q.rowptr, Q.val,
+                     T.rowptr, T.val, A.rowptr, A.val, mode, G.k, f, d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = apply(Q, f, f, s)) != hipSuccess) return e;
-  if ((e = apply(A, f + n, f, s)) != hipSuccess) return e;
-  return apply(T, f, f + n, s);
+  if ((e = apply(Q, nnzq, f, f, G.q, s)) != hipSuccess) return e;
+  if ((e = apply(A, nnza, f + n, f, G.a, s)) != hipSuccess) return e;
+  return apply(T, nnza, f, f + n, G.t, s);
 }
 
 }  // namespace
 
-hipError_t launch_precondition(const DevMat& Q, const DevMat& A, const DevMat& T, int ruiz_iters, int pock_chambolle,
-                               double* f, double* d, hipStream_t s) {
+hipError_t launch_precondition(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq, int64_t nnza,
+                               int ruiz_iters, int pock_chambolle, double* f, double* d, hipStream_t s) {
+  Groups G;
+  G.q = lanes_for(nnzq, Q.nrows);
+  G.a = lanes_for(nnza, A.nrows);
+  G.t = lanes_for(nnza, T.nrows);
+  G.k = lanes_for(nnzq + 2 * nnza, (int64_t)Q.nrows + A.nrows);
   hipError_t e = hipSuccess;
-  for (int it = 0; it < ruiz_iters && e == hipSuccess; ++it) e = step(Q, A, T, 0, f, d, s);
-  if (e == hipSuccess && pock_chambolle) e = step(Q, A, T, 1, f, d, s);
+  for (int it = 0; it < ruiz_iters && e == hipSuccess; ++it) e = step(Q, A, T, nnzq, nnza, G, 0, f, d, s);
+  if (e == hipSuccess && pock_chambolle) e = step(Q, A, T, nnzq, nnza, G, 1, f, d, s);
   return e;
 }
 
