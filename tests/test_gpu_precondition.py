@@ -168,3 +168,27 @@ def test_preconditioned_powerlaw_solve_matches_oracle(precision):
     assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
     assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-3
     assert abs(O.kkt(qp, x, y)["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-5
+
+
+def test_powerlaw_full_size_preconditioned():
+    """The power-law configuration at its full size (n = 2e6, m = 1e6), in the
+    launch configuration of the preconditioning benchmark (default plan, FP32
+    products, tol 1e-4): D1, D2 against the oracle's element by element; the
+    solve reaches tol, and its reported relKKT equals the oracle's FP64
+    recomputation on the oracle-scaled problem at the returned point."""
+    say("[precondition] powerlaw full size n=2e6 m=1e6")
+    qp = I.powerlaw_qp()
+    e1, e2 = P.scaling(qp.Q, qp.A, 10, True)
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-4, precision=1, **PRE))
+    d1, d2 = sol.scaling()
+    np.testing.assert_allclose(d2.cpu().numpy(), e2, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(d1.cpu().numpy(), e1, rtol=1e-13, atol=0)
+    x, y, r = sol.solve()
+    sol.close()
+    say(f"  status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} kkt={r['rel_kkt']:.2e}")
+    assert r["status"] == 0
+    x, y = x.cpu().numpy(), y.cpu().numpy()
+    assert np.all(y >= 0.0)
+    k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
+    assert k["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+    assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6)
