@@ -52,3 +52,33 @@ def test_error_strings():
     L = pdhcg.lib()
     assert L.pdhcg_error_string(-1) == b"invalid argument"
     assert L.pdhcg_error_string(-3) == b"HIP error"
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler gives
+    it in include/pdhcg.h, and each struct has the header's size (a C program
+    built with gcc prints sizeof and offsetof)."""
+    import ctypes as C
+    import subprocess
+    from paper_2405_16160_amd import pdhcg
+    structs = [pdhcg.pdhcg_csr, pdhcg.pdhcg_settings, pdhcg.pdhcg_lowrank, pdhcg.pdhcg_result]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pdhcg.h"', "int main(void) {"]
+    for st in structs:
+        t = st.__name__
+        lines.append(f'  printf("{t} sizeof %zu\\n", sizeof({t}));')
+        for name, _ in st._fields_:
+            lines.append(f'  printf("{t} {name} %zu\\n", offsetof({t}, {name}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        t, name, v = line.split()
+        got[(t, name)] = int(v)
+    for st in structs:
+        t = st.__name__
+        assert got[(t, "sizeof")] == C.sizeof(st), t
+        for name, _ in st._fields_:
+            assert got[(t, name)] == getattr(st, name).offset, (t, name)
