@@ -484,7 +484,7 @@ def bench_precondition(args):
     [[Q, A'], [A, 0]]): the random QP n = 1e5 as generated and with its rows of
     A (and b) rescaled by exp(U[-3, 3]), each solved to tol without and with
     the preconditioning; the power-law QP n = 2e6 for the cost of the setup
-    kernels and a time-limited solve.  With preconditioning the reported relKKT
+    kernels and a time-limited solve; portfolio instances 0-15 one by one.  With preconditioning the reported relKKT
     refers to the scaled problem; x_rel_diff compares the returned x with the
     unpreconditioned solve's."""
     import torch
@@ -516,6 +516,22 @@ def bench_precondition(args):
         row["x_rel_diff"] = float(torch.linalg.norm(xs["preconditioned"] - xs["plain"]) /
                                   torch.linalg.norm(xs["plain"]))
         rows.append(row)
+    # portfolio instances 0-15 (n log-uniform in [50, 2000], dense Q as CSR), one single-QP solve each
+    port = {"workload": "portfolio_qp instances 0-15, single-QP solves"}
+    qps = [I.portfolio_qp(i) for i in range(16)]
+    for tag, pre in (("plain", {}), ("preconditioned", {"ruiz_iters": 10, "pock_chambolle": 1})):
+        tot_ms, tot_it, solved = 0.0, 0, 0
+        for qp in qps:
+            sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, **pre))
+            _, _, r = sol.solve()
+            sol.close()
+            tot_ms += r["kernel_s"] * 1e3
+            tot_it += r["iters"]
+            solved += r["status"] == 0
+        port[tag] = {"kernel_ms_total": tot_ms, "iters_total": tot_it, "solved": solved}
+        progress(f"portfolio 0-15 {tag}: {solved}/16 solved, {tot_it} iterations, {tot_ms:.1f} ms")
+    port["n"] = [q.n for q in qps]
+    rows.append(port)
     return {"config": f"preconditioning, tol {args.tol:g}, precision {args.precision}", "rows": rows}
 
 
