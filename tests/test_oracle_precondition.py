@@ -1,10 +1,14 @@
 """Pins of the oracle's diagonal preconditioning (Ruiz + Pock-Chambolle on
 K = [[Q, A'], [A, 0]], Section 5) against hand-derived closed forms, the
 defining property of Ruiz equilibration and the invariance of the solution
-under the rescaling.  CPU only."""
+under the rescaling, and a check that each pin set catches planted mistakes.
+CPU only."""
 import math
+import pathlib
+import types
 
 import numpy as np
+import pytest
 import scipy.sparse as sp
 
 from oracle import oracle as O
@@ -92,3 +96,43 @@ def test_solution_maps_back_to_the_unscaled_optimum():
         assert abs(k["primal_obj"] - ref.primal_obj) <= 1e-8 * (1 + abs(ref.primal_obj))
         # the scaled objective equals the original one at corresponding points
         assert math.isclose(r.primal_obj, ref.primal_obj, rel_tol=1e-7, abs_tol=1e-9)
+
+
+# ------------------------------------------------- planted mistakes are caught
+# Each case plants one mistake in a copy of oracle/precondition.py, loads the
+# copy as a module in place of the real one, and checks that at least one pin
+# above fails against it.
+
+_SRC = pathlib.Path(P.__file__).read_text()
+
+MUTATIONS = [
+    ("Ruiz step uses the 1-norm", "f = _factor(abs(K).max(axis=1).toarray().ravel())",
+     "f = _factor(np.asarray(abs(K).sum(axis=1)).ravel())"),
+    ("Pock-Chambolle step uses the maximum", "f = _factor(np.asarray(abs(K).sum(axis=1)).ravel())",
+     "f = _factor(abs(K).max(axis=1).toarray().ravel())"),
+    ("factor without the square root", "out[pos] = 1.0 / np.sqrt(s[pos])", "out[pos] = 1.0 / s[pos]"),
+    ("zero rows get factor 0", "out = np.ones_like(s)", "out = np.zeros_like(s)"),
+    ("one-sided rescaling of K", "K.data * (f[K.row] * f[K.col])", "K.data * f[K.row]"),
+    ("A~ drops the column factor", "As.data * (d1[As.row] * d2[As.col])", "As.data * d1[As.row]"),
+    ("b~ divided by D1", "b=qp.b * d1", "b=qp.b / d1"),
+    ("c not scaled", "c=qp.c * d2", "c=qp.c"),
+    ("x mapped back the wrong way", "return d2 * r.x, d1 * r.y", "return r.x / d2, d1 * r.y"),
+]
+
+PINS = [test_one_by_one_closed_form, test_pock_chambolle_alone_closed_form, test_empty_rows_and_columns_keep_factor_one,
+        test_ruiz_equilibrates_every_row_and_column_of_the_scaled_blocks, test_solution_maps_back_to_the_unscaled_optimum]
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, old, new, monkeypatch):
+    assert _SRC.count(old) == 1, name
+    mutant = types.ModuleType("precondition_mutant")
+    mutant.__file__ = P.__file__
+    exec(compile(_SRC.replace(old, new), "precondition_mutant", "exec"), mutant.__dict__)
+    monkeypatch.setitem(globals(), "P", mutant)
+    for pin in PINS:
+        try:
+            pin()
+        except Exception:
+            return
+    pytest.fail(f"no pin caught the planted mistake: {name}")
