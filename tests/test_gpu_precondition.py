@@ -192,3 +192,20 @@ def test_powerlaw_full_size_preconditioned():
     k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
     assert k["rel_kkt"] <= 1e-4 * (1 + 1e-6)
     assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6)
+
+
+def test_preconditioning_is_bit_reproducible():
+    """Fixed-order reductions in the factor kernel, elementwise scaling: two
+    handles on the same data give identical D1, D2 and identical solves."""
+    say("[precondition] reproducibility, powerlaw n=4000")
+    qp = CASES["powerlaw n=4000"]()
+    out = []
+    for _ in range(2):
+        sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-6, precision=1, **PRE))
+        d1, d2 = sol.scaling()
+        x, y, r = sol.solve()
+        out.append((d1.clone(), d2.clone(), x.clone(), y.clone(), r["iters"]))
+        sol.close()
+    (a1, a2, ax, ay, ai), (b1, b2, bx, by, bi) = out
+    assert torch.equal(a1, b1) and torch.equal(a2, b2)
+    assert torch.equal(ax, bx) and torch.equal(ay, by) and ai == bi
