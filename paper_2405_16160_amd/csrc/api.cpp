@@ -719,7 +719,7 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
     double* f = nullptr;
     if ((rc = h->alloc(&f, n + m))) return bail(rc);
     if (launch_precondition(h->mat(0), h->mat(1), h->mat(2), h->nnzQ, h->nnzA, s->ruiz_iters, s->pock_chambolle, f,
-                            h->dscale, h->stream) != hipSuccess ||
+                            h->dscale, h->dscale + n, h->stream) != hipSuccess ||
         launch_diag(h->b, h->dscale + n, m, 0, h->b, h->stream) != hipSuccess ||
         launch_diag(h->c, h->dscale, n, 0, h->c, h->stream) != hipSuccess)
       return bail(fail(PDHCG_ERR_HIP, "preconditioning kernels failed to launch"));
@@ -1078,8 +1078,10 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
   const double t0 = now_s();
   int rc;
   if ((rc = check_settings(s))) return rc;
-  if (s->ruiz_iters != 0 || s->pock_chambolle != 0)
-    return fail(PDHCG_ERR_INVALID_ARGUMENT, "preconditioning is available on single-QP handles only");
+  // preconditioning (Sec. 5) per instance: every instance gets its own CSR blocks
+  // (no sharing, no dense layout), scaled on the device after the upload
+  const bool pre = s->ruiz_iters != 0 || s->pock_chambolle != 0;
+  if (pre && Ls) return fail(PDHCG_ERR_INVALID_ARGUMENT, "preconditioning is not available with a factored Q");
   if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
   if (count == 0) return 0;
   if ((!Qs && !Ls) || !As || !bs || !cs || !x_outs || !y_outs)
@@ -1128,7 +1130,7 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     I.n = (int32_t)Q.nrows;
     I.m = (int32_t)A.nrows;
     const Key qk{Q.rowptr, Q.col, Q.val}, ak{A.rowptr, A.col, A.val};
-    auto qit = q_seen.find(qk);
+    auto qit = pre ? q_seen.end() : q_seen.find(qk);
     if (qit == q_seen.end() && Ls) {
       I.dense = 2;
       I.q_rank = (int32_t)Ls[i].k;
@@ -1139,7 +1141,7 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
       q_first[i] = i;
     } else if (qit == q_seen.end()) {
       if ((rc = check_structure(Q.rowptr, Q.col, Q.nrows, Q.ncols, Q.nnz, tag + " Q"))) return rc;
-      const bool dense = is_dense(Q.rowptr, Q.nrows);
+      const bool dense = !pre && is_dense(Q.rowptr, Q.nrows);
       if (!symmetric_ptrs(Q.rowptr, Q.col, Q.val, Q.nrows, dense))
         return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": Q is not exactly symmetric");
       I.dense = dense ? 1 : 0;
@@ -1154,7 +1156,7 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
       I.dense = F.dense; I.q_rank = F.q_rank; I.q_rp = F.q_rp; I.q_nz = F.q_nz;
       q_first[i] = qit->second;
     }
-    auto ait = a_seen.find(ak);
+    auto ait = pre ? a_seen.end() : a_seen.find(ak);
     if (ait == a_seen.end()) {
       if ((rc = check_structure(A.rowptr, A.col, A.nrows, A.ncols, A.nnz, tag + " A"))) return rc;
       HostCsr Ah;
@@ -1290,6 +1292,44 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     if (I.x0_given && (rc = up(d_x0 + I.voff_n, x0s[i], sizeof(double) * I.n))) return rc;
     if (I.y0_given && (rc = up(d_y0 + I.voff_m, y0s[i], sizeof(double) * I.m))) return rc;
   }
+  // ---- preconditioning: D2 packed like x, D1 like y; b, c and the start points
+  // scaled in place; the norms relKKT uses are taken from the scaled b and c
+  double *d_d2 = nullptr, *d_d1 = nullptr;
+  if (pre) {
+    int64_t fmax_len = 1;
+    for (int i = 0; i < count; ++i) fmax_len = std::max<int64_t>(fmax_len, (int64_t)inst[i].n + inst[i].m);
+    double* d_f = nullptr;
+    if ((rc = D.alloc(&d_f, fmax_len))) return rc;
+    if ((rc = D.alloc(&d_d2, vn_tot))) return rc;
+    if ((rc = D.alloc(&d_d1, std::max<int64_t>(vm_tot, 1)))) return rc;
+    const std::vector<double> ones((size_t)std::max(vn_tot, vm_tot), 1.0);
+    if ((rc = up(d_d2, ones.data(), sizeof(double) * vn_tot))) return rc;
+    if ((rc = up(d_d1, ones.data(), sizeof(double) * vm_tot))) return rc;
+    for (int i = 0; i < count; ++i) {
+      const BatchInst& I = inst[i];
+      const DevMat Qm{I.n, I.n, d_rp + I.q_rp, d_col + I.q_nz, d_val + I.q_nz, nullptr, 0, 0};
+      const DevMat Am{I.m, I.n, d_rp + I.a_rp, d_col + I.a_nz, d_val + I.a_nz, nullptr, 0, 0};
+      const DevMat Tm{I.n, I.m, d_rp + I.t_rp, d_col + I.t_nz, d_val + I.t_nz, nullptr, 0, 0};
+      HIPX(launch_precondition(Qm, Am, Tm, Qs[i].nnz, As[i].nnz, s->ruiz_iters, s->pock_chambolle, d_f,
+                               d_d2 + I.voff_n, d_d1 + I.voff_m, stream));
+    }
+    HIPX(launch_diag(d_c, d_d2, vn_tot, 0, d_c, stream));
+    HIPX(launch_diag(d_b, d_d1, vm_tot, 0, d_b, stream));
+    if (d_x0) HIPX(launch_diag(d_x0, d_d2, vn_tot, 1, d_x0, stream));
+    if (d_y0) HIPX(launch_diag(d_y0, d_d1, vm_tot, 1, d_y0, stream));
+    std::vector<double> hb_s(std::max<int64_t>(vm_tot, 1)), hc_s(vn_tot);
+    HIPX(hipMemcpyAsync(hc_s.data(), d_c, sizeof(double) * vn_tot, hipMemcpyDeviceToHost, stream));
+    if (vm_tot) HIPX(hipMemcpyAsync(hb_s.data(), d_b, sizeof(double) * vm_tot, hipMemcpyDeviceToHost, stream));
+    HIPX(hipStreamSynchronize(stream));
+    for (int i = 0; i < count; ++i) {
+      BatchInst& I = inst[i];
+      const double* bi = hb_s.data() + I.voff_m;
+      const double* ci = hc_s.data() + I.voff_n;
+      I.nc_inf = max_abs_nan(ci, I.n);
+      I.nb_inf = max_abs_nan(bi, I.m);
+      I.kkt_zero = (s->warm_fallback && (I.x0_given || I.y0_given)) ? kkt_at_zero(bi, I.m, ci, I.n) : 0.0;
+    }
+  }
   // one parameter block per QP, all pointers resolved against the packed arrays
   std::vector<SolveParams> hp(count);
   for (int i = 0; i < count; ++i) {
@@ -1368,6 +1408,10 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
   // ---- results
   std::vector<SolverState> st(count);
   std::vector<double> hx(vn_tot), hy(std::max<int64_t>(vm_tot, 1));
+  if (pre) {  // x = D2 x~, y = D1 y~
+    HIPX(launch_diag(nv[0], d_d2, vn_tot, 0, nv[0], stream));
+    HIPX(launch_diag(mv[0], d_d1, vm_tot, 0, mv[0], stream));
+  }
   HIPX(hipMemcpyAsync(st.data(), d_st, sizeof(SolverState) * count, hipMemcpyDeviceToHost, stream));
   HIPX(hipMemcpyAsync(hx.data(), nv[0], sizeof(double) * vn_tot, hipMemcpyDeviceToHost, stream));
   if (vm_tot) HIPX(hipMemcpyAsync(hy.data(), mv[0], sizeof(double) * vm_tot, hipMemcpyDeviceToHost, stream));

@@ -228,11 +228,12 @@ int spmv_stream_tile_rows();
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 // diagonal preconditioning (precond_kernels.hip): ruiz_iters Ruiz steps and an
 // optional Pock-Chambolle step on [[Q, A'], [A, 0]], applied to the FP64 values
-// of Q, A and T = A' in place; f is scratch of n + m doubles, d (n + m, set to
-// 1 by the caller) accumulates D2 (first n) and D1 (last m); nnzq, nnza are the
-// entry counts of Q and A (they size the lane groups per row)
+// of Q, A and T = A' in place (CSR, row pointers relative to the col/val
+// pointers); f is scratch of n + m doubles; d2 (n) and d1 (m), set to 1 by
+// the caller, accumulate D2 and D1; nnzq, nnza are the entry counts of Q and
+// A (they size the lane groups per row)
 hipError_t launch_precondition(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq, int64_t nnza,
-                               int ruiz_iters, int pock_chambolle, double* f, double* d, hipStream_t s);
+                               int ruiz_iters, int pock_chambolle, double* f, double* d2, double* d1, hipStream_t s);
 // out = x .* scale (op 0) or x ./ scale (op 1), n entries; out may be x
 hipError_t launch_diag(const double* x, const double* scale, int64_t n, int op, double* out, hipStream_t s);
 // workgroups per CU that the persistent kernels can keep resident (the

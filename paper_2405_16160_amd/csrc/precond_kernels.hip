@@ -8,8 +8,8 @@
 // of the row's 1-norm.  An all-zero row keeps factor 1.  After each step the
 // factors are applied to Q, A and A' in place, each entry times f_i * f_j
 // (the product is formed first, so Q stays exactly symmetric and A' stays
-// the exact transpose of A).  The accumulated diagonal d holds D2 in d[0, n)
-// and D1 in d[n, n + m).
+// the exact transpose of A).  The accumulated diagonals are D2 (n entries)
+// and D1 (m entries).
 //
 // A one-time setup pass.  Each row is walked by a group of g lanes (a power
 // of two up to 64, sized by the host to the mean row length) reading
@@ -34,11 +34,11 @@ __device__ __forceinline__ double row_stat(const int32_t* rp, const double* v, i
   return acc;
 }
 
-// f[i] = 1 / sqrt(stat of row i of K) (1 for a zero row), d[i] *= f[i];
-// mode 0: largest magnitude, mode 1: 1-norm
+// f[i] = 1 / sqrt(stat of row i of K) (1 for a zero row), and the factor is
+// folded into D2[i] (i < n) or D1[i - n]; mode 0: largest magnitude, mode 1: 1-norm
 __global__ void scale_factor_kernel(int64_t n, int64_t m, const int32_t* qrp, const double* qv, const int32_t* trp,
                                     const double* tv, const int32_t* arp, const double* av, int mode, int g,
-                                    double* f, double* d) {
+                                    double* f, double* d2, double* d1) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int lane = (int)(t & (g - 1));
   const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / g;
@@ -57,7 +57,10 @@ __global__ void scale_factor_kernel(int64_t n, int64_t m, const int32_t* qrp, co
     if (lane == 0) {
       const double fi = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
       f[i] = fi;
-      d[i] *= fi;
+      if (i < n)
+        d2[i] *= fi;
+      else
+        d1[i - n] *= fi;
     }
   }
 }
@@ -107,10 +110,10 @@ hipError_t apply(const DevMat& M, int64_t nnz, const double* fr, const double* f
 }
 
 hipError_t step(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq, int64_t nnza, const Groups& G,
-                int mode, double* f, double* d, hipStream_t s) {
+                int mode, double* f, double* d2, double* d1, hipStream_t s) {
   const int64_t n = Q.nrows, m = A.nrows;
   hipLaunchKernelGGL(scale_factor_kernel, dim3(grid_for((n + m) * G.k)), dim3(kBlock), 0, s, n, m, Q.rowptr, Q.val,
-                     T.rowptr, T.val, A.rowptr, A.val, mode, G.k, f, d);
+                     T.rowptr, T.val, A.rowptr, A.val, mode, G.k, f, d2, d1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = apply(Q, nnzq, f, f, G.q, s)) != hipSuccess) return e;
@@ -121,15 +124,15 @@ hipError_t step(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq,
 }  // namespace
 
 hipError_t launch_precondition(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq, int64_t nnza,
-                               int ruiz_iters, int pock_chambolle, double* f, double* d, hipStream_t s) {
+                               int ruiz_iters, int pock_chambolle, double* f, double* d2, double* d1, hipStream_t s) {
   Groups G;
   G.q = lanes_for(nnzq, Q.nrows);
   G.a = lanes_for(nnza, A.nrows);
   G.t = lanes_for(nnza, T.nrows);
   G.k = lanes_for(nnzq + 2 * nnza, (int64_t)Q.nrows + A.nrows);
   hipError_t e = hipSuccess;
-  for (int it = 0; it < ruiz_iters && e == hipSuccess; ++it) e = step(Q, A, T, nnzq, nnza, G, 0, f, d, s);
-  if (e == hipSuccess && pock_chambolle) e = step(Q, A, T, nnzq, nnza, G, 1, f, d, s);
+  for (int it = 0; it < ruiz_iters && e == hipSuccess; ++it) e = step(Q, A, T, nnzq, nnza, G, 0, f, d2, d1, s);
+  if (e == hipSuccess && pock_chambolle) e = step(Q, A, T, nnzq, nnza, G, 1, f, d2, d1, s);
   return e;
 }
 

@@ -115,11 +115,12 @@ def test_preconditioned_solve_matches_oracle(precision):
     sol.close()
 
 
-def test_batch_rejects_preconditioning_and_settings_are_fixed():
-    say("[precondition] batch rejection, fixed settings")
+def test_factored_batch_rejects_preconditioning_and_settings_are_fixed():
+    say("[precondition] factored-batch rejection, fixed settings")
     qp = I.random_qp(n=200, m=80, r_rows=100, q_density=0.05, a_density=0.05, family=1, instance=5)
-    with pytest.raises(RuntimeError, match="single-QP"):
-        pdhcg.solve_batch([qp], pdhcg.Settings(**PRE))
+    pq = I.portfolio_qp(0, nmax=300)
+    with pytest.raises(RuntimeError, match="factored"):
+        pdhcg.solve_batch([pq], pdhcg.Settings(**PRE), lowrank=[I.portfolio_factor(0, nmax=300)])
     sol = pdhcg.Solver(qp, pdhcg.Settings(**PRE))
     with pytest.raises(RuntimeError, match="fixed at pdhcg_create"):
         sol.set_settings(pdhcg.Settings())
@@ -127,6 +128,27 @@ def test_batch_rejects_preconditioning_and_settings_are_fixed():
     x, y, r = sol.solve()
     assert r["status"] == 0
     sol.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_preconditioned_matches_oracle(precision):
+    """Per-instance preconditioning in the batched kernel: portfolio instances
+    (dense Q given as CSR), a row-rescaled random QP and a tiny dense QP in one
+    launch, each against the oracle's preconditioned solve."""
+    say(f"[precondition] batch of 8, precision={precision}")
+    qps = [I.portfolio_qp(i, nmax=400) for i in range(6)] + [CASES["random n=1000"](), I.tiny_qp(6, 10, instance=4)]
+    outs = pdhcg.solve_batch(qps, pdhcg.Settings(tol_rel_kkt=1e-6, precision=precision, **PRE))
+    for j, (qp, (x, y, r)) in enumerate(zip(qps, outs)):
+        xr, yr, rr, e1, e2 = P.solve(qp, O.Settings(tol=1e-9, max_iters=400_000))
+        say(f"  instance {j} n={qp.n}: status={r['status_name']} iters={r['iters']} (oracle at 1e-9: {rr.iters}) "
+            f"kkt={r['rel_kkt']:.2e}")
+        assert r["status"] == 0 and rr.status == O.OPTIMAL
+        assert np.all(y >= 0.0)
+        k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
+        assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+        assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
+        assert np.linalg.norm(x - xr) / max(np.linalg.norm(xr), 1e-12) <= 1e-3
+        assert abs(O.kkt(qp, x, y)["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-5
 
 
 def test_unconstrained_preconditioned():
