@@ -116,6 +116,8 @@ def parse():
                     choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "kappa", "precondition"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--precondition", action="store_true",
+                    help="batch mode: 10 Ruiz steps + Pock-Chambolle per instance (no factored run)")
     ap.add_argument("--train", type=int, default=20_000)
     ap.add_argument("--test", type=int, default=4_000)
     ap.add_argument("--epochs", type=int, default=300)
@@ -384,7 +386,8 @@ def bench_batch(args):
         if (i + 1) % 256 == 0:
             progress(f"generated {i + 1} portfolio QPs")
     gen_s = time.perf_counter() - t
-    s = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=200_000)
+    pre = {"ruiz_iters": 10, "pock_chambolle": 1} if args.precondition else {}
+    s = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=200_000, **pre)
     t = time.perf_counter()
     done = threading.Event()
 
@@ -423,6 +426,17 @@ def bench_batch(args):
         sol.close()
         progress(f"one-by-one instance {i} (n={qps[i].n}): {r['solve_s']:.3f} s")
     alg = sum(solve_bytes(q, r, args.precision, dense_q=True) for q, r in zip(qps, rs))
+    head = {"solved": ok, "batch_kernel_s": kernel_s, "batch_wall_s": wall, "setup_s": setup_s,
+            "roofline": {"kernel": "pdhcg_batch_kernel", "bound": "hbm", "algorithmic_bytes": alg,
+                         "achieved": alg / kernel_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / kernel_s / 1e9 / HBM_PEAK_GBS},
+            "QPs/s_batched": args.batch_count / kernel_s, "gen_s": gen_s,
+            "iters_mean": float(np.mean([r["iters"] for r in rs])),
+            "one_by_one_estimated_s": single_s, "QPs/s_one_by_one": args.batch_count / single_s,
+            "one_by_one_sample": len(sample), "speedup": single_s / kernel_s}
+    if pre:  # a factored Q is not preconditioned
+        return dict({"config": f"batched portfolio QPs x{args.batch_count}, n log-uniform [50, 2000], dense Q, "
+                               f"10 Ruiz steps + Pock-Chambolle per instance, tol {args.tol:g}"}, **head)
     # the same QPs with Q given by its factor (Q = F F' + diag(d), k = ceil(n/10))
     progress("factored form: generating the factors")
     fac = [I.portfolio_factor(i) for i in range(args.batch_count)]

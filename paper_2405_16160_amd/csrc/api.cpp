@@ -1078,8 +1078,10 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
   const double t0 = now_s();
   int rc;
   if ((rc = check_settings(s))) return rc;
-  // preconditioning (Sec. 5) per instance: every instance gets its own CSR blocks
-  // (no sharing, no dense layout), scaled on the device after the upload
+  // preconditioning (Sec. 5) per instance: every instance gets its own blocks (no
+  // sharing), scaled on the device after the upload; a dense Q keeps its layout
+  // (its CSR values are the row-major block) and is scaled through a temporary
+  // CSR view of it
   const bool pre = s->ruiz_iters != 0 || s->pock_chambolle != 0;
   if (pre && Ls) return fail(PDHCG_ERR_INVALID_ARGUMENT, "preconditioning is not available with a factored Q");
   if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
@@ -1141,7 +1143,7 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
       q_first[i] = i;
     } else if (qit == q_seen.end()) {
       if ((rc = check_structure(Q.rowptr, Q.col, Q.nrows, Q.ncols, Q.nnz, tag + " Q"))) return rc;
-      const bool dense = !pre && is_dense(Q.rowptr, Q.nrows);
+      const bool dense = is_dense(Q.rowptr, Q.nrows);
       if (!symmetric_ptrs(Q.rowptr, Q.col, Q.val, Q.nrows, dense))
         return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": Q is not exactly symmetric");
       I.dense = dense ? 1 : 0;
@@ -1254,6 +1256,21 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
   };
   std::vector<std::vector<int32_t>> rp_keep;
   std::vector<std::vector<double>> val_keep;  // factor blocks, alive until the uploads complete
+  // preconditioning: temporary CSR views (row pointers, columns) of the dense Q blocks
+  std::vector<int64_t> vrp_off(count, 0), vcol_off(count, 0);
+  int32_t *d_vrp = nullptr, *d_vcol = nullptr;
+  if (pre) {
+    int64_t vrp_tot = 0, vcol_tot = 0;
+    for (int i = 0; i < count; ++i)
+      if (inst[i].dense) {
+        vrp_off[i] = vrp_tot;
+        vrp_tot += inst[i].n + 1;
+        vcol_off[i] = vcol_tot;
+        vcol_tot += Qs[i].nnz;
+      }
+    if (vrp_tot && (rc = D.alloc(&d_vrp, vrp_tot))) return rc;
+    if (vcol_tot && (rc = D.alloc(&d_vcol, vcol_tot))) return rc;
+  }
   for (int i = 0; i < count; ++i) {
     const BatchInst& I = inst[i];
     if (q_first[i] == i && Ls) {  // block [F (n x k) | F' (k x n) | d (n)], row-major
@@ -1272,6 +1289,10 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
         rp_keep.emplace_back(Q.rowptr, Q.rowptr + Q.nrows + 1);
         if ((rc = up(d_rp + I.q_rp, rp_keep.back().data(), sizeof(int32_t) * (Q.nrows + 1)))) return rc;
         if ((rc = up(d_col + I.q_nz, Q.col, sizeof(int32_t) * Q.nnz))) return rc;
+      } else if (pre) {
+        rp_keep.emplace_back(Q.rowptr, Q.rowptr + Q.nrows + 1);
+        if ((rc = up(d_vrp + vrp_off[i], rp_keep.back().data(), sizeof(int32_t) * (Q.nrows + 1)))) return rc;
+        if ((rc = up(d_vcol + vcol_off[i], Q.col, sizeof(int32_t) * Q.nnz))) return rc;
       }
       if ((rc = up(d_val + I.q_nz, Q.val, sizeof(double) * Q.nnz))) return rc;
     }
@@ -1307,7 +1328,8 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     if ((rc = up(d_d1, ones.data(), sizeof(double) * vm_tot))) return rc;
     for (int i = 0; i < count; ++i) {
       const BatchInst& I = inst[i];
-      const DevMat Qm{I.n, I.n, d_rp + I.q_rp, d_col + I.q_nz, d_val + I.q_nz, nullptr, 0, 0};
+      const DevMat Qm{I.n, I.n, I.dense ? d_vrp + vrp_off[i] : d_rp + I.q_rp,
+                      I.dense ? d_vcol + vcol_off[i] : d_col + I.q_nz, d_val + I.q_nz, nullptr, 0, 0};
       const DevMat Am{I.m, I.n, d_rp + I.a_rp, d_col + I.a_nz, d_val + I.a_nz, nullptr, 0, 0};
       const DevMat Tm{I.n, I.m, d_rp + I.t_rp, d_col + I.t_nz, d_val + I.t_nz, nullptr, 0, 0};
       HIPX(launch_precondition(Qm, Am, Tm, Qs[i].nnz, As[i].nnz, s->ruiz_iters, s->pock_chambolle, d_f,
