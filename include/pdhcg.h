@@ -94,14 +94,15 @@ typedef struct {
                                         per step with (r, u, s) gathered (Chronopoulos-Gear),
                                         2 = textbook CG, two barriers per step with only the
                                         direction gathered */
-    int32_t ruiz_iters;              /* 0 (off); diagonal preconditioning of the single-QP handle
-                                        (Sec. 5, preprocessing): Ruiz equilibration steps on
-                                        K = [[Q, A'], [A, 0]], the paper runs 10.  The solver then
-                                        works on D2 Q D2, D1 A D2, D1 b, D2 c; relKKT, the
-                                        residuals and the termination refer to that scaled problem,
-                                        the objective values are those of the original one, and
-                                        x = D2 x~, y = D1 y~ are returned.  Fixed at pdhcg_create;
-                                        the batched entry points reject a nonzero value */
+    int32_t ruiz_iters;              /* 0 (off); diagonal preconditioning (Sec. 5, preprocessing):
+                                        Ruiz equilibration steps on K = [[Q, A'], [A, 0]], the paper
+                                        runs 10.  The solver then works on D2 Q D2, D1 A D2, D1 b,
+                                        D2 c; relKKT, the residuals and the termination refer to that
+                                        scaled problem, the objective values are those of the
+                                        original one, and x = D2 x~, y = D1 y~ are returned.  Fixed
+                                        at pdhcg_create for a handle; the batched entry points scale
+                                        every instance on its own (its Q and A are then stored
+                                        unshared); pdhcg_solve_batch_lowrank rejects a nonzero value */
     int32_t pock_chambolle;          /* 0 (off); 1: one Pock-Chambolle step (alpha = 1) after the
                                         Ruiz steps; same rules as ruiz_iters */
 } pdhcg_settings;
