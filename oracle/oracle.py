@@ -27,6 +27,11 @@ class _Csr(C.Structure):
                 ("col", C.c_void_p), ("val", C.c_void_p)]
 
 
+class _Original(C.Structure):
+    _fields_ = [("Q", C.POINTER(_Csr)), ("A", C.POINTER(_Csr)), ("b", C.c_void_p), ("c", C.c_void_p),
+                ("d1", C.c_void_p), ("d2", C.c_void_p)]
+
+
 class _Settings(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int64), ("max_cg", C.c_int32),
                 ("cg_rule", C.c_int32), ("cg_eps_factor", C.c_double), ("beta_suf", C.c_double),
@@ -125,7 +130,7 @@ def lib():
         L.or_primal_weight.argtypes = [C.c_double] * 4
         L.or_primal_weight.restype = C.c_double
         L.or_solve.argtypes = [C.POINTER(_Csr), C.POINTER(_Csr), P, P, C.POINTER(_Settings), P, P, P, P, P,
-                               C.c_int64, P, P, P, P, P]
+                               C.c_int64, P, P, P, P, P, C.POINTER(_Original)]
         L.or_solve.restype = C.c_int32
         L.or_num_threads.restype = C.c_int32
         _lib = L
@@ -203,8 +208,19 @@ def num_threads():
     return lib().or_num_threads()
 
 
-def solve(qp, settings: Settings | None = None, x0=None, y0=None, trace_len=0) -> Result:
+def solve(qp, settings: Settings | None = None, x0=None, y0=None, trace_len=0, original=None) -> Result:
+    """Run the oracle on qp.  original = (qp0, d1, d2) declares qp a
+    preconditioned copy of qp0 (Q = D2 Q0 D2, A = D1 A0 D2, b = D1 b0,
+    c = D2 c0): every relKKT is then taken on qp0 at (D2 x, D1 y), and the
+    reported residuals and objectives are qp0's; x, y stay those of qp."""
     s = settings or Settings()
+    orig = None
+    if original is not None:
+        q0, d1, d2 = original
+        Q0, A0 = _Mat(q0.Q), _Mat(q0.A)
+        b0, c0, d1, d2 = _f64(q0.b), _f64(q0.c), _f64(d1), _f64(d2)
+        orig_keep = (Q0, A0, b0, c0, d1, d2)  # noqa: F841 (alive during the call)
+        orig = _Original(C.pointer(Q0.c), C.pointer(A0.c), _p(b0), _p(c0), _p(d1), _p(d2))
     Q, A = _Mat(qp.Q), _Mat(qp.A)
     n, m = qp.Q.nrows, qp.A.nrows
     b, c = _f64(qp.b), _f64(qp.c)
@@ -220,7 +236,8 @@ def solve(qp, settings: Settings | None = None, x0=None, y0=None, trace_len=0) -
     tc = np.zeros(max(trace_len, 1), dtype=np.int32)
     sc = s._c()
     lib().or_solve(C.byref(Q.c), C.byref(A.c), _p(b), _p(c), C.byref(sc), _p(x0), _p(y0), _p(x), _p(y),
-                   _p(info), trace_len, _p(tx), _p(ty), _p(txa), _p(tya), _p(tc))
+                   _p(info), trace_len, _p(tx), _p(ty), _p(txa), _p(tya), _p(tc),
+                   None if orig is None else C.byref(orig))
     r = Result(x, y, int(info[0]), int(info[1]), int(info[2]), int(info[3]), bool(info[4]), *info[5:12].tolist())
     if trace_len:
         k = min(trace_len, r.iters)

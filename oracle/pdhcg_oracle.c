@@ -135,6 +135,38 @@ void or_kkt(const or_csr* Q, const or_csr* A, const double* b, const double* c,
     free(Ax);
 }
 
+/*
+ * The caller's problem when the solve runs on a diagonally preconditioned copy
+ * (Sec. 4, "Preprocessing"): the iterates live in the scaled problem
+ * Q~ = D2 Q D2, A~ = D1 A D2, b~ = D1 b, c~ = D2 c, and a scaled point
+ * (x~, y~) stands for x = D2 x~, y = D1 y~ of problem (1).
+ * READING: the progress metric is defined for problem (1) as posed, so every
+ * relKKT the method uses (termination, the epsilon_k schedule of the CG, the
+ * restart tests) is that of the caller's problem at the mapped point.
+ */
+typedef struct {
+    const or_csr* Q;
+    const or_csr* A;
+    const double* b;
+    const double* c;
+    const double* d1;   /* m entries */
+    const double* d2;   /* n entries */
+} or_original;
+
+/* relKKT pieces of the point (x, y) of the problem the solve iterates on:
+ * or_kkt on that problem, or, with `o`, on the caller's problem at
+ * (D2 x, D1 y); xm (n) and ym (m) are work space. */
+static void kkt_at(const or_csr* Q, const or_csr* A, const double* b, const double* c, const or_original* o,
+                   const double* x, const double* y, double* out, double* xm, double* ym) {
+    if (!o) {
+        or_kkt(Q, A, b, c, x, y, out);
+        return;
+    }
+    for (int64_t j = 0; j < Q->nrows; ++j) xm[j] = o->d2[j] * x[j];
+    for (int64_t i = 0; i < A->nrows; ++i) ym[i] = o->d1[i] * y[i];
+    or_kkt(o->Q, o->A, o->b, o->c, xm, ym, out);
+}
+
 /* ------------------------------------------------------ operator norm of A */
 
 /*
@@ -276,6 +308,10 @@ enum { OR_OPTIMAL = 0, OR_ITER_LIMIT = 1, OR_NUMERICAL = 3 };
  *
  * info[0..11]: status, iterations, total CG steps, restarts, returned_average,
  *   r_primal, r_dual, r_gap, relKKT, primal obj, dual obj, ||A|| estimate.
+ * With `orig` (may be NULL) the data passed are a preconditioned copy of the
+ * caller's problem and every relKKT is taken on the caller's problem at the
+ * mapped point (see or_original); the reported r_*, relKKT and objectives are
+ * then those of the caller's problem, while x_out, y_out stay scaled.
  * trace_len > 0 records x, y and the running averages after each of the first
  * trace_len iterations (trace_x, trace_xa: trace_len*n; trace_y, trace_ya:
  * trace_len*m) and the CG steps of each (trace_cg: trace_len), for tests of
@@ -285,7 +321,7 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
                  const or_settings* s, const double* x0, const double* y0,
                  double* x_out, double* y_out, double* info,
                  int64_t trace_len, double* trace_x, double* trace_y, double* trace_xa, double* trace_ya,
-                 int32_t* trace_cg) {
+                 int32_t* trace_cg, const or_original* orig) {
     int64_t n = Q->nrows, m = A->nrows;
     double* x = alloc(n);
     double* y = alloc(m);
@@ -299,6 +335,8 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
     double* Aty = alloc(n);
     double* Ax = alloc(m);
     double* Axn = alloc(m);
+    double* xm = alloc(n);  /* work space of kkt_at */
+    double* ym = alloc(m);
     double kk[8], ka[8];
 
     double normA = or_opnorm(A, s->power_iters);
@@ -314,7 +352,7 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
     double K_anchor, K_prev = INFINITY;
     int32_t status = OR_ITER_LIMIT, ret_avg = 0;
 
-    or_kkt(Q, A, b, c, x, y, kk);
+    kkt_at(Q, A, b, c, orig, x, y, kk, xm, ym);
     K_anchor = kk[3];
     memcpy(x_anc, x, sizeof(double) * n);
     memcpy(y_anc, y, sizeof(double) * m);
@@ -323,18 +361,18 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
 
     for (;;) {
         /* relKKT of the current iterate: termination and the CG tolerance */
-        or_kkt(Q, A, b, c, x, y, kk);
+        kkt_at(Q, A, b, c, orig, x, y, kk, xm, ym);
         if (!isfinite(kk[3])) {
             status = OR_NUMERICAL;
             memcpy(x, x_anc, sizeof(double) * n);
             memcpy(y, y_anc, sizeof(double) * m);
-            or_kkt(Q, A, b, c, x, y, kk);
+            kkt_at(Q, A, b, c, orig, x, y, kk, xm, ym);
             break;
         }
         if (kk[3] <= s->tol) { status = OR_OPTIMAL; break; }
 
         if (k > 0 && k % s->eval_period == 0) {
-            or_kkt(Q, A, b, c, xa, ya, ka);
+            kkt_at(Q, A, b, c, orig, xa, ya, ka, xm, ym);
             if (ka[3] <= s->tol) {
                 status = OR_OPTIMAL;
                 memcpy(x, xa, sizeof(double) * n);
@@ -374,7 +412,7 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
 
         if (k_total >= s->max_iters) {
             if (k > 0) {
-                or_kkt(Q, A, b, c, xa, ya, ka);
+                kkt_at(Q, A, b, c, orig, xa, ya, ka, xm, ym);
                 if (ka[3] < kk[3]) {
                     memcpy(x, xa, sizeof(double) * n);
                     memcpy(y, ya, sizeof(double) * m);
@@ -431,7 +469,7 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
     info[10] = kk[5];
     info[11] = normA;
     free(x); free(y); free(xn); free(yn); free(xa); free(ya); free(x_anc); free(y_anc);
-    free(g); free(Aty); free(Ax); free(Axn);
+    free(g); free(Aty); free(Ax); free(Axn); free(xm); free(ym);
     return status;
 }
 

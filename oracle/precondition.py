@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark may use this module; the GPU library never imports it and
 it imports nothing from the GPU library.
 
-What is computed (Section 5, "Preprocessing"): positive diagonal matrices D1
+What is computed (Sec. 4, "Preprocessing"): positive diagonal matrices D1
 (one entry per constraint row) and D2 (one per variable) such that the solver
 works on  A~ = D1 A D2,  b~ = D1 b,  c~ = D2 c,  Q~ = D2 Q D2.  D1 and D2 come
 from 10 Ruiz equilibration steps followed by one Pock-Chambolle step on the
@@ -19,8 +19,10 @@ one of the cited PDLP work):
   * Pock-Chambolle step: exponent alpha = 1, i.e. every row (and its column)
     is divided by the square root of the row's 1-norm; zero rows keep 1.
   * The problem form A x <= b has no equality block G, so Q is not augmented.
-  * Termination is measured on the scaled problem (the solver only ever sees
-    the scaled data); only the returned point is mapped back.
+  * The solver iterates on the scaled data, but every relKKT it uses
+    (termination, the CG tolerance schedule, the restart tests) is that of
+    the caller's problem at the mapped point (x, y) = (D2 x~, D1 y~): the
+    progress metric of Section 4 is defined for the problem as posed.
 """
 from __future__ import annotations
 
@@ -31,7 +33,7 @@ from oracle import oracle as O
 
 
 def kkt_matrix(Q, A) -> sp.csr_matrix:
-    """K = [[Q, A'], [A, 0]] as an (n + m) x (n + m) CSR matrix (Section 5)."""
+    """K = [[Q, A'], [A, 0]] as an (n + m) x (n + m) CSR matrix (Sec. 4, preprocessing)."""
     Qs, As = Q.to_scipy(), A.to_scipy()
     if A.nrows == 0:
         return sp.csr_matrix(Qs)
@@ -79,10 +81,22 @@ def scale_qp(qp, d1: np.ndarray, d2: np.ndarray):
                    x_star=None, y_star=None)
 
 
-def solve(qp, settings: O.Settings | None = None, ruiz_iters: int = 10, pock_chambolle: bool = True):
-    """Scale, solve the scaled problem with the oracle, map the point back.
+def solve_scaled(qp, d1: np.ndarray, d2: np.ndarray, settings: O.Settings | None = None, x0=None, y0=None):
+    """Solve qp through its copy scaled by the given D1, D2 (start points of
+    the original problem are mapped as x~ = x / D2, y~ = y / D1), with every
+    relKKT taken on qp itself; map the point back.
 
-    Returns (x, y, result of the scaled solve, d1, d2)."""
+    Returns (x, y, result); the result's residuals and objectives are qp's."""
+    x0s = None if x0 is None else np.asarray(x0, float) / d2
+    y0s = None if y0 is None else np.asarray(y0, float) / d1
+    r = O.solve(scale_qp(qp, d1, d2), settings, x0=x0s, y0=y0s, original=(qp, d1, d2))
+    return d2 * r.x, d1 * r.y, r
+
+
+def solve(qp, settings: O.Settings | None = None, ruiz_iters: int = 10, pock_chambolle: bool = True):
+    """Scale with Ruiz + Pock-Chambolle, solve, map the point back.
+
+    Returns (x, y, result, d1, d2); the result refers to the caller's problem."""
     d1, d2 = scaling(qp.Q, qp.A, ruiz_iters, pock_chambolle)
-    r = O.solve(scale_qp(qp, d1, d2), settings)
-    return d2 * r.x, d1 * r.y, r, d1, d2
+    x, y, r = solve_scaled(qp, d1, d2, settings)
+    return x, y, r, d1, d2

@@ -1,5 +1,5 @@
 """Pins of the oracle's diagonal preconditioning (Ruiz + Pock-Chambolle on
-K = [[Q, A'], [A, 0]], Section 5) against hand-derived closed forms, the
+K = [[Q, A'], [A, 0]], Sec. 4, "Preprocessing") against hand-derived closed forms, the
 defining property of Ruiz equilibration and the invariance of the solution
 under the rescaling, and a check that each pin set catches planted mistakes.
 CPU only."""
@@ -98,6 +98,61 @@ def test_solution_maps_back_to_the_unscaled_optimum():
         assert math.isclose(r.primal_obj, ref.primal_obj, rel_tol=1e-7, abs_tol=1e-9)
 
 
+W = ([[2.0, 0.0], [0.0, 1.0]], [[1.0, 1.0]], [1.0], [-2.0, -1.0])  # the hand-worked example
+
+
+def test_termination_is_measured_on_the_callers_problem():
+    # Example W: at (0, 0) relKKT = r_dual = ||c||/(1 + ||c||) = 2/3.  Scaled
+    # by D2 = diag(2, 1), D1 = 4 the copy has c~ = (-4, -1), so its own relKKT
+    # at (0, 0) is 4/5; scaled by D2 = diag(1/2, 1/2), D1 = 1 it has
+    # c~ = (-1, -1/2) and relKKT 1/2.  With tol between the two values the
+    # start point passes or fails on the caller's 2/3 alone.
+    qp = _qp(*W)
+    x, y, r = P.solve_scaled(qp, np.array([4.0]), np.array([2.0, 1.0]), O.Settings(tol=0.7))
+    assert r.status == O.OPTIMAL and r.iters == 0
+    assert math.isclose(r.rel_kkt, 2.0 / 3.0, rel_tol=1e-15) and math.isclose(r.r_dual, 2.0 / 3.0, rel_tol=1e-15)
+    x, y, r = P.solve_scaled(qp, np.array([1.0]), np.array([0.5, 0.5]), O.Settings(tol=0.6))
+    assert r.status == O.OPTIMAL and r.iters > 0 and r.rel_kkt <= 0.6
+    # the reported pieces are those of the returned point on the caller's data
+    k = O.kkt(qp, x, y)
+    assert math.isclose(r.rel_kkt, k["rel_kkt"], rel_tol=1e-12)
+    # a start at W's optimum (x*, y*) = ((2/3, 1/3), 2/3) maps to the scaled
+    # copy and back unchanged: relKKT 0 there, no iteration
+    x, y, r = P.solve_scaled(qp, np.array([4.0]), np.array([2.0, 1.0]), O.Settings(tol=1e-12),
+                             x0=[2.0 / 3.0, 1.0 / 3.0], y0=[2.0 / 3.0])
+    assert r.iters == 0 and r.rel_kkt <= 1e-15
+    np.testing.assert_allclose(x, [2.0 / 3.0, 1.0 / 3.0], rtol=1e-15)
+    # to tight tolerance the scaled solve reaches W's exact optimum
+    x, y, r = P.solve_scaled(qp, np.array([4.0]), np.array([2.0, 1.0]), O.Settings(tol=1e-12))
+    np.testing.assert_allclose(x, [2.0 / 3.0, 1.0 / 3.0], rtol=1e-10)
+    np.testing.assert_allclose(y, [2.0 / 3.0], rtol=1e-10)
+
+
+def test_row_scaled_manufactured_optimum_to_tolerance():
+    # A manufactured QP (exact x*, y*) with rows of A and b rescaled by
+    # exp(U[-3, 3]): the preconditioned solve must meet the tolerance on the
+    # caller's data and land on the exact optimum.
+    qp = I.row_scaled(I.manufactured(n=300, m=150, q_density=0.03, a_density=0.03, instance=2))
+    x, y, r, d1, d2 = P.solve(qp, O.Settings(tol=1e-9, max_iters=200_000))
+    assert r.status == O.OPTIMAL and r.rel_kkt <= 1e-9
+    assert np.linalg.norm(x - qp.x_star) <= 1e-6 * np.linalg.norm(qp.x_star)
+    assert np.all(y >= 0.0)
+    np.testing.assert_allclose(qp.A.to_scipy().T @ y, qp.A.to_scipy().T @ qp.y_star, rtol=0,
+                               atol=1e-5 * np.abs(qp.A.to_scipy().T @ qp.y_star).max())
+
+
+def test_scaled_termination_mistake_is_caught(tmp_path):
+    # the former reading (relKKT of the scaled copy) planted in the C oracle
+    from test_oracle_mutations import build_mutant
+    O.use_library(build_mutant(tmp_path, "    if (!o) {\n        or_kkt(Q, A, b, c, x, y, out);",
+                               "    if (1) {\n        or_kkt(Q, A, b, c, x, y, out);"))
+    try:
+        with pytest.raises(AssertionError):
+            test_termination_is_measured_on_the_callers_problem()
+    finally:
+        O.use_library(None)
+
+
 # ------------------------------------------------- planted mistakes are caught
 # Each case plants one mistake in a copy of oracle/precondition.py, loads the
 # copy as a module in place of the real one, and checks that at least one pin
@@ -117,10 +172,13 @@ MUTATIONS = [
     ("b~ divided by D1", "b=qp.b * d1", "b=qp.b / d1"),
     ("c not scaled", "c=qp.c * d2", "c=qp.c"),
     ("x mapped back the wrong way", "return d2 * r.x, d1 * r.y", "return r.x / d2, d1 * r.y"),
+    ("relKKT taken on the scaled copy", "original=(qp, d1, d2))", "original=None)"),
+    ("start point mapped the wrong way", "np.asarray(x0, float) / d2", "np.asarray(x0, float) * d2"),
 ]
 
 PINS = [test_one_by_one_closed_form, test_pock_chambolle_alone_closed_form, test_empty_rows_and_columns_keep_factor_one,
-        test_ruiz_equilibrates_every_row_and_column_of_the_scaled_blocks, test_solution_maps_back_to_the_unscaled_optimum]
+        test_ruiz_equilibrates_every_row_and_column_of_the_scaled_blocks, test_solution_maps_back_to_the_unscaled_optimum,
+        test_termination_is_measured_on_the_callers_problem]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
