@@ -37,7 +37,7 @@ class _Settings(C.Structure):
                 ("cg_rule", C.c_int32), ("cg_eps_factor", C.c_double), ("beta_suf", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("restart_to", C.c_int32),
                 ("eval_period", C.c_int32), ("pw_theta", C.c_double), ("pw_init", C.c_double),
-                ("eta_factor", C.c_double), ("power_iters", C.c_int32)]
+                ("eta_factor", C.c_double), ("power_iters", C.c_int32), ("step_rule", C.c_int32)]
 
 
 @dataclass
@@ -58,11 +58,12 @@ class Settings:
     pw_init: float = 1.0
     eta_factor: float = 0.5
     power_iters: int = 100
+    step_rule: int = 0   # 0: constant eta per epoch, 1: adaptive step (Sec. 4)
 
     def _c(self) -> _Settings:
         return _Settings(self.tol, self.max_iters, self.max_cg, self.cg_rule, self.cg_eps_factor,
                          self.beta_suf, self.beta_nec, self.beta_art, self.restart_to, self.eval_period,
-                         self.pw_theta, self.pw_init, self.eta_factor, self.power_iters)
+                         self.pw_theta, self.pw_init, self.eta_factor, self.power_iters, self.step_rule)
 
 
 @dataclass
@@ -81,11 +82,13 @@ class Result:
     primal_obj: float
     dual_obj: float
     norm_A: float
+    rejections: int = 0
     trace_x: np.ndarray | None = None
     trace_y: np.ndarray | None = None
     trace_xa: np.ndarray | None = None
     trace_ya: np.ndarray | None = None
     trace_cg: np.ndarray | None = None
+    trace_step: np.ndarray | None = None   # per iteration: eta used, its limit eta_bar, attempts
 
 
 def build(force: bool = False) -> str:
@@ -130,7 +133,11 @@ def lib():
         L.or_primal_weight.argtypes = [C.c_double] * 4
         L.or_primal_weight.restype = C.c_double
         L.or_solve.argtypes = [C.POINTER(_Csr), C.POINTER(_Csr), P, P, C.POINTER(_Settings), P, P, P, P, P,
-                               C.c_int64, P, P, P, P, P, C.POINTER(_Original)]
+                               C.c_int64, P, P, P, P, P, P, C.POINTER(_Original)]
+        L.or_step_limit.argtypes = [C.POINTER(_Csr), C.POINTER(_Csr), P, P, P, P, C.c_double]
+        L.or_step_limit.restype = C.c_double
+        L.or_next_step.argtypes = [C.c_double, C.c_double, C.c_int64]
+        L.or_next_step.restype = C.c_double
         L.or_solve.restype = C.c_int32
         L.or_num_threads.restype = C.c_int32
         _lib = L
@@ -204,6 +211,17 @@ def primal_weight(omega, dx, dy, theta=0.2):
     return lib().or_primal_weight(omega, dx, dy, theta)
 
 
+def step_limit(qp, x, xn, y, yn, omega=1.0):
+    """eta_bar of the adaptive step for the trial z = (x, y) -> (xn, yn)."""
+    Q, A = _Mat(qp.Q), _Mat(qp.A)
+    x, xn, y, yn = _f64(x), _f64(xn), _f64(y), _f64(yn)
+    return lib().or_step_limit(C.byref(Q.c), C.byref(A.c), _p(x), _p(xn), _p(y), _p(yn), omega)
+
+
+def next_step(eta, eta_bar, t):
+    return lib().or_next_step(eta, eta_bar, t)
+
+
 def num_threads():
     return lib().or_num_threads()
 
@@ -228,17 +246,19 @@ def solve(qp, settings: Settings | None = None, x0=None, y0=None, trace_len=0, o
     y0 = None if y0 is None else _f64(y0)
     x = np.zeros(n)
     y = np.zeros(m)
-    info = np.zeros(12)
+    info = np.zeros(13)
     tx = np.zeros(max(trace_len, 1) * n)
     ty = np.zeros(max(trace_len, 1) * m)
     txa = np.zeros(max(trace_len, 1) * n)
     tya = np.zeros(max(trace_len, 1) * m)
     tc = np.zeros(max(trace_len, 1), dtype=np.int32)
+    tst = np.zeros(3 * max(trace_len, 1))
     sc = s._c()
     lib().or_solve(C.byref(Q.c), C.byref(A.c), _p(b), _p(c), C.byref(sc), _p(x0), _p(y0), _p(x), _p(y),
-                   _p(info), trace_len, _p(tx), _p(ty), _p(txa), _p(tya), _p(tc),
+                   _p(info), trace_len, _p(tx), _p(ty), _p(txa), _p(tya), _p(tc), _p(tst),
                    None if orig is None else C.byref(orig))
-    r = Result(x, y, int(info[0]), int(info[1]), int(info[2]), int(info[3]), bool(info[4]), *info[5:12].tolist())
+    r = Result(x, y, int(info[0]), int(info[1]), int(info[2]), int(info[3]), bool(info[4]), *info[5:12].tolist(),
+               rejections=int(info[12]))
     if trace_len:
         k = min(trace_len, r.iters)
         r.trace_x = tx[: k * n].reshape(k, n)
@@ -246,4 +266,5 @@ def solve(qp, settings: Settings | None = None, x0=None, y0=None, trace_len=0, o
         r.trace_xa = txa[: k * n].reshape(k, n)
         r.trace_ya = tya[: k * m].reshape(k, m)
         r.trace_cg = tc[:k].copy()
+        r.trace_step = tst[: 3 * k].reshape(k, 3)
     return r

@@ -47,6 +47,7 @@ typedef struct {
     double pw_init;           /* initial primal weight */
     double eta_factor;        /* eta = eta_factor / ||A||_2 (sigma = tau = 1/(2||A||), Thm 2) */
     int32_t power_iters;      /* power-iteration steps for ||A||_2 */
+    int32_t step_rule;        /* 0: constant eta per epoch (Thm 2), 1: adaptive step (Sec. 4) */
 } or_settings;
 
 /* ---------------------------------------------------------------- basics */
@@ -279,6 +280,50 @@ double or_primal_weight(double omega, double dx, double dy, double theta) {
     return omega;
 }
 
+/* ------------------------------------------------------ adaptive step size */
+
+/*
+ * Step-size limit of the adaptive step (Sec. 4, "Adaptive step-size"): for a
+ * trial step from z = (x, y) to z' = (x', y'),
+ *   eta_bar = ||z' - z||_w^2 / (2 |(x' - x)' A' (y' - y)| + (x' - x)' Q (x' - x)),
+ * with ||(dx, dy)||_w^2 = omega ||dx||^2 + ||dy||^2 / omega (the primal-weight
+ * norm of the cited PDLP rule, whose limit the paper extends by the Q term).
+ * READING: the bilinear term enters with its magnitude, as in the PDLP rule
+ * (the paper's sign convention for y makes the printed sign ambiguous); a zero
+ * denominator gives +inf.  (The augmented penalty is not used: rho = 0.)
+ */
+double or_step_limit(const or_csr* Q, const or_csr* A, const double* x, const double* xn, const double* y,
+                     const double* yn, double omega) {
+    int64_t n = Q->nrows, m = A->nrows;
+    double* dx = alloc(n);
+    double* dy = alloc(m);
+    double* Qdx = alloc(n);
+    double* Adx = alloc(m);
+    for (int64_t j = 0; j < n; ++j) dx[j] = xn[j] - x[j];
+    for (int64_t i = 0; i < m; ++i) dy[i] = yn[i] - y[i];
+    or_matvec(Q, dx, Qdx);
+    or_matvec(A, dx, Adx);
+    double num = omega * dot(n, dx, dx) + dot(m, dy, dy) / omega;
+    double den = 2.0 * fabs(dot(m, dy, Adx)) + dot(n, dx, Qdx);
+    free(dx); free(dy); free(Qdx); free(Adx);
+    return den > 0.0 ? num / den : INFINITY;
+}
+
+/*
+ * The step size after an attempt at the t-th iteration (t >= 1, counting the
+ * iteration being taken), by the update of the cited PDLP rule:
+ *   eta' = min((1 - (t + 1)^-0.3) eta_bar, (1 + (t + 1)^-0.6) eta).
+ * The attempt is accepted when eta <= eta_bar; either way eta' is the step
+ * of the next attempt or iteration.  READING: the exponents and the update are
+ * the PDLP rule the paper says it follows; t counts from 1 so that the first
+ * factor is positive.
+ */
+double or_next_step(double eta, double eta_bar, int64_t t) {
+    double a = (1.0 - pow((double)t + 1.0, -0.3)) * eta_bar;
+    double b = (1.0 + pow((double)t + 1.0, -0.6)) * eta;
+    return a < b ? a : b;
+}
+
 /* ---------------------------------------------------------------- solve */
 
 enum { OR_OPTIMAL = 0, OR_ITER_LIMIT = 1, OR_NUMERICAL = 3 };
@@ -306,22 +351,33 @@ enum { OR_OPTIMAL = 0, OR_ITER_LIMIT = 1, OR_NUMERICAL = 3 };
  * returned with ITER_LIMIT.  A non-finite relKKT returns the epoch's anchor
  * with NUMERICAL_ERROR.
  *
- * info[0..11]: status, iterations, total CG steps, restarts, returned_average,
- *   r_primal, r_dual, r_gap, relKKT, primal obj, dual obj, ||A|| estimate.
+ * With step_rule = 1 the step size adapts (Sec. 4, "Adaptive step-size"): each
+ * iteration's primal and dual steps are a trial at the current eta; the trial
+ * is accepted when eta <= or_step_limit of it, and eta becomes or_next_step
+ * either way, so a rejected trial is repeated from z^k (the CG from x^k with
+ * the new tau) with the smaller step.  tau = eta/omega, sigma = eta*omega as in
+ * the constant rule; eta starts at eta_factor/||A|| and persists across
+ * restarts.  CG steps of rejected trials count in the CG total.
+ *
+ * info[0..12]: status, iterations, total CG steps, restarts, returned_average,
+ *   r_primal, r_dual, r_gap, relKKT, primal obj, dual obj, ||A|| estimate,
+ *   rejected trial steps.
  * With `orig` (may be NULL) the data passed are a preconditioned copy of the
  * caller's problem and every relKKT is taken on the caller's problem at the
  * mapped point (see or_original); the reported r_*, relKKT and objectives are
  * then those of the caller's problem, while x_out, y_out stay scaled.
  * trace_len > 0 records x, y and the running averages after each of the first
  * trace_len iterations (trace_x, trace_xa: trace_len*n; trace_y, trace_ya:
- * trace_len*m) and the CG steps of each (trace_cg: trace_len), for tests of
- * the first steps and of invariants.
+ * trace_len*m), the CG steps of each (trace_cg: trace_len) and, when
+ * trace_step is not NULL, the step size of the accepted trial, its limit
+ * eta_bar (+inf with the constant rule) and the attempts taken (trace_step:
+ * 3*trace_len), for tests of the first steps and of invariants.
  */
 int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double* c,
                  const or_settings* s, const double* x0, const double* y0,
                  double* x_out, double* y_out, double* info,
                  int64_t trace_len, double* trace_x, double* trace_y, double* trace_xa, double* trace_ya,
-                 int32_t* trace_cg, const or_original* orig) {
+                 int32_t* trace_cg, double* trace_step, const or_original* orig) {
     int64_t n = Q->nrows, m = A->nrows;
     double* x = alloc(n);
     double* y = alloc(m);
@@ -347,7 +403,7 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
     for (int64_t j = 0; j < n; ++j) x[j] = x0 ? x0[j] : 0.0;
     for (int64_t i = 0; i < m; ++i) y[i] = y0 ? (y0[i] > 0.0 ? y0[i] : 0.0) : 0.0;
 
-    int64_t k = 0, k_total = 0, cg_total = 0, restarts = 0;
+    int64_t k = 0, k_total = 0, cg_total = 0, restarts = 0, rejections = 0;
     double eps = 0.0;
     double K_anchor, K_prev = INFINITY;
     int32_t status = OR_ITER_LIMIT, ret_avg = 0;
@@ -426,18 +482,35 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
 
         eps += s->cg_eps_factor * kk[3];
 
-        /* primal step: CG on (Q + I/tau) x = x^k/tau - c - A'y^k from x^k */
+        /* g = Q x^k + A'y^k + c: the CG's starting residual is -g */
         or_matvec(Q, x, g);
         or_matvec_t(A, y, Aty);
         for (int64_t j = 0; j < n; ++j) g[j] += Aty[j] + c[j];
-        memcpy(xn, x, sizeof(double) * n);
-        int32_t steps = or_cg(Q, tau, g, xn, eps, s->max_cg, s->cg_rule);
-        cg_total += steps;
-
-        /* dual step at the extrapolated point 2x^{k+1} - x^k */
         or_matvec(A, x, Ax);
-        or_matvec(A, xn, Axn);
-        for (int64_t i = 0; i < m; ++i) yn[i] = fmax(0.0, y[i] + sigma * (2.0 * Axn[i] - Ax[i] - b[i]));
+        int32_t steps = 0, attempts = 0;
+        double eta_used = eta, eta_bar = INFINITY;
+        for (;;) {
+            /* primal step: CG on (Q + I/tau) x = x^k/tau - c - A'y^k from x^k */
+            memcpy(xn, x, sizeof(double) * n);
+            steps += or_cg(Q, tau, g, xn, eps, s->max_cg, s->cg_rule);
+            /* dual step at the extrapolated point 2x^{k+1} - x^k */
+            or_matvec(A, xn, Axn);
+            for (int64_t i = 0; i < m; ++i) yn[i] = fmax(0.0, y[i] + sigma * (2.0 * Axn[i] - Ax[i] - b[i]));
+            attempts++;
+            if (s->step_rule == 0) break;
+            /* adaptive step (Sec. 4): accept when eta <= eta_bar; the next
+             * attempt or iteration uses eta' either way (64 attempts at most,
+             * the last accepted: a bound never reached in the tests) */
+            eta_used = eta;
+            eta_bar = or_step_limit(Q, A, x, xn, y, yn, omega);
+            int accept = eta <= eta_bar || attempts >= 64;
+            eta = or_next_step(eta, eta_bar, k_total + 1);
+            tau = eta / omega;
+            sigma = eta * omega;
+            if (accept) break;
+            rejections++;
+        }
+        cg_total += steps;
 
         /* running averages, weight 1/(k+1) */
         double w = 1.0 / (double)(k + 1);
@@ -452,6 +525,11 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
             memcpy(trace_xa + k_total * n, xa, sizeof(double) * n);
             memcpy(trace_ya + k_total * m, ya, sizeof(double) * m);
             trace_cg[k_total] = steps;
+            if (trace_step) {
+                trace_step[3 * k_total] = eta_used;
+                trace_step[3 * k_total + 1] = eta_bar;
+                trace_step[3 * k_total + 2] = (double)attempts;
+            }
         }
         k++;
         k_total++;
@@ -468,6 +546,7 @@ int32_t or_solve(const or_csr* Q, const or_csr* A, const double* b, const double
     info[9] = kk[4];
     info[10] = kk[5];
     info[11] = normA;
+    info[12] = (double)rejections;
     free(x); free(y); free(xn); free(yn); free(xa); free(ya); free(x_anc); free(y_anc);
     free(g); free(Aty); free(Ax); free(Axn); free(xm); free(ym);
     return status;

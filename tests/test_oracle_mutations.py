@@ -1,12 +1,14 @@
 """The oracle's pins are strong enough to catch plausible mistakes: each test
 plants one mistake in a copy of oracle/pdhcg_oracle.c, compiles it, and
-checks that at least one pin of tests/test_oracle_pins.py fails against it.
+checks that at least one pin of tests/test_oracle_pins.py or
+tests/test_oracle_adaptive.py fails against it.
 CPU only; the planted copies live in a temporary directory."""
 import os
 import subprocess
 
 import pytest
 
+import test_oracle_adaptive as adaptive
 import test_oracle_pins as pins
 from oracle import oracle as O
 
@@ -28,6 +30,19 @@ MUTATIONS = [
     ("primal residual ignores b", "maxp(Ax[i] - b[i], 0.0)", "maxp(Ax[i], 0.0)"),
     ("CG stop certificate without tau", "tau * sqrt(rho_new) <= eps", "sqrt(rho_new) <= eps"),
     ("power iteration normalisation", "v[j] = w[j] / lam;", "v[j] = w[j];"),
+    # adaptive step size (Sec. 4)
+    ("step limit drops the Q term", "double den = 2.0 * fabs(dot(m, dy, Adx)) + dot(n, dx, Qdx);",
+     "double den = 2.0 * fabs(dot(m, dy, Adx));"),
+    ("step limit bilinear term by sign", "double den = 2.0 * fabs(dot(m, dy, Adx)) + dot(n, dx, Qdx);",
+     "double den = 2.0 * dot(m, dy, Adx) + dot(n, dx, Qdx);"),
+    ("step limit weights inverted", "double num = omega * dot(n, dx, dx) + dot(m, dy, dy) / omega;",
+     "double num = dot(n, dx, dx) / omega + omega * dot(m, dy, dy);"),
+    ("step update exponents swapped", "double a = (1.0 - pow((double)t + 1.0, -0.3)) * eta_bar;",
+     "double a = (1.0 - pow((double)t + 1.0, -0.6)) * eta_bar;"),
+    ("acceptance test reversed", "int accept = eta <= eta_bar || attempts >= 64;",
+     "int accept = eta >= eta_bar || attempts >= 64;"),
+    ("repeated trial keeps the old tau", "            tau = eta / omega;\n            sigma = eta * omega;\n            if (accept) break;",
+     "            sigma = eta * omega;\n            if (accept) break;"),
 ]
 
 PINS = [
@@ -43,6 +58,10 @@ PINS = [
     pins.test_invariants_along_iterations,
     pins.test_manufactured_solution_tiny_case_size,
     pins.test_warm_start_resume_and_negative_y0,
+    adaptive.test_step_limit_worked_example,
+    adaptive.test_next_step_closed_form,
+    adaptive.test_first_adaptive_iteration_on_w_is_accepted,
+    adaptive.test_rejected_trial_on_w,
 ] + [lambda row=row: pins.test_restart_decision_table(row) for row in pins._load_restart_table()]
 
 
