@@ -1,18 +1,22 @@
 """Benchmark: time and QPs/s to relKKT <= 1e-4 with restarted PDHCG on one GPU.
 
-Default workload (one step = one full solve of the hot path: stacked [Q|A']
-pass, inexact CG, projected dual step, averaging, restart evaluation):
-random sparse convex QP with n = 100 000, m = 50 000, Q = R'R + 1e-2 I
-(R 5e4 x 1e5 at density 2e-5), A 5e4 x 1e5 at density 2e-4, N(0,1) values,
-b = A x0 + U[0,1]; FP32 products with FP64 reductions and an FP64-certified
-relKKT; cold start from (0, 0).  The problem is uploaded and set up
-(pdhcg_create: A' build, plan, ||A|| power iteration) before the timed region.
+Default workload (the largest configuration that fits one GPU; one step = one
+batched solve of the whole hot path for every instance: stacked [Q|A'] pass,
+inexact CG, projected dual step, averaging, restart evaluation): 4096
+portfolio QPs, n log-uniform in [50, 2000], Q = F F' + diag(d) given by its
+factor (F n x ceil(n/10), N(0, 1/n)), d ~ U[0.01, 0.1], c = -mu with
+mu ~ N(0.05, 0.02^2), rows 1'x <= 1, -1'x <= -1, -x <= 0; diagonal
+preconditioning per instance (10 Ruiz steps + Pock-Chambolle, relKKT on each
+caller's problem); FP32 products with FP64 reductions; cold start; tol 1e-4.
+The batch is generated, packed, uploaded and preconditioned
+(pdhcg_batch_create) before the timed region; each timed step is one
+pdhcg_batch_solve with device-resident outputs.
 
 Prints one JSON line.  Besides the contract fields it carries the roofline
-of the dominant kernel (the persistent solve kernel, timed with HIP events on
-its own stream), the FP64 CPU oracle timed on this host (a bounded sample),
-standalone SpMV bandwidths, and the in-run comparison with CG capped at one
-step.
+of the dominant kernel (the batched solve kernel, timed with HIP events on its
+own stream), the FP64 CPU oracle timed on this host on a sample of the same
+instances, and side measurements (one-by-one solves of a sample, the random
+QP n = 1e5, the power-law QP n = 2e6 to 1e-4, learned warm start vs cold).
 """
 from __future__ import annotations
 
@@ -28,7 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "pdhcg_solve_kernel_random_qp_1e5_counters.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "pdhcg_batch_kernel_portfolio_4096_counters.md")
+HEADLINE_KERNEL = "pdhcg_batch_kernel"
 CALIBRATION_BYTES = 1 << 30   # the --calibrate-copy kernel reads and writes 1 GiB
 
 
@@ -60,13 +65,13 @@ def read_counter_csv(d):
     return rows
 
 
-def summarize_counters(d, algorithmic_bytes):
-    """Scale the solve kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
-    what the same counters read for a plain 1 GiB device copy."""
+def summarize_counters(d, algorithmic_bytes, kernel=HEADLINE_KERNEL):
+    """Scale the kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what
+    the same counters read for a plain 1 GiB device copy."""
     out = {}
     for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         solve = [v for k, c, v in read_counter_csv(os.path.join(d, sub))
-                 if c == counter and "pdhcg_solve_kernel" in k]
+                 if c == counter and kernel in k]
         copy = [v for k, c, v in read_counter_csv(os.path.join(d, "copy_" + sub)) if c == counter]
         if not solve or not copy:
             raise SystemExit(f"no {counter} rows under {d}/{sub} or {d}/copy_{sub}")
@@ -80,12 +85,13 @@ def summarize_counters(d, algorithmic_bytes):
             "counters": out}
 
 
-def measured_traffic():
-    """Bytes per launch of the solve kernel from the committed counter summary,
-    or None when there is none or the sources changed since it was taken."""
-    if not os.path.exists(COUNTERS_FILE):
+def measured_traffic(path=COUNTERS_FILE):
+    """Bytes per launch of a kernel from a committed counter summary (the
+    headline kernel's by default), or None when there is none or the sources
+    changed since it was taken."""
+    if not os.path.exists(path):
         return None, None
-    for line in open(COUNTERS_FILE):
+    for line in open(path):
         if line.startswith("counters-json: "):
             d = json.loads(line[len("counters-json: "):])
             if d.get("source_sha256") == kernel_source_hash():
@@ -109,11 +115,13 @@ def parse():
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="turn rocprofv3 --pmc CSV runs under DIR/{fetch,write,copy_fetch,copy_write} into "
                          "the counter summary line (prints it; runs on the CPU)")
+    ap.add_argument("--counter-kernel", default=HEADLINE_KERNEL,
+                    help="with --summarize-counters: the kernel whose dispatches are summarised")
     ap.add_argument("--bench-line", metavar="FILE",
                     help="with --summarize-counters: a file holding the bench line of the profiled run "
                          "(its algorithmic bytes per launch)")
-    ap.add_argument("--config", default="random1e5",
-                    choices=["random1e5", "tiny", "powerlaw", "batch", "learned", "kappa", "precondition"],
+    ap.add_argument("--config", default="portfolio",
+                    choices=["portfolio", "random1e5", "tiny", "powerlaw", "batch", "learned", "kappa", "precondition"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--precondition", action="store_true",
@@ -136,16 +144,20 @@ def csr_bytes(nnz, nrows, ncols, sv, sx, sy=None):
     return nnz * (sv + 4) + 4 * (nrows + 1) + ncols * sx + nrows * (sx if sy is None else sy)
 
 
-def solve_bytes(qp, r, precision, dense_q=False, rank=0):
+def solve_bytes(qp, r, precision, dense_q=False, rank=0, scaled=False):
     """Algorithmic HBM bytes of one solve, from the counts the solver reports.
     Per iteration: the n-side pass [Q|A'][x;y] in FP64 (r0 and relKKT), the
     dual step y = proj(y + sigma(A(2x+ - x) - b)) with its vectors, and the
     average update; per CG step nnz(Q)(sv+4) + 4(n+1) + 11 n sx (product, dot,
     axpy and direction update with their vectors); per restart evaluation the
-    n-side pass and an A product at the average."""
+    n-side pass and an A product at the average.  The n-side pass is FP64 in
+    both precision modes by design: it forms r0 and the relKKT pieces, so the
+    termination test is taken on the FP64 data.  With preconditioning
+    (scaled) every relKKT also reads D2 (n-side) and D1 (m-side)."""
     n, m = qp.n, qp.m
     nq, na = qp.Q.nnz, qp.A.nnz
     sv = sx = 4 if precision == 1 else 8
+    dsc = (8 * n + 8 * m) if scaled else 0
     if dense_q:   # a dense Q is stored as n x n values without indices: count it as such
         nq_b64, nq_bv = n * n * 8, n * n * sv
         if rank:  # Q = F F' + diag(d) from its factor: F and F' streamed, d read
@@ -154,12 +166,12 @@ def solve_bytes(qp, r, precision, dense_q=False, rank=0):
         cg = nq_bv + 11 * n * sx
         ev = nq_b64 + na * 12 + 4 * (n + 1) + (n + m) * 8 + n * 8 + csr_bytes(na, m, n, 8, 8) + 2 * m * 8
         dual = csr_bytes(na, m, n, sv, sx) - m * sx + 7 * m * 8 + 3 * n * 8
-        return r["iters"] * (a1 + dual) + r["cg_iters_total"] * cg + r["kkt_evals"] * ev
+        return r["iters"] * (a1 + dual + dsc) + r["cg_iters_total"] * cg + r["kkt_evals"] * (ev + dsc)
     a1 = (nq + na) * 12 + 8 * (n + 1) + (n + m) * 8 + 2 * n * 8           # matrices, x, y, c, r
     dual = csr_bytes(na, m, n, sv, sx) - m * sx + 7 * m * 8 + 3 * n * 8   # + y, ax, b, ya (r/w); xa update
     cg = nq * (sv + 4) + 4 * (n + 1) + 11 * n * sx
     ev = (nq + na) * 12 + 8 * (n + 1) + (n + m) * 8 + n * 8 + csr_bytes(na, m, n, 8, 8) + 2 * m * 8
-    return r["iters"] * (a1 + dual) + r["cg_iters_total"] * cg + r["kkt_evals"] * ev
+    return r["iters"] * (a1 + dual + dsc) + r["cg_iters_total"] * cg + r["kkt_evals"] * (ev + dsc)
 
 
 def cpu_model():
@@ -609,6 +621,170 @@ def bench_learned(args):
             "speedup_warm_vs_cold": tc / tw, "speedup_warm_vs_cold_incl_inference": tc / (tw + infer_s)}
 
 
+PRE = {"ruiz_iters": 10, "pock_chambolle": 1}
+HEADLINE_WORKLOAD = ("4096 portfolio QPs batched, n log-uniform [50, 2000], Q = FF' + diag(d) as its factor "
+                     "(k = ceil(n/10)), rows 1'x<=1, -1'x<=-1, -x<=0; per-instance Ruiz(10) + Pock-Chambolle "
+                     "preconditioning, relKKT on each caller's problem; FP32 products + FP64 reductions; "
+                     "cold start; tol 1e-4")
+
+
+def portfolio_set(count):
+    """The headline instances in factored form: [(qp, (F, d))]."""
+    from paper_2405_16160_amd import instances as I
+    out = []
+    for i in range(count):
+        out.append(I.portfolio_lowrank(i))
+        if (i + 1) % 1024 == 0:
+            progress(f"generated {i + 1} portfolio QPs")
+    return out
+
+
+def _oracle_worker(job):
+    """One oracle solve of a portfolio instance in a worker pinned to one core
+    (single-threaded oracle): the preprocessing and the FP64 solve of the
+    oracle package, on the dense Q, to tol.  Returns seconds."""
+    core, inst, tol = job
+    os.sched_setaffinity(0, {core})
+    from oracle import oracle as O, precondition as P
+    from paper_2405_16160_amd import instances as I
+    qp = I.portfolio_qp(inst)
+    t = time.perf_counter()
+    _, _, r, _, _ = P.solve(qp, O.Settings(tol=tol, max_iters=400_000))
+    return time.perf_counter() - t, r.status, qp.n
+
+
+def cpu_baseline_portfolio(count, tol, stride=32):
+    """The FP64 oracle on this host's cores over a sample of the headline
+    instances (every stride-th id, which has the same size distribution):
+    instances spread over single-threaded worker processes, one per core and
+    pinned to it, as QPs/s of the sample (instances / wall seconds)."""
+    import multiprocessing as mp
+    from oracle import oracle as O
+    O.build()
+    cores = sorted(os.sched_getaffinity(0))[:16]
+    ids = list(range(0, count, stride))
+    jobs = [(cores[k % len(cores)], i, tol) for k, i in enumerate(ids)]
+    progress(f"CPU oracle: {len(ids)} portfolio instances on {len(cores)} pinned single-threaded workers")
+    env_old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        t = time.perf_counter()
+        with ctx.Pool(len(cores)) as pool:
+            res = pool.map(_oracle_worker, jobs, chunksize=1)
+        wall = time.perf_counter() - t
+    finally:
+        if env_old is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = env_old
+    secs = [r[0] for r in res]
+    return {"value": len(ids) / wall, "unit": "QPs/s", "cores": len(cores), "kind": "oracle",
+            "sample": f"{len(ids)} of the {count} portfolio instances (ids 0, {stride}, ..., dense Q, the oracle's "
+                      f"Ruiz + Pock-Chambolle preprocessing and FP64 solve to relKKT <= {tol:g}), one "
+                      f"single-threaded worker process per pinned core; {wall:.1f} s wall",
+            "wall_s": wall, "cpu_s_total": float(sum(secs)), "solved": sum(r[1] == 0 for r in res),
+            "cpu_model": cpu_model()}
+
+
+def one_by_one_sample(pairs, args, per_bin=2):
+    """Single-QP solves (pdhcg_solve, cooperative kernel, preconditioned, dense
+    Q as CSR) of a stratified sample: per_bin instances per log-size bin,
+    weighted by the bin's count; kernel seconds against kernel seconds."""
+    from paper_2405_16160_amd import instances as I, pdhcg
+    ns = np.array([q.n for q, _ in pairs])
+    edges = np.exp(np.linspace(np.log(50), np.log(2000), 17))
+    est, sample = 0.0, 0
+    s = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=200_000, **PRE)
+    for a, b in zip(edges[:-1], edges[1:]):
+        idx = np.nonzero((ns >= a) & (ns < b + 1e-9))[0]
+        if not idx.size:
+            continue
+        pick = idx[:per_bin]
+        for i in pick:
+            sol = pdhcg.Solver(I.portfolio_qp(int(i)), s)
+            _, _, r = sol.solve()
+            sol.close()
+            est += (idx.size / pick.size) * r["kernel_s"]
+            sample += 1
+    progress(f"one-by-one sample of {sample}: estimated {est:.2f} s of kernel time for all")
+    return {"sample": sample, "estimated_kernel_s_all": est, "QPs/s": len(pairs) / est}
+
+
+def side_random1e5(args):
+    """The random sparse QP n = 1e5 (plain, cold, FP32 products): kernel ms
+    and QPs/s over args.steps solves, and CG capped at one step beside it."""
+    import torch
+    from paper_2405_16160_amd import pdhcg
+    qp = workload()
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=args.tol, precision=1))
+    sol.solve()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ks = []
+    for _ in range(5):
+        _, _, r = sol.solve()
+        ks.append(r["kernel_s"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 5
+    sol.set_settings(pdhcg.Settings(tol_rel_kkt=args.tol, precision=1, max_cg_iters=1, cg_rule=1, max_iters=200_000))
+    _, _, r1 = sol.solve()
+    sol.close()
+    return {"workload": "random sparse QP n=1e5 m=5e4, plain, FP32 products, cold, tol 1e-4",
+            "QPs/s": 1.0 / dt, "ms_per_solve": dt * 1e3, "kernel_ms": float(np.mean(ks)) * 1e3,
+            "iters": r["iters"], "cg_steps": r["cg_iters_total"], "status": r["status_name"],
+            "cg_cap_1": {"iters": r1["iters"], "kernel_ms": r1["kernel_s"] * 1e3, "status": r1["status_name"]}}
+
+
+def side_powerlaw(args):
+    """The power-law QP n = 2e6, m = 1e6 to relKKT 1e-4 on its own problem
+    (preconditioned, FP32 products): time to tolerance."""
+    import torch
+    from paper_2405_16160_amd import instances as I, pdhcg
+    qp = I.powerlaw_qp()
+    t = time.perf_counter()
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=args.tol, precision=1, time_limit_s=30.0, **PRE))
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t
+    _, _, r = sol.solve()
+    sol.close()
+    return {"workload": "power-law QP n=2e6 m=1e6, preconditioned, FP32 products, cold, tol 1e-4",
+            "status": r["status_name"], "kernel_ms": r["kernel_s"] * 1e3, "solve_ms": r["solve_s"] * 1e3,
+            "iters": r["iters"], "cg_steps": r["cg_iters_total"], "rel_kkt": r["rel_kkt"], "create_s": create_s}
+
+
+def side_warm_start(args, train=4096, test=1024, epochs=60):
+    """Learned warm start on the MPC family at a reduced size (train solves,
+    epochs and held-out instances below the configuration's 100k / 10k):
+    batched cold vs warm kernel time on the held-out instances, inference
+    included in the second ratio."""
+    from paper_2405_16160_amd import instances as I, pdhcg, warmstart as W
+    fam = I.mpc_family()
+    plus, minus = W.pair_index(fam)
+    th, X, Y, _, gen_s = W.solve_family(fam, range(train), pdhcg.Settings(tol_rel_kkt=1e-6))
+    Y = W.canonical_duals(Y, plus, minus)
+    t = time.perf_counter()
+    ws, losses = W.train(th, X, Y, W.DualCode(fam.A.nrows, plus, minus), epochs=epochs)
+    train_s = time.perf_counter() - t
+    ids = range(100_000, 100_000 + test)
+    th_t, _ = W.family_qps(fam, ids)
+    t = time.perf_counter()
+    x0, y0 = ws.predict(th_t)
+    infer_s = time.perf_counter() - t
+    ws.net.close()
+    s = pdhcg.Settings(tol_rel_kkt=args.tol, warm_fallback=0)
+    _, _, _, rc, tc = W.solve_family(fam, ids, s)
+    _, _, _, rw, tw = W.solve_family(fam, ids, s, x0s=x0, y0s=y0)
+    progress(f"warm start: cold {tc:.3f} s, warm {tw:.3f} s, inference {infer_s:.3f} s")
+    return {"workload": f"MPC T=50 (n=1500, m=5000), reduced: {train} training solves, {epochs} epochs, "
+                        f"{test} held-out, batched, tol {args.tol:g}",
+            "cold_kernel_s": tc, "warm_kernel_s": tw, "infer_s": infer_s, "train_s": train_s,
+            "cold_iters_mean": float(np.mean([r["iters"] for r in rc])),
+            "warm_iters_mean": float(np.mean([r["iters"] for r in rw])),
+            "speedup_warm_vs_cold": tc / tw, "speedup_incl_inference": tc / (tw + infer_s),
+            "solved": [sum(r["status"] == 0 for r in rc), sum(r["status"] == 0 for r in rw)]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -618,7 +794,7 @@ def main():
     if args.summarize_counters:
         line = [json.loads(x) for x in open(args.bench_line) if x.startswith('{"metric"')][-1]
         alg = line["roofline"]["algorithmic_bytes_per_launch"]
-        print("counters-json: " + json.dumps(summarize_counters(args.summarize_counters, alg)))
+        print("counters-json: " + json.dumps(summarize_counters(args.summarize_counters, alg, args.counter_kernel)))
         return
     import torch
     from paper_2405_16160_amd import pdhcg
@@ -640,11 +816,94 @@ def main():
                           "copy_GB/s_read_plus_write": 2 * a.numel() * 8 / (ms * 1e-3) / 1e9}))
         return
 
-    if args.config != "random1e5":
-        line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch, "kappa": bench_kappa, "precondition": bench_precondition,
-                "learned": bench_learned}[args.config](args)
+    if args.config not in ("portfolio", "random1e5"):
+        line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch, "kappa": bench_kappa,
+                "precondition": bench_precondition, "learned": bench_learned}[args.config](args)
         print(json.dumps(line), flush=True)
         return
+    if args.config == "random1e5":
+        bench_random1e5(args)
+        return
+
+    # ---- headline: the batched portfolio configuration
+    count = args.batch_count
+    pairs = portfolio_set(count)
+    qps, facs = [q for q, _ in pairs], [f for _, f in pairs]
+    settings = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=200_000, **PRE)
+    t = time.perf_counter()
+    batch = pdhcg.Batch(qps, settings, lowrank=facs)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t
+    progress(f"batch created in {create_s:.2f} s (pack, upload, preconditioning)")
+    for _ in range(args.warmup):
+        batch.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for _ in range(args.steps):
+        _, _, rs = batch.solve()
+        runs.append(rs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rs = runs[-1]
+    solved = sum(r["status"] == 0 for r in rs)
+    assert all(r["status"] == 0 for run in runs for r in run), "an instance did not reach the tolerance"
+    kernel_s = float(np.mean([run[0]["kernel_s"] for run in runs]))   # one launch per batched solve
+    bytes_alg = sum(solve_bytes(q, r, args.precision, dense_q=True, rank=f[0].shape[1], scaled=True)
+                    for q, r, f in zip(qps, rs, facs))
+    achieved = bytes_alg / kernel_s / 1e9
+    traffic, _ = measured_traffic()
+    progress(f"{args.steps} batched solves: {dt / args.steps:.3f} s each, kernel {kernel_s:.3f} s")
+    line = {
+        "metric": "time & QPs/s to rel. KKT<=1e-4 (batched/warm-start vs plain); SpMV HBM GB/s",
+        "value": count * args.steps / dt,
+        "unit": "QPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": HEADLINE_WORKLOAD, "instances": count, "sum_n": int(sum(q.n for q in qps)),
+                   "sum_m": int(sum(q.m for q in qps)), "tol": args.tol,
+                   "precision": "fp32-products/fp64-reductions" if args.precision == 1 else "fp64"},
+        "solve": {"solved": solved, "iters_mean": float(np.mean([r["iters"] for r in rs])),
+                  "iters_max": int(max(r["iters"] for r in rs)),
+                  "cg_steps_mean": float(np.mean([r["cg_iters_total"] for r in rs])),
+                  "rel_kkt_max": float(max(r["rel_kkt"] for r in rs)), "create_s": create_s,
+                  "kernel_s": kernel_s, "launches_per_solve": 1},
+        "roofline": {"kernel": HEADLINE_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_alg},
+    }
+    if traffic is not None:
+        line["roofline"]["traffic_over_algorithmic"] = traffic / bytes_alg
+    batch.close()
+    if not args.no_extras:
+        extras = {}
+        obo = one_by_one_sample(pairs, args)
+        obo["speedup_of_batch_kernel_s"] = obo["estimated_kernel_s_all"] / kernel_s
+        extras["one_by_one_single_qp"] = obo
+        extras["random_qp_1e5"] = side_random1e5(args)
+        progress(f"random QP n=1e5: {extras['random_qp_1e5']['kernel_ms']:.1f} ms per solve")
+        extras["powerlaw_2e6"] = side_powerlaw(args)
+        progress(f"power-law n=2e6: {extras['powerlaw_2e6']['status']} in {extras['powerlaw_2e6']['kernel_ms']:.1f} ms")
+        extras["learned_warm_start"] = side_warm_start(args)
+        line["extras"] = extras
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_portfolio(count, args.tol)
+    print(json.dumps(line), flush=True)
+    torch.cuda.synchronize()
+
+
+def bench_random1e5(args):
+    """The random sparse QP n = 1e5 as its own bench line (single-QP solve
+    kernel, FP32 products, cold start, tol 1e-4)."""
+    import torch
+    from paper_2405_16160_amd import pdhcg
     qp = workload()
     settings = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, num_blocks=args.num_blocks)
     solver = pdhcg.Solver(qp, settings)
@@ -665,7 +924,7 @@ def main():
     launches = 1   # one solve-kernel launch per solve at this size (5000-iteration chunks)
     bytes_alg = solve_bytes(qp, r, args.precision)
     achieved = bytes_alg / kernel_s / 1e9
-    traffic, _ = measured_traffic()
+    traffic, _ = measured_traffic(os.path.join(ROOT, "profiles", "pdhcg_solve_kernel_random_qp_1e5_counters.md"))
     line = {
         "metric": "time & QPs/s to rel. KKT<=1e-4 (batched/warm-start vs plain); SpMV HBM GB/s",
         "value": args.steps / dt,
@@ -712,6 +971,9 @@ def main():
         line["cpu_baseline"] = cpu_baseline(qp, args.tol)
     print(json.dumps(line), flush=True)
     solver.close()
+    torch.cuda.synchronize()
+
+
 
 
 if __name__ == "__main__":

@@ -94,17 +94,29 @@ typedef struct {
                                         per step with (r, u, s) gathered (Chronopoulos-Gear),
                                         2 = textbook CG, two barriers per step with only the
                                         direction gathered */
-    int32_t ruiz_iters;              /* 0 (off); diagonal preconditioning (Sec. 5, preprocessing):
+    int32_t ruiz_iters;              /* 0 (off); diagonal preconditioning (Sec. 4, preprocessing):
                                         Ruiz equilibration steps on K = [[Q, A'], [A, 0]], the paper
-                                        runs 10.  The solver then works on D2 Q D2, D1 A D2, D1 b,
-                                        D2 c; relKKT, the residuals and the termination refer to that
-                                        scaled problem, the objective values are those of the
-                                        original one, and x = D2 x~, y = D1 y~ are returned.  Fixed
+                                        runs 10.  The solver then iterates on D2 Q D2, D1 A D2, D1 b,
+                                        D2 c, while relKKT, the residuals, the termination, the CG
+                                        tolerance schedule and the restart tests are those of the
+                                        caller's problem at x = D2 x~, y = D1 y~ (the progress metric
+                                        is defined for problem (1) as posed); x and y of the caller's
+                                        problem are returned.  Fixed
                                         at pdhcg_create for a handle; the batched entry points scale
                                         every instance on its own (its Q and A are then stored
-                                        unshared); pdhcg_solve_batch_lowrank rejects a nonzero value */
+                                        unshared; a factored Q keeps its factor form) */
     int32_t pock_chambolle;          /* 0 (off); 1: one Pock-Chambolle step (alpha = 1) after the
                                         Ruiz steps; same rules as ruiz_iters */
+    int32_t step_rule;               /* 0: constant eta per epoch (Thm 2; changed only through the
+                                        primal weight).  1: adaptive step size (Sec. 4): each
+                                        iteration's primal and dual steps are a trial at the current
+                                        eta, accepted when eta <= eta_bar = ||dz||_w^2 /
+                                        (2 |dy'A dx| + dx'Q dx) (||.||_w the primal-weight norm);
+                                        eta becomes min((1 - (t+1)^-0.3) eta_bar, (1 + (t+1)^-0.6) eta)
+                                        after every trial, and a rejected trial is repeated from
+                                        z^k.  eta starts at step_eta_factor / ||A||_2 and persists
+                                        across restarts.  The single-QP solve then keeps its CG
+                                        state in device memory (no chained steps) */
 } pdhcg_settings;
 
 typedef struct {
@@ -122,6 +134,8 @@ typedef struct {
                                         handle's stream) */
     int64_t kkt_evals;               /* restart evaluations (relKKT of the average) performed */
     int32_t cold_fallback;           /* 1 if the given start point was replaced by (0, 0) */
+    int64_t rejected_steps;          /* trials rejected by the adaptive step size (step_rule 1) */
+    double step_eta;                 /* eta at the end of the solve */
 } pdhcg_result;
 
 typedef struct pdhcg_handle pdhcg_handle;
@@ -149,10 +163,12 @@ int pdhcg_set_b(pdhcg_handle* h, const double* b, int32_t vec_on_device);
 int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_out, double* y_out,
                 int32_t vec_on_device, pdhcg_result* r);
 
-/* Solve `count` independent QPs (host CSR and host vectors).  Instances are
- * packed once, then solved by one workgroup per instance in a persistent
- * kernel; every instance gets its own status in rs[i].  x0s/y0s may be NULL
- * (cold start) or hold NULL entries. */
+/* Solve `count` independent QPs in one call (pdhcg_batch_create, one
+ * pdhcg_batch_solve, pdhcg_batch_destroy).  The CSR matrices may be host or
+ * device arrays (their on_device flags); bs, cs, x0s, y0s, x_outs, y_outs are
+ * host arrays.  Every instance is solved by one workgroup of a persistent
+ * kernel and gets its own status in rs[i].  x0s/y0s may be NULL (cold start)
+ * or hold NULL entries. */
 int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
                       const double* const* bs, const double* const* cs,
                       const double* const* x0s, const double* const* y0s,
@@ -160,12 +176,14 @@ int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
                       const pdhcg_settings* s, void* hip_stream);
 
 /* A dense Q given by its factor: Q = F F' + diag(d), F n x k (row-major,
- * k <= n), d (n); host arrays.  The portfolio model's form (Sec. 5): the
- * batched products then read 2 n k values per product instead of n^2. */
+ * k <= n), d (n).  The low-rank form of Q (Sec. 2, low-rank acceleration; the
+ * portfolio model of Sec. 5.1): the batched products then read 2 n k values
+ * per product instead of n^2. */
 typedef struct {
     int64_t n, k;
     const double* F;
     const double* d;
+    int32_t on_device;               /* 1: F and d are device pointers */
 } pdhcg_lowrank;
 
 /* pdhcg_solve_batch with every Q given by its factor (Qs[i]); A, b, c, start
@@ -189,7 +207,46 @@ int pdhcg_solve_multi_rhs(int32_t count, const pdhcg_csr* Q, const pdhcg_csr* A,
                           const double* c, const double* X0, const double* Y0, double* X, double* Y,
                           pdhcg_result* rs, const pdhcg_settings* s, void* hip_stream);
 
-/* The diagonals of the preconditioning of a handle (Sec. 5, preprocessing):
+/* ----------------------------------------------------------------- batches
+ * A batch of independent QPs packed into device memory once and solved any
+ * number of times (Alg. 1 on every instance, one workgroup per instance).
+ * Vectors of the instances are packed end to end: x of instance i occupies
+ * entries n_off[i] .. n_off[i+1]-1 of a packed n-vector, y of instance i
+ * entries m_off[i] .. m_off[i+1]-1 of a packed m-vector (pdhcg_batch_layout). */
+typedef struct pdhcg_batch pdhcg_batch;
+
+/* Validate, pack and upload `count` QPs.  Exactly one of Qs (CSR; a dense
+ * n x n pattern is detected and stored as a dense block) and Ls (factors of
+ * Q = F F' + diag(d)) is non-NULL.  CSR and factor arrays are device or host
+ * arrays by their own on_device flags; bs[i] (m_i) and cs[i] (n_i) are device
+ * pointers when vec_on_device = 1.  Matrices given by the same pointers are
+ * stored once (not with preconditioning, which scales every instance on its
+ * own in one launch).  The caller's arrays may be freed afterwards.  Errors:
+ * INVALID_ARGUMENT (null pointers, bad shapes, CSR structure, Q not exactly
+ * symmetric), OUT_OF_MEMORY, HIP; on error *h is NULL. */
+int pdhcg_batch_create(pdhcg_batch** h, int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls,
+                       const pdhcg_csr* As, const double* const* bs, const double* const* cs,
+                       int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream);
+
+/* n_off and m_off (count + 1 entries each) receive the packed offsets. */
+int pdhcg_batch_layout(const pdhcg_batch* h, int64_t* n_off, int64_t* m_off);
+
+/* Solve every instance from the packed start points x0 / y0 (NULL: cold
+ * start (0, 0); y0 is projected onto y >= 0) and write the returned points to
+ * the packed x_out / y_out.  All four are device pointers when
+ * vec_on_device = 1, else host pointers.  rs (count entries, may be NULL)
+ * receives each instance's result; kernel_s is the device time of the one
+ * batched launch.  Solve outcomes are per instance (rs[i].status). */
+int pdhcg_batch_solve(pdhcg_batch* h, const double* x0, const double* y0, double* x_out, double* y_out,
+                      int32_t vec_on_device, pdhcg_result* rs);
+
+/* The packed D1 (rows) and D2 (variables) of the batch's preconditioning
+ * (ones when it is off); device pointers when vec_on_device = 1. */
+int pdhcg_batch_get_scaling(const pdhcg_batch* h, double* d1_out, double* d2_out, int32_t vec_on_device);
+
+void pdhcg_batch_destroy(pdhcg_batch* h);
+
+/* The diagonals of the preconditioning of a handle (Sec. 4, preprocessing):
  * d1_out[m] = D1 (constraint rows), d2_out[n] = D2 (variables); all ones when
  * ruiz_iters = 0 and pock_chambolle = 0 at pdhcg_create.  Outputs are device
  * pointers when vec_on_device = 1, else host pointers; d1_out may be NULL when

@@ -78,9 +78,13 @@ int check_structure(const int64_t* rowptr, const int32_t* col, int64_t nrows, in
                     const std::string& name) {
   if (rowptr[0] != 0 || rowptr[nrows] != nnz)
     return fail(PDHCG_ERR_INVALID_ARGUMENT, name + ": rowptr[0] != 0 or rowptr[nrows] != nnz");
+  // every row pointer is checked before any column is read, so that a bad
+  // pointer cannot send the column scan past the end of col
+  for (int64_t i = 0; i < nrows; ++i)
+    if (rowptr[i + 1] < rowptr[i] || rowptr[i + 1] > nnz)
+      return fail(PDHCG_ERR_INVALID_ARGUMENT,
+                  name + ": rowptr not monotone or beyond nnz at row " + std::to_string(i));
   for (int64_t i = 0; i < nrows; ++i) {
-    if (rowptr[i + 1] < rowptr[i])
-      return fail(PDHCG_ERR_INVALID_ARGUMENT, name + ": rowptr not monotone at row " + std::to_string(i));
     for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
       if (col[k] < 0 || col[k] >= ncols)
         return fail(PDHCG_ERR_INVALID_ARGUMENT, name + ": column out of range in row " + std::to_string(i));
@@ -266,6 +270,7 @@ struct pdhcg_handle {
          *x_anc = nullptr, *y_anc = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   float *x32 = nullptr, *r32 = nullptr, *p32_0 = nullptr, *p32_1 = nullptr, *xs32 = nullptr;
   double *r_alt = nullptr, *u0 = nullptr, *u1 = nullptr, *s0 = nullptr, *s1 = nullptr;
+  double *x_prev = nullptr, *y_trial = nullptr, *ax_trial = nullptr;  // adaptive step size
   float4 *v32_0 = nullptr, *v32_1 = nullptr;   // interleaved FP32 (r, u, s) of the one-reduction CG
   double *part = nullptr, *tmp_x0 = nullptr, *tmp_y0 = nullptr, *scratch = nullptr;
   double* dscale = nullptr;  // D2 (n) then D1 (m) of the preconditioning; ones when off
@@ -397,6 +402,7 @@ int check_settings(const pdhcg_settings* s) {
   if (s->ruiz_iters < 0 || s->ruiz_iters > 100) return fail(PDHCG_ERR_INVALID_ARGUMENT, "ruiz_iters must be in [0, 100]");
   if (s->pock_chambolle != 0 && s->pock_chambolle != 1)
     return fail(PDHCG_ERR_INVALID_ARGUMENT, "pock_chambolle must be 0 or 1");
+  if (s->step_rule != 0 && s->step_rule != 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "step_rule must be 0 or 1");
   return 0;
 }
 
@@ -509,7 +515,9 @@ int plan_residency(pdhcg_handle* h, SolveParams& p) {
   const int64_t bq = block(h->cg_bounds, h->qrp_h);
   const int64_t ba = h->m ? block(h->m_bounds, h->arp_h) : 0;
   int64_t total = 0;
-  if (p.u0 && bo > 0 && bo <= budget) {
+  // (the adaptive step size gathers the FP64 x of every row after the primal
+  // step, so the CG state then stays in device memory)
+  if (p.u0 && bo > 0 && bo <= budget && !h->s.step_rule) {
     p.own_cg = 1;
     total = bo;
   }
@@ -572,6 +580,8 @@ SolveParams make_params(pdhcg_handle* h) {
   p.pt = h->pt.view();
   p.nb_inf = h->nb_inf;
   p.nc_inf = h->nc_inf;
+  p.dn = h->scaled ? h->dscale : nullptr;
+  p.dm = h->scaled && h->m > 0 ? h->dscale + h->n : nullptr;
   const pdhcg_settings& s = h->s;
   p.tol = s.tol_rel_kkt;
   p.eps_factor = s.cg_eps_factor;
@@ -587,6 +597,12 @@ SolveParams make_params(pdhcg_handle* h) {
   p.restart_to = s.restart_to;
   p.eval_period = s.eval_period;
   p.mixed_allowed = s.precision == 1;
+  p.step_rule = s.step_rule;
+  if (s.step_rule) {
+    p.x_prev = h->x_prev;
+    p.y_trial = h->y_trial;
+    p.ax_trial = h->ax_trial;
+  }
   return p;
 }
 
@@ -648,6 +664,7 @@ void pdhcg_default_settings(pdhcg_settings* s) {
   s->cg_form = 0;
   s->ruiz_iters = 0;
   s->pock_chambolle = 0;
+  s->step_rule = 0;
 }
 
 int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, const double* b, const double* c,
@@ -694,10 +711,10 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
   if ((rc = upload_csr(h, T, &h->t_rowptr, &h->t_col, &h->t_val))) return bail(rc);
   const int64_t n = h->n, m = h->m;
   double** nvecs[] = {&h->c, &h->x, &h->xa, &h->x_anc, &h->r, &h->p0, &h->p1, &h->q, &h->tmp_x0,
-                      &h->r_alt, &h->u0, &h->u1, &h->s0, &h->s1};
+                      &h->r_alt, &h->u0, &h->u1, &h->s0, &h->s1, &h->x_prev};
   for (double** v : nvecs)
     if ((rc = h->alloc(v, n))) return bail(rc);
-  double** mvecs[] = {&h->b, &h->y, &h->ya, &h->ax, &h->ax_avg, &h->y_anc, &h->tmp_y0};
+  double** mvecs[] = {&h->b, &h->y, &h->ya, &h->ax, &h->ax_avg, &h->y_anc, &h->tmp_y0, &h->y_trial, &h->ax_trial};
   for (double** v : mvecs)
     if ((rc = h->alloc(v, m))) return bail(rc);
   if ((rc = h->alloc(&h->scratch, 16))) return bail(rc);
@@ -714,8 +731,9 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
     if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(PDHCG_ERR_HIP, "stream sync failed"));
   }
   if (s->ruiz_iters > 0 || s->pock_chambolle) {
-    // preconditioning (Sec. 5): scale Q, A, A', b, c on the device, then take
-    // the norms that relKKT uses from the scaled b and c
+    // preconditioning (Sec. 4, preprocessing): scale Q, A, A', b, c on the
+    // device; relKKT stays that of the caller's problem, so the norms of b and
+    // c and relKKT(0, 0) keep the values taken above from the unscaled data
     double* f = nullptr;
     if ((rc = h->alloc(&f, n + m))) return bail(rc);
     if (launch_precondition(h->mat(0), h->mat(1), h->mat(2), h->nnzQ, h->nnzA, s->ruiz_iters, s->pock_chambolle, f,
@@ -723,14 +741,7 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
         launch_diag(h->b, h->dscale + n, m, 0, h->b, h->stream) != hipSuccess ||
         launch_diag(h->c, h->dscale, n, 0, h->c, h->stream) != hipSuccess)
       return bail(fail(PDHCG_ERR_HIP, "preconditioning kernels failed to launch"));
-    if ((m > 0 && hipMemcpyAsync(hb.data(), h->b, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess) ||
-        hipMemcpyAsync(hc.data(), h->c, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess)
-      return bail(fail(PDHCG_ERR_HIP, "preconditioning failed"));
-    h->nb_inf = max_abs_nan(hb.data(), m);
-    h->nc_inf = max_abs_nan(hc.data(), n);
-    h->kkt_zero = kkt_at_zero(hb.data(), m, hc.data(), n);
-    h->c_host = hc;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(PDHCG_ERR_HIP, "preconditioning failed"));
     h->scaled = true;
   }
   if ((rc = plan(h, Q, A, T))) return bail(rc);
@@ -769,10 +780,7 @@ int pdhcg_set_b(pdhcg_handle* h, const double* b, int32_t vec_on_device) {
   if (h->m > 0) {
     HIPX(hipMemcpy(hb.data(), b, sizeof(double) * h->m, vec_on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
     HIPX(hipMemcpyAsync(h->b, hb.data(), sizeof(double) * h->m, hipMemcpyHostToDevice, h->stream));
-    if (h->scaled) {  // b~ = D1 b
-      HIPX(launch_diag(h->b, h->dscale + h->n, h->m, 0, h->b, h->stream));
-      HIPX(hipMemcpyAsync(hb.data(), h->b, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->stream));
-    }
+    if (h->scaled) HIPX(launch_diag(h->b, h->dscale + h->n, h->m, 0, h->b, h->stream));  // b~ = D1 b
     HIPX(hipStreamSynchronize(h->stream));
   }
   h->nb_inf = max_abs_nan(hb.data(), h->m);
@@ -864,6 +872,8 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
     res->kernel_s = kernel_ms * 1e-3;
     res->kkt_evals = st.evals;
     res->cold_fallback = st.cold_fallback;
+    res->rejected_steps = st.rejections;
+    res->step_eta = st.eta;
   }
   return 0;
 }
@@ -1047,8 +1057,13 @@ void batch_parts(const int64_t* qrp, bool dense, int64_t n, const HostCsr& A, co
   if (dense) g[0] = pow2_ceil(m ? (double)T.rowptr[n] / (double)n : 1.0);
 }
 
+// Device buffers of a batch: allocated with hipMalloc (and freed with the
+// batch), or, with an arena, carved from that region (the static scratch of
+// the allocation-free entry point: nothing is allocated or freed).
 struct DevBuf {
   std::vector<void*> ptrs;
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
   ~DevBuf() {
     for (void* p : ptrs) (void)hipFree(p);
   }
@@ -1056,6 +1071,17 @@ struct DevBuf {
   int alloc(T** p, int64_t count) {
     *p = nullptr;
     const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    if (arena) {
+      const size_t off = (used + 255) & ~(size_t)255;
+      if (off + bytes > cap)
+        return fail(PDHCG_ERR_INVALID_ARGUMENT,
+                    "the batch needs more device memory than the " + std::to_string(cap >> 20) +
+                        " MiB static scratch of pdhcg_solve_batch_noalloc holds (at least " +
+                        std::to_string(off + bytes) + " bytes); use pdhcg_solve_batch");
+      *p = (T*)(arena + off);
+      used = off + bytes;
+      return 0;
+    }
     const hipError_t e = hipMalloc((void**)p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -1069,30 +1095,170 @@ struct DevBuf {
 
 }  // namespace
 
-// The batched solve; Q of instance i is Qs[i] (CSR, dense detected) or, when
-// Ls is given instead, the factor Ls[i] of Q = F F' + diag(d).
-int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls, const pdhcg_csr* As,
-                     const double* const* bs, const double* const* cs, const double* const* x0s,
-                     const double* const* y0s, double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
-                     const pdhcg_settings* s, void* hip_stream) {
+// A batch packed on the device once and solved any number of times: the
+// matrices, vectors, row partitions, parameter blocks and (with
+// preconditioning) the scaled data and D1, D2 stay resident in HBM.
+struct pdhcg_batch {
+  int32_t count = 0;
+  hipStream_t stream = nullptr;
+  pdhcg_settings s{};
+  bool pre = false, mixed = false;
+  DevBuf D;
+  std::vector<BatchInst> inst;
+  std::vector<int64_t> off_n, off_m;  // count + 1 offsets of the packed vectors
+  int64_t vn_tot = 0, vm_tot = 0;
+  std::vector<int32_t> given0;        // start flags of the last solve (bit 0 x0, bit 1 y0)
+  SolveParams* d_params = nullptr;
+  int32_t* d_order = nullptr;
+  SolverState* d_st = nullptr;
+  uint64_t* d_t0 = nullptr;
+  uint8_t* d_given = nullptr;
+  double *d_x0 = nullptr, *d_y0 = nullptr, *d_d2 = nullptr, *d_d1 = nullptr;
+  double *x = nullptr, *y = nullptr;    // packed iterates (of the scaled problems when preconditioned)
+  double *xo = nullptr, *yo = nullptr;  // returned points of the callers' problems
+  BatchParams bp{};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double setup_s = 0.0;
+  ~pdhcg_batch() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+namespace {
+
+// One instance's input as host arrays: the caller's own, or copies of
+// device-resident input fetched once.
+struct HostInst {
+  pdhcg_csr Q{}, A{};
+  pdhcg_lowrank L{};
+  const double* b = nullptr;
+  const double* c = nullptr;
+  std::vector<int64_t> qrp, arp;
+  std::vector<int32_t> qcol, acol;
+  std::vector<double> qval, aval, bv, cv, F, d;
+};
+
+int fetch_dev(void* dst, const void* src, size_t bytes) {
+  if (bytes) HIPX(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+// host copies of a CSR given in device memory (sizes are checked by the caller)
+int host_csr(const pdhcg_csr& M, std::vector<int64_t>& rp, std::vector<int32_t>& col, std::vector<double>& val,
+             pdhcg_csr& out) {
+  out = M;
+  if (!M.on_device) return 0;
+  if (!M.rowptr || (M.nnz > 0 && (!M.col || !M.val))) return 0;  // reported as null arrays later
+  int rc;
+  rp.resize(M.nrows + 1);
+  col.resize(M.nnz);
+  val.resize(M.nnz);
+  if ((rc = fetch_dev(rp.data(), M.rowptr, sizeof(int64_t) * (M.nrows + 1)))) return rc;
+  if ((rc = fetch_dev(col.data(), M.col, sizeof(int32_t) * M.nnz))) return rc;
+  if ((rc = fetch_dev(val.data(), M.val, sizeof(double) * M.nnz))) return rc;
+  out.rowptr = rp.data();
+  out.col = col.data();
+  out.val = val.data();
+  out.on_device = 0;
+  return 0;
+}
+
+}  // namespace
+
+// Pack and upload a batch; Q of instance i is Qs[i] (CSR, dense detected) or,
+// when Ls is given instead, the factor Ls[i] of Q = F F' + diag(d).
+int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, const pdhcg_lowrank* Ls_in,
+                      const pdhcg_csr* As_in, const double* const* bs_in, const double* const* cs_in,
+                      int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream, char* arena = nullptr,
+                      size_t arena_bytes = 0) {
   const double t0 = now_s();
   int rc;
+  if (!out) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle pointer");
+  *out = nullptr;
   if ((rc = check_settings(s))) return rc;
-  // preconditioning (Sec. 5) per instance: every instance gets its own blocks (no
-  // sharing), scaled on the device after the upload; a dense Q keeps its layout
-  // (its CSR values are the row-major block) and is scaled through a temporary
-  // CSR view of it
+  if (count < 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 1");
+  if ((!Qs_in && !Ls_in) || (Qs_in && Ls_in) || !As_in || !bs_in || !cs_in)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument (exactly one of Qs and Ls must be given)");
+  const bool lowrank = Ls_in != nullptr;
+  // preconditioning (Sec. 4, preprocessing) per instance: every instance gets
+  // its own blocks (no sharing), scaled on the device after the upload by one
+  // launch (one workgroup per instance); a dense Q keeps its dense block and a
+  // factored Q its factor form
   const bool pre = s->ruiz_iters != 0 || s->pock_chambolle != 0;
-  if (pre && Ls) return fail(PDHCG_ERR_INVALID_ARGUMENT, "preconditioning is not available with a factored Q");
-  if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
-  if (count == 0) return 0;
-  if ((!Qs && !Ls) || !As || !bs || !cs || !x_outs || !y_outs)
-    return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
-  hipStream_t stream = (hipStream_t)hip_stream;
   const bool mixed = s->precision == 1;
 
+  // ---- host views of the inputs (device-resident inputs are fetched once)
+  std::vector<HostInst> H(count);
+  for (int i = 0; i < count; ++i) {
+    HostInst& hi = H[i];
+    const std::string tag = "instance " + std::to_string(i);
+    if ((rc = host_csr(As_in[i], hi.arp, hi.acol, hi.aval, hi.A))) return rc;
+    if (lowrank) {
+      hi.L = Ls_in[i];
+      const pdhcg_lowrank& L = Ls_in[i];
+      if (L.n < 1 || L.k < 1 || L.k > L.n || L.n >= (1 << 30) || L.n * L.k >= (1ll << 31))
+        return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": factor sizes must satisfy 1 <= k <= n < 2^30");
+      if (!L.F || !L.d) return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": null factor array");
+      if (L.on_device) {
+        hi.F.resize((size_t)(L.n * L.k));
+        hi.d.resize((size_t)L.n);
+        if ((rc = fetch_dev(hi.F.data(), L.F, sizeof(double) * hi.F.size()))) return rc;
+        if ((rc = fetch_dev(hi.d.data(), L.d, sizeof(double) * hi.d.size()))) return rc;
+        hi.L.F = hi.F.data();
+        hi.L.d = hi.d.data();
+        hi.L.on_device = 0;
+      }
+    } else {
+      if ((rc = host_csr(Qs_in[i], hi.qrp, hi.qcol, hi.qval, hi.Q))) return rc;
+    }
+    const int64_t n = lowrank ? Ls_in[i].n : Qs_in[i].nrows;
+    const int64_t m = As_in[i].nrows;
+    if (n < 1 || n >= (1 << 30) || m < 0 || m >= (1 << 30))
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": bad shapes");
+    hi.b = bs_in[i];
+    hi.c = cs_in[i];
+    if (!hi.c || (m > 0 && !hi.b)) return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": null array");
+    if (vec_on_device) {
+      hi.cv.resize(n);
+      hi.bv.resize(std::max<int64_t>(m, 1), 0.0);
+      if ((rc = fetch_dev(hi.cv.data(), hi.c, sizeof(double) * n))) return rc;
+      if (m > 0 && (rc = fetch_dev(hi.bv.data(), hi.b, sizeof(double) * m))) return rc;
+      hi.c = hi.cv.data();
+      hi.b = hi.bv.data();
+    }
+  }
+  std::vector<pdhcg_csr> Qv(count), Av(count);
+  std::vector<pdhcg_lowrank> Lv(lowrank ? count : 0);
+  std::vector<const double*> bs(count), cs(count);
+  for (int i = 0; i < count; ++i) {
+    Qv[i] = H[i].Q;
+    Av[i] = H[i].A;
+    if (lowrank) Lv[i] = H[i].L;
+    bs[i] = H[i].b;
+    cs[i] = H[i].c;
+  }
+  const pdhcg_csr* Qs = lowrank ? nullptr : Qv.data();
+  const pdhcg_lowrank* Ls = lowrank ? Lv.data() : nullptr;
+  const pdhcg_csr* As = Av.data();
+  hipStream_t stream = (hipStream_t)hip_stream;
+
+  pdhcg_batch* h = new pdhcg_batch();
+  auto bail = [&](int code) {
+    delete h;
+    return code;
+  };
+  h->count = count;
+  h->stream = stream;
+  h->s = *s;
+  h->pre = pre;
+  h->mixed = mixed;
+  h->D.arena = arena;
+  h->D.cap = arena_bytes;
+
   // ---- validate, detect dense Q, build A', de-duplicate shared matrices
-  std::vector<BatchInst> inst(count);
+  std::vector<BatchInst>& inst = h->inst;
+  inst.resize(count);
   std::vector<HostCsr> At(count);
   std::vector<int32_t> parts;
   struct Key {
@@ -1107,10 +1273,6 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     pdhcg_csr Qf{};
     if (Ls) {
       const pdhcg_lowrank& L = Ls[i];
-      const std::string tag = "instance " + std::to_string(i);
-      if (L.n < 1 || L.k < 1 || L.k > L.n || L.n >= (1 << 30) || L.n * L.k >= (1ll << 31))
-        return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": factor sizes must satisfy 1 <= k <= n < 2^30");
-      if (!L.F || !L.d) return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": null factor array");
       Qf.nrows = Qf.ncols = L.n;
       Qf.nnz = 2 * L.n * L.k + L.n;  // stored values: F, F', d
       Qf.rowptr = reinterpret_cast<const int64_t*>(L.F);  // (identity of the factor for sharing; not read)
@@ -1120,14 +1282,13 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     const pdhcg_csr& Q = Ls ? Qf : Qs[i];
     const pdhcg_csr& A = As[i];
     const std::string tag = "instance " + std::to_string(i);
-    if (Q.on_device || A.on_device) return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": batch inputs must be host arrays");
     if (Q.nrows != Q.ncols || Q.nrows < 1 || A.ncols != Q.nrows || A.nrows < 0)
-      return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": bad shapes");
-    if (Q.nrows >= (1 << 30) || A.nrows >= (1 << 30) || Q.nnz >= (1ll << 31) || A.nnz >= (1ll << 31))
-      return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": sizes beyond 32-bit indexing");
-    if (!Q.rowptr || !A.rowptr || (Q.nnz && (!Q.col || !Q.val)) || (A.nnz && (!A.col || !A.val)) || !cs[i] ||
-        (A.nrows && !bs[i]) || !x_outs[i] || (A.nrows && !y_outs[i]))
-      return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": null array");
+      return bail(fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": bad shapes"));
+    if (Q.nrows >= (1 << 30) || A.nrows >= (1 << 30) || Q.nnz >= (1ll << 31) || A.nnz >= (1ll << 31) ||
+        Q.nnz < 0 || A.nnz < 0)
+      return bail(fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": sizes beyond 32-bit indexing"));
+    if (!Q.rowptr || !A.rowptr || (Q.nnz && (!Q.col || !Q.val)) || (A.nnz && (!A.col || !A.val)))
+      return bail(fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": null array"));
     BatchInst& I = inst[i];
     I.n = (int32_t)Q.nrows;
     I.m = (int32_t)A.nrows;
@@ -1142,10 +1303,10 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
       q_seen[qk] = i;
       q_first[i] = i;
     } else if (qit == q_seen.end()) {
-      if ((rc = check_structure(Q.rowptr, Q.col, Q.nrows, Q.ncols, Q.nnz, tag + " Q"))) return rc;
+      if ((rc = check_structure(Q.rowptr, Q.col, Q.nrows, Q.ncols, Q.nnz, tag + " Q"))) return bail(rc);
       const bool dense = is_dense(Q.rowptr, Q.nrows);
       if (!symmetric_ptrs(Q.rowptr, Q.col, Q.val, Q.nrows, dense))
-        return fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": Q is not exactly symmetric");
+        return bail(fail(PDHCG_ERR_INVALID_ARGUMENT, tag + ": Q is not exactly symmetric"));
       I.dense = dense ? 1 : 0;
       I.q_rp = dense ? 0 : rp_tot;
       I.q_nz = nz_tot;
@@ -1160,7 +1321,7 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     }
     auto ait = pre ? a_seen.end() : a_seen.find(ak);
     if (ait == a_seen.end()) {
-      if ((rc = check_structure(A.rowptr, A.col, A.nrows, A.ncols, A.nnz, tag + " A"))) return rc;
+      if ((rc = check_structure(A.rowptr, A.col, A.nrows, A.ncols, A.nnz, tag + " A"))) return bail(rc);
       HostCsr Ah;
       Ah.nrows = A.nrows;
       Ah.ncols = A.ncols;
@@ -1181,12 +1342,21 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     }
     I.voff_n = vn_tot; vn_tot += I.n;
     I.voff_m = vm_tot; vm_tot += I.m;
+    // relKKT is that of the caller's problem: norms of the unscaled b and c
     I.nc_inf = max_abs_nan(cs[i], I.n);
     I.nb_inf = max_abs_nan(bs[i], I.m);
-    I.x0_given = (x0s && x0s[i]) ? 1 : 0;
-    I.y0_given = (y0s && y0s[i] && I.m) ? 1 : 0;
-    I.kkt_zero = (s->warm_fallback && (I.x0_given || I.y0_given)) ? kkt_at_zero(bs[i], I.m, cs[i], I.n) : 0.0;
+    I.kkt_zero = kkt_at_zero(bs[i], I.m, cs[i], I.n);
   }
+  h->vn_tot = vn_tot;
+  h->vm_tot = vm_tot;
+  h->off_n.resize(count + 1);
+  h->off_m.resize(count + 1);
+  for (int i = 0; i < count; ++i) {
+    h->off_n[i] = inst[i].voff_n;
+    h->off_m[i] = inst[i].voff_m;
+  }
+  h->off_n[count] = vn_tot;
+  h->off_m[count] = vm_tot;
   // partitions (per distinct (Q, A) pair the lists are identical; built per instance for simplicity)
   for (int i = 0; i < count; ++i) {
     BatchInst& I = inst[i];
@@ -1211,66 +1381,55 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
   });
 
   // ---- device buffers
-  DevBuf D;
-  int32_t *d_rp, *d_col, *d_parts, *d_order;
+  DevBuf& D = h->D;
+  int32_t *d_rp, *d_col, *d_parts;
   double* d_val;
   float* d_val32 = nullptr;
-  SolveParams* d_params;
-  SolverState* d_st;
-  uint64_t* d_t0;
-  double *d_b, *d_c, *d_x0 = nullptr, *d_y0 = nullptr, *d_part;
-  double* nv[8];  // x xa x_anc r p0 p1 q (+ spare)
-  double* mv[5];  // y ya ax ax_avg y_anc
+  double *d_b, *d_c, *d_part;
+  double* nv[9];  // x xa x_anc r p0 p1 q x_prev (+ F' v of a factored Q)
+  double* mv[7];  // y ya ax ax_avg y_anc y_trial ax_trial
   float* fv[4] = {nullptr, nullptr, nullptr, nullptr};
-  if ((rc = D.alloc(&d_rp, rp_tot))) return rc;
-  if ((rc = D.alloc(&d_col, nz_tot))) return rc;
-  if ((rc = D.alloc(&d_val, nz_tot))) return rc;
-  if (mixed && (rc = D.alloc(&d_val32, nz_tot))) return rc;
-  if ((rc = D.alloc(&d_parts, (int64_t)parts.size()))) return rc;
-  if ((rc = D.alloc(&d_params, count))) return rc;
-  if ((rc = D.alloc(&d_st, count))) return rc;
-  if ((rc = D.alloc(&d_t0, 1))) return rc;
-  if ((rc = D.alloc(&d_b, vm_tot))) return rc;
-  if ((rc = D.alloc(&d_c, vn_tot))) return rc;
-  if ((rc = D.alloc(&d_part, (int64_t)count * NSLOT))) return rc;
-  if ((rc = D.alloc(&d_order, count))) return rc;
-  for (int k = 0; k < (Ls ? 8 : 7); ++k)  // (+ F' v of a factored Q, k <= n entries)
-    if ((rc = D.alloc(&nv[k], vn_tot))) return rc;
-  for (int k = 0; k < 5; ++k)
-    if ((rc = D.alloc(&mv[k], vm_tot))) return rc;
+  if ((rc = D.alloc(&d_rp, rp_tot))) return bail(rc);
+  if ((rc = D.alloc(&d_col, nz_tot))) return bail(rc);
+  if ((rc = D.alloc(&d_val, nz_tot))) return bail(rc);
+  if (mixed && (rc = D.alloc(&d_val32, nz_tot))) return bail(rc);
+  if ((rc = D.alloc(&d_parts, (int64_t)parts.size()))) return bail(rc);
+  if ((rc = D.alloc(&h->d_params, count))) return bail(rc);
+  if ((rc = D.alloc(&h->d_st, count))) return bail(rc);
+  if ((rc = D.alloc(&h->d_t0, 1))) return bail(rc);
+  if ((rc = D.alloc(&h->d_given, count))) return bail(rc);
+  if ((rc = D.alloc(&d_b, vm_tot))) return bail(rc);
+  if ((rc = D.alloc(&d_c, vn_tot))) return bail(rc);
+  if ((rc = D.alloc(&d_part, (int64_t)count * NSLOT))) return bail(rc);
+  if ((rc = D.alloc(&h->d_order, count))) return bail(rc);
+  const bool adaptive = s->step_rule == 1;
+  for (int k = 0; k < 9; ++k) {
+    nv[k] = nullptr;
+    if ((k == 7 && !adaptive) || (k == 8 && !Ls)) continue;
+    if ((rc = D.alloc(&nv[k], vn_tot))) return bail(rc);
+  }
+  for (int k = 0; k < 7; ++k) {
+    mv[k] = nullptr;
+    if (k >= 5 && !adaptive) continue;
+    if ((rc = D.alloc(&mv[k], vm_tot))) return bail(rc);
+  }
   if (mixed)
     for (int k = 0; k < 4; ++k)
-      if ((rc = D.alloc(&fv[k], vn_tot))) return rc;
-  bool any_x0 = false, any_y0 = false;
-  for (int i = 0; i < count; ++i) {
-    any_x0 |= inst[i].x0_given != 0;
-    any_y0 |= inst[i].y0_given != 0;
-  }
-  if (any_x0 && (rc = D.alloc(&d_x0, vn_tot))) return rc;
-  if (any_y0 && (rc = D.alloc(&d_y0, vm_tot))) return rc;
+      if ((rc = D.alloc(&fv[k], vn_tot))) return bail(rc);
+  if ((rc = D.alloc(&h->d_x0, vn_tot))) return bail(rc);
+  if ((rc = D.alloc(&h->d_y0, vm_tot))) return bail(rc);
+  if ((rc = D.alloc(&h->xo, vn_tot))) return bail(rc);
+  if ((rc = D.alloc(&h->yo, vm_tot))) return bail(rc);
+  h->x = nv[0];
+  h->y = mv[0];
 
-  // ---- uploads (matrix blocks straight from the caller's arrays)
+  // ---- uploads (matrix blocks straight from the host arrays)
   auto up = [&](void* dst, const void* src, size_t bytes) -> int {
     if (bytes) HIPX(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
     return 0;
   };
   std::vector<std::vector<int32_t>> rp_keep;
   std::vector<std::vector<double>> val_keep;  // factor blocks, alive until the uploads complete
-  // preconditioning: temporary CSR views (row pointers, columns) of the dense Q blocks
-  std::vector<int64_t> vrp_off(count, 0), vcol_off(count, 0);
-  int32_t *d_vrp = nullptr, *d_vcol = nullptr;
-  if (pre) {
-    int64_t vrp_tot = 0, vcol_tot = 0;
-    for (int i = 0; i < count; ++i)
-      if (inst[i].dense) {
-        vrp_off[i] = vrp_tot;
-        vrp_tot += inst[i].n + 1;
-        vcol_off[i] = vcol_tot;
-        vcol_tot += Qs[i].nnz;
-      }
-    if (vrp_tot && (rc = D.alloc(&d_vrp, vrp_tot))) return rc;
-    if (vcol_tot && (rc = D.alloc(&d_vcol, vcol_tot))) return rc;
-  }
   for (int i = 0; i < count; ++i) {
     const BatchInst& I = inst[i];
     if (q_first[i] == i && Ls) {  // block [F (n x k) | F' (k x n) | d (n)], row-major
@@ -1282,75 +1441,74 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
         for (int64_t c = 0; c < k; ++c) blk[(size_t)(n * k + c * n + r)] = L.F[r * k + c];
       memcpy(blk.data() + 2 * n * k, L.d, sizeof(double) * (size_t)n);
       val_keep.push_back(std::move(blk));
-      if ((rc = up(d_val + I.q_nz, val_keep.back().data(), sizeof(double) * val_keep.back().size()))) return rc;
+      if ((rc = up(d_val + I.q_nz, val_keep.back().data(), sizeof(double) * val_keep.back().size()))) return bail(rc);
     } else if (q_first[i] == i) {
       const pdhcg_csr& Q = Qs[i];
       if (!I.dense) {
         rp_keep.emplace_back(Q.rowptr, Q.rowptr + Q.nrows + 1);
-        if ((rc = up(d_rp + I.q_rp, rp_keep.back().data(), sizeof(int32_t) * (Q.nrows + 1)))) return rc;
-        if ((rc = up(d_col + I.q_nz, Q.col, sizeof(int32_t) * Q.nnz))) return rc;
-      } else if (pre) {
-        rp_keep.emplace_back(Q.rowptr, Q.rowptr + Q.nrows + 1);
-        if ((rc = up(d_vrp + vrp_off[i], rp_keep.back().data(), sizeof(int32_t) * (Q.nrows + 1)))) return rc;
-        if ((rc = up(d_vcol + vcol_off[i], Q.col, sizeof(int32_t) * Q.nnz))) return rc;
+        if ((rc = up(d_rp + I.q_rp, rp_keep.back().data(), sizeof(int32_t) * (Q.nrows + 1)))) return bail(rc);
+        if ((rc = up(d_col + I.q_nz, Q.col, sizeof(int32_t) * Q.nnz))) return bail(rc);
       }
-      if ((rc = up(d_val + I.q_nz, Q.val, sizeof(double) * Q.nnz))) return rc;
+      if ((rc = up(d_val + I.q_nz, Q.val, sizeof(double) * Q.nnz))) return bail(rc);
     }
     if (a_first[i] == i) {
       const pdhcg_csr& A = As[i];
       const HostCsr& T = At[i];
       rp_keep.emplace_back(A.rowptr, A.rowptr + A.nrows + 1);
-      if ((rc = up(d_rp + I.a_rp, rp_keep.back().data(), sizeof(int32_t) * (A.nrows + 1)))) return rc;
+      if ((rc = up(d_rp + I.a_rp, rp_keep.back().data(), sizeof(int32_t) * (A.nrows + 1)))) return bail(rc);
       rp_keep.emplace_back(T.rowptr.begin(), T.rowptr.end());
-      if ((rc = up(d_rp + I.t_rp, rp_keep.back().data(), sizeof(int32_t) * (T.nrows + 1)))) return rc;
-      if ((rc = up(d_col + I.a_nz, A.col, sizeof(int32_t) * A.nnz))) return rc;
-      if ((rc = up(d_val + I.a_nz, A.val, sizeof(double) * A.nnz))) return rc;
-      if ((rc = up(d_col + I.t_nz, T.col.data(), sizeof(int32_t) * A.nnz))) return rc;
-      if ((rc = up(d_val + I.t_nz, T.val.data(), sizeof(double) * A.nnz))) return rc;
+      if ((rc = up(d_rp + I.t_rp, rp_keep.back().data(), sizeof(int32_t) * (T.nrows + 1)))) return bail(rc);
+      if ((rc = up(d_col + I.a_nz, A.col, sizeof(int32_t) * A.nnz))) return bail(rc);
+      if ((rc = up(d_val + I.a_nz, A.val, sizeof(double) * A.nnz))) return bail(rc);
+      if ((rc = up(d_col + I.t_nz, T.col.data(), sizeof(int32_t) * A.nnz))) return bail(rc);
+      if ((rc = up(d_val + I.t_nz, T.val.data(), sizeof(double) * A.nnz))) return bail(rc);
     }
-    if ((rc = up(d_c + I.voff_n, cs[i], sizeof(double) * I.n))) return rc;
-    if (I.m && (rc = up(d_b + I.voff_m, bs[i], sizeof(double) * I.m))) return rc;
-    if (I.x0_given && (rc = up(d_x0 + I.voff_n, x0s[i], sizeof(double) * I.n))) return rc;
-    if (I.y0_given && (rc = up(d_y0 + I.voff_m, y0s[i], sizeof(double) * I.m))) return rc;
+    if ((rc = up(d_c + I.voff_n, cs[i], sizeof(double) * I.n))) return bail(rc);
+    if (I.m && (rc = up(d_b + I.voff_m, bs[i], sizeof(double) * I.m))) return bail(rc);
   }
-  // ---- preconditioning: D2 packed like x, D1 like y; b, c and the start points
-  // scaled in place; the norms relKKT uses are taken from the scaled b and c
-  double *d_d2 = nullptr, *d_d1 = nullptr;
+  // ---- preconditioning: one launch scales every instance's blocks; D2 packed
+  // like x, D1 like y; b and c scaled in place
   if (pre) {
-    int64_t fmax_len = 1;
-    for (int i = 0; i < count; ++i) fmax_len = std::max<int64_t>(fmax_len, (int64_t)inst[i].n + inst[i].m);
     double* d_f = nullptr;
-    if ((rc = D.alloc(&d_f, fmax_len))) return rc;
-    if ((rc = D.alloc(&d_d2, vn_tot))) return rc;
-    if ((rc = D.alloc(&d_d1, std::max<int64_t>(vm_tot, 1)))) return rc;
+    PrecInst* d_pi = nullptr;
+    if ((rc = D.alloc(&d_f, vn_tot + vm_tot))) return bail(rc);
+    if ((rc = D.alloc(&h->d_d2, vn_tot))) return bail(rc);
+    if ((rc = D.alloc(&h->d_d1, std::max<int64_t>(vm_tot, 1)))) return bail(rc);
+    if ((rc = D.alloc(&d_pi, count))) return bail(rc);
     const std::vector<double> ones((size_t)std::max(vn_tot, vm_tot), 1.0);
-    if ((rc = up(d_d2, ones.data(), sizeof(double) * vn_tot))) return rc;
-    if ((rc = up(d_d1, ones.data(), sizeof(double) * vm_tot))) return rc;
+    if ((rc = up(h->d_d2, ones.data(), sizeof(double) * vn_tot))) return bail(rc);
+    if ((rc = up(h->d_d1, ones.data(), sizeof(double) * vm_tot))) return bail(rc);
+    std::vector<PrecInst> pi(count);
     for (int i = 0; i < count; ++i) {
       const BatchInst& I = inst[i];
-      const DevMat Qm{I.n, I.n, I.dense ? d_vrp + vrp_off[i] : d_rp + I.q_rp,
-                      I.dense ? d_vcol + vcol_off[i] : d_col + I.q_nz, d_val + I.q_nz, nullptr, 0, 0};
-      const DevMat Am{I.m, I.n, d_rp + I.a_rp, d_col + I.a_nz, d_val + I.a_nz, nullptr, 0, 0};
-      const DevMat Tm{I.n, I.m, d_rp + I.t_rp, d_col + I.t_nz, d_val + I.t_nz, nullptr, 0, 0};
-      HIPX(launch_precondition(Qm, Am, Tm, Qs[i].nnz, As[i].nnz, s->ruiz_iters, s->pock_chambolle, d_f,
-                               d_d2 + I.voff_n, d_d1 + I.voff_m, stream));
+      PrecInst& P = pi[i];
+      P.n = I.n;
+      P.m = I.m;
+      P.qkind = I.dense;
+      P.k = I.q_rank;
+      P.qrp = I.dense ? nullptr : d_rp + I.q_rp;
+      P.qcol = I.dense ? nullptr : d_col + I.q_nz;
+      P.qval = d_val + I.q_nz;
+      P.arp = d_rp + I.a_rp;
+      P.acol = d_col + I.a_nz;
+      P.aval = d_val + I.a_nz;
+      P.trp = d_rp + I.t_rp;
+      P.tcol = d_col + I.t_nz;
+      P.tval = d_val + I.t_nz;
+      P.d2 = h->d_d2 + I.voff_n;
+      P.d1 = h->d_d1 + I.voff_m;
+      P.f = d_f + I.voff_n + I.voff_m;
+      const int64_t nnzq = I.dense ? 0 : Qs[i].nnz;
+      P.gk = precond_lanes(nnzq + 2 * As[i].nnz, (int64_t)I.n + I.m);
+      P.gq = precond_lanes(nnzq, I.n);
+      P.ga = precond_lanes(As[i].nnz, I.m);
+      P.gt = precond_lanes(As[i].nnz, I.n);
     }
-    HIPX(launch_diag(d_c, d_d2, vn_tot, 0, d_c, stream));
-    HIPX(launch_diag(d_b, d_d1, vm_tot, 0, d_b, stream));
-    if (d_x0) HIPX(launch_diag(d_x0, d_d2, vn_tot, 1, d_x0, stream));
-    if (d_y0) HIPX(launch_diag(d_y0, d_d1, vm_tot, 1, d_y0, stream));
-    std::vector<double> hb_s(std::max<int64_t>(vm_tot, 1)), hc_s(vn_tot);
-    HIPX(hipMemcpyAsync(hc_s.data(), d_c, sizeof(double) * vn_tot, hipMemcpyDeviceToHost, stream));
-    if (vm_tot) HIPX(hipMemcpyAsync(hb_s.data(), d_b, sizeof(double) * vm_tot, hipMemcpyDeviceToHost, stream));
-    HIPX(hipStreamSynchronize(stream));
-    for (int i = 0; i < count; ++i) {
-      BatchInst& I = inst[i];
-      const double* bi = hb_s.data() + I.voff_m;
-      const double* ci = hc_s.data() + I.voff_n;
-      I.nc_inf = max_abs_nan(ci, I.n);
-      I.nb_inf = max_abs_nan(bi, I.m);
-      I.kkt_zero = (s->warm_fallback && (I.x0_given || I.y0_given)) ? kkt_at_zero(bi, I.m, ci, I.n) : 0.0;
-    }
+    if ((rc = up(d_pi, pi.data(), sizeof(PrecInst) * count))) return bail(rc);
+    if (launch_batch_precondition(d_pi, count, s->ruiz_iters, s->pock_chambolle, stream) != hipSuccess ||
+        launch_diag(d_c, h->d_d2, vn_tot, 0, d_c, stream) != hipSuccess ||
+        launch_diag(d_b, h->d_d1, vm_tot, 0, d_b, stream) != hipSuccess)
+      return bail(fail(PDHCG_ERR_HIP, "preconditioning kernels failed to launch"));
   }
   // one parameter block per QP, all pointers resolved against the packed arrays
   std::vector<SolveParams> hp(count);
@@ -1359,7 +1517,7 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     SolveParams& P = hp[i];
     P.Q = DevMat{I.n, I.n, I.dense ? nullptr : d_rp + I.q_rp, I.dense ? nullptr : d_col + I.q_nz, d_val + I.q_nz,
                  d_val32 ? d_val32 + I.q_nz : nullptr, I.dense, I.q_rank};
-    P.lr_t = Ls ? nv[7] + I.voff_n : nullptr;
+    P.lr_t = Ls ? nv[8] + I.voff_n : nullptr;
     P.A = DevMat{I.m, I.n, d_rp + I.a_rp, d_col + I.a_nz, d_val + I.a_nz, d_val32 ? d_val32 + I.a_nz : nullptr, 0};
     P.At = DevMat{I.n, I.m, d_rp + I.t_rp, d_col + I.t_nz, d_val + I.t_nz, d_val32 ? d_val32 + I.t_nz : nullptr, 0};
     P.n = I.n;
@@ -1384,9 +1542,11 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     P.pt = part(3, I.g_t);
     P.nb_inf = I.nb_inf;
     P.nc_inf = I.nc_inf;
-    P.kkt_zero = I.kkt_zero;
-    P.x0 = I.x0_given ? d_x0 + I.voff_n : nullptr;
-    P.y0 = I.y0_given ? d_y0 + I.voff_m : nullptr;
+    P.dn = pre ? h->d_d2 + I.voff_n : nullptr;
+    P.dm = pre && I.m > 0 ? h->d_d1 + I.voff_m : nullptr;
+    P.kkt_zero = I.kkt_zero;  // (applied only to a given start, per solve)
+    P.x0 = h->d_x0 + I.voff_n;
+    P.y0 = h->d_y0 + I.voff_m;
     P.tol = s->tol_rel_kkt; P.eps_factor = s->cg_eps_factor; P.beta_suf = s->beta_sufficient;
     P.beta_nec = s->beta_necessary; P.beta_art = s->beta_artificial; P.theta = s->primal_weight_theta;
     P.max_iters = s->max_iters;
@@ -1395,78 +1555,207 @@ int solve_batch_impl(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
     P.max_cg = s->max_cg_iters; P.cg_rule = s->cg_rule; P.restart_to = s->restart_to;
     P.eval_period = s->eval_period;
     P.mixed_allowed = mixed ? 1 : 0;
+    P.step_rule = s->step_rule;
+    if (adaptive) {
+      P.x_prev = nv[7] + I.voff_n;
+      P.y_trial = mv[5] + I.voff_m;
+      P.ax_trial = mv[6] + I.voff_m;
+    }
   }
-  if ((rc = up(d_parts, parts.data(), sizeof(int32_t) * parts.size()))) return rc;
-  if ((rc = up(d_order, order.data(), sizeof(int32_t) * count))) return rc;
-  if ((rc = up(d_params, hp.data(), sizeof(SolveParams) * count))) return rc;
-  if (mixed) HIPX(launch_to_f32(d_val, d_val32, nz_tot, stream));
-  HIPX(hipStreamSynchronize(stream));
+  if ((rc = up(d_parts, parts.data(), sizeof(int32_t) * parts.size()))) return bail(rc);
+  if ((rc = up(h->d_order, order.data(), sizeof(int32_t) * count))) return bail(rc);
+  if ((rc = up(h->d_params, hp.data(), sizeof(SolveParams) * count))) return bail(rc);
+  if (mixed && launch_to_f32(d_val, d_val32, nz_tot, stream) != hipSuccess)
+    return bail(fail(PDHCG_ERR_HIP, "FP32 conversion failed to launch"));
+  if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(PDHCG_ERR_HIP, "batch upload or setup failed"));
   rp_keep.clear();
+  // (without events in the allocation-free form: its solve time is host wall time)
+  if (!arena && (hipEventCreate(&h->e0) != hipSuccess || hipEventCreate(&h->e1) != hipSuccess))
+    return bail(fail(PDHCG_ERR_HIP, "hipEventCreate failed"));
 
-  BatchParams bp{};
-  bp.params = d_params;
-  bp.order = d_order;
-  bp.st = d_st;
-  bp.t0 = d_t0;
+  BatchParams& bp = h->bp;
+  bp.params = h->d_params;
+  bp.order = h->d_order;
+  bp.st = h->d_st;
+  bp.t0 = h->d_t0;
   bp.pw_init = s->primal_weight_init;
   bp.eta_factor = s->step_eta_factor;
   bp.power_iters = s->power_iters;
   bp.mixed = mixed ? 1 : 0;
+  bp.given = h->d_given;
+  bp.warm_fallback = s->warm_fallback;
+  h->setup_s = now_s() - t0;
+  *out = h;
+  return 0;
+}
 
-  const double t_setup = now_s() - t0;
-  hipEvent_t e0, e1;
-  HIPX(hipEventCreate(&e0));
-  HIPX(hipEventCreate(&e1));
-  HIPX(hipEventRecord(e0, stream));
-  HIPX(launch_batch(bp, count, stream));
-  HIPX(hipEventRecord(e1, stream));
-  HIPX(hipStreamSynchronize(stream));
-  float ms = 0.0f;
-  HIPX(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  const double t_solve = now_s() - t0 - t_setup;
+namespace {
 
-  // ---- results
-  std::vector<SolverState> st(count);
-  std::vector<double> hx(vn_tot), hy(std::max<int64_t>(vm_tot, 1));
-  if (pre) {  // x = D2 x~, y = D1 y~
-    HIPX(launch_diag(nv[0], d_d2, vn_tot, 0, nv[0], stream));
-    HIPX(launch_diag(mv[0], d_d1, vm_tot, 0, mv[0], stream));
-  }
-  HIPX(hipMemcpyAsync(st.data(), d_st, sizeof(SolverState) * count, hipMemcpyDeviceToHost, stream));
-  HIPX(hipMemcpyAsync(hx.data(), nv[0], sizeof(double) * vn_tot, hipMemcpyDeviceToHost, stream));
-  if (vm_tot) HIPX(hipMemcpyAsync(hy.data(), mv[0], sizeof(double) * vm_tot, hipMemcpyDeviceToHost, stream));
-  HIPX(hipStreamSynchronize(stream));
+// Solve every instance of a packed batch.  x0 / y0: packed start points
+// (device pointers when in_dev; may be null) with per-instance flags in
+// `given` (bit 0 x0, bit 1 y0; null: every instance takes the given vectors);
+// x_out / y_out: packed outputs (device pointers when out_dev).
+int batch_solve_impl(pdhcg_batch* h, const double* x0, const double* y0, bool in_dev, const uint8_t* given,
+                     double* x_out, double* y_out, bool out_dev, pdhcg_result* rs) {
+  const double t0 = now_s();
+  hipStream_t stream = h->stream;
+  const int count = h->count;
+  const hipMemcpyKind in_kind = in_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  std::vector<uint8_t> g(count, 0);
   for (int i = 0; i < count; ++i) {
-    const BatchInst& I = inst[i];
-    memcpy(x_outs[i], hx.data() + I.voff_n, sizeof(double) * I.n);
-    if (I.m) memcpy(y_outs[i], hy.data() + I.voff_m, sizeof(double) * I.m);
-    if (rs) {
-      const SolverState& S = st[i];
-      pdhcg_result& r = rs[i];
-      r.status = S.status;
-      r.returned_average = S.returned_average;
-      r.rel_primal = S.r_p; r.rel_dual = S.r_d; r.rel_gap = S.r_g; r.rel_kkt = S.kkt;
-      r.primal_obj = S.pobj; r.dual_obj = S.dobj;
-      r.iters = S.k_total; r.cg_iters_total = S.cg_total; r.restarts = S.restarts;
-      r.norm_A = S.norm_A;
-      r.setup_s = t_setup;
-      r.solve_s = t_solve;
-      r.kernel_s = ms * 1e-3;
-      r.kkt_evals = S.evals;
-      r.cold_fallback = S.cold_fallback;
-    }
+    const bool has_m = h->inst[i].m > 0;
+    g[i] = given ? (uint8_t)(given[i] & (has_m ? 3 : 1)) : (uint8_t)((x0 ? 1 : 0) | (y0 && has_m ? 2 : 0));
+  }
+  if (x0) HIPX(hipMemcpyAsync(h->d_x0, x0, sizeof(double) * h->vn_tot, in_kind, stream));
+  if (y0 && h->vm_tot) HIPX(hipMemcpyAsync(h->d_y0, y0, sizeof(double) * h->vm_tot, in_kind, stream));
+  if (h->pre) {  // x~ = x / D2, y~ = y / D1
+    if (x0) HIPX(launch_diag(h->d_x0, h->d_d2, h->vn_tot, 1, h->d_x0, stream));
+    if (y0) HIPX(launch_diag(h->d_y0, h->d_d1, h->vm_tot, 1, h->d_y0, stream));
+  }
+  HIPX(hipMemcpyAsync(h->d_given, g.data(), (size_t)count, hipMemcpyHostToDevice, stream));
+  if (h->e0) HIPX(hipEventRecord(h->e0, stream));
+  HIPX(launch_batch(h->bp, count, stream));
+  if (h->e1) HIPX(hipEventRecord(h->e1, stream));
+  const double* xr = h->x;
+  const double* yr = h->y;
+  if (h->pre) {  // x = D2 x~, y = D1 y~
+    HIPX(launch_diag(h->x, h->d_d2, h->vn_tot, 0, h->xo, stream));
+    HIPX(launch_diag(h->y, h->d_d1, h->vm_tot, 0, h->yo, stream));
+    xr = h->xo;
+    yr = h->yo;
+  }
+  const hipMemcpyKind out_kind = out_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  std::vector<SolverState> st(count);
+  HIPX(hipMemcpyAsync(st.data(), h->d_st, sizeof(SolverState) * count, hipMemcpyDeviceToHost, stream));
+  HIPX(hipMemcpyAsync(x_out, xr, sizeof(double) * h->vn_tot, out_kind, stream));
+  if (h->vm_tot) HIPX(hipMemcpyAsync(y_out, yr, sizeof(double) * h->vm_tot, out_kind, stream));
+  HIPX(hipStreamSynchronize(stream));
+  const double t_solve = now_s() - t0;
+  float ms = (float)(t_solve * 1e3);
+  if (h->e0) HIPX(hipEventElapsedTime(&ms, h->e0, h->e1));
+  for (int i = 0; i < count; ++i) {
+    if (!rs) break;
+    const SolverState& S = st[i];
+    pdhcg_result& r = rs[i];
+    r.status = S.status;
+    r.returned_average = S.returned_average;
+    r.rel_primal = S.r_p; r.rel_dual = S.r_d; r.rel_gap = S.r_g; r.rel_kkt = S.kkt;
+    r.primal_obj = S.pobj; r.dual_obj = S.dobj;
+    r.iters = S.k_total; r.cg_iters_total = S.cg_total; r.restarts = S.restarts;
+    r.norm_A = S.norm_A;
+    r.setup_s = h->setup_s;
+    r.solve_s = t_solve;
+    r.kernel_s = ms * 1e-3;
+    r.kkt_evals = S.evals;
+    r.cold_fallback = S.cold_fallback;
+    r.rejected_steps = S.rejections;
+    r.step_eta = S.eta;
   }
   return 0;
 }
+
+// The one-call batched entry points: create, solve from per-instance start
+// points (null entries: cold), unpack, destroy.
+int solve_batch_once(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls, const pdhcg_csr* As,
+                     const double* const* bs, const double* const* cs, const double* const* x0s,
+                     const double* const* y0s, double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                     const pdhcg_settings* s, void* hip_stream, char* arena = nullptr, size_t arena_bytes = 0) {
+  if (count < 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "count must be >= 0");
+  if (count == 0) return 0;
+  if (!x_outs || !y_outs) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
+  for (int i = 0; i < count; ++i) {
+    const int64_t m = As ? As[i].nrows : 0;
+    if (!x_outs[i] || (m > 0 && !y_outs[i]))
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, "instance " + std::to_string(i) + ": null array");
+  }
+  pdhcg_batch* h = nullptr;
+  int rc = batch_create_impl(&h, count, Qs, Ls, As, bs, cs, 0, s, hip_stream, arena, arena_bytes);
+  if (rc) return rc;
+  std::vector<double> X0, Y0, X((size_t)h->vn_tot), Y((size_t)std::max<int64_t>(h->vm_tot, 1));
+  std::vector<uint8_t> given(count, 0);
+  bool any = false;
+  for (int i = 0; i < count; ++i) {
+    const bool gx = x0s && x0s[i], gy = y0s && y0s[i] && h->inst[i].m > 0;
+    given[i] = (uint8_t)((gx ? 1 : 0) | (gy ? 2 : 0));
+    any |= gx || gy;
+  }
+  if (any) {
+    X0.assign((size_t)h->vn_tot, 0.0);
+    Y0.assign((size_t)std::max<int64_t>(h->vm_tot, 1), 0.0);
+    for (int i = 0; i < count; ++i) {
+      const BatchInst& I = h->inst[i];
+      if (given[i] & 1) memcpy(X0.data() + I.voff_n, x0s[i], sizeof(double) * I.n);
+      if (given[i] & 2) memcpy(Y0.data() + I.voff_m, y0s[i], sizeof(double) * I.m);
+    }
+  }
+  rc = batch_solve_impl(h, any ? X0.data() : nullptr, any ? Y0.data() : nullptr, false, given.data(), X.data(),
+                        Y.data(), false, rs);
+  if (rc == 0)
+    for (int i = 0; i < count; ++i) {
+      const BatchInst& I = h->inst[i];
+      memcpy(x_outs[i], X.data() + I.voff_n, sizeof(double) * I.n);
+      if (I.m) memcpy(y_outs[i], Y.data() + I.voff_m, sizeof(double) * I.m);
+    }
+  delete h;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int pdhcg_batch_create(pdhcg_batch** h, int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls,
+                                  const pdhcg_csr* As, const double* const* bs, const double* const* cs,
+                                  int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream) {
+  return batch_create_impl(h, count, Qs, Ls, As, bs, cs, vec_on_device, s, hip_stream);
+}
+
+extern "C" int pdhcg_batch_layout(const pdhcg_batch* h, int64_t* n_off, int64_t* m_off) {
+  if (!h || !n_off || !m_off) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle or output");
+  memcpy(n_off, h->off_n.data(), sizeof(int64_t) * h->off_n.size());
+  memcpy(m_off, h->off_m.data(), sizeof(int64_t) * h->off_m.size());
+  return 0;
+}
+
+extern "C" int pdhcg_batch_solve(pdhcg_batch* h, const double* x0, const double* y0, double* x_out, double* y_out,
+                                 int32_t vec_on_device, pdhcg_result* rs) {
+  if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
+  if (!x_out || (h->vm_tot > 0 && !y_out)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null output");
+  return batch_solve_impl(h, x0, y0, vec_on_device != 0, nullptr, x_out, y_out, vec_on_device != 0, rs);
+}
+
+extern "C" int pdhcg_batch_get_scaling(const pdhcg_batch* h, double* d1_out, double* d2_out, int32_t vec_on_device) {
+  if (!h || !d2_out || (h->vm_tot > 0 && !d1_out)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle or output");
+  const hipMemcpyKind kind = vec_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (h->pre) {
+    HIPX(hipMemcpyAsync(d2_out, h->d_d2, sizeof(double) * h->vn_tot, kind, h->stream));
+    if (h->vm_tot) HIPX(hipMemcpyAsync(d1_out, h->d_d1, sizeof(double) * h->vm_tot, kind, h->stream));
+    HIPX(hipStreamSynchronize(h->stream));
+    return 0;
+  }
+  const std::vector<double> ones((size_t)std::max(h->vn_tot, h->vm_tot), 1.0);
+  const hipMemcpyKind hk = vec_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+  HIPX(hipMemcpy(d2_out, ones.data(), sizeof(double) * h->vn_tot, hk));
+  if (h->vm_tot) HIPX(hipMemcpy(d1_out, ones.data(), sizeof(double) * h->vm_tot, hk));
+  return 0;
+}
+
+extern "C" void pdhcg_batch_destroy(pdhcg_batch* h) { delete h; }
 
 extern "C" int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As, const double* const* bs,
                                  const double* const* cs, const double* const* x0s, const double* const* y0s,
                                  double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
                                  const pdhcg_settings* s, void* hip_stream) {
   if (!Qs) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
-  return solve_batch_impl(count, Qs, nullptr, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream);
+  return solve_batch_once(count, Qs, nullptr, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream);
+}
+
+int pdhcg::solve_batch_in_region(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As, const double* const* bs,
+                                 const double* const* cs, const double* const* x0s, const double* const* y0s,
+                                 double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                                 const pdhcg_settings* s, void* hip_stream, char* region, size_t region_bytes) {
+  if (!Qs) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
+  if (!region) return fail(PDHCG_ERR_HIP, "no device region");
+  return solve_batch_once(count, Qs, nullptr, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream, region,
+                          region_bytes);
 }
 
 extern "C" int pdhcg_solve_batch_lowrank(int32_t count, const pdhcg_lowrank* Qs, const pdhcg_csr* As,
@@ -1475,7 +1764,7 @@ extern "C" int pdhcg_solve_batch_lowrank(int32_t count, const pdhcg_lowrank* Qs,
                                          double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
                                          const pdhcg_settings* s, void* hip_stream) {
   if (!Qs) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
-  return solve_batch_impl(count, nullptr, Qs, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream);
+  return solve_batch_once(count, nullptr, Qs, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream);
 }
 
 // One family, many right-hand sides: the batch entry point with the shared

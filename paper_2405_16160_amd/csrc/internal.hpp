@@ -103,6 +103,16 @@ enum Slot {
   S_DY,          // sum (y_c - y_anchor)^2
   S_FLAG,        // max of a per-workgroup flag (time limit)
   S_PW,          // power iteration: sum w^2
+  // adaptive step size: m-side partials of a trial point (max (u - b)^+,
+  // max |u|, sum b.y), and the pieces of its step limit: sum dx^2, sum dy^2,
+  // sum dy.(A dx), sum dx.(Q dx) for dx = x' - x, dy = y' - y
+  S_TVIOL,
+  S_TMAX,
+  S_TBY,
+  S_DX2,
+  S_DY2,
+  S_DYADX,
+  S_DXQDX,
   NSLOT
 };
 
@@ -128,6 +138,9 @@ struct SolverState {
   double r_p, r_d, r_g, kkt, pobj, dobj;  // of the returned point
   double norm_A;        // ||A||_2 estimate (batched solves)
   uint64_t t_start;     // wall_clock64() at the start of the solve
+  int64_t rejections;   // rejected trial steps (adaptive step size)
+  int32_t attempts;     // trials of the current iteration (adaptive step size)
+  int32_t pad_;
 };
 
 struct SolveParams {
@@ -168,7 +181,13 @@ struct SolveParams {
   // FP32 products, Q rows and CG state in LDS and one CG tile per workgroup in
   // every workgroup: the CG steps run chained (cg_chain)
   int32_t cg_chain;
-  double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf (enter every relKKT)
+  double nb_inf, nc_inf;  // ||b||_inf, ||c||_inf of the caller's problem (enter every relKKT)
+  // diagonal preconditioning: the data above are D2 Q D2, D1 A D2, D1 b, D2 c
+  // and the iterates (x~, y~) stand for x = D2 x~, y = D1 y~ of the caller's
+  // problem; every relKKT is taken there, so the residual maxima of row j
+  // (i) are divided by dn[j] = D2_j (dm[i] = D1_i).  Null when not scaled.
+  const double* dn;
+  const double* dm;
   double kkt_zero;        // relKKT(0, 0) when the warm-start fallback applies, else 0
   // start point of a batched solve (null: zero)
   const double* x0;
@@ -180,6 +199,12 @@ struct SolveParams {
   uint64_t time_limit_ticks;   // 0 = none; wall_clock64() ticks
   int32_t max_cg, cg_rule, restart_to, eval_period;
   int32_t mixed_allowed;
+  // adaptive step size (step_rule = 1): the point x^k of the iteration (saved
+  // by the n-side pass), and the trial dual point and its A x' (m)
+  int32_t step_rule;
+  double* x_prev;
+  double* y_trial;
+  double* ax_trial;
 };
 
 struct PowerParams {
@@ -206,10 +231,25 @@ struct BatchParams {
   double pw_init, eta_factor;
   int32_t power_iters;
   int32_t mixed;
+  // per instance: bit 0 = x0 given, bit 1 = y0 given (the parameter blocks
+  // always point at the packed start buffers; without the bit the start is 0)
+  const uint8_t* given;
+  int32_t warm_fallback;  // compare a given start with (0, 0) (params' kkt_zero)
 };
 
 // records the message returned by pdhcg_last_error() and returns code
 int set_error(int code, const char* msg);
+
+}  // namespace pdhcg
+#include "../../include/pdhcg.h"
+namespace pdhcg {
+// pdhcg_solve_batch with every device buffer carved from the given device
+// region (region_bytes long) instead of allocated: INVALID_ARGUMENT when the
+// batch does not fit
+int solve_batch_in_region(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As, const double* const* bs,
+                          const double* const* cs, const double* const* x0s, const double* const* y0s,
+                          double* const* x_outs, double* const* y_outs, pdhcg_result* rs, const pdhcg_settings* s,
+                          void* hip_stream, char* region, size_t region_bytes);
 
 hipError_t launch_batch(const BatchParams& p, int count, hipStream_t s);
 hipError_t launch_solve(const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s);
@@ -234,6 +274,33 @@ hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s)
 // A (they size the lane groups per row)
 hipError_t launch_precondition(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq, int64_t nnza,
                                int ruiz_iters, int pock_chambolle, double* f, double* d2, double* d1, hipStream_t s);
+// One instance of a batched preconditioning (launch_batch_precondition): its
+// blocks in the packed batch arrays, scaled in place; Q is CSR (qkind 0), a
+// dense n x n block (1) or the factor block [F (n x k) | F' (k x n) | d (n)]
+// of Q = F F' + diag(d) (2); d2 (n) and d1 (m) hold ones on entry and receive
+// D2, D1; f is scratch of n + m doubles; gk, gq, ga, gt are the lanes per row
+// of the rows of K and of Q, A, A' (powers of two up to 64).
+struct PrecInst {
+  int32_t n, m, qkind, k;
+  const int32_t* qrp;
+  const int32_t* qcol;
+  double* qval;
+  const int32_t* arp;
+  const int32_t* acol;
+  double* aval;
+  const int32_t* trp;
+  const int32_t* tcol;
+  double* tval;
+  double* d2;
+  double* d1;
+  double* f;
+  int32_t gk, gq, ga, gt;
+};
+// one workgroup per instance, every step in one launch
+hipError_t launch_batch_precondition(const PrecInst* insts, int count, int ruiz_iters, int pock_chambolle,
+                                     hipStream_t s);
+// lanes per row the preconditioning kernels give rows of mean length nnz / nrows
+int precond_lanes(int64_t nnz, int64_t nrows);
 // out = x .* scale (op 0) or x ./ scale (op 1), n entries; out may be x
 hipError_t launch_diag(const double* x, const double* scale, int64_t n, int op, double* out, hipStream_t s);
 // workgroups per CU that the persistent kernels can keep resident (the

@@ -1,4 +1,4 @@
-// Diagonal preconditioning of the data (Section 5, preprocessing).
+// Diagonal preconditioning of the data (Sec. 4, preprocessing).
 //
 // The factors belong to the symmetric matrix K = [[Q, A'], [A, 0]]: index
 // i < n is variable i (row i of Q followed by row i of A'), index n + i is
@@ -121,7 +121,174 @@ hipError_t step(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq,
   return apply(T, nnza, f, f + n, G.t, s);
 }
 
+// ------------------------------------------------------------ batched form
+//
+// One workgroup per instance of a batch runs all steps on that instance's
+// blocks, with workgroup barriers between the passes of a step: the factor
+// statistics of every index of K, the factors (folded into D2, D1), then the
+// scaling of Q, A and A' in place.  Q is a CSR block, a dense n x n block, or
+// a factor [F (n x k) | F' (k x n) | d (n)] of Q = F F' + diag(d); for the
+// factor the row statistics of F F' + diag(d) are formed from F in tiles
+// (the entries of Q are never stored), and the scaling keeps the form:
+// diag(f) (F F' + diag(d)) diag(f) = (diag(f) F)(diag(f) F)' + diag(f^2 d).
+
+__device__ __forceinline__ double stat_comb(double a, double b, int mode) { return mode == 0 ? fmax(a, b) : a + b; }
+
+// statistic of every row of F F' + diag(d), combined into st[0 .. n): tiles
+// of 128 rows x 64 columns, F staged in LDS in chunks of 32 of its columns,
+// 4 x 4 products per thread; the 16 lanes that share rows combine their
+// partial statistics with lane exchanges
+constexpr int kFtJ = 128, kFtK = 64, kFtL = 32;
+
+__device__ void factor_row_stats(const double* F, const double* d, int n, int k, int mode, double* st,
+                                 double* lds) {
+  double* Fj = lds;               // [kFtL][kFtJ]
+  double* Fk = lds + kFtL * kFtJ;  // [kFtL][kFtK]
+  const int tid = (int)threadIdx.x;
+  const int tj = tid / 16, tk = tid % 16;  // rows tj*4 .. +3, columns tk*4 .. +3 of a tile
+  for (int j0 = 0; j0 < n; j0 += kFtJ) {
+    double rs[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += kFtK) {
+      double acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+      for (int l0 = 0; l0 < k; l0 += kFtL) {
+        __syncthreads();
+        for (int e = tid; e < kFtJ * kFtL; e += kBlock) {
+          const int row = e / kFtL, l = e % kFtL, gr = j0 + row, gl = l0 + l;
+          Fj[l * kFtJ + row] = (gr < n && gl < k) ? F[(int64_t)gr * k + gl] : 0.0;
+        }
+        for (int e = tid; e < kFtK * kFtL; e += kBlock) {
+          const int row = e / kFtL, l = e % kFtL, gr = k0 + row, gl = l0 + l;
+          Fk[l * kFtK + row] = (gr < n && gl < k) ? F[(int64_t)gr * k + gl] : 0.0;
+        }
+        __syncthreads();
+        for (int l = 0; l < kFtL; ++l) {
+          const double2* pa = (const double2*)(Fj + l * kFtJ + tj * 4);
+          const double2* pb = (const double2*)(Fk + l * kFtK + tk * 4);
+          const double2 a01 = pa[0], a23 = pa[1], b01 = pb[0], b23 = pb[1];
+          const double a[4] = {a01.x, a01.y, a23.x, a23.y}, b[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int gr = j0 + tj * 4 + r, gc = k0 + tk * 4 + c;
+          if (gr < n && gc < n) rs[r] = stat_comb(rs[r], fabs(acc[r][c] + (gr == gc ? d[gr] : 0.0)), mode);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      for (int off = 8; off > 0; off >>= 1) rs[r] = stat_comb(rs[r], __shfl_xor(rs[r], off, 16), mode);
+    if (tk == 0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = j0 + tj * 4 + r;
+        if (gr < n) st[gr] = stat_comb(st[gr], rs[r], mode);
+      }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) batch_precondition_kernel(const PrecInst* insts, int ruiz_iters,
+                                                                    int pock_chambolle) {
+  __shared__ __align__(16) double lds[kFtL * (kFtJ + kFtK)];
+  const PrecInst I = insts[blockIdx.x];
+  const int n = I.n, m = I.m, tid = (int)threadIdx.x;
+  double* const f = I.f;  // statistics, then factors: n entries of the variables, then m of the rows
+  for (int step = 0; step < ruiz_iters + pock_chambolle; ++step) {
+    const int mode = step < ruiz_iters ? 0 : 1;
+    // CSR rows of K: Q (when CSR) and A' for a variable, A for a row
+    {
+      const int g = I.gk, lane = tid & (g - 1);
+      for (int i = tid / g; i < n + m; i += kBlock / g) {
+        double sv;
+        if (i < n) {
+          sv = I.qkind == 0 ? row_stat(I.qrp, I.qval, i, mode, lane, g, 0.0) : 0.0;
+          if (m > 0) sv = row_stat(I.trp, I.tval, i, mode, lane, g, sv);
+        } else {
+          sv = row_stat(I.arp, I.aval, i - n, mode, lane, g, 0.0);
+        }
+        for (int off = g >> 1; off > 0; off >>= 1) sv = stat_comb(sv, __shfl_xor(sv, off, g), mode);
+        if (lane == 0) f[i] = sv;
+      }
+    }
+    __syncthreads();
+    if (I.qkind == 1) {  // dense symmetric Q: the statistic of row c is that of column c
+      for (int c = tid; c < n; c += kBlock) {
+        double sv = 0.0;
+        for (int r = 0; r < n; ++r) sv = stat_comb(sv, fabs(I.qval[(int64_t)r * n + c]), mode);
+        f[c] = stat_comb(f[c], sv, mode);
+      }
+    } else if (I.qkind == 2) {
+      factor_row_stats(I.qval, I.qval + 2 * (int64_t)n * I.k, n, I.k, mode, f, lds);
+    }
+    __syncthreads();
+    for (int i = tid; i < n + m; i += kBlock) {
+      const double sv = f[i];
+      const double fi = sv > 0.0 ? 1.0 / sqrt(sv) : 1.0;
+      f[i] = fi;
+      if (i < n)
+        I.d2[i] *= fi;
+      else
+        I.d1[i - n] *= fi;
+    }
+    __syncthreads();
+    // scale in place: entry (i, j) times f_i * f_j
+    if (I.qkind == 0) {
+      const int g = I.gq, lane = tid & (g - 1);
+      for (int i = tid / g; i < n; i += kBlock / g) {
+        const double a = f[i];
+        for (int32_t e = I.qrp[i] + lane; e < I.qrp[i + 1]; e += g) I.qval[e] *= a * f[I.qcol[e]];
+      }
+    } else if (I.qkind == 1) {
+      for (int r = 0; r < n; ++r) {
+        const double a = f[r];
+        for (int c = tid; c < n; c += kBlock) I.qval[(int64_t)r * n + c] *= a * f[c];
+      }
+    } else {
+      const int k = I.k;
+      double* F = I.qval;
+      double* Ft = F + (int64_t)n * k;
+      double* dd = Ft + (int64_t)k * n;
+      for (int64_t e = tid; e < (int64_t)n * k; e += kBlock) {
+        F[e] *= f[e / k];
+        Ft[e] *= f[e % n];
+      }
+      for (int j = tid; j < n; j += kBlock) dd[j] *= f[j] * f[j];
+    }
+    if (m > 0) {
+      const int ga = I.ga, la = tid & (ga - 1);
+      for (int i = tid / ga; i < m; i += kBlock / ga) {
+        const double a = f[n + i];
+        for (int32_t e = I.arp[i] + la; e < I.arp[i + 1]; e += ga) I.aval[e] *= a * f[I.acol[e]];
+      }
+      const int gt = I.gt, lt = tid & (gt - 1);
+      for (int j = tid / gt; j < n; j += kBlock / gt) {
+        const double a = f[j];
+        for (int32_t e = I.trp[j] + lt; e < I.trp[j + 1]; e += gt) I.tval[e] *= a * f[n + I.tcol[e]];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+int precond_lanes(int64_t nnz, int64_t nrows) { return lanes_for(nnz, nrows); }
+
+hipError_t launch_batch_precondition(const PrecInst* insts, int count, int ruiz_iters, int pock_chambolle,
+                                     hipStream_t s) {
+  if (count <= 0 || ruiz_iters + pock_chambolle <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_precondition_kernel, dim3(count), dim3(kBlock), 0, s, insts, ruiz_iters, pock_chambolle);
+  return hipGetLastError();
+}
 
 hipError_t launch_precondition(const DevMat& Q, const DevMat& A, const DevMat& T, int64_t nnzq, int64_t nnza,
                                int ruiz_iters, int pock_chambolle, double* f, double* d2, double* d1, hipStream_t s) {

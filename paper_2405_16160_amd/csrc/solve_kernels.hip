@@ -215,21 +215,33 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
   double mx[3] = {0.0, 0.0, 0.0};  // |g|, |Qx|, |A'y|
   GatherVec<double> gx{xv}, gy{yv};
   struct Row {
-    double c, x, q;
+    double c, x, q, d;
   };
-  auto pre = [&](int i) { return Row{gld(P.c + i), gld(xv + i), dense ? gld(P.q + i) : 0.0}; };
+  // d = D2_j when the data are preconditioned: the residual maxima are those
+  // of the caller's problem, (Qx)_j = (Q~x~)_j / D2_j and likewise A'y and c
+  const double* dn = P.dn;
+  auto pre = [&](int i) {
+    return Row{gld(P.c + i), gld(xv + i), dense ? gld(P.q + i) : 0.0, dn ? gld(dn + i) : 1.0};
+  };
   auto epi = [&](int i, double qx, double aty, const Row& rw) {
     const double g = qx + aty + rw.c;
     if (r) {
       gst(r + i, -g);
       if (r32) gst(r32 + (int64_t)r32_stride * i, (float)(-g));
+      if (P.x_prev) gst(P.x_prev + i, rw.x);  // x^k, for the adaptive step's trials
     }
     s[0] += g * g;
     s[1] += rw.x * qx;
     s[2] += rw.c * rw.x;
-    mx[0] = maxp(mx[0], fabs(g));
-    mx[1] = maxp(mx[1], fabs(qx));
-    mx[2] = maxp(mx[2], fabs(aty));
+    if (dn) {
+      mx[0] = maxp(mx[0], fabs(g) / rw.d);
+      mx[1] = maxp(mx[1], fabs(qx) / rw.d);
+      mx[2] = maxp(mx[2], fabs(aty) / rw.d);
+    } else {
+      mx[0] = maxp(mx[0], fabs(g));
+      mx[1] = maxp(mx[1], fabs(qx));
+      mx[2] = maxp(mx[2], fabs(aty));
+    }
   };
   for (int t = pt.t0; t < pt.t1; ++t)
     tile_rows2(dense ? nullptr : P.Q.rowptr, P.Q.col, P.Q.val, gx, P.m > 0 ? P.At.rowptr : nullptr, P.At.col,
@@ -282,10 +294,23 @@ __device__ void mside_rows(const SolveParams& P, Block B, const V* aval, const T
   }
 }
 
-// per-row inputs of the m-side epilogues
+// per-row inputs of the m-side epilogues (d = D1_i when preconditioned, else 1)
 struct MRow {
-  double b, y, ax, ya;
+  double b, y, ax, ya, d;
 };
+
+__device__ __forceinline__ double mrow_scale(const SolveParams& P, int i) { return P.dm ? gld(P.dm + i) : 1.0; }
+
+// the m-side maxima (u - b)^+ and |u| of a row, in the caller's units
+__device__ __forceinline__ void mside_max(const SolveParams& P, double* mx, double u, const MRow& rw) {
+  if (P.dm) {
+    mx[0] = maxp(mx[0], pos_part(u - rw.b) / rw.d);
+    mx[1] = maxp(mx[1], fabs(u) / rw.d);
+  } else {
+    mx[0] = maxp(mx[0], pos_part(u - rw.b));
+    mx[1] = maxp(mx[1], fabs(u));
+  }
+}
 
 __device__ void store_mside(const SolveParams& P, Block B, int slot0, double* s1, double* mx, double* lds) {
   block_reduce<1, 2>(s1, mx, lds);
@@ -300,11 +325,10 @@ __device__ void store_mside(const SolveParams& P, Block B, int slot0, double* s1
 __device__ __attribute__((noinline)) void phase_ax(const SolveParams& P, Block B, double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(
-      P, B, P.A.val, P.x, lds, [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), 0.0, 0.0}; },
+      P, B, P.A.val, P.x, lds, [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), 0.0, 0.0, mrow_scale(P, i)}; },
       [&](int i, double u, const MRow& rw) {
         gst(P.ax + i, u);
-        mx[0] = maxp(mx[0], pos_part(u - rw.b));
-        mx[1] = maxp(mx[1], fabs(u));
+        mside_max(P, mx, u, rw);
         s1[0] += rw.b * rw.y;
       });
   store_mside(P, B, 0, s1, mx, lds);
@@ -316,11 +340,10 @@ __device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, B
   phase_nside<DENSE>(P, P.w_n1, B, P.xa, P.ya, nullptr, nullptr, 1, S_AVG0, lds, svec);
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(
-      P, B, P.A.val, P.xa, lds, [&](int i) { return MRow{gld(P.b + i), 0.0, 0.0, gld(P.ya + i)}; },
+      P, B, P.A.val, P.xa, lds, [&](int i) { return MRow{gld(P.b + i), 0.0, 0.0, gld(P.ya + i), mrow_scale(P, i)}; },
       [&](int i, double u, const MRow& rw) {
         gst(P.ax_avg + i, u);
-        mx[0] = maxp(mx[0], pos_part(u - rw.b));
-        mx[1] = maxp(mx[1], fabs(u));
+        mside_max(P, mx, u, rw);
         s1[0] += rw.b * rw.ya;
       });
   store_mside(P, B, S_AVG0, s1, mx, lds);
@@ -564,14 +587,14 @@ __device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, Block
                                                      double sigma, double w, const double* xo, double* lds) {
   double s1[1] = {0.0}, mx[2] = {0.0, 0.0};
   mside_rows(
-      P, B, aval, xg, lds, [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), gld(P.ax + i), gld(P.ya + i)}; },
+      P, B, aval, xg, lds,
+      [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), gld(P.ax + i), gld(P.ya + i), mrow_scale(P, i)}; },
       [&](int i, double u, const MRow& rw) {
         const double yn = pos_part(rw.y + sigma * (2.0 * u - rw.ax - rw.b));
         gst(P.y + i, yn);
         gst(P.ax + i, u);
         gst(P.ya + i, rw.ya + w * (yn - rw.ya));
-        mx[0] = maxp(mx[0], pos_part(u - rw.b));
-        mx[1] = maxp(mx[1], fabs(u));
+        mside_max(P, mx, u, rw);
         s1[0] += rw.b * yn;
       });
   const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
@@ -587,6 +610,101 @@ __device__ __attribute__((noinline)) void phase_dual(const SolveParams& P, Block
     gst(P.xa + j, xaj + w * (xj - xaj));
   }
   store_mside(P, B, 0, s1, mx, lds);
+}
+
+// Adaptive step size (Sec. 4): the dual step of a trial, kept apart from the
+// iterate until the trial is accepted.  u = A x', y' = max(0, y + sigma (2u -
+// Ax - b)) go to y_trial and ax_trial, the m-side partials of (x', y') to the
+// trial slots, and the pieces of the trial's step limit to theirs:
+// ||dy||^2 and dy.(A dx) = dy.(u - Ax) over the m rows, ||dx||^2 and
+// dx.(Q dx) over the CG rows, with dx = x' - x^k gathered in FP64 and Q's
+// FP64 values.
+struct GatherDiff {
+  const double* a;
+  const double* b;
+  __device__ __forceinline__ double operator()(int j) const { return gld(a + j) - gld(b + j); }
+};
+
+template <bool DENSE, typename V, typename Tx>
+__device__ __attribute__((noinline)) void phase_dual_trial(const SolveParams& P, Block B, const V* aval,
+                                                           const Tx* xg, double sigma, double* lds, double* svec) {
+  double sm[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // b.y', dy.dy, dy.(u - Ax), dx.dx, dx.(Q dx)
+  double mx[2] = {0.0, 0.0};
+  mside_rows(
+      P, B, aval, xg, lds,
+      [&](int i) { return MRow{gld(P.b + i), gld(P.y + i), gld(P.ax + i), 0.0, mrow_scale(P, i)}; },
+      [&](int i, double u, const MRow& rw) {
+        const double yn = pos_part(rw.y + sigma * (2.0 * u - rw.ax - rw.b));
+        gst(P.y_trial + i, yn);
+        gst(P.ax_trial + i, u);
+        mside_max(P, mx, u, rw);
+        const double dy = yn - rw.y;
+        sm[0] += rw.b * yn;
+        sm[1] += dy * dy;
+        sm[2] += dy * (u - rw.ax);
+      });
+  auto epi = [&](int i, double qd) {
+    const double dx = gld(P.x + i) - gld(P.x_prev + i);
+    sm[3] += dx * dx;
+    sm[4] += dx * qd;
+  };
+  if constexpr (DENSE) {
+    dense_rows(P.Q.val, P.Q, svec, P.lr_t, [&](int j, bool) { return gld(P.x + j) - gld(P.x_prev + j); }, epi);
+  } else {
+    const WgPart& pt = P.w_cg;
+    const GatherDiff g{P.x, P.x_prev};
+    for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.Q.rowptr, P.Q.col, P.Q.val, pt.tile(t), pt.group, g, epi);
+    for (int t = pt.l0; t < pt.l1; ++t) {
+      const int i = pt.long_rows[t];
+      double v[1] = {row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, g)};
+      double dummy[1] = {0.0};
+      block_reduce<1, 0>(v, dummy, lds);
+      if (B.tid == 0) epi(i, v[0]);
+    }
+  }
+  block_reduce<5, 2>(sm, mx, lds);
+  if (B.tid == 0) {
+    P.part[S_TBY * B.nb + B.b] = sm[0];
+    P.part[S_DY2 * B.nb + B.b] = sm[1];
+    P.part[S_DYADX * B.nb + B.b] = sm[2];
+    P.part[S_DX2 * B.nb + B.b] = sm[3];
+    P.part[S_DXQDX * B.nb + B.b] = sm[4];
+    P.part[S_TVIOL * B.nb + B.b] = mx[0];
+    P.part[S_TMAX * B.nb + B.b] = mx[1];
+  }
+}
+
+// An accepted trial becomes the iterate: y = y', Ax = A x', the averages take
+// it with weight w (Alg. 1), and the trial's m-side partials become those of
+// the current point (each workgroup moves its own).
+__device__ __attribute__((noinline)) void phase_commit(const SolveParams& P, Block B, double w) {
+  const int m0 = P.w_m.r0, m1 = P.w_m.r1;
+  for (int i = m0 + B.tid; i < m1; i += kBlock) {
+    const double yn = gld(P.y_trial + i), ya = gld(P.ya + i);
+    gst(P.y + i, yn);
+    gst(P.ax + i, gld(P.ax_trial + i));
+    gst(P.ya + i, ya + w * (yn - ya));
+  }
+  const int n0 = P.w_cg.r0, n1 = P.w_cg.r1;
+  for (int j = n0 + B.tid; j < n1; j += kBlock) {
+    const double xa = gld(P.xa + j);
+    gst(P.xa + j, xa + w * (gld(P.x + j) - xa));
+  }
+  if (B.tid == 0) {
+    P.part[S_MVIOL * B.nb + B.b] = P.part[S_TVIOL * B.nb + B.b];
+    P.part[S_MAX * B.nb + B.b] = P.part[S_TMAX * B.nb + B.b];
+    P.part[S_BY * B.nb + B.b] = P.part[S_TBY * B.nb + B.b];
+  }
+}
+
+// A rejected trial: back to x^k (y and Ax were left as they were).
+__device__ __attribute__((noinline)) void phase_retry(const SolveParams& P, Block B) {
+  const int n0 = P.w_cg.r0, n1 = P.w_cg.r1;
+  for (int j = n0 + B.tid; j < n1; j += kBlock) {
+    const double xk = gld(P.x_prev + j);
+    gst(P.x + j, xk);
+    if (P.x32) gst(P.x32 + j, (float)xk);
+  }
 }
 
 // Restart: move to the candidate (average when use_avg), measure the
@@ -733,6 +851,9 @@ enum Op : int32_t {
   OP_DUAL,         // dual step and averages
   OP_COPY_AVG,     // return the average (no barrier follows)
   OP_COPY_ANCHOR,  // return the epoch's anchor (no barrier follows)
+  OP_DUAL_TRIAL,   // adaptive step size: dual step of a trial and its step limit
+  OP_COMMIT,       // adaptive step size: the accepted trial becomes the iterate
+  OP_RETRY,        // adaptive step size: a rejected trial, back to x^k
 };
 
 struct Ctl {
@@ -746,17 +867,20 @@ struct Ctl {
   int64_t budget;     // iterations left in this launch
   int32_t op, l, steps, have_avg, use_avg, first, cur;
   int32_t xlds;       // the primal step left x of the CG rows in LDS (P.cg_own)
+  int32_t retry;      // the n-side pass repeats x^k's for a rejected trial
+  double rt[4];       // sums of a trial: dx.dx, dy.dy, dy.(A dx), dx.(Q dx)
 };
 
-__device__ void ctl_end_cg(Ctl& C) {
+__device__ void ctl_end_cg(const SolveParams& P, Ctl& C) {
   C.S.cg_total += C.steps;
   C.w = 1.0 / (double)(C.S.k + 1);  // averages with weight 1/(k+1)
-  C.op = OP_DUAL;
+  C.op = P.step_rule ? OP_DUAL_TRIAL : OP_DUAL;
 }
 
-// primal step: inexact CG on (Q + I/tau) x = x^k/tau - c - A'y^k (Alg. 1)
-__device__ void ctl_start_cg(const SolveParams& P, Ctl& C) {
-  C.S.eps += P.eps_factor * C.kc.kkt;
+// primal step: inexact CG on (Q + I/tau) x = x^k/tau - c - A'y^k (Alg. 1);
+// the CG tolerance grows once per iteration (not again for a repeated trial)
+__device__ void ctl_start_cg(const SolveParams& P, Ctl& C, bool grow_eps = true) {
+  if (grow_eps) C.S.eps += P.eps_factor * C.kc.kkt;
   C.inv_tau = 1.0 / C.S.tau;
   C.steps = 0;
   C.xlds = 0;
@@ -774,7 +898,7 @@ __device__ void ctl_start_cg(const SolveParams& P, Ctl& C) {
     C.l = 1;
     C.op = OP_CG_SPMV;
   } else {
-    ctl_end_cg(C);
+    ctl_end_cg(P, C);
   }
 }
 
@@ -894,10 +1018,46 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       C.op = OP_NSIDE;
       break;
     case OP_NSIDE:
+      if (C.retry) {  // x^k again for a repeated trial: only r_0 is needed
+        C.retry = 0;
+        C.rho = r.ra;
+        ctl_start_cg(P, C, false);
+        break;
+      }
       C.kc = r.rk;
       C.rho = r.ra;
       C.tflag = r.rb;
       ctl_after_nside(P, C);
+      break;
+    case OP_DUAL_TRIAL: {
+      // step limit of the trial (Sec. 4, adaptive step size: the PDLP rule
+      // with the QP-specific term), ||dz||_w^2 / (2 |dy'A dx| + dx'Q dx) in
+      // the primal-weight norm, +inf for a zero denominator; the trial is
+      // accepted when eta <= eta_bar (or after 64 trials), and the step of the
+      // next trial or iteration is min((1 - (t+1)^-0.3) eta_bar,
+      // (1 + (t+1)^-0.6) eta) with t = k_total + 1 either way
+      const double om = C.S.omega;
+      const double num = om * C.rt[0] + C.rt[1] / om, den = 2.0 * fabs(C.rt[2]) + C.rt[3];
+      const double eta_bar = den > 0.0 ? num / den : INFINITY;
+      C.S.attempts += 1;
+      const bool accept = C.S.eta <= eta_bar || C.S.attempts >= 64;
+      const double t1 = (double)C.S.k_total + 2.0;
+      const double ea = (1.0 - pow(t1, -0.3)) * eta_bar, eb = (1.0 + pow(t1, -0.6)) * C.S.eta;
+      C.S.eta = ea < eb ? ea : eb;
+      C.S.tau = C.S.eta / om;
+      C.S.sigma = C.S.eta * om;
+      if (accept) {
+        C.S.attempts = 0;
+        C.op = OP_COMMIT;
+      } else {
+        C.S.rejections += 1;
+        C.op = OP_RETRY;
+      }
+      break;
+    }
+    case OP_RETRY:
+      C.retry = 1;
+      C.op = OP_NSIDE;
       break;
     case OP_ZERO:
       C.op = OP_AX_ZERO;
@@ -946,7 +1106,7 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       const int l = C.l;
       if (l > 0) C.steps = l;
       if (l >= P.max_cg) {  // the last allowed step only advanced x
-        ctl_end_cg(C);
+        ctl_end_cg(P, C);
         break;
       }
       if (l == 0) {
@@ -957,7 +1117,7 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       }
       const double gl = r.ra, dl = r.rb;
       if ((P.cg_rule == 0 && C.S.tau * sqrt(gl) <= C.S.eps) || !(gl > 0.0)) {
-        ctl_end_cg(C);
+        ctl_end_cg(P, C);
         break;
       }
       C.beta = gl / C.gamma;
@@ -974,7 +1134,7 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       const double rho_new = r.ra;
       C.steps = C.l;
       if (C.l == P.max_cg || (P.cg_rule == 0 && C.S.tau * sqrt(rho_new) <= C.S.eps) || !(rho_new > 0.0)) {
-        ctl_end_cg(C);
+        ctl_end_cg(P, C);
         break;
       }
       C.beta = rho_new / C.rho;
@@ -986,6 +1146,7 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       break;
     }
     case OP_DUAL:
+    case OP_COMMIT:
       C.S.k += 1;
       C.S.k_total += 1;
       C.budget -= 1;
@@ -1147,6 +1308,7 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
   if (B.tid == 0) {
     C.budget = budget;
     C.have_avg = 0;
+    C.retry = 0;
     C.op = C.S.done || budget <= 0 ? OP_END : (C.S.K_anchor != C.S.K_anchor ? OP_AX_START : OP_NSIDE);
   }
   __syncthreads();
@@ -1224,6 +1386,18 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         else
           phase_dual(P, B, P.A.val, (const double*)P.x, C.S.sigma, C.w, C.xlds ? P.cg_own : nullptr, lds);
         break;
+      case OP_DUAL_TRIAL:
+        if (mixed)
+          phase_dual_trial<DENSE>(P, B, P.A.val32, (const float*)P.x32, C.S.sigma, lds, svec);
+        else
+          phase_dual_trial<DENSE>(P, B, P.A.val, (const double*)P.x, C.S.sigma, lds, svec);
+        break;
+      case OP_COMMIT:
+        phase_commit(P, B, C.w);
+        break;
+      case OP_RETRY:
+        phase_retry(P, B);
+        break;
       case OP_COPY_AVG:
         phase_copy_point(P, B, P.xa, P.ya);
         break;
@@ -1271,6 +1445,15 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
       case OP_CG_UPDATE:
         a = reduce_one(P, B, S_RR, lds);
         break;
+      case OP_DUAL_TRIAL: {
+        const int ss[4] = {S_DX2, S_DY2, S_DYADX, S_DXQDX};
+        const int ms[1] = {0};
+        double t4[4], m0[1];
+        reduce_partials<4, 0>(P.part, B.nb, ss, ms, t4, m0, lds);
+        if (B.tid == 0)
+          for (int k = 0; k < 4; ++k) C.rt[k] = t4[k];
+        break;
+      }
       default:
         break;
     }
@@ -1474,6 +1657,13 @@ __global__ void __launch_bounds__(kBlock) pdhcg_batch_kernel(BatchParams BP) {
   const int idx = BP.order[blockIdx.x];
   __shared__ SolveParams Ps;
   load_params(Ps, BP.params + idx, 0);
+  if (threadIdx.x == 0) {  // this solve's start point and warm-start fallback
+    const uint32_t gv = BP.given ? BP.given[idx] : 0u;
+    if (!(gv & 1u)) Ps.x0 = nullptr;
+    if (!(gv & 2u)) Ps.y0 = nullptr;
+    if (!(gv & 3u) || !BP.warm_fallback) Ps.kkt_zero = 0.0;
+  }
+  __syncthreads();
   const SolveParams& P = Ps;
   Block B{0, 1, (int)threadIdx.x};
   GridSync gs{nullptr, 1u, 0};

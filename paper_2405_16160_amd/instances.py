@@ -228,6 +228,26 @@ def portfolio_factor(instance=0, n=None, family=4, nmin=50, nmax=2000):
     return F, d
 
 
+def _portfolio_rows(n):
+    """A = [1'; -1'; -I] (budget equality as a +/- pair, x >= 0) and b = [1; -1; 0]."""
+    rowptr = np.concatenate([[0, n, 2 * n], 2 * n + 1 + np.arange(n)]).astype(np.int64)
+    col = np.concatenate([np.arange(n), np.arange(n), np.arange(n)]).astype(np.int32)
+    val = np.concatenate([np.ones(n), -np.ones(n), -np.ones(n)])
+    return CSR(n + 2, n, rowptr, col, val), np.concatenate([[1.0, -1.0], np.zeros(n)])
+
+
+def portfolio_lowrank(instance=0, n=None, family=4, nmin=50, nmax=2000):
+    """The same QP as ``portfolio_qp`` with Q left in factored form: returns
+    (qp, (F, d)) where qp.Q is a placeholder n x n identity pattern that the
+    factored entry points do not read (Q = F F' + diag(d)).  A, b, c are
+    identical to ``portfolio_qp``'s; the dense Q is never formed."""
+    n, F, d, rng = _portfolio_factor(instance, n, family, nmin, nmax)
+    mu = rng.normal(0.05, 0.02, n)
+    A, b = _portfolio_rows(n)
+    eye = CSR(n, n, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), np.ones(n))
+    return QP(eye, A, b, -mu, name=f"portfolio_lowrank(n={n},seed={family}/{instance})"), (F, d)
+
+
 def portfolio_qp(instance=0, n=None, family=4, nmin=50, nmax=2000) -> QP:
     """Portfolio QP in direct form: Q = F F' + diag(d) (dense), F n x ceil(n/10)
     with N(0, 1/n) entries, d ~ U[0.01, 0.1], c = -mu with mu ~ N(0.05, 0.02^2);

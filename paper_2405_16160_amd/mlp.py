@@ -64,6 +64,7 @@ class Network:
         h = C.c_void_p()
         _p._check(_lib().pdhcg_mlp_create(C.byref(h), n_in, n_hid, n_out, max_batch, _p._stream_ptr()))
         self.h = h
+        _p._live.add(self)
         self.np = _lib().pdhcg_mlp_num_params(h)
         self.set_params(params if params is not None else init_params(n_in, n_hid, n_out))
         self._torch = torch

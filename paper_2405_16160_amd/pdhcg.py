@@ -8,15 +8,38 @@ current stream.  There is no CPU fallback: if the library cannot be loaded,
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import dataclasses
 import os
+import weakref
 
 import numpy as np
 
 from . import build as _build
 
 _lib = None
+_live = weakref.WeakSet()   # open Solver / mlp.Network objects, closed at interpreter exit
+
+
+@atexit.register
+def _close_live():
+    """Release every handle still open while the HIP runtime and torch are
+    fully alive (Python's exit handlers run before its module teardown and
+    before the C runtime's), after the device has finished its work."""
+    objs = list(_live)
+    if not objs:
+        return
+    try:
+        import torch
+        torch.cuda.synchronize()
+    except Exception:
+        pass
+    for o in objs:
+        try:
+            o.close()
+        except Exception:
+            pass
 
 
 class pdhcg_csr(C.Structure):
@@ -32,11 +55,11 @@ class pdhcg_settings(C.Structure):
                 ("primal_weight_init", C.c_double), ("step_eta_factor", C.c_double), ("power_iters", C.c_int32),
                 ("precision", C.c_int32), ("time_limit_s", C.c_double), ("num_blocks", C.c_int32),
                 ("warm_fallback", C.c_int32), ("verbose", C.c_int32), ("cg_form", C.c_int32),
-                ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32)]
+                ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32), ("step_rule", C.c_int32)]
 
 
 class pdhcg_lowrank(C.Structure):
-    _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("F", C.c_void_p), ("d", C.c_void_p)]
+    _fields_ = [("n", C.c_int64), ("k", C.c_int64), ("F", C.c_void_p), ("d", C.c_void_p), ("on_device", C.c_int32)]
 
 
 class pdhcg_result(C.Structure):
@@ -45,13 +68,16 @@ class pdhcg_result(C.Structure):
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("iters", C.c_int64),
                 ("cg_iters_total", C.c_int64), ("restarts", C.c_int64), ("norm_A", C.c_double),
                 ("setup_s", C.c_double), ("solve_s", C.c_double), ("kernel_s", C.c_double),
-                ("kkt_evals", C.c_int64), ("cold_fallback", C.c_int32)]
+                ("kkt_evals", C.c_int64), ("cold_fallback", C.c_int32), ("rejected_steps", C.c_int64),
+                ("step_eta", C.c_double)]
 
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
 EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_get_scaling", "pdhcg_autotune", "pdhcg_plan_info",
-           "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error"]
+           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_get_scaling",
+           "pdhcg_autotune", "pdhcg_plan_info", "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error",
+           "pdhcg_batch_create", "pdhcg_batch_layout", "pdhcg_batch_solve", "pdhcg_batch_get_scaling",
+           "pdhcg_batch_destroy"]
 
 
 class PdhcgError(RuntimeError):
@@ -98,6 +124,12 @@ def lib():
         L.pdhcg_error_string.restype = C.c_char_p
         L.pdhcg_last_error.argtypes = []
         L.pdhcg_last_error.restype = C.c_char_p
+        L.pdhcg_batch_create.argtypes = [C.POINTER(P), C.c_int32, P, P, P, P, P, C.c_int32, C.POINTER(pdhcg_settings), P]
+        L.pdhcg_batch_layout.argtypes = [P, P, P]
+        L.pdhcg_batch_solve.argtypes = [P, P, P, P, P, C.c_int32, P]
+        L.pdhcg_batch_get_scaling.argtypes = [P, P, P, C.c_int32]
+        L.pdhcg_batch_destroy.argtypes = [P]
+        L.pdhcg_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -132,6 +164,7 @@ class Settings:
     cg_form: int = 0
     ruiz_iters: int = 0
     pock_chambolle: int = 0
+    step_rule: int = 0
 
     def c(self) -> pdhcg_settings:
         s = pdhcg_settings()
@@ -186,6 +219,7 @@ class Solver:
         _check(lib().pdhcg_create(C.byref(h), C.byref(Qc), C.byref(Ac), b.data_ptr(), c.data_ptr(), 1,
                                   C.byref(self.settings.c()), _stream_ptr()))
         self.h = h
+        _live.add(self)
         del keep
 
     def set_settings(self, settings: Settings):
@@ -280,7 +314,7 @@ def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None, lowra
     for i, qp in enumerate(qps):
         if Ls is not None:
             F, d = arr(lowrank[i][0], np.float64), arr(lowrank[i][1], np.float64)
-            Ls[i] = pdhcg_lowrank(F.shape[0], F.shape[1], F.ctypes.data, d.ctypes.data)
+            Ls[i] = pdhcg_lowrank(F.shape[0], F.shape[1], F.ctypes.data, d.ctypes.data, 0)
         for M, dst in (((qp.A, As),) if Ls is not None else ((qp.Q, Qs), (qp.A, As))):
             rp, col, val = arr(M.rowptr, np.int64), arr(M.col, np.int32), arr(M.val, np.float64)
             dst[i] = pdhcg_csr(M.nrows, M.ncols, int(M.rowptr[-1]), rp.ctypes.data, col.ctypes.data,
@@ -337,3 +371,100 @@ def solve_multi_rhs(Q, A, c, B, settings: Settings | None = None, X0=None, Y0=No
                                        opt(X0, (cnt, n)), opt(Y0, (cnt, m)), X.ctypes.data, Y.ctypes.data, rs,
                                        C.byref(settings.c()), _stream_ptr()))
     return X, Y[:, :m], [_result_dict(rs[i]) for i in range(cnt)]
+
+
+class Batch:
+    """A batch packed on the device once (pdhcg_batch_create) and solved any
+    number of times (pdhcg_batch_solve) with device-resident start points and
+    outputs: ``Batch(qps, settings, lowrank=None)`` then ``solve()``.
+
+    ``qps`` are ``instances.QP`` objects (host CSR); with ``lowrank`` (a list
+    of (F, d) with Q_i = F F' + diag(d)) their Q is not read.  Matrices and
+    vectors are handed over as host arrays (the library copies them once)."""
+
+    def __init__(self, qps, settings: Settings | None = None, lowrank=None, device_inputs: bool = False):
+        import torch
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.settings = settings or Settings()
+        self.count = cnt = len(qps)
+        keep = []
+        on_dev = 1 if device_inputs else 0
+        tdt = {np.int64: torch.int64, np.int32: torch.int32, np.float64: torch.float64}
+
+        class _Ptr:  # what a ctypes field needs from a host array or a device tensor
+            def __init__(self, data):
+                self.data = data
+
+        def arr(a, dt):
+            """a host array, or (device_inputs) a device tensor; .ctypes.data is its address"""
+            a = np.ascontiguousarray(a, dtype=dt)
+            if device_inputs:
+                t = torch.as_tensor(a, dtype=tdt[dt]).to(self.dev)
+                keep.append(t)
+                return type("DevArr", (), {"ctypes": _Ptr(t.data_ptr() if t.numel() else None), "shape": a.shape})()
+            keep.append(a)
+            return a
+
+        Qs = (pdhcg_csr * cnt)() if lowrank is None else None
+        Ls = (pdhcg_lowrank * cnt)() if lowrank is not None else None
+        As = (pdhcg_csr * cnt)()
+        bs = (C.c_void_p * cnt)()
+        cs = (C.c_void_p * cnt)()
+        for i, qp in enumerate(qps):
+            if Ls is not None:
+                F, d = arr(lowrank[i][0], np.float64), arr(lowrank[i][1], np.float64)
+                Ls[i] = pdhcg_lowrank(F.shape[0], F.shape[1], F.ctypes.data, d.ctypes.data, on_dev)
+            for M, dst in (((qp.A, As),) if Ls is not None else ((qp.Q, Qs), (qp.A, As))):
+                rp, col, val = arr(M.rowptr, np.int64), arr(M.col, np.int32), arr(M.val, np.float64)
+                dst[i] = pdhcg_csr(M.nrows, M.ncols, int(M.rowptr[-1]), rp.ctypes.data, col.ctypes.data,
+                                   val.ctypes.data, on_dev)
+            bs[i] = arr(qp.b if qp.A.nrows else np.zeros(1), np.float64).ctypes.data
+            cs[i] = arr(qp.c, np.float64).ctypes.data
+        h = C.c_void_p()
+        if device_inputs:
+            torch.cuda.synchronize()
+        _check(lib().pdhcg_batch_create(C.byref(h), cnt, Qs, Ls, As, bs, cs, on_dev, C.byref(self.settings.c()),
+                                        _stream_ptr()))
+        self.h = h
+        _live.add(self)
+        del keep
+        n_off = np.zeros(cnt + 1, dtype=np.int64)
+        m_off = np.zeros(cnt + 1, dtype=np.int64)
+        _check(lib().pdhcg_batch_layout(self.h, n_off.ctypes.data, m_off.ctypes.data))
+        self.n_off, self.m_off = n_off, m_off
+        self.x = torch.empty(int(n_off[-1]), dtype=torch.float64, device=self.dev)
+        self.y = torch.empty(max(int(m_off[-1]), 1), dtype=torch.float64, device=self.dev)
+
+    def solve(self, x0=None, y0=None):
+        """Solve all instances; x0 / y0: packed float64 device tensors or None.
+        Returns (x, y, results) with x, y the packed device outputs (views
+        that the next solve overwrites) and one result dict per instance."""
+        rs = (pdhcg_result * self.count)()
+        ptr = lambda t: None if t is None else t.contiguous().data_ptr()
+        _check(lib().pdhcg_batch_solve(self.h, ptr(x0), ptr(y0), self.x.data_ptr(), self.y.data_ptr(), 1, rs))
+        return self.x, self.y[: int(self.m_off[-1])], [_result_dict(rs[i]) for i in range(self.count)]
+
+    def split(self, x, y):
+        """Per-instance numpy views of packed x, y."""
+        xs, ys = x.cpu().numpy(), y.cpu().numpy()
+        return ([xs[self.n_off[i]:self.n_off[i + 1]] for i in range(self.count)],
+                [ys[self.m_off[i]:self.m_off[i + 1]] for i in range(self.count)])
+
+    def scaling(self):
+        """(d1, d2) packed (ones when preconditioning is off), device tensors."""
+        import torch
+        d1 = torch.empty(max(int(self.m_off[-1]), 1), dtype=torch.float64, device=self.dev)
+        d2 = torch.empty(int(self.n_off[-1]), dtype=torch.float64, device=self.dev)
+        _check(lib().pdhcg_batch_get_scaling(self.h, d1.data_ptr(), d2.data_ptr(), 1))
+        return d1[: int(self.m_off[-1])], d2
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pdhcg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -64,7 +64,7 @@ def test_counter_summary_scales_by_the_copy_calibration(tmp_path):
                 {"Kernel_Name": "other", "Counter_Name": "FETCH_SIZE", "Counter_Value": 5.0}])
     _write_csv(os.path.join(d, "write", "run_counter_collection.csv"),
                [{"Kernel_Name": "pdhcg::pdhcg_solve_kernel(x)", "Counter_Name": "WRITE_SIZE", "Counter_Value": 300.0}])
-    s = bench.summarize_counters(d, 1e6)
+    s = bench.summarize_counters(d, 1e6, kernel="pdhcg_solve_kernel")
     assert np.isclose(s["counters"]["FETCH_SIZE"]["factor"], 0.5)
     assert np.isclose(s["counters"]["FETCH_SIZE"]["bytes_per_launch"], 1000.0 * 1024 / 0.5)
     assert np.isclose(s["counters"]["WRITE_SIZE"]["bytes_per_launch"], 300.0 * 1024)

@@ -1,15 +1,16 @@
 """GPU parity of the diagonal preconditioning (Ruiz + Pock-Chambolle on
-K = [[Q, A'], [A, 0]], Section 5) against the FP64 oracle.
+K = [[Q, A'], [A, 0]], Sec. 4 "Preprocessing") against the FP64 oracle.
 
 Factors: D1, D2 from the device kernels against the oracle's, rtol 1e-13 (both
 sides form the same maxima exactly and the same correctly rounded square roots
 and quotients; the 1-norms of the Pock-Chambolle step may be summed in another
 order).  Scaled data: the library's products with the scaled Q, A, A' against
-the oracle-scaled matrices.  Solve: the relKKT the library reports refers to
-the scaled problem, so the oracle recomputes it there from the returned point
-(mapped back by D1, D2) and the two must agree; the returned point must solve
-the original problem (x within 1e-3 of the oracle's optimum, objective within
-1e-5, y >= 0)."""
+the oracle-scaled matrices.  Solve: the solver iterates on the scaled copy but
+every relKKT it takes is that of the caller's problem (the progress metric of
+Sec. 4 is defined for problem (1) as posed), so the full parity contract holds
+on the caller's problem: relKKT of the returned point recomputed by the oracle
+<= tol and equal to the reported value, x within 1e-4 of the oracle's optimum
+(run to 1e-9), objective within 1e-6, y >= 0."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -78,6 +79,19 @@ def test_factors_and_scaled_products_match_oracle(case):
 _REF = {}
 
 
+def check_contract(qp, x, y, r, xr, rr, tol):
+    """The parity contract on the caller's problem: relKKT recomputed by the
+    oracle <= tol and equal to the reported one, x within 1e-4 of the
+    oracle's optimum, objective within 1e-6, y >= 0."""
+    assert np.all(y >= 0.0)
+    k = O.kkt(qp, x, y)
+    assert k["rel_kkt"] <= tol * (1 + 1e-6)
+    assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
+    assert np.linalg.norm(x - xr) / max(np.linalg.norm(xr), 1e-12) <= 1e-4
+    assert abs(k["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-6
+    assert r["primal_obj"] == pytest.approx(k["primal_obj"], rel=1e-9, abs=1e-12)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_preconditioned_solve_matches_oracle(precision):
     say(f"[precondition] solve, random n=1000 rows rescaled, precision={precision}")
@@ -91,14 +105,14 @@ def test_preconditioned_solve_matches_oracle(precision):
     say(f"  status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} kkt={r['rel_kkt']:.2e}")
     assert r["status"] == 0
     x, y = x.cpu().numpy(), y.cpu().numpy()
-    assert np.all(y >= 0.0)
-    k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
-    assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
-    assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
-    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-3
-    ko = O.kkt(qp, x, y)
-    assert abs(ko["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-5
-    assert r["primal_obj"] == pytest.approx(ko["primal_obj"], rel=1e-6, abs=1e-9)
+    check_contract(qp, x, y, r, xr, rr, 1e-6)
+    # the same reading on both sides: the oracle's preconditioned solve at the
+    # same tolerance takes (nearly) the same number of iterations
+    if "ref6" not in _REF:
+        _REF["ref6"] = P.solve_scaled(qp, e1, e2, O.Settings(tol=1e-6, max_iters=400_000))[2]
+    r6 = _REF["ref6"]
+    say(f"  oracle at 1e-6: iters={r6.iters} cg={r6.cg_steps}")
+    assert abs(r["iters"] - r6.iters) <= max(64, 0.05 * r6.iters)
     # a warm start from the returned (unscaled) point is mapped into the scaled
     # space: it is accepted (no cold fallback) and finishes sooner than the cold start
     x2, y2, r2 = sol.solve(x0=x, y0=y)
@@ -110,17 +124,15 @@ def test_preconditioned_solve_matches_oracle(precision):
     assert r3["status"] == 0
     from dataclasses import replace
     q2 = replace(qp, b=b2)
-    k3 = O.kkt(P.scale_qp(q2, e1, e2), x3.cpu().numpy() / e2, y3.cpu().numpy() / e1)
+    k3 = O.kkt(q2, x3.cpu().numpy(), y3.cpu().numpy())
     assert k3["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+    assert r3["rel_kkt"] == pytest.approx(k3["rel_kkt"], rel=1e-6, abs=1e-12)
     sol.close()
 
 
-def test_factored_batch_rejects_preconditioning_and_settings_are_fixed():
-    say("[precondition] factored-batch rejection, fixed settings")
+def test_preconditioning_settings_are_fixed_at_create():
+    say("[precondition] fixed settings")
     qp = I.random_qp(n=200, m=80, r_rows=100, q_density=0.05, a_density=0.05, family=1, instance=5)
-    pq = I.portfolio_qp(0, nmax=300)
-    with pytest.raises(RuntimeError, match="factored"):
-        pdhcg.solve_batch([pq], pdhcg.Settings(**PRE), lowrank=[I.portfolio_factor(0, nmax=300)])
     sol = pdhcg.Solver(qp, pdhcg.Settings(**PRE))
     with pytest.raises(RuntimeError, match="fixed at pdhcg_create"):
         sol.set_settings(pdhcg.Settings())
@@ -137,18 +149,16 @@ def test_batch_preconditioned_matches_oracle(precision):
     launch, each against the oracle's preconditioned solve."""
     say(f"[precondition] batch of 8, precision={precision}")
     qps = [I.portfolio_qp(i, nmax=400) for i in range(6)] + [CASES["random n=1000"](), I.tiny_qp(6, 10, instance=4)]
-    outs = pdhcg.solve_batch(qps, pdhcg.Settings(tol_rel_kkt=1e-6, precision=precision, **PRE))
+    # as in the unscaled batch tests, relKKT <= 1e-6 alone does not imply the
+    # objective bar on these families (the tiny instance at 1e-6 is 1.0e-6 off),
+    # so the batch runs to 1e-7, which meets the three bars
+    outs = pdhcg.solve_batch(qps, pdhcg.Settings(tol_rel_kkt=1e-7, precision=precision, **PRE))
     for j, (qp, (x, y, r)) in enumerate(zip(qps, outs)):
         xr, yr, rr, e1, e2 = P.solve(qp, O.Settings(tol=1e-9, max_iters=400_000))
         say(f"  instance {j} n={qp.n}: status={r['status_name']} iters={r['iters']} (oracle at 1e-9: {rr.iters}) "
             f"kkt={r['rel_kkt']:.2e}")
         assert r["status"] == 0 and rr.status == O.OPTIMAL
-        assert np.all(y >= 0.0)
-        k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
-        assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
-        assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
-        assert np.linalg.norm(x - xr) / max(np.linalg.norm(xr), 1e-12) <= 1e-3
-        assert abs(O.kkt(qp, x, y)["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-5
+        check_contract(qp, x, y, r, xr, rr, 1e-7)
 
 
 def test_unconstrained_preconditioned():
@@ -184,20 +194,15 @@ def test_preconditioned_powerlaw_solve_matches_oracle(precision):
     say(f"  status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} kkt={r['rel_kkt']:.2e}")
     assert r["status"] == 0
     x, y = x.cpu().numpy(), y.cpu().numpy()
-    assert np.all(y >= 0.0)
-    k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
-    assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
-    assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
-    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-3
-    assert abs(O.kkt(qp, x, y)["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-5
+    check_contract(qp, x, y, r, xr, rr, 1e-6)
 
 
 def test_powerlaw_full_size_preconditioned():
     """The power-law configuration at its full size (n = 2e6, m = 1e6), in the
     launch configuration of the preconditioning benchmark (default plan, FP32
     products, tol 1e-4): D1, D2 against the oracle's element by element; the
-    solve reaches tol, and its reported relKKT equals the oracle's FP64
-    recomputation on the oracle-scaled problem at the returned point."""
+    solve reaches tol on the caller's problem, and its reported relKKT equals
+    the oracle's FP64 recomputation there at the returned point."""
     say("[precondition] powerlaw full size n=2e6 m=1e6")
     qp = I.powerlaw_qp()
     e1, e2 = P.scaling(qp.Q, qp.A, 10, True)
@@ -211,7 +216,7 @@ def test_powerlaw_full_size_preconditioned():
     assert r["status"] == 0
     x, y = x.cpu().numpy(), y.cpu().numpy()
     assert np.all(y >= 0.0)
-    k = O.kkt(P.scale_qp(qp, e1, e2), x / e2, y / e1)
+    k = O.kkt(qp, x, y)
     assert k["rel_kkt"] <= 1e-4 * (1 + 1e-6)
     assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6)
 

@@ -33,3 +33,15 @@ def test_row_scaled_keeps_the_optimum():
     rs = I.row_scaled(qp)
     assert rs.A.nnz == qp.A.nnz and not np.allclose(rs.b, qp.b)
     assert O.kkt(rs, rs.x_star, rs.y_star)["rel_kkt"] <= max(1e-12, 10 * k0)
+
+
+def test_portfolio_lowrank_is_the_same_qp():
+    """The factored generator draws the same F, d, A, b, c as the dense one,
+    and F F' + diag(d) equals the dense Q up to rounding."""
+    for i in (0, 3, 11):
+        q = I.portfolio_qp(i, nmax=300)
+        ql, (F, d) = I.portfolio_lowrank(i, nmax=300)
+        assert np.array_equal(q.A.to_scipy().toarray(), ql.A.to_scipy().toarray())
+        assert np.array_equal(q.b, ql.b) and np.array_equal(q.c, ql.c)
+        Qd = q.Q.to_scipy().toarray()
+        np.testing.assert_allclose(F @ F.T + np.diag(d), Qd, rtol=0, atol=1e-14)
