@@ -1,0 +1,175 @@
+"""GPU parity of the adaptive step size (Sec. 4, "Adaptive step-size": each
+iteration's primal and dual steps are a trial at the current eta, accepted when
+eta <= ||dz||_w^2 / (2 |dy'A dx| + dx'Q dx), eta updated after every trial and
+a rejected trial repeated from z^k) against the FP64 oracle, through the C ABI.
+
+Checks: the first accepted trial and the first rejected one on the worked
+example W against the hand-derived values that pin the oracle
+(tests/golden/adaptive_step_W.txt); the first iterations of a random QP
+against the oracle's trace (iterates, step size, rejected trials); whole
+solves in both precisions against the full parity contract (relKKT
+recomputed by the oracle <= tol, x within 1e-4 of the oracle's optimum,
+objective within 1e-6, y >= 0) with iteration counts close to the oracle's;
+the manufactured optimum; the unconstrained case; preconditioning combined
+with the adaptive rule."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_16160_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_16160_amd import pdhcg  # noqa: E402
+
+SQ2 = math.sqrt(2.0)
+X1 = np.array([SQ2 - 1.0, 1.0 / (1.0 + 2.0 * SQ2)])
+Y1 = 0.1240388594792434
+ETA_BAR_1 = 0.4407895889587272
+RED, GROW = 1.0 - 2.0 ** -0.3, 1.0 + 2.0 ** -0.6
+REJ_ETA_1 = 0.3413374000616747
+REJ_ETA_BAR_2 = 0.44825557519401565
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def example_w():
+    import scipy.sparse as sp
+    return I.QP(I.CSR.from_scipy(sp.csr_matrix(np.diag([2.0, 1.0]))), I.CSR.from_scipy(sp.csr_matrix([[1.0, 1.0]])),
+                np.array([1.0]), np.array([-2.0, -1.0]))
+
+
+def gpu_solve(qp, x0=None, y0=None, **kw):
+    sol = pdhcg.Solver(qp, pdhcg.Settings(step_rule=1, **kw))
+    x, y, r = sol.solve(x0=x0, y0=y0)
+    sol.close()
+    return x.cpu().numpy(), y.cpu().numpy(), r
+
+
+def check_contract(qp, x, y, ref, tol):
+    k = O.kkt(qp, x, y)
+    assert k["rel_kkt"] <= tol * (1 + 1e-6), k
+    assert np.all(y >= 0.0)
+    assert abs(k["primal_obj"] - ref.primal_obj) / (1 + abs(ref.primal_obj)) <= 1e-6
+    assert np.linalg.norm(x - ref.x) / max(np.linalg.norm(ref.x), 1e-300) <= 1e-4
+    return k
+
+
+def test_first_trial_accepted_on_w():
+    """eta0 = 0.5/sqrt2 <= eta_bar: the trial is the constant rule's x1, y1
+    and eta becomes min((1 - 2^-0.3) eta_bar, (1 + 2^-0.6) eta0)."""
+    say("[adaptive] W, one accepted trial")
+    x, y, r = gpu_solve(example_w(), tol_rel_kkt=1e-14, max_iters=1, max_cg_iters=2, cg_eps_factor=0.0,
+                        eval_period=1000)
+    assert r["rejected_steps"] == 0
+    assert np.allclose(x, X1, atol=1e-14)
+    assert y[0] == pytest.approx(Y1, abs=1e-14)
+    assert r["step_eta"] == pytest.approx(min(RED * ETA_BAR_1, GROW * 0.5 / SQ2), rel=1e-12)
+    assert r["cg_iters_total"] == 2
+
+
+def test_first_trial_rejected_on_w():
+    """eta0 = 4/sqrt2 violates the limit (eta_bar = 1.818): the trial is
+    rejected, eta becomes (1 - 2^-0.3) eta_bar, and the repeated trial from
+    (0, 0) at tau = sigma = that eta (closed form, diagonal Q, exact CG) is
+    accepted; its CG steps count too."""
+    say("[adaptive] W, one rejected trial")
+    x, y, r = gpu_solve(example_w(), tol_rel_kkt=1e-14, max_iters=1, max_cg_iters=2, cg_eps_factor=0.0,
+                        eval_period=1000, step_eta_factor=4.0)
+    assert r["rejected_steps"] == 1
+    tau = REJ_ETA_1
+    x1 = np.array([2.0, 1.0]) / (np.array([2.0, 1.0]) + 1.0 / tau)
+    y1 = tau * (2 * x1.sum() - 1.0)
+    assert np.allclose(x, x1, atol=1e-14)
+    assert y[0] == pytest.approx(y1, abs=1e-14)
+    assert r["step_eta"] == pytest.approx(min(RED * REJ_ETA_BAR_2, GROW * REJ_ETA_1), rel=1e-12)
+    assert r["cg_iters_total"] == 4
+
+
+@pytest.mark.parametrize("eta_factor", [0.5, 8.0])
+def test_first_iterations_match_oracle_trace(eta_factor):
+    """Iterates, step size and rejected trials after 1..12 iterations of a
+    random QP (n = 300) equal the oracle's (FP64, CG to its tolerance); with
+    eta_factor = 8 the first trials are rejected."""
+    say(f"[adaptive] random n=300, first iterations, eta_factor={eta_factor}")
+    qp = I.random_qp(n=300, m=150, r_rows=150, q_density=0.03, a_density=0.03, family=1, instance=7)
+    for iters in (1, 2, 5, 12):
+        ro = O.solve(qp, O.Settings(tol=1e-14, max_iters=iters, step_rule=1, eta_factor=eta_factor,
+                                    eval_period=1000))
+        x, y, r = gpu_solve(qp, tol_rel_kkt=1e-14, max_iters=iters, step_eta_factor=eta_factor, eval_period=1000)
+        say(f"  iters={iters} rejected gpu={r['rejected_steps']} oracle={ro.rejections} "
+            f"cg gpu={r['cg_iters_total']} oracle={ro.cg_steps}")
+        assert r["rejected_steps"] == ro.rejections
+        assert r["cg_iters_total"] == ro.cg_steps
+        assert np.linalg.norm(x - ro.x) <= 1e-10 * (1 + np.linalg.norm(ro.x))
+        assert np.linalg.norm(y - ro.y) <= 1e-10 * (1 + np.linalg.norm(ro.y))
+    if eta_factor == 8.0:
+        assert ro.rejections > 0
+
+
+_REF = {}
+
+
+def oracle_ref(qp, key):
+    if key not in _REF:
+        _REF[key] = O.solve(qp, O.Settings(tol=1e-9, max_iters=400_000))
+        assert _REF[key].status == O.OPTIMAL
+    return _REF[key]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("inst", range(3))
+def test_whole_solve_parity(inst, precision):
+    """Random QP n = 1000, m = 500 with the adaptive rule: the full contract
+    against the oracle's optimum, and the iteration count within 5 % (or 64
+    iterations) of the oracle's own adaptive solve.  On instance 0 relKKT
+    1e-6 alone does not imply the objective bar (the oracle's adaptive solve
+    stopped at 1e-6 is 7.2e-7 off, the FP32-product one 1.2e-6), so the solves
+    run to 1e-7, where the oracle is 1.0e-7 off."""
+    say(f"[adaptive] random n=1000 instance={inst} precision={precision}")
+    qp = I.random_qp(family=1, instance=inst)
+    ref = oracle_ref(qp, ("rq1", inst))
+    ro = O.solve(qp, O.Settings(tol=1e-7, step_rule=1))
+    x, y, r = gpu_solve(qp, tol_rel_kkt=1e-7, precision=precision)
+    say(f"  gpu iters={r['iters']} rejected={r['rejected_steps']} oracle iters={ro.iters} rejected={ro.rejections}")
+    assert r["status"] == 0
+    k = check_contract(qp, x, y, ref, 1e-7)
+    assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
+    assert abs(r["iters"] - ro.iters) <= max(64, 0.05 * ro.iters)
+
+
+def test_manufactured_and_unconstrained():
+    say("[adaptive] manufactured optimum n=2000, unconstrained n=80")
+    qp = I.manufactured(n=2000, m=1000, q_density=0.005, a_density=0.005, instance=4)
+    x, y, r = gpu_solve(qp, tol_rel_kkt=1e-9)
+    assert r["status"] == 0
+    assert np.linalg.norm(x - qp.x_star) <= 1e-6 * np.linalg.norm(qp.x_star)
+    qu = I.unconstrained(80)
+    xs = -np.linalg.solve(qu.Q.to_scipy().toarray(), qu.c)
+    x, y, r = gpu_solve(qu, tol_rel_kkt=1e-11)
+    assert r["status"] == 0 and np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_large_grid_with_preconditioning():
+    """n = 1e5 random QP (the benchmark family) on the full grid with the
+    adaptive rule, FP32 products, with and without diagonal preconditioning:
+    relKKT recomputed by the oracle on the caller's problem <= tol."""
+    say("[adaptive] random n=1e5, grid, plain and preconditioned")
+    qp = I.random_qp(100_000, 50_000, 50_000, 2e-5, 2e-4, family=2)
+    for pre in (dict(), dict(ruiz_iters=10, pock_chambolle=1)):
+        x, y, r = gpu_solve(qp, tol_rel_kkt=1e-4, precision=1, **pre)
+        say(f"  pre={bool(pre)} status={r['status_name']} iters={r['iters']} rejected={r['rejected_steps']} "
+            f"eta={r['step_eta']:.3e} kkt={r['rel_kkt']:.2e}")
+        assert r["status"] == 0
+        k = O.kkt(qp, x, y)
+        assert k["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+        assert r["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-6, abs=1e-12)
+        assert np.all(y >= 0)
