@@ -150,7 +150,9 @@ def solve_bytes(qp, r, precision, dense_q=False, rank=0, scaled=False):
     dual step y = proj(y + sigma(A(2x+ - x) - b)) with its vectors, and the
     average update; per CG step nnz(Q)(sv+4) + 4(n+1) + 11 n sx (product, dot,
     axpy and direction update with their vectors); per restart evaluation the
-    n-side pass and an A product at the average.  The n-side pass is FP64 in
+    n-side pass and an A product at the average.  For a dense or factored Q
+    in the batch the Q part of the n-side pass is counted for the passes that
+    formed Q x (qx_formed); the others read the kept Q x.  The n-side pass is FP64 in
     both precision modes by design: it forms r0 and the relKKT pieces, so the
     termination test is taken on the FP64 data.  With preconditioning
     (scaled) every relKKT also reads D2 (n-side) and D1 (m-side)."""
@@ -162,11 +164,17 @@ def solve_bytes(qp, r, precision, dense_q=False, rank=0, scaled=False):
         nq_b64, nq_bv = n * n * 8, n * n * sv
         if rank:  # Q = F F' + diag(d) from its factor: F and F' streamed, d read
             nq_b64, nq_bv = (2 * n * rank + n) * 8, (2 * n * rank + n) * sv
-        a1 = nq_b64 + na * 12 + 4 * (n + 1) + (n + m) * 8 + 2 * n * 8
+        a1 = na * 12 + 4 * (n + 1) + (n + m) * 8 + 2 * n * 8
         cg = nq_bv + 11 * n * sx
         ev = nq_b64 + na * 12 + 4 * (n + 1) + (n + m) * 8 + n * 8 + csr_bytes(na, m, n, 8, 8) + 2 * m * 8
         dual = csr_bytes(na, m, n, sv, sx) - m * sx + 7 * m * 8 + 3 * n * 8
-        return r["iters"] * (a1 + dual + dsc) + r["cg_iters_total"] * cg + r["kkt_evals"] * (ev + dsc)
+        # Q x is formed (FP64 product) in qx_formed n-side passes; with Q x
+        # kept by linearity the other passes read it (8n) and every CG step
+        # updates it (16n)
+        formed = r.get("qx_formed", r["iters"])
+        kept = formed < r["iters"]
+        return (r["iters"] * (a1 + dual + dsc) + formed * nq_b64 + (r["iters"] - formed) * 8 * n * kept
+                + r["cg_iters_total"] * (cg + 16 * n * kept) + r["kkt_evals"] * (ev + dsc))
     a1 = (nq + na) * 12 + 8 * (n + 1) + (n + m) * 8 + 2 * n * 8           # matrices, x, y, c, r
     dual = csr_bytes(na, m, n, sv, sx) - m * sx + 7 * m * 8 + 3 * n * 8   # + y, ax, b, ya (r/w); xa update
     cg = nq * (sv + 4) + 4 * (n + 1) + 11 * n * sx

@@ -136,6 +136,12 @@ typedef struct {
     int32_t cold_fallback;           /* 1 if the given start point was replaced by (0, 0) */
     int64_t rejected_steps;          /* trials rejected by the adaptive step size (step_rule 1) */
     double step_eta;                 /* eta at the end of the solve */
+    int64_t qx_formed;               /* n-side passes at the current point that formed Q x with a
+                                        product: one per iteration, except in the batch with a dense
+                                        or factored Q and the constant step rule, where Q x is kept
+                                        by linearity through the CG updates and formed only at the
+                                        start, every eval_period iterations, after a restart to the
+                                        average and before a termination or a limit is reported */
 } pdhcg_result;
 
 typedef struct pdhcg_handle pdhcg_handle;

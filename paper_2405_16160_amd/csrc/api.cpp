@@ -873,6 +873,7 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
     res->kkt_evals = st.evals;
     res->cold_fallback = st.cold_fallback;
     res->rejected_steps = st.rejections;
+    res->qx_formed = st.qx_formed;
     res->step_eta = st.eta;
   }
   return 0;
@@ -1386,7 +1387,7 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
   double* d_val;
   float* d_val32 = nullptr;
   double *d_b, *d_c, *d_part;
-  double* nv[9];  // x xa x_anc r p0 p1 q x_prev (+ F' v of a factored Q)
+  double* nv[10];  // x xa x_anc r p0 p1 q x_prev (+ F' v of a factored Q) (+ kept Q x of a dense Q)
   double* mv[7];  // y ya ax ax_avg y_anc y_trial ax_trial
   float* fv[4] = {nullptr, nullptr, nullptr, nullptr};
   if ((rc = D.alloc(&d_rp, rp_tot))) return bail(rc);
@@ -1403,9 +1404,11 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
   if ((rc = D.alloc(&d_part, (int64_t)count * NSLOT))) return bail(rc);
   if ((rc = D.alloc(&h->d_order, count))) return bail(rc);
   const bool adaptive = s->step_rule == 1;
-  for (int k = 0; k < 9; ++k) {
+  bool any_dense = false;
+  for (int i = 0; i < count; ++i) any_dense |= inst[i].dense != 0;
+  for (int k = 0; k < 10; ++k) {
     nv[k] = nullptr;
-    if ((k == 7 && !adaptive) || (k == 8 && !Ls)) continue;
+    if ((k == 7 && !adaptive) || (k == 8 && !Ls) || (k == 9 && (adaptive || !any_dense))) continue;
     if ((rc = D.alloc(&nv[k], vn_tot))) return bail(rc);
   }
   for (int k = 0; k < 7; ++k) {
@@ -1556,6 +1559,7 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
     P.eval_period = s->eval_period;
     P.mixed_allowed = mixed ? 1 : 0;
     P.step_rule = s->step_rule;
+    if (I.dense && nv[9]) P.qx = nv[9] + I.voff_n;
     if (adaptive) {
       P.x_prev = nv[7] + I.voff_n;
       P.y_trial = mv[5] + I.voff_m;
@@ -1649,6 +1653,7 @@ int batch_solve_impl(pdhcg_batch* h, const double* x0, const double* y0, bool in
     r.kkt_evals = S.evals;
     r.cold_fallback = S.cold_fallback;
     r.rejected_steps = S.rejections;
+    r.qx_formed = S.qx_formed;
     r.step_eta = S.eta;
   }
   return 0;
@@ -1753,7 +1758,7 @@ int pdhcg::solve_batch_in_region(int32_t count, const pdhcg_csr* Qs, const pdhcg
                                  double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
                                  const pdhcg_settings* s, void* hip_stream, char* region, size_t region_bytes) {
   if (!Qs) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null array argument");
-  if (!region) return fail(PDHCG_ERR_HIP, "no device region");
+  if (!region && count > 0) return fail(PDHCG_ERR_HIP, "no device region");
   return solve_batch_once(count, Qs, nullptr, As, bs, cs, x0s, y0s, x_outs, y_outs, rs, s, hip_stream, region,
                           region_bytes);
 }

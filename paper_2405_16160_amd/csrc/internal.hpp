@@ -141,6 +141,7 @@ struct SolverState {
   int64_t rejections;   // rejected trial steps (adaptive step size)
   int32_t attempts;     // trials of the current iteration (adaptive step size)
   int32_t pad_;
+  int64_t qx_formed;    // n-side passes at the current point that formed Q x with a product
 };
 
 struct SolveParams {
@@ -202,6 +203,12 @@ struct SolveParams {
   // adaptive step size (step_rule = 1): the point x^k of the iteration (saved
   // by the n-side pass), and the trial dual point and its A x' (m)
   int32_t step_rule;
+  // Q x of the current point kept by linearity (a dense or factored Q in the
+  // batch with the constant step rule; null otherwise): the n-side pass then
+  // forms Q x with a product only every eval_period iterations, after a
+  // restart and before a termination or a limit is reported, and reads the
+  // kept vector in between
+  double* qx;
   double* x_prev;
   double* y_trial;
   double* ax_trial;

@@ -172,9 +172,9 @@ __device__ void dense_rows(const V* M, const DevMat& Q, double* svec, double* ts
   rect_rows(Ft, k, n, svec, get_t, fin);
 }
 
-// q = Q xv for a dense Q owned by one workgroup
-__device__ __attribute__((noinline)) void dense_qx(const SolveParams& P, const double* xv, double* svec) {
-  dense_rows(P.Q.val, P.Q, svec, P.lr_t, [&](int j, bool) { return xv[j]; }, [&](int i, double v) { P.q[i] = v; });
+// out = Q xv for a dense Q owned by one workgroup
+__device__ __attribute__((noinline)) void dense_qx(const SolveParams& P, const double* xv, double* svec, double* out) {
+  dense_rows(P.Q.val, P.Q, svec, P.lr_t, [&](int j, bool) { return xv[j]; }, [&](int i, double v) { out[i] = v; });
 }
 
 // CG product for a dense Q owned by one workgroup: stage p in LDS, stream Q
@@ -200,16 +200,22 @@ __device__ __attribute__((noinline)) void dense_cg_spmv(const SolveParams& P, Bl
   if (B.tid == 0) P.part[S_PQ * B.nb + B.b] = s[0];
 }
 
+// How the n-side pass of a dense Q obtains Q xv: formed into the free CG
+// buffer q (the average's evaluation), formed into qx (the current point, which
+// then keeps it), or read from qx as kept by the CG updates (no product).
+enum QxMode { QX_INTO_Q = 0, QX_FORM = 1, QX_KEPT = 2 };
+
 // n-side product at (xv, yv): g = Q xv + A' yv + c, row by row over the
 // workgroup's rows of the partition `pt`.  Writes r = -g (and its FP32 copy)
 // when r != null and stores the six n-side partials at slot0.
 template <bool DENSE>
 __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, const WgPart& pt, Block B, const double* xv,
                             const double* yv, double* r, float* r32, int r32_stride, int slot0, double* lds,
-                            double* svec) {
-  // dense Q (one workgroup per QP): Q xv first, into the free CG buffer q
+                            double* svec, int qmode = QX_INTO_Q) {
+  // dense Q (one workgroup per QP): Q xv first, into q or qx, unless qx is kept
   constexpr bool dense = DENSE;
-  if (dense) dense_qx(P, xv, svec);
+  double* const qsrc = qmode == QX_INTO_Q ? P.q : P.qx;
+  if (dense && qmode != QX_KEPT) dense_qx(P, xv, svec, qsrc);
   const int G = pt.group;
   double s[3] = {0.0, 0.0, 0.0};   // g.g, x.Qx, c.x
   double mx[3] = {0.0, 0.0, 0.0};  // |g|, |Qx|, |A'y|
@@ -221,7 +227,7 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
   // of the caller's problem, (Qx)_j = (Q~x~)_j / D2_j and likewise A'y and c
   const double* dn = P.dn;
   auto pre = [&](int i) {
-    return Row{gld(P.c + i), gld(xv + i), dense ? gld(P.q + i) : 0.0, dn ? gld(dn + i) : 1.0};
+    return Row{gld(P.c + i), gld(xv + i), dense ? gld(qsrc + i) : 0.0, dn ? gld(dn + i) : 1.0};
   };
   auto epi = [&](int i, double qx, double aty, const Row& rw) {
     const double g = qx + aty + rw.c;
@@ -383,14 +389,19 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Bl
   if (B.tid == 0) P.part[S_PQ * B.nb + B.b] = s[0];
 }
 
-// CG update on the owned rows: x += alpha p, r -= alpha q; partial r.r
+// CG update on the owned rows: x += alpha p, r -= alpha q; partial r.r.
+// With qx kept (a dense Q in the batch), Q x moves with x by linearity:
+// Q x += alpha Q p, Q p = q - p / tau.
 __device__ __attribute__((noinline)) void phase_cg_update(const SolveParams& P, Block B, const double* pcur, double alpha, int mixed,
-                                double* lds) {
+                                double inv_tau, double* lds) {
   const int r0 = P.w_cg.r0, r1 = P.w_cg.r1;
   double s[1] = {0.0};
+  double* const qx = P.qx;
   for (int i = r0 + B.tid; i < r1; i += kBlock) {
-    const double xi = P.x[i] + alpha * pcur[i];
-    const double ri = P.r[i] - alpha * P.q[i];
+    const double pi = pcur[i], qi = P.q[i];
+    const double xi = P.x[i] + alpha * pi;
+    const double ri = P.r[i] - alpha * qi;
+    if (qx) qx[i] += alpha * (qi - pi * inv_tau);
     P.x[i] = xi;
     P.r[i] = ri;
     if (mixed) {
@@ -868,6 +879,9 @@ struct Ctl {
   int32_t op, l, steps, have_avg, use_avg, first, cur;
   int32_t xlds;       // the primal step left x of the CG rows in LDS (P.cg_own)
   int32_t retry;      // the n-side pass repeats x^k's for a rejected trial
+  // kept Q x (P.qx): the next n-side pass forms Q x with a product (exact),
+  // and whether the current point's relKKT pieces (kc) came from such a pass
+  int32_t exact, kc_exact;
   double rt[4];       // sums of a trial: dx.dx, dy.dy, dy.(A dx), dx.(Q dx)
 };
 
@@ -935,6 +949,11 @@ __device__ void ctl_limits(const SolveParams& P, Ctl& C) {
   const bool at_cap = C.S.k_total >= P.max_iters;
   const bool at_time = C.tflag > 0.0;
   if (at_cap || at_time) {
+    if (P.qx && !C.kc_exact) {  // the reported relKKT from a formed Q x
+      C.exact = 1;
+      C.op = OP_NSIDE;
+      return;
+    }
     if (C.S.mixed) {  // exact FP64 m-side partials for the reported relKKT
       C.op = OP_LIMIT_AX;
       return;
@@ -1003,6 +1022,11 @@ __device__ void ctl_after_nside(const SolveParams& P, Ctl& C) {
     C.op = OP_COPY_ANCHOR;
     return;
   }
+  if (C.kc.kkt <= P.tol && P.qx && !C.kc_exact) {  // Q x was the kept one: form it before stopping
+    C.exact = 1;
+    C.op = OP_NSIDE;
+    return;
+  }
   if (C.kc.kkt <= P.tol && C.S.mixed) {  // the m-side partials came from FP32 products
     C.op = OP_CERTIFY;
     return;
@@ -1015,9 +1039,13 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
   const Ctl& r = C;
   switch (op) {
     case OP_AX_START:
+      C.exact = 1;
       C.op = OP_NSIDE;
       break;
     case OP_NSIDE:
+      if (!P.qx || C.exact) C.S.qx_formed += 1;
+      C.kc_exact = C.exact;
+      C.exact = 0;
       if (C.retry) {  // x^k again for a repeated trial: only r_0 is needed
         C.retry = 0;
         C.rho = r.ra;
@@ -1064,6 +1092,7 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       break;
     case OP_AX_ZERO:
       C.S.cold_fallback = 1;
+      C.exact = 1;
       C.op = OP_NSIDE;
       break;
     case OP_CERTIFY:
@@ -1087,6 +1116,7 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       C.S.eps = 0.0;
       C.S.restarts += 1;
       C.have_avg = 0;
+      C.exact = 1;
       if (C.use_avg)
         C.op = OP_NSIDE;  // the point moved: redo the n-side pass there
       else
@@ -1150,6 +1180,9 @@ __device__ void control(const SolveParams& P, Ctl& C, int op) {
       C.S.k += 1;
       C.S.k_total += 1;
       C.budget -= 1;
+      // a kept Q x is formed anew at every restart evaluation, so its
+      // rounding drift never spans more than eval_period iterations
+      C.exact = C.S.k % P.eval_period == 0;
       C.op = C.budget > 0 ? OP_NSIDE : OP_END;
       break;
     default:
@@ -1309,6 +1342,8 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
     C.budget = budget;
     C.have_avg = 0;
     C.retry = 0;
+    C.exact = 1;
+    C.kc_exact = 0;
     C.op = C.S.done || budget <= 0 ? OP_END : (C.S.K_anchor != C.S.K_anchor ? OP_AX_START : OP_NSIDE);
   }
   __syncthreads();
@@ -1338,7 +1373,8 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         if (P.v32_0)
           phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? (float*)P.v32_0 : nullptr, 4, 0, lds, svec);
         else
-          phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? P.r32 : nullptr, 1, 0, lds, svec);
+          phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? P.r32 : nullptr, 1, 0, lds, svec,
+                             P.qx ? (C.exact ? QX_FORM : QX_KEPT) : QX_INTO_Q);
         if (B.tid == 0) {
           double f = 0.0;
           if (B.b == 0 && P.time_limit_ticks && wall_clock64() - C.S.t_start > P.time_limit_ticks) f = 1.0;
@@ -1378,7 +1414,7 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         break;
       }
       case OP_CG_UPDATE:
-        phase_cg_update(P, B, C.cur ? P.p1 : P.p0, C.alpha, mixed, lds);
+        phase_cg_update(P, B, C.cur ? P.p1 : P.p0, C.alpha, mixed, C.inv_tau, lds);
         break;
       case OP_DUAL:
         if (mixed)
@@ -1387,8 +1423,12 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
           phase_dual(P, B, P.A.val, (const double*)P.x, C.S.sigma, C.w, C.xlds ? P.cg_own : nullptr, lds);
         break;
       case OP_DUAL_TRIAL:
+        // with FP32 values of A, x is gathered in FP64: A x' and the A x^k of
+        // the previous trial then share the rounding of A, and dy.(A x' - A x^k)
+        // in the step limit keeps its accuracy as the steps shrink (the rounding
+        // of x to FP32 would not cancel)
         if (mixed)
-          phase_dual_trial<DENSE>(P, B, P.A.val32, (const float*)P.x32, C.S.sigma, lds, svec);
+          phase_dual_trial<DENSE>(P, B, P.A.val32, (const double*)P.x, C.S.sigma, lds, svec);
         else
           phase_dual_trial<DENSE>(P, B, P.A.val, (const double*)P.x, C.S.sigma, lds, svec);
         break;

@@ -371,6 +371,22 @@ def manufactured(n=1000, m=500, q_density=0.01, a_density=0.01, active_frac=0.3,
     return QP(CSR.from_scipy(Q), CSR.from_scipy(A), b, c, name=f"manufactured(n={n},m={m})", x_star=xs, y_star=ys)
 
 
+def powerlaw_manufactured(n=2_000_000, m=1_000_000, active_frac=0.3, family=31, instance=0) -> QP:
+    """The power-law set's Q and A (``powerlaw_qp`` with this family's seed)
+    with a known optimum, drawn as in ``manufactured``: x* ~ N(0,1), an active
+    set S (each row w.p. active_frac) with y*_i ~ U[0.1, 1] on S, c = -(Q x* +
+    A' y*), b_i = (A x*)_i on S and (A x*)_i + U[0.1, 1] off S."""
+    base = powerlaw_qp(n, m, family=family, instance=instance)
+    rng = _rng(family, 1_000_000 + instance)
+    Q, A = base.Q.to_scipy(), base.A.to_scipy()
+    xs = rng.standard_normal(n)
+    active = rng.uniform(size=m) < active_frac
+    ys = np.where(active, rng.uniform(0.1, 1.0, m), 0.0)
+    c = -(Q @ xs + A.T @ ys)
+    b = A @ xs + np.where(active, 0.0, rng.uniform(0.1, 1.0, m))
+    return QP(base.Q, base.A, b, c, name=f"powerlaw_manufactured(n={n},m={m})", x_star=xs, y_star=ys)
+
+
 def row_scaled(qp: QP, spread=3.0, seed=3) -> QP:
     """The same QP with row i of A and b_i multiplied by exp(U[-spread, spread]):
     the same feasible set and optimum x, a badly scaled A (the case diagonal

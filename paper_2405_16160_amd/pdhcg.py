@@ -69,12 +69,13 @@ class pdhcg_result(C.Structure):
                 ("cg_iters_total", C.c_int64), ("restarts", C.c_int64), ("norm_A", C.c_double),
                 ("setup_s", C.c_double), ("solve_s", C.c_double), ("kernel_s", C.c_double),
                 ("kkt_evals", C.c_int64), ("cold_fallback", C.c_int32), ("rejected_steps", C.c_int64),
-                ("step_eta", C.c_double)]
+                ("step_eta", C.c_double), ("qx_formed", C.c_int64)]
 
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
 EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_get_scaling",
+           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs",
+           "pdhcg_spmv", "pdhcg_get_scaling",
            "pdhcg_autotune", "pdhcg_plan_info", "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error",
            "pdhcg_batch_create", "pdhcg_batch_layout", "pdhcg_batch_solve", "pdhcg_batch_get_scaling",
            "pdhcg_batch_destroy"]

@@ -170,3 +170,32 @@ def test_batch_lowrank_portfolio(precision):
         if precision == 0 and qp.n <= 400:
             ref = O.solve(qp, O.Settings(tol=1e-9, max_iters=1_000_000))
             contract(qp, x, y, ref, 1e-6)
+
+
+@pytest.mark.parametrize("form", ["dense", "factored"])
+def test_batch_portfolio_maximum_size_contract(form):
+    """The largest portfolio size (n = 2000) in a batch beside small ones, with
+    per-instance diagonal preconditioning and FP32 products, Q dense or
+    factored, held to the full contract against the oracle (its own Ruiz +
+    Pock-Chambolle preprocessing, FP64, run to 1e-9): relKKT on the caller's
+    problem <= 1e-7 (where relKKT implies the objective bar on this family),
+    x within 1e-4, objective within 1e-6, y >= 0."""
+    from oracle import precondition as PC
+    say(f"[batch max contract] n = 2000 + 3 small, {form} Q, preconditioned, FP32, tol 1e-7")
+    ids = [900, 0, 1, 2]
+    qps = [I.portfolio_qp(900, n=2000)] + [I.portfolio_qp(i, nmax=120) for i in ids[1:]]
+    fac = [I.portfolio_factor(900, n=2000)] + [I.portfolio_factor(i, nmax=120) for i in ids[1:]] \
+        if form == "factored" else None
+    s = pdhcg.Settings(tol_rel_kkt=1e-7, precision=1, max_iters=400_000, ruiz_iters=10, pock_chambolle=1)
+    out = pdhcg.solve_batch(qps, s, lowrank=fac)
+    for qp, (x, y, r) in zip(qps, out):
+        xr, _, rr, _, _ = PC.solve(qp, O.Settings(tol=1e-9, max_iters=1_000_000))
+        assert rr.status == O.OPTIMAL
+        k = O.kkt(qp, x, y)
+        say(f"  n={qp.n} status={r['status_name']} iters={r['iters']} relKKT={k['rel_kkt']:.2e} "
+            f"x err={np.linalg.norm(x - xr) / np.linalg.norm(xr):.2e}")
+        assert r["status"] == 0, r
+        assert k["rel_kkt"] <= 1e-7 * (1 + 1e-6), k
+        assert np.all(y >= 0)
+        assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-4
+        assert abs(k["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-6
