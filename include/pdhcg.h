@@ -181,6 +181,31 @@ int pdhcg_solve_batch(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
                       double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
                       const pdhcg_settings* s, void* hip_stream);
 
+/* Bytes of the static device array behind pdhcg_solve_batch_noalloc (one copy
+ * per GPU the library runs on, held until the process ends). */
+#define PDHCG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): pdhcg_solve_batch with the same
+ * arguments, results and errors, except that every device buffer of the
+ * batch (packed matrices and vectors, row partitions, parameter blocks,
+ * per-instance state, preconditioning factors) is carved from a static device
+ * array of PDHCG_NOALLOC_SCRATCH_BYTES instead of being allocated; no
+ * hipMalloc, hipFree or allocating library routine is called (host memory is
+ * still used for packing).  A batch that does not fit returns
+ * PDHCG_ERR_INVALID_ARGUMENT with the bytes it needs in pdhcg_last_error().
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (other threads, other streams) race and must be serialised by the
+ * caller; a call returns after its stream has finished using the array.
+ * kernel_s in rs is the solve's host wall time, as solve_s (no events are
+ * created).  The call synchronizes its stream, so it cannot be captured into
+ * a HIP graph. */
+int pdhcg_solve_batch_noalloc(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* As,
+                              const double* const* bs, const double* const* cs,
+                              const double* const* x0s, const double* const* y0s,
+                              double* const* x_outs, double* const* y_outs, pdhcg_result* rs,
+                              const pdhcg_settings* s, void* hip_stream);
+
 /* A dense Q given by its factor: Q = F F' + diag(d), F n x k (row-major,
  * k <= n), d (n).  The low-rank form of Q (Sec. 2, low-rank acceleration; the
  * portfolio model of Sec. 5.1): the batched products then read 2 n k values

@@ -74,7 +74,7 @@ class pdhcg_result(C.Structure):
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
 EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs",
+           "pdhcg_solve_batch", "pdhcg_solve_batch_noalloc", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs",
            "pdhcg_spmv", "pdhcg_get_scaling",
            "pdhcg_autotune", "pdhcg_plan_info", "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error",
            "pdhcg_batch_create", "pdhcg_batch_layout", "pdhcg_batch_solve", "pdhcg_batch_get_scaling",
@@ -112,6 +112,7 @@ def lib():
         L.pdhcg_set_b.argtypes = [P, P, C.c_int32]
         L.pdhcg_solve.argtypes = [P, P, P, P, P, C.c_int32, C.POINTER(pdhcg_result)]
         L.pdhcg_solve_batch.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
+        L.pdhcg_solve_batch_noalloc.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_solve_batch_lowrank.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_solve_multi_rhs.argtypes = [C.c_int32, C.POINTER(pdhcg_csr), C.POINTER(pdhcg_csr), P, P, P, P, P, P,
                                             P, C.POINTER(pdhcg_settings), P]
@@ -288,11 +289,13 @@ class Solver:
             pass
 
 
-def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None, lowrank=None):
+def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None, lowrank=None, noalloc=False):
     """Solve a list of QPs with pdhcg_solve_batch (host arrays in and out).
     lowrank: optional list of (F, d) with Q_i = F F' + diag(d) (then
-    pdhcg_solve_batch_lowrank; qps[i].Q is not read).  Returns a list of
-    (x, y, result) with numpy arrays."""
+    pdhcg_solve_batch_lowrank; qps[i].Q is not read).  noalloc: use
+    pdhcg_solve_batch_noalloc (device buffers carved from the library's static
+    scratch; CSR Q only).  Returns a list of (x, y, result) with numpy
+    arrays."""
     settings = settings or Settings()
     cnt = len(qps)
     keep = []
@@ -333,11 +336,13 @@ def solve_batch(qps, settings: Settings | None = None, x0s=None, y0s=None, lowra
             y0[i] = arr(y0s[i], np.float64).ctypes.data
     rs = (pdhcg_result * cnt)()
     if Ls is not None:
+        if noalloc:
+            raise ValueError("the allocation-free entry point takes Q in CSR form only")
         _check(lib().pdhcg_solve_batch_lowrank(cnt, Ls, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()),
                                                _stream_ptr()))
     else:
-        _check(lib().pdhcg_solve_batch(cnt, Qs, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()),
-                                       _stream_ptr()))
+        fn = lib().pdhcg_solve_batch_noalloc if noalloc else lib().pdhcg_solve_batch
+        _check(fn(cnt, Qs, As, bs, cs, x0, y0, xo, yo, rs, C.byref(settings.c()), _stream_ptr()))
     return [(outs[i][0], outs[i][1][: qps[i].A.nrows], _result_dict(rs[i])) for i in range(cnt)]
 
 
