@@ -9,11 +9,11 @@
 namespace pdhcg {
 
 // max that propagates NaN (the hardware max returns the non-NaN operand, which
-// would hide a diverged iterate from the termination test)
+// would hide a diverged iterate from the termination test); written with
+// selects only, so that reductions of maxima compile without branches
 __device__ __forceinline__ double maxp(double a, double b) {
-  if (a != a) return a;
-  if (b != b) return b;
-  return a > b ? a : b;
+  const double m = a > b ? a : b;
+  return (a != a || b != b) ? a + b : m;  // a + b is NaN when either is
 }
 
 // A value that every lane of the wave holds equal, marked as such for the
@@ -101,6 +101,13 @@ __device__ __forceinline__ void block_reduce(double* s, double* mx, double* lds)
 template <int NS, int NM>
 __device__ __forceinline__ void reduce_partials(const double* part, int nb, const int* sum_slots,
                                                 const int* max_slots, double* s, double* mx, double* lds) {
+  if (nb == 1) {  // one workgroup: its own partial is the total (every thread reads it)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s[k] = part[sum_slots[k]];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) mx[k] = part[max_slots[k]];
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < NS; ++k) s[k] = 0.0;
 #pragma unroll
@@ -250,6 +257,14 @@ __device__ __forceinline__ double ldv(const V* p, int k) { return (double)p[k]; 
 template <typename T>
 __device__ __forceinline__ T gld(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// The same with the non-temporal hint, for a matrix streamed once per
+// product: its lines should not displace the reused vectors and index data
+// (of this workgroup and of the others on the XCD) from the L2 and the MALL.
+template <typename T>
+__device__ __forceinline__ T gld_nt(const T* p) {
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
 }
 
 template <typename T>
