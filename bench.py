@@ -121,7 +121,8 @@ def parse():
                     help="with --summarize-counters: a file holding the bench line of the profiled run "
                          "(its algorithmic bytes per launch)")
     ap.add_argument("--config", default="portfolio",
-                    choices=["portfolio", "random1e5", "tiny", "powerlaw", "batch", "learned", "kappa", "precondition"],
+                    choices=["portfolio", "random1e5", "tiny", "powerlaw", "batch", "learned", "kappa", "precondition",
+                             "lowrank"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--precondition", action="store_true",
@@ -513,14 +514,48 @@ def bench_kappa(args):
                       f"precision {args.precision}", "rows": rows}
 
 
+def bench_lowrank(args):
+    """Low-rank Q (the experiment of Tables 3 and 4: Q = P P' with growing
+    rank k, each product with Q formed as P (P' v) against the explicit Q):
+    lowrank_qp n = 1e5, m = 5e4, P at density 1e-3 (plus d ~ U[0.01, 0.1]),
+    k in 1e3 .. 1e4, solved to tol by PDHCG and by CG capped at one step (the
+    linearised primal step), each with Q in low-rank form
+    (pdhcg_create_lowrank) and explicit (pdhcg_create), kernel time from the
+    HIP events of each solve; ratio = low-rank / explicit."""
+    import torch
+    from paper_2405_16160_amd import instances as I, pdhcg
+    rows = []
+    for k in (1_000, 2_000, 5_000, 10_000):
+        qp, P, d = I.lowrank_qp(n=100_000, m=50_000, k=k)
+        row = {"k": k, "nnz_P": P.nnz, "nnz_Q": qp.Q.nnz}
+        for name, extra in (("pdhcg", {}), ("cg_cap_1", {"max_cg_iters": 1, "cg_rule": 1})):
+            out = {}
+            for form, lr in (("low_rank", (P, d)), ("explicit", None)):
+                st = pdhcg.Settings(tol_rel_kkt=args.tol, precision=args.precision, max_iters=1_000_000,
+                                    time_limit_s=30.0, **extra)
+                sol = pdhcg.Solver(qp, st, lowrank=lr)
+                _, _, r = sol.solve()
+                torch.cuda.synchronize()
+                sol.close()
+                out[form] = {"status": r["status_name"], "iters": r["iters"], "cg_steps": r["cg_iters_total"],
+                             "kernel_ms": r["kernel_s"] * 1e3}
+                progress(f"k {k} {name} {form}: {r['status_name']} {r['iters']} iterations, "
+                         f"{r['cg_iters_total']} CG steps, {r['kernel_s'] * 1e3:.1f} ms")
+            out["ratio"] = out["low_rank"]["kernel_ms"] / out["explicit"]["kernel_ms"]
+            row[name] = out
+        rows.append(row)
+    return {"config": f"low-rank Q, lowrank_qp n=1e5 m=5e4, P density 1e-3, tol {args.tol:g}, "
+                      f"precision {args.precision}", "rows": rows}
+
+
 def bench_precondition(args):
     """Diagonal preconditioning (10 Ruiz steps + one Pock-Chambolle step on
     [[Q, A'], [A, 0]]): the random QP n = 1e5 as generated and with its rows of
     A (and b) rescaled by exp(U[-3, 3]), each solved to tol without and with
     the preconditioning; the power-law QP n = 2e6 for the cost of the setup
-    kernels and a time-limited solve; portfolio instances 0-15 one by one.  With preconditioning the reported relKKT
-    refers to the scaled problem; x_rel_diff compares the returned x with the
-    unpreconditioned solve's."""
+    kernels and a time-limited solve; portfolio instances 0-15 one by one.  relKKT
+    always refers to the caller's problem; x_rel_diff compares the returned x
+    with the unpreconditioned solve's."""
     import torch
     from paper_2405_16160_amd import instances as I, pdhcg
     rows = []
@@ -826,7 +861,8 @@ def main():
 
     if args.config not in ("portfolio", "random1e5"):
         line = {"tiny": bench_tiny, "powerlaw": bench_powerlaw, "batch": bench_batch, "kappa": bench_kappa,
-                "precondition": bench_precondition, "learned": bench_learned}[args.config](args)
+                "precondition": bench_precondition, "learned": bench_learned,
+                "lowrank": bench_lowrank}[args.config](args)
         print(json.dumps(line), flush=True)
         return
     if args.config == "random1e5":

@@ -156,6 +156,20 @@ void pdhcg_default_settings(pdhcg_settings* s);
 int pdhcg_create(pdhcg_handle** h, const pdhcg_csr* Q, const pdhcg_csr* A, const double* b,
                  const double* c, int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream);
 
+/* A QP whose Q is given in low-rank form, Q = P P' + diag(d) (Sec. 2,
+ * low-rank acceleration of Q): P is a sparse n x k CSR matrix (k >= 1, FP64
+ * values), d (n entries, finite and >= 0) may be NULL for d = 0.  Every product with Q is formed as t = P' v, then
+ * P t + d v (P' is built and stored beside P at create time), so a CG step
+ * reads nnz(P) twice instead of nnz(P P'); that product takes one more grid
+ * barrier.  A, b, c, settings, stream and errors as pdhcg_create; d is a
+ * device pointer when vec_on_device = 1.  The handle then solves with the
+ * textbook CG form, without diagonal preconditioning and with the constant
+ * step rule (ruiz_iters, pock_chambolle and step_rule must be 0:
+ * INVALID_ARGUMENT otherwise), and pdhcg_spmv takes which = 1 or 2 only. */
+int pdhcg_create_lowrank(pdhcg_handle** h, const pdhcg_csr* P, const double* d, const pdhcg_csr* A,
+                         const double* b, const double* c, int32_t vec_on_device, const pdhcg_settings* s,
+                         void* hip_stream);
+
 /* Replace the settings of a handle (e.g. a different tolerance or CG cap). */
 int pdhcg_set_settings(pdhcg_handle* h, const pdhcg_settings* s);
 

@@ -274,6 +274,16 @@ struct pdhcg_handle {
   float4 *v32_0 = nullptr, *v32_1 = nullptr;   // interleaved FP32 (r, u, s) of the one-reduction CG
   double *part = nullptr, *tmp_x0 = nullptr, *tmp_y0 = nullptr, *scratch = nullptr;
   double* dscale = nullptr;  // D2 (n) then D1 (m) of the preconditioning; ones when off
+  // Q = P P' + diag(d) given by a sparse P (pdhcg_create_lowrank): the Q
+  // arrays then hold P (n x k), and P' (k x n) is stored beside it with a row
+  // partition of its own
+  int lowrank = 0;
+  int64_t k = 0;
+  int32_t *lt_rowptr = nullptr, *lt_col = nullptr;
+  double *lt_val = nullptr, *lr_d = nullptr, *lr_pt = nullptr;
+  float *lt_val32 = nullptr, *lr_pt32 = nullptr;
+  DevPart plr;
+  std::vector<int64_t> lrp_h;
   bool scaled = false;       // the device data are the preconditioned problem
   uint64_t* bar = nullptr;
   SolverState* st = nullptr;
@@ -313,7 +323,7 @@ struct pdhcg_handle {
   }
 
   DevMat mat(int which) const {
-    if (which == 0) return DevMat{(int32_t)n, (int32_t)n, q_rowptr, q_col, q_val, q_val32};
+    if (which == 0) return DevMat{(int32_t)n, (int32_t)(lowrank ? k : n), q_rowptr, q_col, q_val, q_val32};
     if (which == 1) return DevMat{(int32_t)m, (int32_t)n, a_rowptr, a_col, a_val, a_val32};
     return DevMat{(int32_t)n, (int32_t)m, t_rowptr, t_col, t_val, t_val32};
   }
@@ -378,6 +388,10 @@ int ensure_mixed(pdhcg_handle* h) {
   if ((rc = h->alloc(&h->v32_0, h->n))) return rc;
   if ((rc = h->alloc(&h->v32_1, h->n))) return rc;
   HIPX(launch_to_f32(h->q_val, h->q_val32, h->nnzQ, h->stream));
+  if (h->lowrank) {  // P' in FP32 for the products of the CG steps
+    if ((rc = h->alloc(&h->lt_val32, h->nnzQ))) return rc;
+    HIPX(launch_to_f32(h->lt_val, h->lt_val32, h->nnzQ, h->stream));
+  }
   if (h->nnzA > 0) {
     HIPX(launch_to_f32(h->a_val, h->a_val32, h->nnzA, h->stream));
     HIPX(launch_to_f32(h->t_val, h->t_val32, h->nnzA, h->stream));
@@ -426,7 +440,7 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
   const int64_t* qrp = h->qrp_h.data();
   const int64_t* arp = h->m ? h->arp_h.data() : nullptr;
   const int64_t* trp = h->m ? h->trp_h.data() : nullptr;
-  for (DevPart* d : {&h->pn1, &h->pcg, &h->pm, &h->pt}) free_part(h, *d);
+  for (DevPart* d : {&h->pn1, &h->pcg, &h->pm, &h->pt, &h->plr}) free_part(h, *d);
   if ((rc = upload_part(h, build_part(h->n, nb, qrp, trp, gscale), h->pn1))) return rc;
   const HostPart pcg = build_part(h->n, nb, qrp, nullptr, gscale);
   const HostPart pm = build_part(h->m, nb, arp, nullptr, gscale);
@@ -438,6 +452,8 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
   if ((rc = upload_part(h, pcg, h->pcg))) return rc;
   if ((rc = upload_part(h, pm, h->pm))) return rc;
   if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr, gscale), h->pt))) return rc;
+  if (h->lowrank && (rc = upload_part(h, build_part(h->k, nb, h->lrp_h.data(), nullptr, gscale), h->plr)))
+    return rc;
   return 0;
 }
 
@@ -521,7 +537,7 @@ int plan_residency(pdhcg_handle* h, SolveParams& p) {
     p.own_cg = 1;
     total = bo;
   }
-  if (total + bq <= budget) {
+  if (!h->lowrank && total + bq <= budget) {  // (a low-rank Q's products gather t, not p)
     p.res_cg = 1;
     total += bq;
   }
@@ -566,7 +582,8 @@ SolveParams make_params(pdhcg_handle* h) {
   // s), the textbook steps 4 (the direction) at one more grid barrier per step;
   // the first wins while the gathered vector stays in an XCD's L2, the second
   // once the gathers stream from the last-level cache
-  const bool single = h->s.cg_form == 1 || (h->s.cg_form == 0 && 16 * h->n <= h->l2_bytes);
+  // (a low-rank Q takes the textbook form: its products need t = P' p first)
+  const bool single = !h->lowrank && (h->s.cg_form == 1 || (h->s.cg_form == 0 && 16 * h->n <= h->l2_bytes));
   if (!single) {
     p.u0 = nullptr;
     p.v32_0 = p.v32_1 = nullptr;
@@ -578,6 +595,13 @@ SolveParams make_params(pdhcg_handle* h) {
   p.pcg = h->pcg.view();
   p.pm = h->pm.view();
   p.pt = h->pt.view();
+  if (h->lowrank) {
+    p.Lt = DevMat{(int32_t)h->k, (int32_t)h->n, h->lt_rowptr, h->lt_col, h->lt_val, h->lt_val32, 0, 0};
+    p.plr = h->plr.view();
+    p.lr_d = h->lr_d;
+    p.lr_pt = h->lr_pt;
+    p.lr_pt32 = h->lr_pt32;
+  }
   p.nb_inf = h->nb_inf;
   p.nc_inf = h->nc_inf;
   p.dn = h->scaled ? h->dscale : nullptr;
@@ -667,24 +691,48 @@ void pdhcg_default_settings(pdhcg_settings* s) {
   s->step_rule = 0;
 }
 
-int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, const double* b, const double* c,
-                 int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// pdhcg_create, and pdhcg_create_lowrank when lowrank is set (Qc is then P,
+// n x k, and d the diagonal, NULL for zero)
+int create_impl(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, const double* b, const double* c,
+                int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream, bool lowrank, const double* d) {
   const double t0 = now_s();
   if (!out) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle pointer");
   *out = nullptr;
   int rc;
   if ((rc = check_settings(s))) return rc;
   HostCsr Q, A;
-  if ((rc = fetch_csr(Qc, Q, "Q"))) return rc;
+  if ((rc = fetch_csr(Qc, Q, lowrank ? "P" : "Q"))) return rc;
   if ((rc = fetch_csr(Ac, A, "A"))) return rc;
-  if (Q.nrows != Q.ncols) return fail(PDHCG_ERR_INVALID_ARGUMENT, "Q must be square");
   if (A.ncols != Q.nrows) return fail(PDHCG_ERR_INVALID_ARGUMENT, "A must have as many columns as Q");
   if (Q.nrows == 0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "n must be >= 1");
-  if (!exactly_symmetric(Q)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "Q is not exactly symmetric");
+  if (!lowrank) {
+    if (Q.nrows != Q.ncols) return fail(PDHCG_ERR_INVALID_ARGUMENT, "Q must be square");
+    if (!exactly_symmetric(Q)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "Q is not exactly symmetric");
+  } else {
+    if (Q.ncols < 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "P must have k >= 1 columns");
+    if (s->ruiz_iters != 0 || s->pock_chambolle != 0)
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, "a low-rank Q takes no diagonal preconditioning");
+    if (s->step_rule != 0)
+      return fail(PDHCG_ERR_INVALID_ARGUMENT, "a low-rank Q takes the constant step rule (step_rule = 0)");
+  }
   if (!c || (A.nrows > 0 && !b)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null b or c");
+  std::vector<double> hd;
+  if (lowrank) {
+    hd.assign(Q.nrows, 0.0);
+    if (d && hipMemcpy(hd.data(), d, sizeof(double) * Q.nrows,
+                       vec_on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost) != hipSuccess)
+      return fail(PDHCG_ERR_HIP, "copy of d failed");
+    for (double v : hd)
+      if (!(v >= 0.0) || std::isinf(v)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "d must be finite and >= 0");
+  }
   HostCsr T = transpose(A);
 
   pdhcg_handle* h = new pdhcg_handle();
+  h->lowrank = lowrank ? 1 : 0;
   h->n = Q.nrows;
   h->m = A.nrows;
   h->nnzQ = (int64_t)Q.col.size();
@@ -709,6 +757,16 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
   if ((rc = upload_csr(h, Q, &h->q_rowptr, &h->q_col, &h->q_val))) return bail(rc);
   if ((rc = upload_csr(h, A, &h->a_rowptr, &h->a_col, &h->a_val))) return bail(rc);
   if ((rc = upload_csr(h, T, &h->t_rowptr, &h->t_col, &h->t_val))) return bail(rc);
+  if (lowrank) {  // P' beside P, d, and t = P' v (FP64 and an FP32 copy)
+    const HostCsr Lt = transpose(Q);
+    h->k = Q.ncols;
+    h->lrp_h = Lt.rowptr;
+    if ((rc = upload_csr(h, Lt, &h->lt_rowptr, &h->lt_col, &h->lt_val))) return bail(rc);
+    if ((rc = h->alloc(&h->lr_d, h->n))) return bail(rc);
+    if ((rc = h->alloc(&h->lr_pt, h->k))) return bail(rc);
+    if ((rc = h->alloc(&h->lr_pt32, h->k))) return bail(rc);
+    if ((rc = upload(h, h->lr_d, hd.data(), h->n))) return bail(rc);
+  }
   const int64_t n = h->n, m = h->m;
   double** nvecs[] = {&h->c, &h->x, &h->xa, &h->x_anc, &h->r, &h->p0, &h->p1, &h->q, &h->tmp_x0,
                       &h->r_alt, &h->u0, &h->u1, &h->s0, &h->s1, &h->x_prev};
@@ -751,6 +809,7 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
   if ((rc = estimate_norm(h))) return bail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(PDHCG_ERR_HIP, "stream sync failed"));
   h->setup_s = now_s() - t0;
+  if (s->verbose && lowrank) fprintf(stderr, "[pdhcg] low-rank Q = P P' + diag(d), k=%lld\n", (long long)h->k);
   if (s->verbose)
     fprintf(stderr, "[pdhcg] n=%lld m=%lld nnzQ=%lld nnzA=%lld nb=%d groups n1=%d q=%d m=%d ||A||=%.6g setup=%.3fs\n",
             (long long)n, (long long)m, (long long)h->nnzQ, (long long)h->nnzA, h->nb, h->pn1.group, h->pcg.group,
@@ -759,10 +818,27 @@ int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, c
   return 0;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pdhcg_create(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, const double* b, const double* c,
+                 int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream) {
+  return create_impl(out, Qc, Ac, b, c, vec_on_device, s, hip_stream, false, nullptr);
+}
+
+int pdhcg_create_lowrank(pdhcg_handle** out, const pdhcg_csr* P, const double* d, const pdhcg_csr* Ac,
+                         const double* b, const double* c, int32_t vec_on_device, const pdhcg_settings* s,
+                         void* hip_stream) {
+  return create_impl(out, P, Ac, b, c, vec_on_device, s, hip_stream, true, d);
+}
+
 int pdhcg_set_settings(pdhcg_handle* h, const pdhcg_settings* s) {
   if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
   int rc;
   if ((rc = check_settings(s))) return rc;
+  if (h->lowrank && s->step_rule != 0)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "a low-rank Q takes the constant step rule (step_rule = 0)");
   if (s->ruiz_iters != h->s.ruiz_iters || s->pock_chambolle != h->s.pock_chambolle)
     return fail(PDHCG_ERR_INVALID_ARGUMENT, "ruiz_iters and pock_chambolle are fixed at pdhcg_create");
   const bool replan = s->num_blocks != 0 && s->num_blocks != h->nb;
@@ -892,6 +968,8 @@ int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* 
   if (!h || !x || !y) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null argument");
   if (which < 0 || which > 2) return fail(PDHCG_ERR_INVALID_ARGUMENT, "which must be 0 (Q), 1 (A) or 2 (A')");
   if (precision != 0 && precision != 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "precision must be 0 or 1");
+  if (which == 0 && h->lowrank)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "a low-rank handle holds P, not Q: which must be 1 or 2");
   int rc;
   if (precision == 1 && (rc = ensure_mixed(h))) return rc;
   const DevMat M = h->mat(which);

@@ -169,6 +169,17 @@ struct SolveParams {
   // the executing workgroup's share of pn1, pcg, pm (filled in its LDS copy of
   // this block; unused in the copy in device memory)
   WgPart w_n1, w_cg, w_m;
+  // Q = P P' + diag(d) given by a sparse P (n x k) on a single-QP handle
+  // (lr_d null otherwise): the Q above is then P itself, Lt its transpose
+  // (k x n) with the row partition plr (w_lr: the workgroup's share), and
+  // every product with Q first forms t = P' v into lr_pt (FP64) and lr_pt32
+  // (its FP32 copy), then (Q v)_i = (P t)_i + d_i v_i
+  DevMat Lt;
+  Part plr;
+  WgPart w_lr;
+  const double* lr_d;
+  double* lr_pt;
+  float* lr_pt32;
   // LDS residency of Q (CG product rows) and A (dual product rows) in the
   // cooperative kernel: flags, value bytes (4: FP32 copies, 8: FP64), byte
   // offset of the A block in dynamic LDS

@@ -221,7 +221,9 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
   const int G = pt.group;
   double s[3] = {0.0, 0.0, 0.0};   // g.g, x.Qx, c.x
   double mx[3] = {0.0, 0.0, 0.0};  // |g|, |Qx|, |A'y|
-  GatherVec<double> gx{xv}, gy{yv};
+  // a low-rank Q gathers t = P' xv (formed by phase_lr_t) and adds d xv below
+  GatherVec<double> gx{P.lr_d ? P.lr_pt : xv}, gy{yv};
+  auto qxd = [&](int i, double qx, double xi) { return P.lr_d ? qx + gld(P.lr_d + i) * xi : qx; };
   struct Row {
     double c, x, q, d;
   };
@@ -254,7 +256,7 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
   for (int t = pt.t0; t < pt.t1; ++t)
     tile_rows2(dense ? nullptr : P.Q.rowptr, P.Q.col, P.Q.val, gx, P.m > 0 ? P.At.rowptr : nullptr, P.At.col,
                P.At.val, gy, pt.tile(t), G, pre,
-               [&](int i, double qx, double aty, const Row& rw) { epi(i, dense ? rw.q : qx, aty, rw); });
+               [&](int i, double qx, double aty, const Row& rw) { epi(i, dense ? rw.q : qxd(i, qx, rw.x), aty, rw); });
   for (int t = pt.l0; t < pt.l1; ++t) {
     const int i = pt.long_rows[t];
     double v[2] = {dense ? 0.0 : row_partial(P.Q.col, P.Q.val, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gx),
@@ -264,7 +266,7 @@ __device__ __attribute__((noinline)) void phase_nside(const SolveParams& P, cons
     block_reduce<2, 0>(v, dummy, lds);
     if (B.tid == 0) {
       const Row rw = pre(i);
-      epi(i, dense ? rw.q : v[0], v[1], rw);
+      epi(i, dense ? rw.q : qxd(i, v[0], rw.x), v[1], rw);
     }
   }
   block_reduce<3, 3>(s, mx, lds);
@@ -368,8 +370,33 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Bl
     return;
   }
   const WgPart& pt = P.w_cg;
-  GatherDir<T> gp{rg, ppg, beta, first};
   double s[1] = {0.0};
+  if (P.lr_d) {  // low-rank Q: (P t)_i with t = P' p gathered, then + (d_i + 1/tau) p_i
+    const T* tv;
+    if constexpr (sizeof(T) == 4) tv = (const T*)P.lr_pt32; else tv = (const T*)P.lr_pt;
+    const GatherVec<T> gt{tv};
+    auto epi = [&](int i, double pt_i) {
+      const double pi = first ? P.r[i] : P.r[i] + beta * pprev[i];
+      const double qi = pt_i + (gld(P.lr_d + i) + inv_tau) * pi;
+      pcur[i] = pi;
+      if (pcur32) pcur32[i] = (float)pi;
+      P.q[i] = qi;
+      s[0] += pi * qi;
+    };
+    for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.Q.rowptr, P.Q.col, qval, pt.tile(t), pt.group, gt, epi);
+    for (int t = pt.l0; t < pt.l1; ++t) {
+      const int i = pt.long_rows[t];
+      double v[1] = {row_partial(P.Q.col, qval, P.Q.rowptr[i], P.Q.rowptr[i + 1], B.tid, kBlock, gt)};
+      double dummy[1] = {0.0};
+      block_reduce<1, 0>(v, dummy, lds);
+      if (B.tid == 0) epi(i, v[0]);
+    }
+    double dummy[1] = {0.0};
+    block_reduce<1, 0>(s, dummy, lds);
+    if (B.tid == 0) P.part[S_PQ * B.nb + B.b] = s[0];
+    return;
+  }
+  GatherDir<T> gp{rg, ppg, beta, first};
   auto epi = [&](int i, double qp) {
     const double pi = first ? P.r[i] : P.r[i] + beta * pprev[i];
     const double qi = qp + pi * inv_tau;
@@ -389,6 +416,28 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Bl
   double dummy[1] = {0.0};
   block_reduce<1, 0>(s, dummy, lds);
   if (B.tid == 0) P.part[S_PQ * B.nb + B.b] = s[0];
+}
+
+// t = P' v for a low-rank Q = P P' + diag(d): the rows of P' in the
+// workgroup's share of plr, v gathered through g (x or the average for the
+// n-side pass, the direction p = r + beta p_prev formed at gather time for a
+// CG product); t goes to lr_pt and its FP32 copy to lr_pt32.  No partials.
+template <typename V, typename G>
+__device__ __attribute__((noinline)) void phase_lr_t(const SolveParams& P, Block B, const V* lval, const G g,
+                                                     double* lds) {
+  const WgPart& pt = P.w_lr;
+  auto epi = [&](int c, double t) {
+    P.lr_pt[c] = t;
+    P.lr_pt32[c] = (float)t;
+  };
+  for (int t = pt.t0; t < pt.t1; ++t) tile_rows(P.Lt.rowptr, P.Lt.col, lval, pt.tile(t), pt.group, g, epi);
+  for (int t = pt.l0; t < pt.l1; ++t) {
+    const int c = pt.long_rows[t];
+    double v[1] = {row_partial(P.Lt.col, lval, P.Lt.rowptr[c], P.Lt.rowptr[c + 1], B.tid, kBlock, g)};
+    double dummy[1] = {0.0};
+    block_reduce<1, 0>(v, dummy, lds);
+    if (B.tid == 0) epi(c, v[0]);
+  }
 }
 
 // CG update on the owned rows: x += alpha p, r -= alpha q; partial r.r.
@@ -1362,6 +1411,19 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
       if (!(ok = e.ok != 0)) break;
       continue;
     }
+    if (!DENSE && P.lr_d && (op == OP_NSIDE || op == OP_EVAL || op == OP_LIMIT_EVAL || op == OP_CG_SPMV)) {
+      // low-rank Q: t = P' v first (one more grid barrier per product)
+      if (op == OP_CG_SPMV) {
+        const int cur = C.cur;
+        if (mixed)
+          phase_lr_t(P, B, P.Lt.val32, GatherDir<float>{P.r32, cur ? P.p32_0 : P.p32_1, C.beta, C.first}, lds);
+        else
+          phase_lr_t(P, B, P.Lt.val, GatherDir<double>{P.r, cur ? P.p0 : P.p1, C.beta, C.first}, lds);
+      } else {
+        phase_lr_t(P, B, P.Lt.val, GatherVec<double>{op == OP_NSIDE ? P.x : P.xa}, lds);
+      }
+      if (!(ok = gs.sync())) break;
+    }
     switch (op) {
       case OP_AX_START:
       case OP_AX_ZERO:
@@ -1547,6 +1609,7 @@ __device__ void load_params(SolveParams& Ps, const SolveParams* Pg, int b) {
   fill_wg_part(Ps.w_n1, Ps.pn1, b);
   fill_wg_part(Ps.w_cg, Ps.pcg, b);
   fill_wg_part(Ps.w_m, Ps.pm, b);
+  if (Ps.lr_d) fill_wg_part(Ps.w_lr, Ps.plr, b);
   __syncthreads();
 }
 

@@ -350,6 +350,35 @@ def mpc_qp(instance=0, fam: MPCFamily | None = None) -> QP:
     return QP(fam.Q, fam.A, fam.b_for(x_init), fam.c.copy(), name=f"mpc_qp(inst={instance})")
 
 
+def lowrank_qp(n=100_000, m=50_000, k=5_000, p_density=1e-3, a_density=1e-4, family=7, instance=0,
+               explicit=True):
+    """Random QP with Q in low-rank form (the setting of Tables 3 and 4):
+    Q = P P' + diag(d) with P (n x k) Bernoulli(p_density) N(0, 1) entries
+    (each row of P at least one entry, so that no row of P P' is empty) and
+    d ~ U[0.01, 0.1] (strictly convex); A (m x n) Bernoulli(a_density)
+    N(0, 1); c ~ N(0, 1); b = A x0 + U[0, 1] with x0 ~ N(0, 1).  Returns
+    (qp, P, d); qp.Q is the explicit P P' + diag(d) when explicit is set
+    (else an empty n x n placeholder: the low-rank solve does not read it)."""
+    rng = _rng(family, instance)
+    P = _sparse_gaussian(rng, n, k, p_density)
+    empty = np.nonzero(np.diff(P.indptr) == 0)[0]
+    fill = sp.csr_matrix((rng.standard_normal(len(empty)), (empty, rng.integers(0, k, size=len(empty)))),
+                         shape=(n, k))
+    P = sp.csr_matrix(P + fill)
+    P.sort_indices()
+    d = rng.uniform(0.01, 0.1, n)
+    A = _sparse_gaussian(rng, m, n, a_density)
+    c = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    b = A @ x0 + rng.uniform(0.0, 1.0, m)
+    if explicit:
+        Q = _symmetrize(P @ P.T + sp.diags(d, format="csr"))
+    else:
+        Q = sp.csr_matrix((n, n))
+    qp = QP(CSR.from_scipy(Q), CSR.from_scipy(A), b, c, name=f"lowrank_qp(n={n},m={m},k={k},seed={family}/{instance})")
+    return qp, CSR.from_scipy(P), d
+
+
 def manufactured(n=1000, m=500, q_density=0.01, a_density=0.01, active_frac=0.3, family=11,
                  instance=0, r_rows=None) -> QP:
     """A QP with a known optimum: draw Q, A as in ``random_qp``, pick x* ~ N(0,1),

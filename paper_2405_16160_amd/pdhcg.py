@@ -73,9 +73,9 @@ class pdhcg_result(C.Structure):
 
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
-EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_set_settings", "pdhcg_set_b", "pdhcg_solve",
-           "pdhcg_solve_batch", "pdhcg_solve_batch_noalloc", "pdhcg_solve_batch_lowrank", "pdhcg_solve_multi_rhs",
-           "pdhcg_spmv", "pdhcg_get_scaling",
+EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_create_lowrank", "pdhcg_set_settings", "pdhcg_set_b",
+           "pdhcg_solve", "pdhcg_solve_batch", "pdhcg_solve_batch_noalloc", "pdhcg_solve_batch_lowrank",
+           "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_get_scaling",
            "pdhcg_autotune", "pdhcg_plan_info", "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error",
            "pdhcg_batch_create", "pdhcg_batch_layout", "pdhcg_batch_solve", "pdhcg_batch_get_scaling",
            "pdhcg_batch_destroy"]
@@ -108,6 +108,8 @@ def lib():
         L.pdhcg_default_settings.restype = None
         L.pdhcg_create.argtypes = [C.POINTER(P), C.POINTER(pdhcg_csr), C.POINTER(pdhcg_csr), P, P, C.c_int32,
                                    C.POINTER(pdhcg_settings), P]
+        L.pdhcg_create_lowrank.argtypes = [C.POINTER(P), C.POINTER(pdhcg_csr), P, C.POINTER(pdhcg_csr), P, P,
+                                           C.c_int32, C.POINTER(pdhcg_settings), P]
         L.pdhcg_set_settings.argtypes = [P, C.POINTER(pdhcg_settings)]
         L.pdhcg_set_b.argtypes = [P, P, C.c_int32]
         L.pdhcg_solve.argtypes = [P, P, P, P, P, C.c_int32, C.POINTER(pdhcg_result)]
@@ -197,12 +199,14 @@ class Solver:
 
     ``qp`` is an ``instances.QP`` (host CSR, FP64).  The matrices and vectors
     are first moved to torch device tensors and handed to pdhcg_create as
-    device pointers."""
+    device pointers.  With ``lowrank=(P, d)`` (P an instances.CSR n x k, d an
+    n-vector or None) Q = P P' + diag(d) is given in low-rank form through
+    pdhcg_create_lowrank, and ``qp.Q`` is not read."""
 
-    def __init__(self, qp, settings: Settings | None = None):
+    def __init__(self, qp, settings: Settings | None = None, lowrank=None):
         import torch
         self.dev = torch.device("cuda", torch.cuda.current_device())
-        self.n, self.m = qp.Q.nrows, qp.A.nrows
+        self.n, self.m = qp.A.ncols, qp.A.nrows
         self.settings = settings or Settings()
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.dev)
         keep = []
@@ -213,13 +217,22 @@ class Solver:
             return pdhcg_csr(M.nrows, M.ncols, int(M.rowptr[-1]), rp.data_ptr(), col.data_ptr() if col.numel() else None,
                              val.data_ptr() if val.numel() else None, 1)
 
-        Qc, Ac = csr(qp.Q), csr(qp.A)
+        Ac = csr(qp.A)
         b = t(qp.b, torch.float64) if self.m else torch.zeros(1, dtype=torch.float64, device=self.dev)
         c = t(qp.c, torch.float64)
         h = C.c_void_p()
-        torch.cuda.synchronize()
-        _check(lib().pdhcg_create(C.byref(h), C.byref(Qc), C.byref(Ac), b.data_ptr(), c.data_ptr(), 1,
-                                  C.byref(self.settings.c()), _stream_ptr()))
+        if lowrank is not None:
+            Pc = csr(lowrank[0])
+            d = None if lowrank[1] is None else t(lowrank[1], torch.float64)
+            torch.cuda.synchronize()
+            _check(lib().pdhcg_create_lowrank(C.byref(h), C.byref(Pc), None if d is None else d.data_ptr(),
+                                              C.byref(Ac), b.data_ptr(), c.data_ptr(), 1,
+                                              C.byref(self.settings.c()), _stream_ptr()))
+        else:
+            Qc = csr(qp.Q)
+            torch.cuda.synchronize()
+            _check(lib().pdhcg_create(C.byref(h), C.byref(Qc), C.byref(Ac), b.data_ptr(), c.data_ptr(), 1,
+                                      C.byref(self.settings.c()), _stream_ptr()))
         self.h = h
         _live.add(self)
         del keep
