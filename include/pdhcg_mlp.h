@@ -15,8 +15,10 @@
  * Conventions: return 0 on success or a negative PDHCG_ERR_* code (see
  * pdhcg.h); pdhcg_last_error() gives the message.  X, T and Y are FP32
  * row-major device arrays (batch rows).  All work is issued on the stream
- * given at creation, and each call returns after that stream has finished.
- * The handle owns its device buffers; it is not thread-safe.
+ * given at creation; each call returns after that stream has finished,
+ * except pdhcg_mlp_train_step, which only queues its work (its arrays must
+ * stay valid until the stream reaches it).  The handle owns its device
+ * buffers; it is not thread-safe.
  */
 #ifndef PDHCG_MLP_H
 #define PDHCG_MLP_H
@@ -52,6 +54,21 @@ int pdhcg_mlp_loss_grad(pdhcg_mlp* h, const float* X, const float* T, int32_t ba
 
 /* One Adam step with the gradient of the last pdhcg_mlp_loss_grad call. */
 int pdhcg_mlp_adam_step(pdhcg_mlp* h, float lr, float beta1, float beta2, float eps);
+
+/* One training step queued on the network's stream without waiting: the
+ * loss and gradient of pdhcg_mlp_loss_grad on the rows rows[0..batch) of X
+ * (n_in per row) and T (n_out per row) -- rows is an int32 device array, or
+ * NULL for the first batch rows -- then one Adam step.  The minibatch is
+ * gathered by the library's own kernels.  The step's loss is added to the
+ * running sum that pdhcg_mlp_take_loss returns. */
+int pdhcg_mlp_train_step(pdhcg_mlp* h, const float* X, const float* T, const int32_t* rows, int32_t batch, float lr,
+                         float beta1, float beta2, float eps);
+
+/* Wait for the stream; *sum receives the sum of the losses of the
+ * pdhcg_mlp_train_step and pdhcg_mlp_loss_grad calls since the last call (or
+ * since creation) and *steps their number; both are then reset.  Either
+ * pointer may be NULL. */
+int pdhcg_mlp_take_loss(pdhcg_mlp* h, double* sum, int64_t* steps);
 
 void pdhcg_mlp_destroy(pdhcg_mlp* h);
 

@@ -16,7 +16,6 @@
 namespace pdhcg {
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float -> bfloat16, round to nearest, ties to even (NaN kept quiet)
@@ -30,14 +29,65 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
 constexpr int GB = 64;   // block tile (rows and columns)
-constexpr int GK = 32;   // k per LDS stage
-constexpr int GP = 8;    // LDS row padding (bf16 elements)
+constexpr int GK = 32;   // k per LDS stage (one K = 32 MFMA step)
+constexpr int GP = 8;    // LDS row padding (bf16 elements; rows stay 16-byte aligned)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Stage an R x C tile of a strided bf16 matrix M(r, c) = M[r*sr + c*sc]
+// (rows r0.., columns c0.., bounds nr, nc; zeros outside) into T[R][C + GP],
+// 8 elements per thread.  Along a unit stride the 8 elements are one 16-byte
+// load when they are in range and aligned; otherwise they are loaded one by
+// one.  Unit stride along c: the 8 land in one row (one 16-byte LDS store);
+// along r: in 8 rows of one column.
+template <int R, int C>
+__device__ __forceinline__ void stage_bf16(uint16_t (*T)[C + GP], const uint16_t* __restrict__ M, int64_t sr,
+                                           int64_t sc, int r0, int c0, int nr, int nc) {
+  static_assert(R * C == 8 * 256, "one 8-element vector per thread");
+  const int tid = threadIdx.x;
+  if (sc == 1) {  // contiguous along c: thread -> (row, 8 columns)
+    const int r = tid / (C / 8), c = (tid % (C / 8)) * 8;
+    const int gr = r0 + r, gc = c0 + c;
+    const int64_t off = (int64_t)gr * sr + gc;
+    u16x8 v;
+    if (gr < nr && gc + 8 <= nc && (off & 7) == 0) {
+      v = *reinterpret_cast<const u16x8*>(M + off);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (gr < nr && gc + e < nc) ? M[off + e] : (uint16_t)0;
+    }
+    *reinterpret_cast<u16x8*>(&T[r][c]) = v;
+  } else if (sr == 1) {  // contiguous along r: thread -> (8 rows, column)
+    const int c = tid / (R / 8), r = (tid % (R / 8)) * 8;
+    const int gr = r0 + r, gc = c0 + c;
+    const int64_t off = gr + (int64_t)gc * sc;
+    u16x8 v;
+    if (gc < nc && gr + 8 <= nr && (off & 7) == 0) {
+      v = *reinterpret_cast<const u16x8*>(M + off);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (gc < nc && gr + e < nr) ? M[off + e] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) T[r + e][c] = v[e];
+  } else {  // general strides
+    const int r = tid / (C / 8), c = (tid % (C / 8)) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int gr = r0 + r, gc = c0 + c + e;
+      T[r][c + e] = (gr < nr && gc < nc) ? M[(int64_t)gr * sr + (int64_t)gc * sc] : (uint16_t)0;
+    }
+  }
+}
 
 // C = A B on bfloat16 operands with FP32 accumulation.  A(m,k) = A[m*sam +
 // k*sak], B(k,n) = B[k*sbk + n*sbn], so transposed operands need no copy.
 // Each of the four waves owns a 32 x 32 quarter of the 64 x 64 block tile as
-// 2 x 2 MFMA 16x16x16 tiles.  Epilogue: + bias[n]; ReLU; zero where
-// mask(m,n) <= 0 (ReLU derivative); FP32 and/or bfloat16 output.
+// 2 x 2 tiles of the gfx950 MFMA 16x16x32 (eight bfloat16 per lane and
+// operand); a 32-deep k stage of A and of B (kept n-major) sits in LDS.
+// Epilogue: + bias[n]; ReLU; zero where mask(m,n) <= 0 (ReLU derivative);
+// FP32 and/or bfloat16 output.
 __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int64_t sam,
                                                  int64_t sak, const uint16_t* __restrict__ Bm, int64_t sbk,
                                                  int64_t sbn, const float* __restrict__ bias, int relu,
@@ -54,33 +104,20 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const uint
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += GK) {
-    for (int e = tid; e < GB * GK; e += 256) {
-      const int r = sak == 1 ? e / GK : e % GB;
-      const int c = sak == 1 ? e % GK : e / GB;
-      const int gm = m0 + r, gk = k0 + c;
-      As[r][c] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : (uint16_t)0;
-    }
-    for (int e = tid; e < GB * GK; e += 256) {
-      const int nn = sbn == 1 ? e % GB : e / GK;
-      const int kk = sbn == 1 ? e / GB : e % GK;
-      const int gn = n0 + nn, gk = k0 + kk;
-      Bt[nn][kk] = (gn < N && gk < K) ? Bm[gk * sbk + gn * sbn] : (uint16_t)0;
-    }
+    stage_bf16<GB, GK>(As, A, sam, sak, m0, k0, M, K);    // As[m][k]
+    stage_bf16<GB, GK>(Bt, Bm, sbn, sbk, n0, k0, N, K);   // Bt[n][k] = B(k, n)
     __syncthreads();
+    bf16x8 a[2], b[2];
 #pragma unroll
-    for (int kk = 0; kk < GK; kk += 16) {
-      bf16x4 a[2], b[2];
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const bf16x4*>(&As[wm * 32 + i * 16 + (lane & 15)][kk + 4 * (lane >> 4)]);
+    for (int j = 0; j < 2; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&Bt[wn * 32 + j * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const bf16x4*>(&Bt[wn * 32 + j * 16 + (lane & 15)][kk + 4 * (lane >> 4)]);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
@@ -107,13 +144,30 @@ __global__ void f32_to_bf16(const float* __restrict__ in, uint16_t* __restrict__
     out[i] = to_bf16(in[i]);
 }
 
-// G = 2 (O - T) / count (FP32 and bfloat16 copies); per-block partial sums of (O - T)^2
-__global__ void mse_grad(const float* __restrict__ O, const float* __restrict__ T, int64_t n, float scale,
-                         float* __restrict__ G, uint16_t* __restrict__ Gb, double* __restrict__ partial) {
+// out (batch x cols, bfloat16) = rows rows[0..batch) of in (FP32, cols per row)
+__global__ void rows_to_bf16(const float* __restrict__ in, const int32_t* __restrict__ rows, int batch, int cols,
+                             uint16_t* __restrict__ out) {
+  const int64_t n = (int64_t)batch * cols;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / cols, c = i - r * cols;
+    out[i] = to_bf16(in[(int64_t)rows[r] * cols + c]);
+  }
+}
+
+// G = 2 (O - T) / count (FP32 and bfloat16 copies); per-block partial sums of
+// (O - T)^2.  Row r of T is T's row rows[r] when rows is given (cols per row).
+__global__ void mse_grad(const float* __restrict__ O, const float* __restrict__ T, const int32_t* __restrict__ rows,
+                         int cols, int64_t n, float scale, float* __restrict__ G, uint16_t* __restrict__ Gb,
+                         double* __restrict__ partial) {
   __shared__ double red[256];
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float d = O[i] - T[i];
+    int64_t ti = i;
+    if (rows) {
+      const int64_t r = i / cols;
+      ti = (int64_t)rows[r] * cols + (i - r * cols);
+    }
+    const float d = O[i] - T[ti];
     s += (double)d * (double)d;
     const float g = 2.0f * d * scale;
     G[i] = g;
@@ -128,11 +182,16 @@ __global__ void mse_grad(const float* __restrict__ O, const float* __restrict__ 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void sum_partials(const double* __restrict__ partial, int n, double scale, float* __restrict__ out) {
+// the loss of a step, and its running sum over the training steps (acc[0])
+// with their count (acc[1])
+__global__ void sum_partials(const double* __restrict__ partial, int n, double scale, float* __restrict__ out,
+                             double* __restrict__ acc) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double s = 0.0;
     for (int i = 0; i < n; ++i) s += partial[i];
     *out = (float)(s * scale);
+    acc[0] += s * scale;
+    acc[1] += 1.0;
   }
 }
 
@@ -184,6 +243,7 @@ struct pdhcg_mlp {
   uint16_t *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *gob = nullptr, *d2b = nullptr, *d1b = nullptr;
   float *out = nullptr, *go = nullptr, *d2 = nullptr, *d1 = nullptr, *loss = nullptr;
   double* partial = nullptr;
+  double* loss_acc = nullptr;  // [sum of step losses, steps] since the last pdhcg_mlp_take_loss
   std::vector<void*> allocs;
   ~pdhcg_mlp() {
     for (void* p : allocs) (void)hipFree(p);
@@ -222,12 +282,17 @@ int check_batch(const pdhcg_mlp* h, int32_t batch) {
   return 0;
 }
 
-// forward pass of `batch` rows of X (device FP32) into h->out; keeps the
-// bfloat16 activations for the backward pass
-int run_forward(pdhcg_mlp* h, const float* X, int batch) {
+// forward pass of `batch` rows of X (device FP32: the first batch rows, or
+// rows[0..batch) when rows is given) into h->out; keeps the bfloat16
+// activations for the backward pass
+int run_forward(pdhcg_mlp* h, const float* X, const int32_t* rows, int batch) {
   const int a = h->n_in, d = h->n_hid, o = h->n_out;
-  hipLaunchKernelGGL(f32_to_bf16, dim3(grid_for((int64_t)batch * a)), dim3(256), 0, h->stream, X, h->xb,
-                     (int64_t)batch * a);
+  if (rows)
+    hipLaunchKernelGGL(rows_to_bf16, dim3(grid_for((int64_t)batch * a)), dim3(256), 0, h->stream, X, rows, batch, a,
+                       h->xb);
+  else
+    hipLaunchKernelGGL(f32_to_bf16, dim3(grid_for((int64_t)batch * a)), dim3(256), 0, h->stream, X, h->xb,
+                       (int64_t)batch * a);
   MLPX(hipGetLastError());
   MLPX(gemm(h->stream, batch, d, a, h->xb, a, 1, h->wb + h->off[0], d, 1, h->w + h->off[1], 1, nullptr, nullptr, h->h1,
             d));
@@ -235,6 +300,48 @@ int run_forward(pdhcg_mlp* h, const float* X, int batch) {
             d));
   MLPX(gemm(h->stream, batch, o, d, h->h2, d, 1, h->wb + h->off[4], o, 1, h->w + h->off[5], 0, nullptr, h->out,
             nullptr, o));
+  return 0;
+}
+
+// forward pass, MSE gradient and backward pass of one batch, queued on the
+// network's stream (no wait); the gradient stays in h->g, the loss in h->loss
+int queue_loss_grad(pdhcg_mlp* h, const float* X, const float* T, const int32_t* rows, int batch) {
+  int rc;
+  if ((rc = run_forward(h, X, rows, batch))) return rc;
+  const int a = h->n_in, d = h->n_hid, o = h->n_out;
+  const int64_t no = (int64_t)batch * o;
+  const int pg = 512;
+  hipLaunchKernelGGL(mse_grad, dim3(pg), dim3(256), 0, h->stream, h->out, T, rows, o, no, (float)(1.0 / (double)no),
+                     h->go, h->gob, h->partial);
+  MLPX(hipGetLastError());
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, h->stream, h->partial, pg, 1.0 / (double)no, h->loss,
+                     h->loss_acc);
+  MLPX(hipGetLastError());
+  float* g = h->g;
+  // layer 3: dW3 = H2' G, db3 = colsum G, dH2 = (G W3') masked by H2 > 0
+  MLPX(gemm(h->stream, d, o, batch, h->h2, 1, d, h->gob, o, 1, nullptr, 0, nullptr, g + h->off[4], nullptr, o));
+  hipLaunchKernelGGL(colsum, dim3((o + 255) / 256), dim3(256), 0, h->stream, h->go, batch, o, g + h->off[5]);
+  MLPX(hipGetLastError());
+  MLPX(gemm(h->stream, batch, d, o, h->gob, o, 1, h->wb + h->off[4], 1, o, nullptr, 0, h->h2, h->d2, h->d2b, d));
+  // layer 2
+  MLPX(gemm(h->stream, d, d, batch, h->h1, 1, d, h->d2b, d, 1, nullptr, 0, nullptr, g + h->off[2], nullptr, d));
+  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d2, batch, d, g + h->off[3]);
+  MLPX(hipGetLastError());
+  MLPX(gemm(h->stream, batch, d, d, h->d2b, d, 1, h->wb + h->off[2], 1, d, nullptr, 0, h->h1, h->d1, h->d1b, d));
+  // layer 1
+  MLPX(gemm(h->stream, a, d, batch, h->xb, 1, a, h->d1b, d, 1, nullptr, 0, nullptr, g + h->off[0], nullptr, d));
+  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d1, batch, d, g + h->off[1]);
+  MLPX(hipGetLastError());
+  return 0;
+}
+
+int queue_adam(pdhcg_mlp* h, float lr, float beta1, float beta2, float eps) {
+  h->t += 1;
+  const float c1 = (float)(1.0 - pow((double)beta1, (double)h->t));
+  const float c2 = (float)(1.0 - pow((double)beta2, (double)h->t));
+  hipLaunchKernelGGL(adam, dim3(grid_for(h->np)), dim3(256), 0, h->stream, h->w, h->g, h->m, h->v, h->np, lr, beta1,
+                     beta2, eps, c1, c2, h->wb);
+  MLPX(hipGetLastError());
   return 0;
 }
 
@@ -267,13 +374,14 @@ int pdhcg_mlp_create(pdhcg_mlp** out, int32_t n_in, int32_t n_hid, int32_t n_out
             h->alloc(&h->h2, B * n_hid) && h->alloc(&h->gob, B * n_out) && h->alloc(&h->d2b, B * n_hid) &&
             h->alloc(&h->d1b, B * n_hid) && h->alloc(&h->out, B * n_out) && h->alloc(&h->go, B * n_out) &&
             h->alloc(&h->d2, B * n_hid) && h->alloc(&h->d1, B * n_hid) && h->alloc(&h->loss, 1) &&
-            h->alloc(&h->partial, 2048);
+            h->alloc(&h->partial, 2048) && h->alloc(&h->loss_acc, 2);
   if (!ok) {
     delete h;
     return set_error(PDHCG_ERR_OUT_OF_MEMORY, "hipMalloc failed for the network");
   }
   if (hipMemsetAsync(h->w, 0, sizeof(float) * acc, h->stream) != hipSuccess ||
       hipMemsetAsync(h->wb, 0, sizeof(uint16_t) * acc, h->stream) != hipSuccess ||
+      hipMemsetAsync(h->loss_acc, 0, sizeof(double) * 2, h->stream) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess) {
     delete h;
     return set_error(PDHCG_ERR_HIP, "initialising the network failed");
@@ -307,7 +415,7 @@ int pdhcg_mlp_forward(pdhcg_mlp* h, const float* X, int32_t batch, float* Y) {
   int rc;
   if ((rc = check_batch(h, batch))) return rc;
   if (!X || !Y) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null X or Y");
-  if ((rc = run_forward(h, X, batch))) return rc;
+  if ((rc = run_forward(h, X, nullptr, batch))) return rc;
   MLPX(hipMemcpyAsync(Y, h->out, sizeof(float) * (int64_t)batch * h->n_out, hipMemcpyDeviceToDevice, h->stream));
   MLPX(hipStreamSynchronize(h->stream));
   return 0;
@@ -317,44 +425,37 @@ int pdhcg_mlp_loss_grad(pdhcg_mlp* h, const float* X, const float* T, int32_t ba
   int rc;
   if ((rc = check_batch(h, batch))) return rc;
   if (!X || !T) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null X or T");
-  if ((rc = run_forward(h, X, batch))) return rc;
-  const int a = h->n_in, d = h->n_hid, o = h->n_out;
-  const int64_t no = (int64_t)batch * o;
-  const int pg = 512;
-  hipLaunchKernelGGL(mse_grad, dim3(pg), dim3(256), 0, h->stream, h->out, T, no, (float)(1.0 / (double)no), h->go,
-                     h->gob, h->partial);
-  MLPX(hipGetLastError());
-  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, h->stream, h->partial, pg, 1.0 / (double)no, h->loss);
-  MLPX(hipGetLastError());
-  float* g = h->g;
-  // layer 3: dW3 = H2' G, db3 = colsum G, dH2 = (G W3') masked by H2 > 0
-  MLPX(gemm(h->stream, d, o, batch, h->h2, 1, d, h->gob, o, 1, nullptr, 0, nullptr, g + h->off[4], nullptr, o));
-  hipLaunchKernelGGL(colsum, dim3((o + 255) / 256), dim3(256), 0, h->stream, h->go, batch, o, g + h->off[5]);
-  MLPX(hipGetLastError());
-  MLPX(gemm(h->stream, batch, d, o, h->gob, o, 1, h->wb + h->off[4], 1, o, nullptr, 0, h->h2, h->d2, h->d2b, d));
-  // layer 2
-  MLPX(gemm(h->stream, d, d, batch, h->h1, 1, d, h->d2b, d, 1, nullptr, 0, nullptr, g + h->off[2], nullptr, d));
-  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d2, batch, d, g + h->off[3]);
-  MLPX(hipGetLastError());
-  MLPX(gemm(h->stream, batch, d, d, h->d2b, d, 1, h->wb + h->off[2], 1, d, nullptr, 0, h->h1, h->d1, h->d1b, d));
-  // layer 1
-  MLPX(gemm(h->stream, a, d, batch, h->xb, 1, a, h->d1b, d, 1, nullptr, 0, nullptr, g + h->off[0], nullptr, d));
-  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d1, batch, d, g + h->off[1]);
-  MLPX(hipGetLastError());
+  if ((rc = queue_loss_grad(h, X, T, nullptr, batch))) return rc;
   if (loss) MLPX(hipMemcpyAsync(loss, h->loss, sizeof(float), hipMemcpyDeviceToHost, h->stream));
-  if (grads) MLPX(hipMemcpyAsync(grads, g, sizeof(float) * h->np, hipMemcpyDeviceToHost, h->stream));
+  if (grads) MLPX(hipMemcpyAsync(grads, h->g, sizeof(float) * h->np, hipMemcpyDeviceToHost, h->stream));
   MLPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+int pdhcg_mlp_train_step(pdhcg_mlp* h, const float* X, const float* T, const int32_t* rows, int32_t batch, float lr,
+                         float beta1, float beta2, float eps) {
+  int rc;
+  if ((rc = check_batch(h, batch))) return rc;
+  if (!X || !T) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null X or T");
+  if ((rc = queue_loss_grad(h, X, T, rows, batch))) return rc;
+  return queue_adam(h, lr, beta1, beta2, eps);
+}
+
+int pdhcg_mlp_take_loss(pdhcg_mlp* h, double* sum, int64_t* steps) {
+  if (!h) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null network handle");
+  double acc[2] = {0.0, 0.0};
+  MLPX(hipMemcpyAsync(acc, h->loss_acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+  MLPX(hipMemsetAsync(h->loss_acc, 0, sizeof(double) * 2, h->stream));
+  MLPX(hipStreamSynchronize(h->stream));
+  if (sum) *sum = acc[0];
+  if (steps) *steps = (int64_t)acc[1];
   return 0;
 }
 
 int pdhcg_mlp_adam_step(pdhcg_mlp* h, float lr, float beta1, float beta2, float eps) {
   if (!h) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null network handle");
-  h->t += 1;
-  const float c1 = (float)(1.0 - pow((double)beta1, (double)h->t));
-  const float c2 = (float)(1.0 - pow((double)beta2, (double)h->t));
-  hipLaunchKernelGGL(adam, dim3(grid_for(h->np)), dim3(256), 0, h->stream, h->w, h->g, h->m, h->v, h->np, lr, beta1,
-                     beta2, eps, c1, c2, h->wb);
-  MLPX(hipGetLastError());
+  int rc;
+  if ((rc = queue_adam(h, lr, beta1, beta2, eps))) return rc;
   MLPX(hipStreamSynchronize(h->stream));
   return 0;
 }

@@ -22,6 +22,8 @@ def _lib():
         L.pdhcg_mlp_forward.argtypes = [P, P, C.c_int32, P]
         L.pdhcg_mlp_loss_grad.argtypes = [P, P, P, C.c_int32, P, P]
         L.pdhcg_mlp_adam_step.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float]
+        L.pdhcg_mlp_train_step.argtypes = [P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]
+        L.pdhcg_mlp_take_loss.argtypes = [P, P, P]
         L.pdhcg_mlp_destroy.argtypes = [P]
         L.pdhcg_mlp_destroy.restype = None
         L._mlp_bound = True
@@ -29,7 +31,8 @@ def _lib():
 
 
 MLP_EXPORTS = ["pdhcg_mlp_create", "pdhcg_mlp_num_params", "pdhcg_mlp_set_params", "pdhcg_mlp_get_params",
-               "pdhcg_mlp_forward", "pdhcg_mlp_loss_grad", "pdhcg_mlp_adam_step", "pdhcg_mlp_destroy"]
+               "pdhcg_mlp_forward", "pdhcg_mlp_loss_grad", "pdhcg_mlp_adam_step", "pdhcg_mlp_train_step",
+               "pdhcg_mlp_take_loss", "pdhcg_mlp_destroy"]
 
 
 def init_params(n_in, n_hid, n_out, seed=0):
@@ -100,6 +103,18 @@ class Network:
         loss, _ = self.loss_grad(X, T)
         self.adam_step(lr)
         return loss
+
+    def train_rows(self, X, T, rows, batch, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Queue one training step on rows[0:batch] (an int32 device tensor or
+        a view into one) of the full data tensors X and T; no wait."""
+        _p._check(_lib().pdhcg_mlp_train_step(self.h, X.data_ptr(), T.data_ptr(), rows.data_ptr(), batch, lr,
+                                              beta1, beta2, eps))
+
+    def take_loss(self):
+        """(sum of the step losses since the last call, number of steps)."""
+        s, k = C.c_double(), C.c_int64()
+        _p._check(_lib().pdhcg_mlp_take_loss(self.h, C.byref(s), C.byref(k)))
+        return s.value, k.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -171,14 +171,16 @@ def train(theta, X, Y, code: DualCode, hidden=512, epochs=300, batch=256, lr=1e-
     rng = np.random.default_rng(seed)
     N = len(theta)
     losses = []
+    net.take_loss()   # (clear the running sum)
     for ep in range(epochs):
-        perm = torch.tensor(rng.permutation(N), device="cuda")
-        tot, cnt = 0.0, 0
+        # the epoch's row order, drawn on the host; the library gathers each
+        # minibatch from the full device arrays and the steps queue without
+        # waiting; the loss is read once per epoch
+        perm = torch.tensor(rng.permutation(N).astype(np.int32), device="cuda")
         step_lr = lr * 0.5 * (1 + np.cos(np.pi * ep / epochs))   # cosine decay
         for a in range(0, N - batch + 1, batch):
-            idx = perm[a:a + batch]
-            tot += net.train_step(Xt[idx], Zt[idx], lr=float(step_lr))
-            cnt += 1
+            net.train_rows(Xt, Zt, perm[a:a + batch], batch, lr=float(step_lr))
+        tot, cnt = net.take_loss()
         losses.append(tot / max(cnt, 1))
         if log:
             log(f"epoch {ep}: loss {losses[-1]:.4e}")

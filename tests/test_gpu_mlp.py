@@ -83,3 +83,34 @@ def test_adam_steps_follow_reference_and_reduce_loss():
     say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.2 * losses[0]
     net.close()
+
+
+def test_queued_training_steps_equal_the_synchronous_ones():
+    """pdhcg_mlp_train_step on rows picked by an index array (gathered by the
+    library) takes exactly the steps of pdhcg_mlp_loss_grad + adam_step on the
+    same rows gathered beforehand, and pdhcg_mlp_take_loss returns the sum of
+    the step losses; shapes with no 8-aligned stride exercise the element-wise
+    staging of the matrix products."""
+    for dims, N, B in (((20, 512, 700), 600, 128), ((7, 33, 5), 40, 9)):
+        n_in, n_hid, n_out = dims
+        say(f"[mlp] queued steps dims={dims} rows={N} batch={B}")
+        rng = np.random.default_rng(11)
+        params = mlp.init_params(n_in, n_hid, n_out, seed=4)
+        Xt = torch.tensor(rng.standard_normal((N, n_in)), dtype=torch.float32, device="cuda")
+        Tt = torch.tensor(rng.standard_normal((N, n_out)), dtype=torch.float32, device="cuda")
+        a = mlp.Network(n_in, n_hid, n_out, max_batch=B, params=params)
+        b = mlp.Network(n_in, n_hid, n_out, max_batch=B, params=params)
+        b.take_loss()
+        losses = []
+        for step in range(4):
+            idx = torch.tensor(rng.permutation(N)[:B].astype(np.int32), device="cuda")
+            losses.append(a.train_step(Xt[idx.long()].contiguous(), Tt[idx.long()].contiguous(), lr=1e-3))
+            b.train_rows(Xt, Tt, idx, B, lr=1e-3)
+            torch.cuda.synchronize()
+        tot, cnt = b.take_loss()
+        assert cnt == 4
+        assert tot == pytest.approx(sum(losses), rel=1e-6)
+        for pa, pb in zip(a.get_params(), b.get_params()):
+            assert np.array_equal(pa, pb)
+        a.close()
+        b.close()
