@@ -87,12 +87,24 @@ __device__ __forceinline__ void stage_bf16(uint16_t (*T)[C + GP], const uint16_t
 // 2 x 2 tiles of the gfx950 MFMA 16x16x32 (eight bfloat16 per lane and
 // operand); a 32-deep k stage of A and of B (kept n-major) sits in LDS.
 // Epilogue: + bias[n]; ReLU; zero where mask(m,n) <= 0 (ReLU derivative);
-// FP32 and/or bfloat16 output.
+// FP32 and/or bfloat16 output.  With Cpart set, workgroup z of the grid's z
+// dimension takes k in [z kchunk, (z + 1) kchunk) and writes its raw partial
+// product to Cpart[z][m][n] (M x N), summed by splitk_finish (split-K for
+// products with few output tiles and a long k).
+__device__ __forceinline__ float gemm_epilogue(float v, int m, int n, const float* __restrict__ bias, int relu,
+                                               const uint16_t* __restrict__ mask, int64_t ldc) {
+  if (bias) v += bias[n];
+  if (relu) v = v > 0.f ? v : 0.f;
+  if (mask && !(from_bf16(mask[(int64_t)m * ldc + n]) > 0.f)) v = 0.f;
+  return v;
+}
+
 __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const uint16_t* __restrict__ A, int64_t sam,
                                                  int64_t sak, const uint16_t* __restrict__ Bm, int64_t sbk,
                                                  int64_t sbn, const float* __restrict__ bias, int relu,
                                                  const uint16_t* __restrict__ mask, float* __restrict__ Cf,
-                                                 uint16_t* __restrict__ Cb, int64_t ldc) {
+                                                 uint16_t* __restrict__ Cb, int64_t ldc, int kchunk,
+                                                 float* __restrict__ Cpart) {
   __shared__ __attribute__((aligned(16))) uint16_t As[GB][GK + GP];
   __shared__ __attribute__((aligned(16))) uint16_t Bt[GB][GK + GP];  // B tile stored as [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -103,9 +115,10 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const uint
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += GK) {
-    stage_bf16<GB, GK>(As, A, sam, sak, m0, k0, M, K);    // As[m][k]
-    stage_bf16<GB, GK>(Bt, Bm, sbn, sbk, n0, k0, N, K);   // Bt[n][k] = B(k, n)
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+    stage_bf16<GB, GK>(As, A, sam, sak, m0, k0, M, ke);    // As[m][k]
+    stage_bf16<GB, GK>(Bt, Bm, sbn, sbk, n0, k0, N, ke);   // Bt[n][k] = B(k, n)
     __syncthreads();
     bf16x8 a[2], b[2];
 #pragma unroll
@@ -129,14 +142,30 @@ __global__ void __launch_bounds__(256) gemm_bf16(int M, int N, int K, const uint
         const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
         const int n = n0 + wn * 32 + j * 16 + (lane & 15);
         if (m < M && n < N) {
-          float v = acc[i][j][r];
-          if (bias) v += bias[n];
-          if (relu) v = v > 0.f ? v : 0.f;
-          if (mask && !(from_bf16(mask[(int64_t)m * ldc + n]) > 0.f)) v = 0.f;
+          if (Cpart) {
+            Cpart[((int64_t)blockIdx.z * M + m) * N + n] = acc[i][j][r];
+            continue;
+          }
+          const float v = gemm_epilogue(acc[i][j][r], m, n, bias, relu, mask, ldc);
           if (Cf) Cf[(int64_t)m * ldc + n] = v;
           if (Cb) Cb[(int64_t)m * ldc + n] = to_bf16(v);
         }
       }
+}
+
+// sum of the split-K partials in order z = 0 .. S-1, then the epilogue
+__global__ void splitk_finish(const float* __restrict__ Cpart, int S, int M, int N, const float* __restrict__ bias,
+                              int relu, const uint16_t* __restrict__ mask, float* __restrict__ Cf,
+                              uint16_t* __restrict__ Cb, int64_t ldc) {
+  const int64_t mn = (int64_t)M * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mn; e += (int64_t)gridDim.x * blockDim.x) {
+    float v = 0.f;
+    for (int z = 0; z < S; ++z) v += Cpart[z * mn + e];
+    const int m = (int)(e / N), n = (int)(e - (int64_t)m * N);
+    v = gemm_epilogue(v, m, n, bias, relu, mask, ldc);
+    if (Cf) Cf[(int64_t)m * ldc + n] = v;
+    if (Cb) Cb[(int64_t)m * ldc + n] = to_bf16(v);
+  }
 }
 
 __global__ void f32_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, int64_t n) {
@@ -184,24 +213,45 @@ __global__ void mse_grad(const float* __restrict__ O, const float* __restrict__ 
 
 // the loss of a step, and its running sum over the training steps (acc[0])
 // with their count (acc[1])
-__global__ void sum_partials(const double* __restrict__ partial, int n, double scale, float* __restrict__ out,
-                             double* __restrict__ acc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += partial[i];
-    *out = (float)(s * scale);
-    acc[0] += s * scale;
+// (one workgroup of 256 threads: strided partial sums, then a fixed-order tree)
+__global__ void __launch_bounds__(256) sum_partials(const double* __restrict__ partial, int n, double scale,
+                                                    float* __restrict__ out, double* __restrict__ acc) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double t = red[0] * scale;
+    *out = (float)t;
+    acc[0] += t;
     acc[1] += 1.0;
   }
 }
 
-// out[c] = sum_r M[r, c] (bias gradients), fixed row order
-__global__ void colsum(const float* __restrict__ Mx, int rows, int cols, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// out[c] = sum_r M[r, c] (bias gradients): a workgroup takes 16 columns, its
+// 16 row groups sum rows g, g + 16, ... and the groups' sums are added in a
+// fixed order
+constexpr int CS_COLS = 16, CS_GROUPS = 16;
+__global__ void __launch_bounds__(CS_COLS * CS_GROUPS) colsum(const float* __restrict__ Mx, int rows, int cols,
+                                                             float* __restrict__ out) {
+  __shared__ float part[CS_GROUPS][CS_COLS];
+  const int cl = threadIdx.x % CS_COLS, g = threadIdx.x / CS_COLS;
+  const int c = blockIdx.x * CS_COLS + cl;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += Mx[(int64_t)r * cols + c];
-  out[c] = s;
+  if (c < cols)
+    for (int r = g; r < rows; r += CS_GROUPS) s += Mx[(int64_t)r * cols + c];
+  part[g][cl] = s;
+  __syncthreads();
+  if (g == 0 && c < cols) {
+    float t = part[0][cl];
+    for (int k = 1; k < CS_GROUPS; ++k) t += part[k][cl];
+    out[c] = t;
+  }
 }
 
 // Adam on FP32 masters; refreshes the bfloat16 copy where wb != null
@@ -244,6 +294,7 @@ struct pdhcg_mlp {
   float *out = nullptr, *go = nullptr, *d2 = nullptr, *d1 = nullptr, *loss = nullptr;
   double* partial = nullptr;
   double* loss_acc = nullptr;  // [sum of step losses, steps] since the last pdhcg_mlp_take_loss
+  float* kpart = nullptr;      // split-K partial products (kSplitMax x kSplitTiles block tiles)
   std::vector<void*> allocs;
   ~pdhcg_mlp() {
     for (void* p : allocs) (void)hipFree(p);
@@ -267,12 +318,32 @@ namespace {
     if (e_ != hipSuccess) return set_error(PDHCG_ERR_HIP, (std::string(#call) + ": " + hipGetErrorString(e_)).c_str()); \
   } while (0)
 
-hipError_t gemm(hipStream_t s, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
-                int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask, float* Cf, uint16_t* Cb,
-                int64_t ldc) {
-  dim3 grid((N + GB - 1) / GB, (M + GB - 1) / GB);
-  hipLaunchKernelGGL(gemm_bf16, grid, dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, relu, mask, Cf, Cb,
-                     ldc);
+// A product with fewer output tiles than this and k >= 512 is split along k
+// (at most kSplitMax parts of >= 256 k each) so that more CUs take part.
+constexpr int kSplitTiles = 128, kSplitMax = 8;
+
+hipError_t gemm(hipStream_t s, float* work, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
+                const uint16_t* B, int64_t sbk, int64_t sbn, const float* bias, int relu, const uint16_t* mask,
+                float* Cf, uint16_t* Cb, int64_t ldc) {
+  const int gx = (N + GB - 1) / GB, gy = (M + GB - 1) / GB;
+  int S = 1, kchunk = K;
+  if (work && gx * gy < kSplitTiles && K >= 512) {
+    S = std::min(std::min(kSplitMax, (2 * kSplitTiles + gx * gy - 1) / (gx * gy)), K / 256);
+    kchunk = ((K + S - 1) / S + GK - 1) / GK * GK;
+    S = (K + kchunk - 1) / kchunk;
+  }
+  if (S <= 1) {
+    hipLaunchKernelGGL(gemm_bf16, dim3(gx, gy, 1), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, relu,
+                       mask, Cf, Cb, ldc, K, (float*)nullptr);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(gemm_bf16, dim3(gx, gy, S), dim3(256), 0, s, M, N, K, A, sam, sak, B, sbk, sbn, bias, relu,
+                     mask, Cf, Cb, ldc, kchunk, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t mn = (int64_t)M * N;
+  hipLaunchKernelGGL(splitk_finish, dim3((int)std::min<int64_t>((mn + 255) / 256, 2048)), dim3(256), 0, s, work, S, M,
+                     N, bias, relu, mask, Cf, Cb, ldc);
   return hipGetLastError();
 }
 
@@ -294,11 +365,11 @@ int run_forward(pdhcg_mlp* h, const float* X, const int32_t* rows, int batch) {
     hipLaunchKernelGGL(f32_to_bf16, dim3(grid_for((int64_t)batch * a)), dim3(256), 0, h->stream, X, h->xb,
                        (int64_t)batch * a);
   MLPX(hipGetLastError());
-  MLPX(gemm(h->stream, batch, d, a, h->xb, a, 1, h->wb + h->off[0], d, 1, h->w + h->off[1], 1, nullptr, nullptr, h->h1,
+  MLPX(gemm(h->stream, h->kpart, batch, d, a, h->xb, a, 1, h->wb + h->off[0], d, 1, h->w + h->off[1], 1, nullptr, nullptr, h->h1,
             d));
-  MLPX(gemm(h->stream, batch, d, d, h->h1, d, 1, h->wb + h->off[2], d, 1, h->w + h->off[3], 1, nullptr, nullptr, h->h2,
+  MLPX(gemm(h->stream, h->kpart, batch, d, d, h->h1, d, 1, h->wb + h->off[2], d, 1, h->w + h->off[3], 1, nullptr, nullptr, h->h2,
             d));
-  MLPX(gemm(h->stream, batch, o, d, h->h2, d, 1, h->wb + h->off[4], o, 1, h->w + h->off[5], 0, nullptr, h->out,
+  MLPX(gemm(h->stream, h->kpart, batch, o, d, h->h2, d, 1, h->wb + h->off[4], o, 1, h->w + h->off[5], 0, nullptr, h->out,
             nullptr, o));
   return 0;
 }
@@ -314,23 +385,26 @@ int queue_loss_grad(pdhcg_mlp* h, const float* X, const float* T, const int32_t*
   hipLaunchKernelGGL(mse_grad, dim3(pg), dim3(256), 0, h->stream, h->out, T, rows, o, no, (float)(1.0 / (double)no),
                      h->go, h->gob, h->partial);
   MLPX(hipGetLastError());
-  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, h->stream, h->partial, pg, 1.0 / (double)no, h->loss,
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(256), 0, h->stream, h->partial, pg, 1.0 / (double)no, h->loss,
                      h->loss_acc);
   MLPX(hipGetLastError());
   float* g = h->g;
   // layer 3: dW3 = H2' G, db3 = colsum G, dH2 = (G W3') masked by H2 > 0
-  MLPX(gemm(h->stream, d, o, batch, h->h2, 1, d, h->gob, o, 1, nullptr, 0, nullptr, g + h->off[4], nullptr, o));
-  hipLaunchKernelGGL(colsum, dim3((o + 255) / 256), dim3(256), 0, h->stream, h->go, batch, o, g + h->off[5]);
+  MLPX(gemm(h->stream, h->kpart, d, o, batch, h->h2, 1, d, h->gob, o, 1, nullptr, 0, nullptr, g + h->off[4], nullptr, o));
+  hipLaunchKernelGGL(colsum, dim3((o + CS_COLS - 1) / CS_COLS), dim3(CS_COLS * CS_GROUPS), 0, h->stream, h->go, batch,
+                     o, g + h->off[5]);
   MLPX(hipGetLastError());
-  MLPX(gemm(h->stream, batch, d, o, h->gob, o, 1, h->wb + h->off[4], 1, o, nullptr, 0, h->h2, h->d2, h->d2b, d));
+  MLPX(gemm(h->stream, h->kpart, batch, d, o, h->gob, o, 1, h->wb + h->off[4], 1, o, nullptr, 0, h->h2, h->d2, h->d2b, d));
   // layer 2
-  MLPX(gemm(h->stream, d, d, batch, h->h1, 1, d, h->d2b, d, 1, nullptr, 0, nullptr, g + h->off[2], nullptr, d));
-  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d2, batch, d, g + h->off[3]);
+  MLPX(gemm(h->stream, h->kpart, d, d, batch, h->h1, 1, d, h->d2b, d, 1, nullptr, 0, nullptr, g + h->off[2], nullptr, d));
+  hipLaunchKernelGGL(colsum, dim3((d + CS_COLS - 1) / CS_COLS), dim3(CS_COLS * CS_GROUPS), 0, h->stream, h->d2, batch,
+                     d, g + h->off[3]);
   MLPX(hipGetLastError());
-  MLPX(gemm(h->stream, batch, d, d, h->d2b, d, 1, h->wb + h->off[2], 1, d, nullptr, 0, h->h1, h->d1, h->d1b, d));
+  MLPX(gemm(h->stream, h->kpart, batch, d, d, h->d2b, d, 1, h->wb + h->off[2], 1, d, nullptr, 0, h->h1, h->d1, h->d1b, d));
   // layer 1
-  MLPX(gemm(h->stream, a, d, batch, h->xb, 1, a, h->d1b, d, 1, nullptr, 0, nullptr, g + h->off[0], nullptr, d));
-  hipLaunchKernelGGL(colsum, dim3((d + 255) / 256), dim3(256), 0, h->stream, h->d1, batch, d, g + h->off[1]);
+  MLPX(gemm(h->stream, h->kpart, a, d, batch, h->xb, 1, a, h->d1b, d, 1, nullptr, 0, nullptr, g + h->off[0], nullptr, d));
+  hipLaunchKernelGGL(colsum, dim3((d + CS_COLS - 1) / CS_COLS), dim3(CS_COLS * CS_GROUPS), 0, h->stream, h->d1, batch,
+                     d, g + h->off[1]);
   MLPX(hipGetLastError());
   return 0;
 }
@@ -374,7 +448,8 @@ int pdhcg_mlp_create(pdhcg_mlp** out, int32_t n_in, int32_t n_hid, int32_t n_out
             h->alloc(&h->h2, B * n_hid) && h->alloc(&h->gob, B * n_out) && h->alloc(&h->d2b, B * n_hid) &&
             h->alloc(&h->d1b, B * n_hid) && h->alloc(&h->out, B * n_out) && h->alloc(&h->go, B * n_out) &&
             h->alloc(&h->d2, B * n_hid) && h->alloc(&h->d1, B * n_hid) && h->alloc(&h->loss, 1) &&
-            h->alloc(&h->partial, 2048) && h->alloc(&h->loss_acc, 2);
+            h->alloc(&h->partial, 2048) && h->alloc(&h->loss_acc, 2) &&
+            h->alloc(&h->kpart, (int64_t)kSplitMax * kSplitTiles * GB * GB);
   if (!ok) {
     delete h;
     return set_error(PDHCG_ERR_OUT_OF_MEMORY, "hipMalloc failed for the network");
