@@ -160,8 +160,10 @@ int pow2_ceil(double v) {
 // the same rows (rp1, rp2: host row pointers, either may be null): contiguous
 // ranges of near-equal work (entries + 2 per row); rows with more than
 // kLongRow entries listed per workgroup; the other rows cut into tiles of at
-// most kTileNnz entries and kTileRows rows.  The lane group is the power of
-// two at or above the mean length of the short rows.
+// most tile_nnz_for(block) entries and tile_rows_for(block) rows, block being
+// the workgroup size of the kernel that runs the partition (the LDS tile of
+// its translation unit).  The lane group is the power of two at or above the
+// mean length of the short rows.
 // Tiles of the standalone product: runs of whole rows with at most
 // spmv_stream_tile_nnz() entries and spmv_stream_tile_rows() rows; a row
 // longer than that forms a tile of its own.  4 ints per tile: first row, end
@@ -183,7 +185,9 @@ std::vector<int32_t> stream_tiles(int64_t nrows, const int64_t* rp) {
   return t;
 }
 
-HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp2, int gscale = 0) {
+HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp2, int gscale = 0,
+                    int block = kSolveBlock) {
+  const int64_t tile_nnz = tile_nnz_for(block), tile_rows = tile_rows_for(block);
   HostPart P;
   auto len = [&](int64_t i) -> int64_t {
     return (rp1 ? rp1[i + 1] - rp1[i] : 0) + (rp2 ? rp2[i + 1] - rp2[i] : 0);
@@ -221,7 +225,7 @@ HostPart build_part(int64_t nrows, int nb, const int64_t* rp1, const int64_t* rp
       }
       const int64_t start = i;
       int64_t acc = 0;
-      while (i < end && len(i) <= kLongRow && acc + len(i) <= kTileNnz && i - start < kTileRows) {
+      while (i < end && len(i) <= kLongRow && acc + len(i) <= tile_nnz && i - start < tile_rows) {
         acc += len(i);
         ++i;
       }
@@ -1110,10 +1114,10 @@ void batch_parts(const int64_t* qrp, bool dense, int64_t n, const HostCsr& A, co
   const int64_t* q = dense ? nullptr : qrp;
   const int64_t* arp = m ? A.rowptr.data() : nullptr;
   const int64_t* trp = m ? T.rowptr.data() : nullptr;
-  HostPart p1 = build_part(n, 1, q, trp);
-  HostPart p2 = build_part(n, 1, q, nullptr);
-  HostPart p3 = build_part(m, 1, arp, nullptr);
-  HostPart p4 = build_part(n, 1, trp, nullptr);
+  HostPart p1 = build_part(n, 1, q, trp, 0, kBatchBlock);
+  HostPart p2 = build_part(n, 1, q, nullptr, 0, kBatchBlock);
+  HostPart p3 = build_part(m, 1, arp, nullptr, 0, kBatchBlock);
+  HostPart p4 = build_part(n, 1, trp, nullptr, 0, kBatchBlock);
   const HostPart* ps[4] = {&p1, &p2, &p3, &p4};
   const int64_t base = (int64_t)out.size();
   for (int k = 0; k < 4; ++k) {

@@ -7,6 +7,9 @@
 #include "internal.hpp"
 
 namespace pdhcg {
+// internal linkage: the workgroup size (kBlock) differs between the
+// translation units that include this header
+namespace {
 
 // max that propagates NaN (the hardware max returns the non-NaN operand, which
 // would hide a diverged iterate from the termination test); written with
@@ -651,4 +654,5 @@ __device__ __forceinline__ void tile_rows2(const int32_t* rowptr1, const int32_t
   __syncthreads();
 }
 
+}  // namespace
 }  // namespace pdhcg

@@ -5,7 +5,18 @@
 
 namespace pdhcg {
 
-constexpr int kBlock = 512;       // threads per workgroup of every solver kernel
+// Threads per workgroup.  The cooperative single-QP kernels run 512 (one
+// workgroup per CU); the batched kernel, one workgroup per QP, runs 256 so
+// that two instances share a CU at the same register budget (two waves per
+// SIMD).  The solver's device code is compiled once per size: a translation
+// unit that defines PDHCG_BATCH_UNIT gets the batched size.
+constexpr int kSolveBlock = 512;
+constexpr int kBatchBlock = 256;
+#ifdef PDHCG_BATCH_UNIT
+constexpr int kBlock = kBatchBlock;
+#else
+constexpr int kBlock = kSolveBlock;
+#endif
 constexpr int kBarWords = 2048;   // grid-barrier words (uint64) per handle, zeroed before each launch
 constexpr int kBarAbortWord = 64; // the barrier word raised when a wait timed out
 constexpr int kWave = 64;         // CDNA wavefront
@@ -55,8 +66,12 @@ __host__ __device__ inline int64_t res_block_bytes(int64_t nrows, int64_t ne, in
   return align16(4 * (nrows + 1)) + align16(4 * ne) + align16((int64_t)vbytes * ne);
 }
 
-constexpr int kTileNnz = 4096;    // staged products per tile (FP64 in LDS)
-constexpr int kTileRows = 1024;   // rows per tile
+// staged products (FP64 in LDS) and rows per tile of a workgroup of `block`
+// threads: 8 entries and 2 rows per thread
+constexpr int tile_nnz_for(int block) { return 8 * block; }
+constexpr int tile_rows_for(int block) { return 2 * block; }
+constexpr int kTileNnz = tile_nnz_for(kBlock);
+constexpr int kTileRows = tile_rows_for(kBlock);
 
 // One workgroup's share of a Part, cached in LDS when a solve kernel starts:
 // owned rows [r0, r1), tiles t0 .. t1-1 (the first kCacheTiles of them copied
