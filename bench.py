@@ -41,6 +41,7 @@ CALIBRATION_BYTES = 1 << 30   # the --calibrate-copy kernel reads and writes 1 G
 # they are launched and fed; the network, the standalone product and the
 # preconditioning kernels do not run in the measured launches
 SOLVER_SOURCES = ["paper_2405_16160_amd/csrc/solve_kernels.hip", "paper_2405_16160_amd/csrc/batch_kernels.hip",
+                  "paper_2405_16160_amd/csrc/batch_kernels_512.hip",
                   "paper_2405_16160_amd/csrc/solver.hpp", "paper_2405_16160_amd/csrc/device.hpp",
                   "paper_2405_16160_amd/csrc/internal.hpp", "paper_2405_16160_amd/csrc/api.cpp",
                   "include/pdhcg.h"]
@@ -132,6 +133,8 @@ def parse():
                              "lowrank"],
                     help="workload; the default is the benchmark line, the others are extra measurements")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--threads", type=int, default=0, choices=(0, 256, 512),
+                    help="threads per workgroup of the batched kernel (0: the batch autotuner picks)")
     ap.add_argument("--precondition", action="store_true",
                     help="batch mode: 10 Ruiz steps + Pock-Chambolle per instance (no factored run)")
     ap.add_argument("--train", type=int, default=20_000)
@@ -878,6 +881,13 @@ def main():
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t
     progress(f"batch created in {create_s:.2f} s (pack, upload, preconditioning)")
+    if args.threads:
+        batch.set_threads(args.threads)
+        tuned = {"threads": args.threads}
+    else:  # untimed set-up: one cold solve of the batch per workgroup size
+        tuned = batch.autotune(reps=1)
+        progress(f"autotuner: {tuned}")
+    kernel_name = HEADLINE_KERNEL if batch.threads == 256 else HEADLINE_KERNEL + "_wg512"
     for _ in range(args.warmup):
         batch.solve()
     torch.cuda.synchronize()
@@ -895,7 +905,7 @@ def main():
     bytes_alg = sum(solve_bytes(q, r, args.precision, dense_q=True, rank=f[0].shape[1], scaled=True)
                     for q, r, f in zip(qps, rs, facs))
     achieved = bytes_alg / kernel_s / 1e9
-    traffic, _ = measured_traffic()
+    traffic, _ = measured_traffic() if kernel_name == HEADLINE_KERNEL else (None, None)
     progress(f"{args.steps} batched solves: {dt / args.steps:.3f} s each, kernel {kernel_s:.3f} s")
     line = {
         "metric": "time & QPs/s to rel. KKT<=1e-4 (batched/warm-start vs plain); SpMV HBM GB/s",
@@ -917,8 +927,9 @@ def main():
                   "iters_max": int(max(r["iters"] for r in rs)),
                   "cg_steps_mean": float(np.mean([r["cg_iters_total"] for r in rs])),
                   "rel_kkt_max": float(max(r["rel_kkt"] for r in rs)), "create_s": create_s,
-                  "kernel_s": kernel_s, "launches_per_solve": 1},
-        "roofline": {"kernel": HEADLINE_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                  "kernel_s": kernel_s, "launches_per_solve": 1, "workgroup_threads": batch.threads,
+                  "autotuner": tuned},
+        "roofline": {"kernel": kernel_name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_alg},
     }

@@ -285,6 +285,23 @@ int pdhcg_batch_layout(const pdhcg_batch* h, int64_t* n_off, int64_t* m_off);
 int pdhcg_batch_solve(pdhcg_batch* h, const double* x0, const double* y0, double* x_out, double* y_out,
                       int32_t vec_on_device, pdhcg_result* rs);
 
+/* Threads per workgroup of the batch's kernel: 256 (the default: two
+ * instances per CU, LDS tiles of 2 048 entries and 512 rows) or 512 (one
+ * instance per CU, tiles of 4 096 entries and 1 024 rows).  A batch made by
+ * pdhcg_batch_create holds the row partitions for both; the result of a solve
+ * differs between the two only in the rounding of its reductions.
+ * INVALID_ARGUMENT for another value. */
+int pdhcg_batch_set_threads(pdhcg_batch* h, int32_t threads);
+
+/* Autotuner of the batched kernel: solve every instance of the batch from a
+ * cold start `reps` times with each workgroup size (256 and 512 threads, with
+ * their tile sizes) and keep the faster for later solves.  *threads receives
+ * the choice; kernel_s (2 entries, may be NULL) the fastest launch time of
+ * each candidate in seconds, 256 first.  The returned points and results of
+ * these solves are discarded.  INVALID_ARGUMENT for reps < 1 or a null
+ * handle; HIP on a failed launch. */
+int pdhcg_batch_autotune(pdhcg_batch* h, int32_t reps, int32_t* threads, double* kernel_s);
+
 /* The packed D1 (rows) and D2 (variables) of the batch's preconditioning
  * (ones when it is off); device pointers when vec_on_device = 1. */
 int pdhcg_batch_get_scaling(const pdhcg_batch* h, double* d1_out, double* d2_out, int32_t vec_on_device);

@@ -1072,12 +1072,15 @@ struct BatchInst {
   int32_t n = 0, m = 0;
   int32_t dense = 0;
   int32_t q_rank = 0;  // k of a factored Q (dense = 2)
-  int32_t g_n1 = 1, g_cg = 1, g_m = 1, g_t = 1;
+  // row partitions per workgroup size (index 0: 256 threads, 1: 512; the
+  // second only for a handle the autotuner may switch): offset into the
+  // packed lists, lane groups of the four partitions (n-side, CG, A, A')
+  int32_t g[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};
   int32_t x0_given = 0, y0_given = 0;
   int64_t q_rp = 0, q_nz = 0, a_rp = 0, a_nz = 0, t_rp = 0, t_nz = 0;
   int64_t voff_n = 0, voff_m = 0;
-  int64_t part_off = 0;
-  int64_t sub_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // long lists and tiles, relative to part_off
+  int64_t part_off[2] = {0, 0};
+  int64_t sub_off[2][8] = {};  // long lists and tiles, relative to part_off
   double nb_inf = 0.0, nc_inf = 0.0, kkt_zero = 0.0;
 };
 
@@ -1108,16 +1111,20 @@ bool is_dense(const int64_t* rowptr, int64_t n) {
 // the n-side, CG, A and A' partitions six ints (bounds[0..1], long_ptr[0..1],
 // tile_ptr[0..1], the last two relative), then the four long-row lists, then
 // the four tile arrays.
-void batch_parts(const int64_t* qrp, bool dense, int64_t n, const HostCsr& A, const HostCsr& T,
+// workgroup sizes of the batched kernel: the default, and the alternative the
+// autotuner may pick (index 1 of BatchInst's partitions)
+constexpr int kBatchSizes[2] = {kBatchBlock, kSolveBlock};
+
+void batch_parts(const int64_t* qrp, bool dense, int64_t n, const HostCsr& A, const HostCsr& T, int block,
                  std::vector<int32_t>& out, int32_t g[4], int64_t off[8]) {
   const int64_t m = A.nrows;
   const int64_t* q = dense ? nullptr : qrp;
   const int64_t* arp = m ? A.rowptr.data() : nullptr;
   const int64_t* trp = m ? T.rowptr.data() : nullptr;
-  HostPart p1 = build_part(n, 1, q, trp, 0, kBatchBlock);
-  HostPart p2 = build_part(n, 1, q, nullptr, 0, kBatchBlock);
-  HostPart p3 = build_part(m, 1, arp, nullptr, 0, kBatchBlock);
-  HostPart p4 = build_part(n, 1, trp, nullptr, 0, kBatchBlock);
+  HostPart p1 = build_part(n, 1, q, trp, 0, block);
+  HostPart p2 = build_part(n, 1, q, nullptr, 0, block);
+  HostPart p3 = build_part(m, 1, arp, nullptr, 0, block);
+  HostPart p4 = build_part(n, 1, trp, nullptr, 0, block);
   const HostPart* ps[4] = {&p1, &p2, &p3, &p4};
   const int64_t base = (int64_t)out.size();
   for (int k = 0; k < 4; ++k) {
@@ -1186,6 +1193,8 @@ struct pdhcg_batch {
   hipStream_t stream = nullptr;
   pdhcg_settings s{};
   bool pre = false, mixed = false;
+  int32_t nsizes = 1;                // workgroup sizes with partitions built (2: the autotuner may switch)
+  int32_t threads = kBatchBlock;     // threads per workgroup of the batched kernel
   DevBuf D;
   std::vector<BatchInst> inst;
   std::vector<int64_t> off_n, off_m;  // count + 1 offsets of the packed vectors
@@ -1253,8 +1262,8 @@ int host_csr(const pdhcg_csr& M, std::vector<int64_t>& rp, std::vector<int32_t>&
 // when Ls is given instead, the factor Ls[i] of Q = F F' + diag(d).
 int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, const pdhcg_lowrank* Ls_in,
                       const pdhcg_csr* As_in, const double* const* bs_in, const double* const* cs_in,
-                      int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream, char* arena = nullptr,
-                      size_t arena_bytes = 0) {
+                      int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream, bool tunable,
+                      char* arena = nullptr, size_t arena_bytes = 0) {
   const double t0 = now_s();
   int rc;
   if (!out) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle pointer");
@@ -1332,6 +1341,8 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
     return code;
   };
   h->count = count;
+  const int nsizes = tunable ? 2 : 1;  // partitions and parameter blocks for both workgroup sizes
+  h->nsizes = nsizes;
   h->stream = stream;
   h->s = *s;
   h->pre = pre;
@@ -1448,10 +1459,11 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
     Ah.nrows = As[i].nrows;
     Ah.ncols = As[i].ncols;
     Ah.rowptr.assign(As[i].rowptr, As[i].rowptr + As[i].nrows + 1);
-    I.part_off = (int64_t)parts.size();
-    int32_t g[4];
-    batch_parts(Ls ? nullptr : Qs[q_first[i]].rowptr, I.dense != 0, I.n, Ah, T, parts, g, I.sub_off);
-    I.g_n1 = g[0]; I.g_cg = g[1]; I.g_m = g[2]; I.g_t = g[3];
+    for (int z = 0; z < nsizes; ++z) {
+      I.part_off[z] = (int64_t)parts.size();
+      batch_parts(Ls ? nullptr : Qs[q_first[i]].rowptr, I.dense != 0, I.n, Ah, T, kBatchSizes[z], parts, I.g[z],
+                  I.sub_off[z]);
+    }
   }
   // largest first: estimated work ~ entries of Q plus twice those of A
   std::vector<int32_t> order(count);
@@ -1477,7 +1489,7 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
   if ((rc = D.alloc(&d_val, nz_tot))) return bail(rc);
   if (mixed && (rc = D.alloc(&d_val32, nz_tot))) return bail(rc);
   if ((rc = D.alloc(&d_parts, (int64_t)parts.size()))) return bail(rc);
-  if ((rc = D.alloc(&h->d_params, count))) return bail(rc);
+  if ((rc = D.alloc(&h->d_params, (int64_t)count * nsizes))) return bail(rc);
   if ((rc = D.alloc(&h->d_st, count))) return bail(rc);
   if ((rc = D.alloc(&h->d_t0, 1))) return bail(rc);
   if ((rc = D.alloc(&h->d_given, count))) return bail(rc);
@@ -1596,7 +1608,7 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
       return bail(fail(PDHCG_ERR_HIP, "preconditioning kernels failed to launch"));
   }
   // one parameter block per QP, all pointers resolved against the packed arrays
-  std::vector<SolveParams> hp(count);
+  std::vector<SolveParams> hp((size_t)count * nsizes);
   for (int i = 0; i < count; ++i) {
     const BatchInst& I = inst[i];
     SolveParams& P = hp[i];
@@ -1617,14 +1629,15 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
       P.x32 = fv[0] + I.voff_n; P.r32 = fv[1] + I.voff_n; P.p32_0 = fv[2] + I.voff_n; P.p32_1 = fv[3] + I.voff_n;
     }
     P.part = d_part + (int64_t)i * NSLOT;
-    const int32_t* pb = d_parts + I.part_off;
-    auto part = [&](int k, int32_t g) {
-      return Part{pb + 6 * k, pb + 6 * k + 2, pb + I.sub_off[k], pb + 6 * k + 4, pb + I.sub_off[4 + k], g};
+    const int32_t* pb = d_parts + I.part_off[0];
+    auto part = [&](int k) {
+      return Part{pb + 6 * k, pb + 6 * k + 2, pb + I.sub_off[0][k], pb + 6 * k + 4, pb + I.sub_off[0][4 + k],
+                  I.g[0][k]};
     };
-    P.pn1 = part(0, I.g_n1);
-    P.pcg = part(1, I.g_cg);
-    P.pm = part(2, I.g_m);
-    P.pt = part(3, I.g_t);
+    P.pn1 = part(0);
+    P.pcg = part(1);
+    P.pm = part(2);
+    P.pt = part(3);
     P.nb_inf = I.nb_inf;
     P.nc_inf = I.nc_inf;
     P.dn = pre ? h->d_d2 + I.voff_n : nullptr;
@@ -1650,7 +1663,22 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
   }
   if ((rc = up(d_parts, parts.data(), sizeof(int32_t) * parts.size()))) return bail(rc);
   if ((rc = up(h->d_order, order.data(), sizeof(int32_t) * count))) return bail(rc);
-  if ((rc = up(h->d_params, hp.data(), sizeof(SolveParams) * count))) return bail(rc);
+  for (int z = 1; z < nsizes; ++z)  // the same blocks with the partitions cut for the other workgroup size
+    for (int i = 0; i < count; ++i) {
+      const BatchInst& I = inst[i];
+      SolveParams& P = hp[(size_t)z * count + i];
+      P = hp[i];
+      const int32_t* pb = d_parts + I.part_off[z];
+      auto part = [&](int k) {
+        return Part{pb + 6 * k, pb + 6 * k + 2, pb + I.sub_off[z][k], pb + 6 * k + 4, pb + I.sub_off[z][4 + k],
+                    I.g[z][k]};
+      };
+      P.pn1 = part(0);
+      P.pcg = part(1);
+      P.pm = part(2);
+      P.pt = part(3);
+    }
+  if ((rc = up(h->d_params, hp.data(), sizeof(SolveParams) * hp.size()))) return bail(rc);
   if (mixed && launch_to_f32(d_val, d_val32, nz_tot, stream) != hipSuccess)
     return bail(fail(PDHCG_ERR_HIP, "FP32 conversion failed to launch"));
   if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(PDHCG_ERR_HIP, "batch upload or setup failed"));
@@ -1677,6 +1705,17 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
 
 namespace {
 
+// The batch's start stamp and its one launch at the handle's workgroup size
+// (the parameter blocks of that size's partitions)
+hipError_t launch_batch(pdhcg_batch* h, hipStream_t stream) {
+  BatchParams bp = h->bp;
+  const int z = h->threads == kBatchSizes[1] ? 1 : 0;
+  bp.params = h->d_params + (size_t)z * h->count;
+  hipError_t e = launch_batch_clock(bp.t0, stream);
+  if (e != hipSuccess) return e;
+  return z ? launch_batch_512(bp, h->count, stream) : launch_batch_256(bp, h->count, stream);
+}
+
 // Solve every instance of a packed batch.  x0 / y0: packed start points
 // (device pointers when in_dev; may be null) with per-instance flags in
 // `given` (bit 0 x0, bit 1 y0; null: every instance takes the given vectors);
@@ -1700,7 +1739,7 @@ int batch_solve_impl(pdhcg_batch* h, const double* x0, const double* y0, bool in
   }
   HIPX(hipMemcpyAsync(h->d_given, g.data(), (size_t)count, hipMemcpyHostToDevice, stream));
   if (h->e0) HIPX(hipEventRecord(h->e0, stream));
-  HIPX(launch_batch(h->bp, count, stream));
+  HIPX(launch_batch(h, stream));
   if (h->e1) HIPX(hipEventRecord(h->e1, stream));
   const double* xr = h->x;
   const double* yr = h->y;
@@ -1756,7 +1795,7 @@ int solve_batch_once(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
       return fail(PDHCG_ERR_INVALID_ARGUMENT, "instance " + std::to_string(i) + ": null array");
   }
   pdhcg_batch* h = nullptr;
-  int rc = batch_create_impl(&h, count, Qs, Ls, As, bs, cs, 0, s, hip_stream, arena, arena_bytes);
+  int rc = batch_create_impl(&h, count, Qs, Ls, As, bs, cs, 0, s, hip_stream, false, arena, arena_bytes);
   if (rc) return rc;
   std::vector<double> X0, Y0, X((size_t)h->vn_tot), Y((size_t)std::max<int64_t>(h->vm_tot, 1));
   std::vector<uint8_t> given(count, 0);
@@ -1792,7 +1831,7 @@ int solve_batch_once(int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls
 extern "C" int pdhcg_batch_create(pdhcg_batch** h, int32_t count, const pdhcg_csr* Qs, const pdhcg_lowrank* Ls,
                                   const pdhcg_csr* As, const double* const* bs, const double* const* cs,
                                   int32_t vec_on_device, const pdhcg_settings* s, void* hip_stream) {
-  return batch_create_impl(h, count, Qs, Ls, As, bs, cs, vec_on_device, s, hip_stream);
+  return batch_create_impl(h, count, Qs, Ls, As, bs, cs, vec_on_device, s, hip_stream, true);
 }
 
 extern "C" int pdhcg_batch_layout(const pdhcg_batch* h, int64_t* n_off, int64_t* m_off) {
@@ -1807,6 +1846,46 @@ extern "C" int pdhcg_batch_solve(pdhcg_batch* h, const double* x0, const double*
   if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
   if (!x_out || (h->vm_tot > 0 && !y_out)) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null output");
   return batch_solve_impl(h, x0, y0, vec_on_device != 0, nullptr, x_out, y_out, vec_on_device != 0, rs);
+}
+
+extern "C" int pdhcg_batch_set_threads(pdhcg_batch* h, int32_t threads) {
+  if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
+  if (threads != kBatchSizes[0] && !(threads == kBatchSizes[1] && h->nsizes == 2))
+    return fail(PDHCG_ERR_INVALID_ARGUMENT,
+                "threads per workgroup must be 256, or 512 for a batch made by pdhcg_batch_create");
+  h->threads = threads;
+  return 0;
+}
+
+extern "C" int pdhcg_batch_autotune(pdhcg_batch* h, int32_t reps, int32_t* threads, double* kernel_s) {
+  if (!h || !threads) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle or output");
+  if (reps < 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "reps must be >= 1");
+  if (h->nsizes != 2 || !h->e0) return fail(PDHCG_ERR_INVALID_ARGUMENT, "the batch was not made by pdhcg_batch_create");
+  const std::vector<uint8_t> cold((size_t)h->count, 0);
+  double best = INFINITY;
+  int32_t pick = h->threads;
+  for (int z = 0; z < 2; ++z) {
+    h->threads = kBatchSizes[z];
+    double tmin = INFINITY;
+    for (int r = 0; r < reps; ++r) {  // a cold solve of every instance; only the launch is timed
+      HIPX(hipMemcpyAsync(h->d_given, cold.data(), cold.size(), hipMemcpyHostToDevice, h->stream));
+      HIPX(hipEventRecord(h->e0, h->stream));
+      HIPX(launch_batch(h, h->stream));
+      HIPX(hipEventRecord(h->e1, h->stream));
+      HIPX(hipStreamSynchronize(h->stream));
+      float ms = 0.0f;
+      HIPX(hipEventElapsedTime(&ms, h->e0, h->e1));
+      tmin = std::min(tmin, 1e-3 * (double)ms);
+    }
+    if (kernel_s) kernel_s[z] = tmin;
+    if (tmin < best) {
+      best = tmin;
+      pick = kBatchSizes[z];
+    }
+  }
+  h->threads = pick;
+  *threads = pick;
+  return 0;
 }
 
 extern "C" int pdhcg_batch_get_scaling(const pdhcg_batch* h, double* d1_out, double* d2_out, int32_t vec_on_device) {

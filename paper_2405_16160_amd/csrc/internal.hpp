@@ -6,14 +6,15 @@
 namespace pdhcg {
 
 // Threads per workgroup.  The cooperative single-QP kernels run 512 (one
-// workgroup per CU); the batched kernel, one workgroup per QP, runs 256 so
-// that two instances share a CU at the same register budget (two waves per
-// SIMD).  The solver's device code is compiled once per size: a translation
-// unit that defines PDHCG_BATCH_UNIT gets the batched size.
+// workgroup per CU); the batched kernel, one workgroup per QP, runs 256 by
+// default so that two instances share a CU at the same register budget (two
+// waves per SIMD), or 512 (one instance per CU) when its autotuner finds that
+// faster.  The solver's device code is compiled once per size: a translation
+// unit that defines PDHCG_BLOCK_SIZE gets that size, the others 512.
 constexpr int kSolveBlock = 512;
 constexpr int kBatchBlock = 256;
-#ifdef PDHCG_BATCH_UNIT
-constexpr int kBlock = kBatchBlock;
+#ifdef PDHCG_BLOCK_SIZE
+constexpr int kBlock = PDHCG_BLOCK_SIZE;
 #else
 constexpr int kBlock = kSolveBlock;
 #endif
@@ -284,7 +285,11 @@ int solve_batch_in_region(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* A
                           double* const* x_outs, double* const* y_outs, pdhcg_result* rs, const pdhcg_settings* s,
                           void* hip_stream, char* region, size_t region_bytes);
 
-hipError_t launch_batch(const BatchParams& p, int count, hipStream_t s);
+// the batched kernel with 256 (batch_kernels.hip) or 512 threads per
+// workgroup (batch_kernels_512.hip); the clock kernel stamps the batch's start
+hipError_t launch_batch_clock(uint64_t* t0, hipStream_t s);
+hipError_t launch_batch_256(const BatchParams& p, int count, hipStream_t s);
+hipError_t launch_batch_512(const BatchParams& p, int count, hipStream_t s);
 hipError_t launch_solve(const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s);
 // static LDS bytes of the solve kernel, and the co-resident workgroups per CU
 // it reaches with dyn_lds bytes of dynamic LDS

@@ -1686,5 +1686,72 @@ __device__ bool power_norm(const DevMat& A, const DevMat& At, double* v, double*
   return true;
 }
 
+// -------------------------------------------------------------- batched solve
+
+// One workgroup per QP: workgroup g solves instance order[g] (the host sorts
+// instances by decreasing work, so the dispatcher hands out the largest
+// first).  Each workgroup runs the same loop as the cooperative kernel with
+// nb = 1 (a grid barrier degenerates to a workgroup barrier), on its own slice
+// of the packed matrices and vectors; dense Q blocks use the streaming dense
+// product.  ||A|| comes from the same power iteration, per instance.
+__device__ __forceinline__ void batch_solve(const BatchParams& BP) {
+  __shared__ double lds[kWaves * 16];
+  __shared__ double svec[kDenseTile];
+  const int idx = BP.order[blockIdx.x];
+  __shared__ SolveParams Ps;
+  // the partial sums of a phase go to LDS: with one workgroup per QP they
+  // are read back only by the same workgroup, after a workgroup barrier
+  __shared__ double part_lds[NSLOT];
+  load_params(Ps, BP.params + idx, 0);
+  if (threadIdx.x == 0) {  // this solve's partials, start point and warm-start fallback
+    Ps.part = part_lds;
+    const uint32_t gv = BP.given ? BP.given[idx] : 0u;
+    if (!(gv & 1u)) Ps.x0 = nullptr;
+    if (!(gv & 2u)) Ps.y0 = nullptr;
+    if (!(gv & 3u) || !BP.warm_fallback) Ps.kkt_zero = 0.0;
+  }
+  __syncthreads();
+  const SolveParams& P = Ps;
+  Block B{0, 1, (int)threadIdx.x};
+  GridSync gs{nullptr, 1u, 0};
+  // start point (x0 or 0; y0 projected onto y >= 0, or 0)
+  for (int j = B.tid; j < P.n; j += kBlock) {
+    const double v = P.x0 ? P.x0[j] : 0.0;
+    P.x[j] = v;
+    P.xa[j] = v;
+    P.x_anc[j] = v;
+    if (BP.mixed) P.x32[j] = (float)v;
+  }
+  for (int i = B.tid; i < P.m; i += kBlock) {
+    const double v = pos_part(P.y0 ? P.y0[i] : 0.0);
+    P.y[i] = v;
+    P.ya[i] = v;
+    P.y_anc[i] = v;
+  }
+  __syncthreads();
+  double nrm = 0.0;
+  if (P.m > 0) power_norm(P.A, P.At, P.p0, P.p1, P.ax_avg, P.part, P.pt, P.pm, BP.power_iters, B, gs, lds, &nrm);
+  __shared__ Ctl C;
+  if (B.tid == 0) {
+    SolverState& S = C.S;
+    S = SolverState{};
+    S.K_anchor = NAN;
+    S.K_prev = INFINITY;
+    S.omega = BP.pw_init;
+    S.eta = BP.eta_factor / (nrm > 0.0 ? nrm : 1.0);
+    S.tau = S.eta / S.omega;
+    S.sigma = S.eta * S.omega;
+    S.mixed = BP.mixed;
+    S.t_start = *BP.t0;
+    S.norm_A = nrm;
+  }
+  __syncthreads();
+  if (P.Q.dense)
+    drive<true>(P, B, gs, C, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
+  else
+    drive<false>(P, B, gs, C, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
+  if (B.tid == 0) BP.st[idx] = C.S;
+}
+
 }  // namespace
 }  // namespace pdhcg

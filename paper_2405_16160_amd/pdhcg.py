@@ -78,7 +78,7 @@ EXPORTS = ["pdhcg_default_settings", "pdhcg_create", "pdhcg_create_lowrank", "pd
            "pdhcg_solve_multi_rhs", "pdhcg_spmv", "pdhcg_get_scaling",
            "pdhcg_autotune", "pdhcg_plan_info", "pdhcg_destroy", "pdhcg_error_string", "pdhcg_last_error",
            "pdhcg_batch_create", "pdhcg_batch_layout", "pdhcg_batch_solve", "pdhcg_batch_get_scaling",
-           "pdhcg_batch_destroy"]
+           "pdhcg_batch_set_threads", "pdhcg_batch_autotune", "pdhcg_batch_destroy"]
 
 
 class PdhcgError(RuntimeError):
@@ -132,6 +132,8 @@ def lib():
         L.pdhcg_batch_layout.argtypes = [P, P, P]
         L.pdhcg_batch_solve.argtypes = [P, P, P, P, P, C.c_int32, P]
         L.pdhcg_batch_get_scaling.argtypes = [P, P, P, C.c_int32]
+        L.pdhcg_batch_set_threads.argtypes = [P, C.c_int32]
+        L.pdhcg_batch_autotune.argtypes = [P, C.c_int32, P, P]
         L.pdhcg_batch_destroy.argtypes = [P]
         L.pdhcg_batch_destroy.restype = None
         _lib = L
@@ -406,6 +408,7 @@ class Batch:
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.settings = settings or Settings()
         self.count = cnt = len(qps)
+        self.threads = 256
         keep = []
         on_dev = 1 if device_inputs else 0
         tdt = {np.int64: torch.int64, np.int32: torch.int32, np.float64: torch.float64}
@@ -462,6 +465,20 @@ class Batch:
         ptr = lambda t: None if t is None else t.contiguous().data_ptr()
         _check(lib().pdhcg_batch_solve(self.h, ptr(x0), ptr(y0), self.x.data_ptr(), self.y.data_ptr(), 1, rs))
         return self.x, self.y[: int(self.m_off[-1])], [_result_dict(rs[i]) for i in range(self.count)]
+
+    def set_threads(self, threads: int):
+        """Threads per workgroup of the batched kernel: 256 (default) or 512."""
+        _check(lib().pdhcg_batch_set_threads(self.h, threads))
+        self.threads = threads
+
+    def autotune(self, reps: int = 1) -> dict:
+        """Time cold solves of the whole batch at 256 and 512 threads per
+        workgroup and keep the faster; returns the choice and both times."""
+        t = C.c_int32()
+        ks = (C.c_double * 2)()
+        _check(lib().pdhcg_batch_autotune(self.h, reps, C.byref(t), ks))
+        self.threads = t.value
+        return {"threads": t.value, "kernel_s": {256: ks[0], 512: ks[1]}}
 
     def split(self, x, y):
         """Per-instance numpy views of packed x, y."""

@@ -199,3 +199,55 @@ def test_batch_portfolio_maximum_size_contract(form):
         assert np.all(y >= 0)
         assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-4
         assert abs(k["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-6
+
+
+def test_batch_workgroup_sizes_and_autotuner():
+    """The batched kernel at 256 threads per workgroup (the default, two per
+    CU, 2 048-entry tiles) and at 512 (one per CU, 4 096-entry tiles) on a
+    preconditioned factored portfolio batch of mixed sizes (n up to 2000):
+    each size holds the contract against the oracle (its own preprocessing,
+    FP64, run to 1e-9) on the instances with n <= 400, every instance ends
+    OPTIMAL with relKKT on its caller's problem <= tol, and the two sizes take
+    iteration counts within 2 % (or 64) of each other.  The autotuner times
+    both, keeps one, and the batch then solves bit for bit as with that size
+    set by hand; 384 threads is rejected."""
+    from oracle import precondition as PC
+    say("[batch threads] 24 portfolio QPs (6 with n <= 400, n = 2000 among the others), 256 / 512 threads")
+    ids = list(range(6))
+    qps = [I.portfolio_qp(i, nmax=400) for i in ids] + [I.portfolio_qp(900 + i) for i in range(17)] \
+        + [I.portfolio_qp(950, n=2000)]
+    fac = [I.portfolio_factor(i, nmax=400) for i in ids] + [I.portfolio_factor(900 + i) for i in range(17)] \
+        + [I.portfolio_factor(950, n=2000)]
+    tol = 1e-7
+    s = pdhcg.Settings(tol_rel_kkt=tol, precision=1, max_iters=400_000, ruiz_iters=10, pock_chambolle=1)
+    b = pdhcg.Batch(qps, s, lowrank=fac)
+    iters, sols = {}, {}
+    for threads in (256, 512):
+        b.set_threads(threads)
+        x, y, rs = b.solve()
+        xs, ys = b.split(x, y)
+        sols[threads] = (x.cpu().numpy().copy(), y.cpu().numpy().copy())
+        iters[threads] = np.array([r["iters"] for r in rs])
+        say(f"  threads={threads} kernel={rs[0]['kernel_s'] * 1e3:.1f} ms iters mean={iters[threads].mean():.1f}")
+        for j, (qp, r) in enumerate(zip(qps, rs)):
+            assert r["status"] == 0, (threads, j, r)
+            k = O.kkt(qp, xs[j], ys[j])
+            assert k["rel_kkt"] <= tol * (1 + 1e-6), (threads, j, k)
+            assert np.all(ys[j] >= 0)
+            if qp.n <= 400:
+                xr, _, rr, _, _ = PC.solve(qp, O.Settings(tol=1e-9, max_iters=1_000_000))
+                assert rr.status == O.OPTIMAL
+                assert np.linalg.norm(xs[j] - xr) / np.linalg.norm(xr) <= 1e-4
+                assert abs(k["primal_obj"] - rr.primal_obj) / (1 + abs(rr.primal_obj)) <= 1e-6
+    assert np.all(np.abs(iters[256] - iters[512]) <= np.maximum(64, 0.02 * iters[512]))
+    t = b.autotune(reps=1)
+    say(f"  autotuner: {t}")
+    assert t["threads"] in (256, 512) and b.threads == t["threads"]
+    assert t["kernel_s"][256] > 0 and t["kernel_s"][512] > 0
+    x, y, rs = b.solve()
+    assert np.array_equal(x.cpu().numpy(), sols[t["threads"]][0])
+    assert np.array_equal(y.cpu().numpy(), sols[t["threads"]][1])
+    with pytest.raises(pdhcg.PdhcgError) as e:
+        b.set_threads(384)
+    assert e.value.code == -1
+    b.close()
