@@ -1487,7 +1487,9 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
   if ((rc = D.alloc(&d_rp, rp_tot))) return bail(rc);
   if ((rc = D.alloc(&d_col, nz_tot))) return bail(rc);
   if ((rc = D.alloc(&d_val, nz_tot))) return bail(rc);
-  if (mixed && (rc = D.alloc(&d_val32, nz_tot))) return bail(rc);
+  // (+4: the 16-byte loads of the dense FP32 products may read up to three
+  // values past the last matrix)
+  if (mixed && (rc = D.alloc(&d_val32, nz_tot + 4))) return bail(rc);
   if ((rc = D.alloc(&d_parts, (int64_t)parts.size()))) return bail(rc);
   if ((rc = D.alloc(&h->d_params, (int64_t)count * nsizes))) return bail(rc);
   if ((rc = D.alloc(&h->d_st, count))) return bail(rc);

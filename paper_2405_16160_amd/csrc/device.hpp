@@ -270,6 +270,17 @@ __device__ __forceinline__ T gld_nt(const T* p) {
   return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
 }
 
+// Four consecutive FP32 values from a 4-byte aligned address in one
+// global_load_dwordx4 (gfx950 takes dword-aligned 16-byte accesses), plain
+// or with the non-temporal hint.
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ f32x4u gld4(const float* p) {
+  return *(const __attribute__((address_space(1))) f32x4u*)p;
+}
+__device__ __forceinline__ f32x4u gld4_nt(const float* p) {
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) f32x4u*)p);
+}
+
 template <typename T>
 __device__ __forceinline__ void gst(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;

@@ -74,10 +74,71 @@ __device__ __forceinline__ void dense_pass(const V* M, int nr, int nc, int i0, d
   }
 }
 
+// The FP32 form of dense_pass with 16-byte loads: thread t owns the four
+// consecutive columns i0 + 4t .. i0 + 4t + 3 (a pass covers 4 kBlock
+// columns), kJ rows in flight per step (16 loads of 16 bytes, where the
+// FP64-value form has 8 x K loads of 8 bytes).  Each column still adds the
+// rows in order, so the sums are those of dense_pass.  A thread whose four
+// columns run past nc reads up to three values beyond its row: the next row,
+// or what follows the matrix in its block (F' after F, d after F'), or the
+// padding of the packed FP32 value array after the last matrix; those columns
+// are dropped.  A thread with no column below nc reads its row's start.
+template <typename Gen>
+__device__ __forceinline__ void dense_pass4(const float* M, int nr, int nc, int i0, double* svec, Gen& gen,
+                                            double* acc) {
+  constexpr int kJ = 16;  // rows per unrolled step
+  const int c0 = i0 + 4 * (int)threadIdx.x;
+  const int cl = c0 < nc ? c0 : 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+  for (int j0 = 0; j0 < nr; j0 += kDenseTile) {
+    const int jt = nr - j0 < kDenseTile ? nr - j0 : kDenseTile;
+    __syncthreads();
+    for (int j = threadIdx.x; j < jt; j += kBlock) svec[j] = gen(j0 + j, i0 == 0);
+    __syncthreads();
+    const float* base = M + (int64_t)j0 * nc + cl;
+    int j = 0;
+    for (; j + kJ <= jt; j += kJ) {
+      f32x4u v[kJ];
+#pragma unroll
+      for (int jj = 0; jj < kJ; ++jj) v[jj] = gld4(base + (int64_t)(j + jj) * nc);
+#pragma unroll
+      for (int jj = 0; jj < kJ; ++jj) {
+        const double sj = svec[j + jj];
+        acc[0] += (double)v[jj].x * sj;
+        acc[1] += (double)v[jj].y * sj;
+        acc[2] += (double)v[jj].z * sj;
+        acc[3] += (double)v[jj].w * sj;
+      }
+    }
+    for (; j < jt; ++j) {
+      const double sj = svec[j];
+      const f32x4u v = gld4(base + (int64_t)j * nc);
+      acc[0] += (double)v.x * sj;
+      acc[1] += (double)v.y * sj;
+      acc[2] += (double)v.z * sj;
+      acc[3] += (double)v.w * sj;
+    }
+  }
+}
+
 // out_c = sum_j M[j, c] v_j for all c < nc, v_j = gen(j, first) (first: the
 // first column pass, where gen may store what it forms), epi(c, out_c)
 template <typename V, typename Gen, typename Epi>
 __device__ void rect_rows(const V* M, int nr, int nc, double* svec, Gen& gen, Epi& epi) {
+  if constexpr (sizeof(V) == 4) {
+    for (int i0 = 0; i0 < nc; i0 += 4 * kBlock) {
+      double acc[4];
+      dense_pass4(M, nr, nc, i0, svec, gen, acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + 4 * (int)threadIdx.x + q;
+        if (i < nc) epi(i, acc[q]);
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int i0 = 0; i0 < nc; i0 += kBlock * kDenseRows) {
     double acc[kDenseRows];
     const int cols = nc - i0;
@@ -143,6 +204,48 @@ __device__ void factor_tv(const V* F, int n, int k, const double* svec, double* 
   __syncthreads();
 }
 
+// factor_tv for FP32 factors with 16-byte loads: lane l takes the columns
+// 4l .. 4l + 3 of every row of its wave (k <= 256), 16 rows in flight per
+// step; each column adds its rows in the same order as factor_tv, so t is the
+// same.  A lane whose columns run past k reads up to three values beyond the
+// row (the next row, or F' after the last row); those are dropped.
+__device__ void factor_tv4(const float* F, int n, int k, const double* svec, double* red, double* t) {
+  constexpr int kJ = 16;  // rows per unrolled step (per wave)
+  const int tid = (int)threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int c0 = 4 * lane;
+  const int cl = c0 < k ? c0 : 0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = w; j < n; j += kWaves * kJ) {
+    f32x4u u[kJ];
+#pragma unroll
+    for (int jj = 0; jj < kJ; ++jj) {
+      const int row = min(j + kWaves * jj, n - 1);
+      u[jj] = gld4_nt(F + (int64_t)row * k + cl);
+    }
+#pragma unroll
+    for (int jj = 0; jj < kJ; ++jj) {
+      const int row = j + kWaves * jj;
+      const double vj = row < n ? svec[row] : 0.0;
+      acc[0] += (double)u[jj].x * vj;
+      acc[1] += (double)u[jj].y * vj;
+      acc[2] += (double)u[jj].z * vj;
+      acc[3] += (double)u[jj].w * vj;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + q;
+    if (c < k) red[w * 256 + c] = acc[q];
+  }
+  __syncthreads();
+  for (int c = tid; c < k; c += kBlock) {
+    double sum = red[c];
+    for (int ww = 1; ww < kWaves; ++ww) sum += red[ww * 256 + c];
+    t[c] = sum;
+  }
+  __syncthreads();
+}
+
 // Q v for a dense Q of one workgroup: full n x n rows (Q.dense = 1), or Q =
 // F F' + diag(d) from its factor (Q.dense = 2; Q.rank = k; the block holds F
 // (n x k), F' (k x n) and d, row-major, at M): t = F' v into tscr (k), then
@@ -162,7 +265,8 @@ __device__ void dense_rows(const V* M, const DevMat& Q, double* svec, double* ts
     for (int j = (int)threadIdx.x; j < n; j += kBlock) svec[j] = gen(j, true);
     __syncthreads();
     double* red = tile_lds().prod;  // no tile is staged during a dense product
-    if (k <= 64) factor_tv<1>(M, n, k, svec, red, tscr);
+    if constexpr (sizeof(V) == 4) factor_tv4(M, n, k, svec, red, tscr);
+    else if (k <= 64) factor_tv<1>(M, n, k, svec, red, tscr);
     else if (k <= 128) factor_tv<2>(M, n, k, svec, red, tscr);
     else if (k <= 192) factor_tv<3>(M, n, k, svec, red, tscr);
     else factor_tv<4>(M, n, k, svec, red, tscr);
