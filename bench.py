@@ -606,9 +606,25 @@ def bench_precondition(args):
     return {"config": f"preconditioning, tol {args.tol:g}, precision {args.precision}", "rows": rows}
 
 
+def held_out_solves(fam, ids, settings, starts):
+    """Batched solves of the family members `ids` from each start in `starts`
+    (pairs of packed float64 device tensors or None), one packed batch;
+    returns [(results, kernel seconds)] in the order of `starts`."""
+    from paper_2405_16160_amd import pdhcg, warmstart as W
+    _, qps = W.family_qps(fam, ids)
+    b = pdhcg.Batch(qps, settings)
+    out = []
+    for x0, y0 in starts:
+        _, _, rs = b.solve(x0=None if x0 is None else x0.reshape(-1), y0=None if y0 is None else y0.reshape(-1))
+        out.append((rs, rs[0]["kernel_s"]))
+    b.close()
+    return out
+
+
 def bench_learned(args):
     """Learned warm start on the MPC family: train on PDHCG solutions, then
-    batched cold vs warm solves of held-out members to tol."""
+    batched cold vs warm solves of held-out members to tol.  The start points
+    are predicted and decoded on the device and handed to the batch there."""
     import dataclasses
     from paper_2405_16160_amd import instances as I, pdhcg, warmstart as W
     fam = I.mpc_family()
@@ -624,14 +640,14 @@ def bench_learned(args):
     train_s = time.perf_counter() - t_train
     ids = range(100_000, 100_000 + args.test)
     th_t, _ = W.family_qps(fam, ids)
+    import torch
     t = time.perf_counter()
-    x0, y0 = ws.predict(th_t)
+    x0, y0 = ws.predict_device(th_t)
+    torch.cuda.synchronize()
     infer_s = time.perf_counter() - t
     s = pdhcg.Settings(tol_rel_kkt=args.tol, warm_fallback=0)
-    _, _, _, rc, tc = W.solve_family(fam, ids, s)
-    _, _, _, rw, tw = W.solve_family(fam, ids, s, x0s=x0, y0s=y0)
-    _, _, _, rf, tf = W.solve_family(fam, ids, dataclasses.replace(s, warm_fallback=1), x0s=x0, y0s=y0)
-    _, _, _, rx, tx = W.solve_family(fam, ids, s, x0s=x0)
+    (rc, tc), (rw, tw), (rx, tx) = held_out_solves(fam, ids, s, [(None, None), (x0, y0), (x0, None)])
+    ((rf, tf),) = held_out_solves(fam, ids, dataclasses.replace(s, warm_fallback=1), [(x0, y0)])
     # single-QP mode on a sample: one handle for the family (Q, A, c shared), b
     # replaced per member, cold and warm solves with the cooperative kernel
     n_single = min(200, args.test)
@@ -813,13 +829,14 @@ def side_warm_start(args, train=4096, test=1024, epochs=60):
     train_s = time.perf_counter() - t
     ids = range(100_000, 100_000 + test)
     th_t, _ = W.family_qps(fam, ids)
+    import torch
     t = time.perf_counter()
-    x0, y0 = ws.predict(th_t)
+    x0, y0 = ws.predict_device(th_t)
+    torch.cuda.synchronize()
     infer_s = time.perf_counter() - t
     ws.net.close()
     s = pdhcg.Settings(tol_rel_kkt=args.tol, warm_fallback=0)
-    _, _, _, rc, tc = W.solve_family(fam, ids, s)
-    _, _, _, rw, tw = W.solve_family(fam, ids, s, x0s=x0, y0s=y0)
+    (rc, tc), (rw, tw) = held_out_solves(fam, ids, s, [(None, None), (x0, y0)])
     progress(f"warm start: cold {tc:.3f} s, warm {tw:.3f} s, inference {infer_s:.3f} s")
     return {"workload": f"MPC T=50 (n=1500, m=5000), reduced: {train} training solves, {epochs} epochs, "
                         f"{test} held-out, batched, tol {args.tol:g}",

@@ -46,6 +46,23 @@ int pdhcg_mlp_get_params(const pdhcg_mlp* h, float* params);
 /* Y (batch x n_out, FP32) = network(X (batch x n_in)). */
 int pdhcg_mlp_forward(pdhcg_mlp* h, const float* X, int32_t batch, float* Y);
 
+/* A start point for `batch` members of a parametric family, on the device:
+ * Z = network(X) (X: batch x n_in FP32, any batch size; run in chunks of
+ * max_batch rows), each output column de-standardised as z * out_sd + out_mu
+ * (FP64, product and sum rounded separately), then columns 0..n-1 are x and
+ * the rest encode y: column n + p (p < n_pair) holds the multiplier lam of the
+ * p-th equality row pair, y[plus[p]] = max(lam, 0), y[minus[p]] = max(-lam, 0);
+ * column n + n_pair + q holds y[rest[q]] before its projection max(., 0).
+ * out_mu, out_sd: n_out FP64 device arrays; plus, minus (n_pair) and rest
+ * (n_rest): int32 device arrays of rows of y, every row 0..m-1 exactly once;
+ * x0 (batch x n) and y0 (batch x m): FP64 row-major device outputs (the
+ * packed start points of a batch of same-sized members).  INVALID_ARGUMENT
+ * unless n + n_pair + n_rest = n_out and 2 n_pair + n_rest = m. */
+int pdhcg_mlp_predict_start(pdhcg_mlp* h, const float* X, int32_t batch, const double* out_mu,
+                            const double* out_sd, int32_t n, int32_t n_pair, const int32_t* plus,
+                            const int32_t* minus, int32_t n_rest, const int32_t* rest, int32_t m, double* x0,
+                            double* y0);
+
 /* Mean-squared-error loss of network(X) against targets T (batch x n_out)
  * and its gradient with respect to every parameter (kept on the device for
  * pdhcg_mlp_adam_step; copied to host `grads` in the packed layout unless

@@ -277,6 +277,38 @@ int grid_for(int64_t n) {
   return (int)g;
 }
 
+// The network's outputs of `rows` rows (Z, FP32, n_out per row) turned into a
+// start point, rows r0 .. r0 + rows of the packed x0 (n per row) and y0 (m per
+// row): column c < n gives x_c = z_c sd_c + mu_c; column n + p (p < n_pair)
+// the multiplier lam of the p-th equality pair, y[plus_p] = max(lam, 0) and
+// y[minus_p] = max(-lam, 0); column n + n_pair + q gives y[rest_q] =
+// max(v, 0).  The product and the sum are rounded separately (contraction
+// into a fused multiply-add is switched off here), as a host computation of
+// the same formula does.
+__global__ void decode_start(const float* __restrict__ Z, int rows, int n_out, const double* __restrict__ mu,
+                             const double* __restrict__ sd, int n, int n_pair, const int32_t* __restrict__ plus,
+                             const int32_t* __restrict__ minus, const int32_t* __restrict__ rest, int m, int64_t r0,
+                             double* __restrict__ x0, double* __restrict__ y0) {
+#pragma clang fp contract(off)
+  const int64_t total = (int64_t)rows * n_out;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n_out;
+    const int c = (int)(e - r * n_out);
+    const double v = (double)Z[e] * sd[c] + mu[c];
+    const int64_t row = r0 + r;
+    if (c < n) {
+      x0[row * n + c] = v;
+    } else if (c < n + n_pair) {
+      const int p = c - n;
+      y0[row * m + plus[p]] = v > 0.0 ? v : 0.0;
+      y0[row * m + minus[p]] = -v > 0.0 ? -v : 0.0;
+    } else {
+      y0[row * m + rest[c - n - n_pair]] = v > 0.0 ? v : 0.0;
+    }
+  }
+}
+
 }  // namespace
 }  // namespace pdhcg
 
@@ -492,6 +524,32 @@ int pdhcg_mlp_forward(pdhcg_mlp* h, const float* X, int32_t batch, float* Y) {
   if (!X || !Y) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null X or Y");
   if ((rc = run_forward(h, X, nullptr, batch))) return rc;
   MLPX(hipMemcpyAsync(Y, h->out, sizeof(float) * (int64_t)batch * h->n_out, hipMemcpyDeviceToDevice, h->stream));
+  MLPX(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+int pdhcg_mlp_predict_start(pdhcg_mlp* h, const float* X, int32_t batch, const double* out_mu,
+                            const double* out_sd, int32_t n, int32_t n_pair, const int32_t* plus,
+                            const int32_t* minus, int32_t n_rest, const int32_t* rest, int32_t m, double* x0,
+                            double* y0) {
+  if (!h) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null network handle");
+  if (batch < 1) return set_error(PDHCG_ERR_INVALID_ARGUMENT, "batch must be >= 1");
+  if (!X || !out_mu || !out_sd || !x0 || (m > 0 && !y0))
+    return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null input or output array");
+  if (n < 0 || n_pair < 0 || n_rest < 0 || m < 0 || n + n_pair + n_rest != h->n_out || 2 * n_pair + n_rest != m)
+    return set_error(PDHCG_ERR_INVALID_ARGUMENT,
+                     "need n + n_pair + n_rest = n_out and 2 n_pair + n_rest = m (every row of y once)");
+  if ((n_pair > 0 && (!plus || !minus)) || (n_rest > 0 && !rest))
+    return set_error(PDHCG_ERR_INVALID_ARGUMENT, "null row index array");
+  int rc;
+  for (int64_t r0 = 0; r0 < batch; r0 += h->cap) {  // chunks of the workspace's rows
+    const int rows = (int)std::min<int64_t>(h->cap, batch - r0);
+    if ((rc = run_forward(h, X + r0 * h->n_in, nullptr, rows))) return rc;
+    const int64_t total = (int64_t)rows * h->n_out;
+    hipLaunchKernelGGL(decode_start, dim3(grid_for(total)), dim3(256), 0, h->stream, h->out, rows, h->n_out, out_mu,
+                       out_sd, n, n_pair, plus, minus, rest, m, r0, x0, y0);
+    MLPX(hipGetLastError());
+  }
   MLPX(hipStreamSynchronize(h->stream));
   return 0;
 }

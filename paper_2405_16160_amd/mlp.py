@@ -24,6 +24,8 @@ def _lib():
         L.pdhcg_mlp_adam_step.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float]
         L.pdhcg_mlp_train_step.argtypes = [P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]
         L.pdhcg_mlp_take_loss.argtypes = [P, P, P]
+        L.pdhcg_mlp_predict_start.argtypes = [P, P, C.c_int32, P, P, C.c_int32, C.c_int32, P, P, C.c_int32, P,
+                                              C.c_int32, P, P]
         L.pdhcg_mlp_destroy.argtypes = [P]
         L.pdhcg_mlp_destroy.restype = None
         L._mlp_bound = True
@@ -32,7 +34,7 @@ def _lib():
 
 MLP_EXPORTS = ["pdhcg_mlp_create", "pdhcg_mlp_num_params", "pdhcg_mlp_set_params", "pdhcg_mlp_get_params",
                "pdhcg_mlp_forward", "pdhcg_mlp_loss_grad", "pdhcg_mlp_adam_step", "pdhcg_mlp_train_step",
-               "pdhcg_mlp_take_loss", "pdhcg_mlp_destroy"]
+               "pdhcg_mlp_take_loss", "pdhcg_mlp_predict_start", "pdhcg_mlp_destroy"]
 
 
 def init_params(n_in, n_hid, n_out, seed=0):
@@ -88,6 +90,21 @@ class Network:
         Y = torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
         _p._check(_lib().pdhcg_mlp_forward(self.h, X.data_ptr(), X.shape[0], Y.data_ptr()))
         return Y
+
+    def predict_start(self, X, mu, sd, n, plus, minus, rest, m):
+        """Packed start points (x0: rows x n, y0: rows x m, float64 device
+        tensors) from the network's outputs on X (pdhcg_mlp_predict_start);
+        mu, sd: float64 device tensors of n_out; plus, minus, rest: int32
+        device tensors of rows of y."""
+        torch = self._torch
+        X = X.contiguous()
+        rows = X.shape[0]
+        x0 = torch.empty((rows, n), dtype=torch.float64, device=X.device)
+        y0 = torch.empty((rows, max(m, 1)), dtype=torch.float64, device=X.device)
+        _p._check(_lib().pdhcg_mlp_predict_start(self.h, X.data_ptr(), rows, mu.data_ptr(), sd.data_ptr(), n,
+                                                 plus.numel(), plus.data_ptr(), minus.data_ptr(), rest.numel(),
+                                                 rest.data_ptr(), m, x0.data_ptr(), y0.data_ptr()))
+        return x0, y0[:, :m]
 
     def loss_grad(self, X, T, want_grads=False):
         loss = C.c_float()

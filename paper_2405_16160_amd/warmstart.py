@@ -128,6 +128,7 @@ class WarmStarter:
 
     def __init__(self, net: _mlp.Network, sin: Scaler, sout: Scaler, n: int, code: DualCode):
         self.net, self.sin, self.sout, self.n, self.code = net, sin, sout, n, code
+        self._dev = None
 
     def predict(self, thetas):
         import torch
@@ -138,6 +139,24 @@ class WarmStarter:
             out.append(self.net.forward(Xt).cpu().numpy().astype(np.float64))
         Z = self.sout.inv(np.concatenate(out))
         return Z[:, : self.n], self.code.decode(Z[:, self.n:])
+
+
+    def predict_device(self, thetas):
+        """The same start points as packed float64 device tensors (x0: rows x
+        n, y0: rows x m), ready for a batch of the family's members: the
+        forward pass, the de-standardisation and the dual decoding run in the
+        library (pdhcg_mlp_predict_start); only the inputs (n_in values per
+        row) are standardised on the host."""
+        import torch
+        if self._dev is None:
+            def dev(a, dt):
+                return torch.as_tensor(np.ascontiguousarray(a, dtype=dt), device="cuda")
+            self._dev = (dev(self.sout.mu, np.float64), dev(self.sout.sd, np.float64),
+                         dev(self.code.plus, np.int32), dev(self.code.minus, np.int32),
+                         dev(self.code.rest, np.int32))
+        mu, sd, plus, minus, rest = self._dev
+        Xt = torch.tensor(self.sin.fwd(thetas), dtype=torch.float32, device="cuda")
+        return self.net.predict_start(Xt, mu, sd, self.n, plus, minus, rest, self.code.m)
 
 
 def validate(fam, ws: "WarmStarter", ids, settings: _pd.Settings):

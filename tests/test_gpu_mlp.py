@@ -114,3 +114,35 @@ def test_queued_training_steps_equal_the_synchronous_ones():
             assert np.array_equal(pa, pb)
         a.close()
         b.close()
+
+
+def test_device_start_points_equal_the_host_decoding():
+    """pdhcg_mlp_predict_start (forward pass, de-standardisation and dual
+    decoding on the device, in chunks of max_batch rows) returns exactly the
+    x0, y0 of the host path (the same forward passes, then numpy: Z * sd + mu,
+    y+ = max(lam, 0), y- = max(-lam, 0), the other rows max(v, 0)), for a batch
+    of 150 rows over a workspace of 64; sizes that do not add up are rejected."""
+    from paper_2405_16160_amd import pdhcg, warmstart as W
+    say("[mlp] start points decoded on the device, 150 rows in chunks of 64")
+    rng = np.random.default_rng(11)
+    n_in, n_hid, n, n_pair, n_rest = 6, 64, 40, 12, 30
+    m = 2 * n_pair + n_rest
+    n_out = n + n_pair + n_rest
+    net = mlp.Network(n_in, n_hid, n_out, max_batch=64, params=mlp.init_params(n_in, n_hid, n_out, seed=3))
+    perm = rng.permutation(m)
+    code = W.DualCode(m, np.sort(perm[:n_pair]), np.sort(perm[n_pair:2 * n_pair]))
+    sin = W.Scaler(rng.standard_normal(n_in), rng.uniform(0.5, 2.0, n_in))
+    sout = W.Scaler(rng.standard_normal(n_out), rng.uniform(0.1, 3.0, n_out))
+    ws = W.WarmStarter(net, sin, sout, n, code)
+    th = rng.standard_normal((150, n_in))
+    xh, yh = ws.predict(th)
+    xd, yd = ws.predict_device(th)
+    assert xd.shape == (150, n) and yd.shape == (150, m)
+    assert np.array_equal(xd.cpu().numpy(), xh)
+    assert np.array_equal(yd.cpu().numpy(), yh)
+    assert np.all(yh >= 0.0) and np.any(yh > 0.0)
+    mu, sd, plus, minus, rest = ws._dev
+    Xt = torch.tensor(sin.fwd(th), dtype=torch.float32, device="cuda")
+    with pytest.raises(pdhcg.PdhcgError):
+        net.predict_start(Xt, mu, sd, n + 1, plus, minus, rest, m)
+    net.close()
