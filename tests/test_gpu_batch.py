@@ -251,3 +251,31 @@ def test_batch_workgroup_sizes_and_autotuner():
         b.set_threads(384)
     assert e.value.code == -1
     b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_sparse_at_both_workgroup_sizes(precision):
+    """Sparse CSR instances (four of the tiny random family and one with
+    n = 2500 whose Q rows hold about 50 entries, so that its products take tens
+    of LDS tiles) solved by the batched kernel at 256 and at 512 threads per
+    workgroup (tiles of 2 048 and 4 096 entries): every instance meets the
+    contract against the oracle at relKKT 1e-6, and the two sizes take
+    iteration counts within 2 % (or 64) of each other."""
+    say(f"[batch threads] 5 sparse QPs, 256 / 512 threads, precision={precision}")
+    qps = [I.random_qp(family=1, instance=i) for i in range(4)] + \
+        [I.random_qp(n=2500, m=1200, q_density=0.004, a_density=0.004, family=1, instance=7)]
+    refs = [O.solve(qp, O.Settings(tol=1e-9, max_iters=400_000)) for qp in qps]
+    assert all(r.status == O.OPTIMAL for r in refs)
+    b = pdhcg.Batch(qps, pdhcg.Settings(tol_rel_kkt=1e-6, precision=precision, max_iters=400_000))
+    iters = {}
+    for threads in (256, 512):
+        b.set_threads(threads)
+        x, y, rs = b.solve()
+        xs, ys = b.split(x, y)
+        iters[threads] = np.array([r["iters"] for r in rs])
+        say(f"  threads={threads} iters={iters[threads].tolist()} nnz(Q) of the last={qps[-1].Q.nnz}")
+        for qp, xi, yi, r, ref in zip(qps, xs, ys, rs, refs):
+            assert r["status"] == 0, r
+            contract(qp, xi, yi, ref, 1e-6)
+    assert np.all(np.abs(iters[256] - iters[512]) <= np.maximum(64, 0.02 * iters[512]))
+    b.close()
