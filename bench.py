@@ -606,6 +606,29 @@ def bench_precondition(args):
     return {"config": f"preconditioning, tol {args.tol:g}, precision {args.precision}", "rows": rows}
 
 
+def stream_ceiling(gib=2, reps=5):
+    """The device's practical streaming rate on this run's GPU, for scale next
+    to the roofline's nominal 8 TB/s: a device copy of `gib` GiB (torch's copy
+    kernel, timed with events, the best of `reps`; it reads and writes its size
+    once each)."""
+    import torch
+    a = torch.ones((gib << 30) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    out = {"copy_GBps": 2 * a.numel() * 4 / best / 1e9}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def held_out_solves(fam, ids, settings, starts):
     """Batched solves of the family members `ids` from each start in `starts`
     (pairs of packed float64 device tensors or None), one packed batch;
@@ -953,6 +976,12 @@ def main():
     if traffic is not None:
         line["roofline"]["traffic_over_algorithmic"] = traffic / bytes_alg
     batch.close()
+    # the practical ceiling of the same GPU, measured after the timed region
+    ceiling = stream_ceiling()
+    line["roofline"]["stream_ceiling"] = ceiling
+    if traffic is not None:
+        line["roofline"]["measured_traffic_GBps"] = traffic / kernel_s / 1e9
+    progress(f"device copy (read + write): {ceiling['copy_GBps']:.0f} GB/s")
     if not args.no_extras:
         extras = {}
         obo = one_by_one_sample(pairs, args)
