@@ -272,7 +272,8 @@ struct pdhcg_handle {
   double *b = nullptr, *c = nullptr;
   double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *ax = nullptr, *ax_avg = nullptr,
          *x_anc = nullptr, *y_anc = nullptr, *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
-  float *x32 = nullptr, *r32 = nullptr, *p32_0 = nullptr, *p32_1 = nullptr, *xs32 = nullptr;
+  float *x32 = nullptr, *xs32 = nullptr;
+  float2* rp32 = nullptr;  // FP32 (r, p) records of the textbook CG
   double *r_alt = nullptr, *u0 = nullptr, *u1 = nullptr, *s0 = nullptr, *s1 = nullptr;
   double *x_prev = nullptr, *y_trial = nullptr, *ax_trial = nullptr;  // adaptive step size
   float4 *v32_0 = nullptr, *v32_1 = nullptr;   // interleaved FP32 (r, u, s) of the one-reduction CG
@@ -385,9 +386,7 @@ int ensure_mixed(pdhcg_handle* h) {
   if ((rc = h->alloc(&h->a_val32, h->nnzA))) return rc;
   if ((rc = h->alloc(&h->t_val32, h->nnzA))) return rc;
   if ((rc = h->alloc(&h->x32, h->n))) return rc;
-  if ((rc = h->alloc(&h->r32, h->n))) return rc;
-  if ((rc = h->alloc(&h->p32_0, h->n))) return rc;
-  if ((rc = h->alloc(&h->p32_1, h->n))) return rc;
+  if ((rc = h->alloc(&h->rp32, h->n))) return rc;
   if ((rc = h->alloc(&h->xs32, std::max(h->n, h->m)))) return rc;
   if ((rc = h->alloc(&h->v32_0, h->n))) return rc;
   if ((rc = h->alloc(&h->v32_1, h->n))) return rc;
@@ -579,11 +578,11 @@ SolveParams make_params(pdhcg_handle* h) {
   p.m = (int32_t)h->m;
   p.x = h->x; p.y = h->y; p.xa = h->xa; p.ya = h->ya; p.ax = h->ax; p.ax_avg = h->ax_avg;
   p.x_anc = h->x_anc; p.y_anc = h->y_anc; p.r = h->r; p.p0 = h->p0; p.p1 = h->p1; p.q = h->q;
-  p.x32 = h->x32; p.r32 = h->r32; p.p32_0 = h->p32_0; p.p32_1 = h->p32_1;
+  p.x32 = h->x32; p.rp32 = h->rp32;
   p.r_alt = h->r_alt; p.u0 = h->u0; p.u1 = h->u1; p.s0 = h->s0; p.s1 = h->s1;
   p.v32_0 = h->v32_0; p.v32_1 = h->v32_1;
   // CG form: the single-reduction steps gather 16 bytes per column (FP32 r, u,
-  // s), the textbook steps 4 (the direction) at one more grid barrier per step;
+  // s), the textbook steps 8 (the FP32 (r, p) record) at one more grid barrier per step;
   // the first wins while the gathered vector stays in an XCD's L2, the second
   // once the gathers stream from the last-level cache
   // (a low-rank Q takes the textbook form: its products need t = P' p first)
@@ -1483,7 +1482,8 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
   double *d_b, *d_c, *d_part;
   double* nv[10];  // x xa x_anc r p0 p1 q x_prev (+ F' v of a factored Q) (+ kept Q x of a dense Q)
   double* mv[7];  // y ya ax ax_avg y_anc y_trial ax_trial
-  float* fv[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* fv[1] = {nullptr};        // x32
+  float2* d_rp32 = nullptr;        // FP32 (r, p) records of the textbook CG
   if ((rc = D.alloc(&d_rp, rp_tot))) return bail(rc);
   if ((rc = D.alloc(&d_col, nz_tot))) return bail(rc);
   if ((rc = D.alloc(&d_val, nz_tot))) return bail(rc);
@@ -1512,9 +1512,7 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
     if (k >= 5 && !adaptive) continue;
     if ((rc = D.alloc(&mv[k], vm_tot))) return bail(rc);
   }
-  if (mixed)
-    for (int k = 0; k < 4; ++k)
-      if ((rc = D.alloc(&fv[k], vn_tot))) return bail(rc);
+  if (mixed && ((rc = D.alloc(&fv[0], vn_tot)) || (rc = D.alloc(&d_rp32, vn_tot)))) return bail(rc);
   if ((rc = D.alloc(&h->d_x0, vn_tot))) return bail(rc);
   if ((rc = D.alloc(&h->d_y0, vm_tot))) return bail(rc);
   if ((rc = D.alloc(&h->xo, vn_tot))) return bail(rc);
@@ -1628,7 +1626,7 @@ int batch_create_impl(pdhcg_batch** out, int32_t count, const pdhcg_csr* Qs_in, 
     P.y = mv[0] + I.voff_m; P.ya = mv[1] + I.voff_m; P.ax = mv[2] + I.voff_m; P.ax_avg = mv[3] + I.voff_m;
     P.y_anc = mv[4] + I.voff_m;
     if (mixed) {
-      P.x32 = fv[0] + I.voff_n; P.r32 = fv[1] + I.voff_n; P.p32_0 = fv[2] + I.voff_n; P.p32_1 = fv[3] + I.voff_n;
+      P.x32 = fv[0] + I.voff_n; P.rp32 = d_rp32 + I.voff_n;
     }
     P.part = d_part + (int64_t)i * NSLOT;
     const int32_t* pb = d_parts + I.part_off[0];

@@ -281,6 +281,15 @@ __device__ __forceinline__ f32x4u gld4_nt(const float* p) {
   return __builtin_nontemporal_load((const __attribute__((address_space(1))) f32x4u*)p);
 }
 
+// an (r, p) record of the textbook CG: one 8-byte load or store
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f32x2 gld2(const float2* p) {
+  return *(const __attribute__((address_space(1))) f32x2*)p;
+}
+__device__ __forceinline__ void gst2(float2* p, float a, float b) {
+  *(__attribute__((address_space(1))) f32x2*)p = f32x2{a, b};
+}
+
 template <typename T>
 __device__ __forceinline__ void gst(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
@@ -353,6 +362,19 @@ struct GatherDir {
   // set its contents are not used), so a tile's gathers issue together
   __device__ __forceinline__ double operator()(int j) const {
     const double rj = (double)gld(r + j), pj = (double)gld(pp + j);
+    return first ? rj : rj + beta * pj;
+  }
+};
+
+// The same from the interleaved FP32 records (r_j, p_prev_j): one 8-byte
+// load, one cache line, per gathered entry
+struct GatherDir2 {
+  const float2* rp;
+  double beta;
+  int first;
+  __device__ __forceinline__ double operator()(int j) const {
+    const f32x2 w = gld2(rp + j);
+    const double rj = (double)w.x, pj = (double)w.y;
     return first ? rj : rj + beta * pj;
   }
 };

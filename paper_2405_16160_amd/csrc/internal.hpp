@@ -172,10 +172,13 @@ struct SolveParams {
   // one-reduction CG (cooperative kernel): second r buffer, u = (Q + I/tau) r
   // and s = (Q + I/tau) p, double-buffered (null in the batched kernel)
   double *r_alt, *u0, *u1, *s0, *s1;
-  // FP32 copies used by the mixed-precision products; v32_0 / v32_1 hold
-  // (r, u, s) of the one-reduction CG interleaved per row (null in the
-  // batched kernel)
-  float *x32, *r32, *p32_0, *p32_1;
+  // FP32 copies used by the mixed-precision products: x32; rp32 holds (r, p)
+  // of the textbook CG per row, the residual and the direction of the last
+  // update, so that a product's gather of p = r + beta p_prev reads one
+  // 8-byte record (one cache line) per entry; v32_0 / v32_1 hold (r, u, s) of
+  // the one-reduction CG interleaved per row (null in the batched kernel)
+  float* x32;
+  float2* rp32;
   float4 *v32_0, *v32_1;
   double* lr_t;  // k-vector F' v of a factored dense Q (batch only)
   double* part;         // [NSLOT][nb]

@@ -465,10 +465,11 @@ __device__ __attribute__((noinline)) void phase_eval_avg(const SolveParams& P, B
 }
 
 // CG product: p = r + beta p_prev on the owned rows (FP64, stored), and
-// q = (Q + I/tau) p with p gathered through GatherDir; partial p.q.
-template <bool DENSE, typename V, typename T>
-__device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Block B, const V* qval, const T* rg, const T* ppg,
-                              const double* pprev, double* pcur, float* pcur32, double beta, int first,
+// q = (Q + I/tau) p with p gathered through gp (GatherDir on the FP64 r and
+// p_prev, or GatherDir2 on the FP32 (r, p) records); partial p.q.
+template <bool DENSE, typename V, typename G>
+__device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Block B, const V* qval, const G gp,
+                              const double* pprev, double* pcur, double beta, int first,
                               double inv_tau, double* lds, double* svec) {
   if constexpr (DENSE) {
     dense_cg_spmv(P, B, qval, pprev, pcur, beta, first, inv_tau, lds, svec);
@@ -476,15 +477,15 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Bl
   }
   const WgPart& pt = P.w_cg;
   double s[1] = {0.0};
+  using T = std::conditional_t<sizeof(V) == 4, float, double>;  // gathered t: FP32 with FP32 values
   if (P.lr_d) {  // low-rank Q: (P t)_i with t = P' p gathered, then + (d_i + 1/tau) p_i
     const T* tv;
-    if constexpr (sizeof(T) == 4) tv = (const T*)P.lr_pt32; else tv = (const T*)P.lr_pt;
+    if constexpr (sizeof(V) == 4) tv = (const T*)P.lr_pt32; else tv = (const T*)P.lr_pt;
     const GatherVec<T> gt{tv};
     auto epi = [&](int i, double pt_i) {
       const double pi = first ? P.r[i] : P.r[i] + beta * pprev[i];
       const double qi = pt_i + (gld(P.lr_d + i) + inv_tau) * pi;
       pcur[i] = pi;
-      if (pcur32) pcur32[i] = (float)pi;
       P.q[i] = qi;
       s[0] += pi * qi;
     };
@@ -501,12 +502,10 @@ __device__ __attribute__((noinline)) void phase_cg_spmv(const SolveParams& P, Bl
     if (B.tid == 0) P.part[S_PQ * B.nb + B.b] = s[0];
     return;
   }
-  GatherDir<T> gp{rg, ppg, beta, first};
   auto epi = [&](int i, double qp) {
     const double pi = first ? P.r[i] : P.r[i] + beta * pprev[i];
     const double qi = qp + pi * inv_tau;
     pcur[i] = pi;
-    if (pcur32) pcur32[i] = (float)pi;
     P.q[i] = qi;
     s[0] += pi * qi;
   };
@@ -562,7 +561,7 @@ __device__ __attribute__((noinline)) void phase_cg_update(const SolveParams& P, 
     P.r[i] = ri;
     if (mixed) {
       P.x32[i] = (float)xi;
-      P.r32[i] = (float)ri;
+      gst2(P.rp32 + i, (float)ri, (float)pi);  // the next product's (r, p_prev)
     }
     s[0] += ri * ri;
   }
@@ -1523,7 +1522,7 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
       if (op == OP_CG_SPMV) {
         const int cur = C.cur;
         if (mixed)
-          phase_lr_t(P, B, P.Lt.val32, GatherDir<float>{P.r32, cur ? P.p32_0 : P.p32_1, C.beta, C.first}, lds);
+          phase_lr_t(P, B, P.Lt.val32, GatherDir2{P.rp32, C.beta, C.first}, lds);
         else
           phase_lr_t(P, B, P.Lt.val, GatherDir<double>{P.r, cur ? P.p0 : P.p1, C.beta, C.first}, lds);
       } else {
@@ -1544,7 +1543,7 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         if (P.v32_0)
           phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? (float*)P.v32_0 : nullptr, 4, 0, lds, svec);
         else
-          phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? P.r32 : nullptr, 1, 0, lds, svec,
+          phase_nside<DENSE>(P, P.w_n1, B, P.x, P.y, P.r, mixed ? (float*)P.rp32 : nullptr, 2, 0, lds, svec,
                              P.qx ? (C.exact ? QX_FORM : QX_KEPT) : QX_INTO_Q);
         if (B.tid == 0) {
           double f = 0.0;
@@ -1577,11 +1576,11 @@ __device__ bool drive(const SolveParams& P, Block B, GridSync& gs, Ctl& C, doubl
         double* pc = cur ? P.p1 : P.p0;
         const double* pp = cur ? P.p0 : P.p1;
         if (mixed)
-          phase_cg_spmv<DENSE>(P, B, P.Q.val32, (const float*)P.r32, (const float*)(cur ? P.p32_0 : P.p32_1), pp,
-                               pc, cur ? P.p32_1 : P.p32_0, C.beta, C.first, C.inv_tau, lds, svec);
+          phase_cg_spmv<DENSE>(P, B, P.Q.val32, GatherDir2{P.rp32, C.beta, C.first}, pp, pc, C.beta, C.first,
+                               C.inv_tau, lds, svec);
         else
-          phase_cg_spmv<DENSE>(P, B, P.Q.val, (const double*)P.r, pp, pp, pc, nullptr, C.beta, C.first, C.inv_tau,
-                               lds, svec);
+          phase_cg_spmv<DENSE>(P, B, P.Q.val, GatherDir<double>{P.r, pp, C.beta, C.first}, pp, pc, C.beta, C.first,
+                               C.inv_tau, lds, svec);
         break;
       }
       case OP_CG_UPDATE:
