@@ -24,15 +24,40 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     """Compile every HIP/C++ source of the library into libpdhcg.so (always
-    recompiles).  Returns the library path."""
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd))
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
+    recompiles): one object per source, compiled in parallel (each hipcc runs
+    its host and device passes), then linked.  Returns the library path."""
+    import shutil
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    inc = ["-I", os.path.join(ROOT, "include")]
+    obj_dir = tempfile.mkdtemp(prefix="pdhcg_build_")
+    try:
+        objs = [os.path.join(obj_dir, os.path.basename(src) + ".o") for src in sources()]
+        compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+        def compile_one(pair):
+            src, obj = pair
+            cmd = ["hipcc", *compile_flags, *inc, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd))
+            return subprocess.run(cmd, capture_output=True, text=True)
+
+        workers = max(1, min(len(objs), os.cpu_count() or 1, 8))
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            results = list(pool.map(compile_one, zip(sources(), objs)))
+        for src, res in zip(sources(), results):
+            if res.returncode != 0:
+                raise RuntimeError(f"hipcc failed on {src}:\n" + res.stdout + res.stderr)
+        tmp = LIB + f".tmp{os.getpid()}"
+        cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd))
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc link failed:\n" + res.stdout + res.stderr)
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(obj_dir, ignore_errors=True)
     return LIB
 
 
