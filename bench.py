@@ -41,7 +41,7 @@ CALIBRATION_BYTES = 1 << 30   # the --calibrate-copy kernel reads and writes 1 G
 # they are launched and fed; the network, the standalone product and the
 # preconditioning kernels do not run in the measured launches
 SOLVER_SOURCES = ["paper_2405_16160_amd/csrc/solve_kernels.hip", "paper_2405_16160_amd/csrc/batch_kernels.hip",
-                  "paper_2405_16160_amd/csrc/batch_kernels_512.hip",
+                  "paper_2405_16160_amd/csrc/batch_kernels_512.hip", "paper_2405_16160_amd/csrc/solve_kernels_256.hip",
                   "paper_2405_16160_amd/csrc/solver.hpp", "paper_2405_16160_amd/csrc/device.hpp",
                   "paper_2405_16160_amd/csrc/internal.hpp", "paper_2405_16160_amd/csrc/api.cpp",
                   "include/pdhcg.h"]

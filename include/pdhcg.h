@@ -117,6 +117,13 @@ typedef struct {
                                         z^k.  eta starts at step_eta_factor / ||A||_2 and persists
                                         across restarts.  The single-QP solve then keeps its CG
                                         state in device memory (no chained steps) */
+    int32_t threads;                 /* threads per workgroup of the single-QP solve and power
+                                        kernels: 0 = planner's choice (256, two workgroups per CU,
+                                        once the gathered vectors outgrow the L2 of one XCD,
+                                        16 n bytes, for a sparse Q; else 512, one per CU), 256
+                                        or 512.  Every setting computes the same iterates up to
+                                        the order of the FP64 reductions (the row partitions
+                                        follow the workgroup count) */
 } pdhcg_settings;
 
 typedef struct {
@@ -333,9 +340,11 @@ int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* 
  * (log2 of the scaling) may be NULL. */
 int pdhcg_autotune(pdhcg_handle* h, int32_t iters, int32_t* num_blocks, int32_t* group_scale);
 
-/* Grid size and row-split parameters the planner chose (for reporting). */
+/* Grid size, row-split parameters and threads per workgroup of the
+ * cooperative kernels that the planner chose (for reporting); any output may
+ * be NULL. */
 int pdhcg_plan_info(const pdhcg_handle* h, int32_t* num_blocks, int32_t* group_n, int32_t* group_q,
-                    int32_t* group_m, int64_t* long_rows);
+                    int32_t* group_m, int64_t* long_rows, int32_t* threads);
 
 void pdhcg_destroy(pdhcg_handle* h);
 

@@ -305,7 +305,8 @@ struct pdhcg_handle {
   std::vector<double> c_host;  // c, for relKKT(0, 0) when b changes
   std::vector<int64_t> qrp_h, arp_h, trp_h;  // host row pointers, for re-planning
   int gscale = 0;              // lane-group scaling (log2) chosen by the autotuner
-  int max_nb = 1;
+  int max_nb = 1;              // co-resident workgroups of the cooperative kernels at `threads`
+  int threads = kSolveBlock;   // threads per workgroup of the cooperative kernels
 
   ~pdhcg_handle() {
     if (ev0) (void)hipEventDestroy(ev0);
@@ -420,6 +421,8 @@ int check_settings(const pdhcg_settings* s) {
   if (s->pock_chambolle != 0 && s->pock_chambolle != 1)
     return fail(PDHCG_ERR_INVALID_ARGUMENT, "pock_chambolle must be 0 or 1");
   if (s->step_rule != 0 && s->step_rule != 1) return fail(PDHCG_ERR_INVALID_ARGUMENT, "step_rule must be 0 or 1");
+  if (s->threads != 0 && s->threads != 256 && s->threads != kSolveBlock)
+    return fail(PDHCG_ERR_INVALID_ARGUMENT, "threads must be 0, 256 or 512");
   return 0;
 }
 
@@ -444,9 +447,9 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
   const int64_t* arp = h->m ? h->arp_h.data() : nullptr;
   const int64_t* trp = h->m ? h->trp_h.data() : nullptr;
   for (DevPart* d : {&h->pn1, &h->pcg, &h->pm, &h->pt, &h->plr}) free_part(h, *d);
-  if ((rc = upload_part(h, build_part(h->n, nb, qrp, trp, gscale), h->pn1))) return rc;
-  const HostPart pcg = build_part(h->n, nb, qrp, nullptr, gscale);
-  const HostPart pm = build_part(h->m, nb, arp, nullptr, gscale);
+  if ((rc = upload_part(h, build_part(h->n, nb, qrp, trp, gscale, h->threads), h->pn1))) return rc;
+  const HostPart pcg = build_part(h->n, nb, qrp, nullptr, gscale, h->threads);
+  const HostPart pm = build_part(h->m, nb, arp, nullptr, gscale, h->threads);
   h->cg_bounds = pcg.bounds;
   h->m_bounds = pm.bounds;
   h->cg_one_tile = 1;
@@ -454,32 +457,55 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
     if (pcg.tile_ptr[b + 1] - pcg.tile_ptr[b] != 1 || pcg.long_ptr[b + 1] != pcg.long_ptr[b]) h->cg_one_tile = 0;
   if ((rc = upload_part(h, pcg, h->pcg))) return rc;
   if ((rc = upload_part(h, pm, h->pm))) return rc;
-  if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr, gscale), h->pt))) return rc;
-  if (h->lowrank && (rc = upload_part(h, build_part(h->k, nb, h->lrp_h.data(), nullptr, gscale), h->plr)))
+  if ((rc = upload_part(h, build_part(h->n, nb, trp, nullptr, gscale, h->threads), h->pt))) return rc;
+  if (h->lowrank && (rc = upload_part(h, build_part(h->k, nb, h->lrp_h.data(), nullptr, gscale, h->threads), h->plr)))
     return rc;
   return 0;
 }
 
-int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) {
-  int rc;
-  int dev = 0, cus = 0;
+// Threads per workgroup of the cooperative kernels: the setting, else 256
+// (two workgroups per CU, twice the gathers in flight per CU at twice the
+// arrivals per grid barrier) once the gathered vectors stream from the
+// last-level cache (16 n bytes beyond the L2 of one XCD, where the planner
+// also takes the textbook CG form), and 512 below that size or for a
+// low-rank Q.  (Power-law QP n = 2e6 to 1e-4: 606 ms against 654 ms;
+// random QP n = 1e5: 66.6 ms against 60.0 ms.)
+int solve_threads(const pdhcg_handle* h, const pdhcg_settings& s) {
+  if (s.threads) return s.threads;
+  return (!h->lowrank && 16 * h->n > h->l2_bytes) ? 256 : kSolveBlock;
+}
+
+// the co-resident workgroups of the cooperative kernels at h->threads
+int set_max_nb(pdhcg_handle* h) {
+  int dev = 0, cus = 0, per_cu = 0;
   HIPX(hipGetDevice(&dev));
   HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  int l2 = 0;
+  HIPX(solve_occupancy(h->threads, &per_cu));
+  h->max_nb = std::max(1, std::min(cus * std::max(per_cu, 1), 1024));
+  return 0;
+}
+
+// The planner's grid: about a thousand work units per workgroup, below which
+// the grid barrier outweighs the work it spreads (n = 1000 random QP: 64
+// workgroups 65 ms, 16 70 ms, 128 69 ms per solve), up to one 512-thread or
+// two 256-thread workgroups per CU of 256.
+int default_nb(const pdhcg_handle* h) {
+  const double work = (double)h->nnzQ + 0.25 * (double)h->nnzA + (double)(h->n + h->m);
+  const int cap = 256 * (kSolveBlock / h->threads);
+  int nb = 8;
+  while (nb < cap && work / nb > 1024.0) nb <<= 1;
+  return nb;
+}
+
+int plan(pdhcg_handle* h, const HostCsr& Q, const HostCsr& A, const HostCsr& T) {
+  int rc;
+  int dev = 0, l2 = 0;
+  HIPX(hipGetDevice(&dev));
   HIPX(hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, dev));
   if (l2 > 0) h->l2_bytes = l2;
-  int per_cu = 0;
-  HIPX(solve_occupancy(&per_cu));
-  h->max_nb = std::max(1, std::min(cus * std::max(per_cu, 1), 1024));
-  int nb = h->s.num_blocks;
-  if (nb == 0) {
-    // about a thousand work units per workgroup: below that the grid barrier
-    // outweighs the work it spreads (n = 1000 random QP: 64 workgroups
-    // 65 ms, 16 70 ms, 128 69 ms per solve)
-    const double work = (double)h->nnzQ + 0.25 * (double)h->nnzA + (double)(h->n + h->m);
-    nb = 8;
-    while (nb < 256 && work / nb > 1024.0) nb <<= 1;
-  }
+  h->threads = solve_threads(h, h->s);
+  if ((rc = set_max_nb(h))) return rc;
+  const int nb = h->s.num_blocks ? h->s.num_blocks : default_nb(h);
   h->qrp_h = Q.rowptr;
   if (A.nrows) {
     h->arp_h = A.rowptr;
@@ -519,7 +545,7 @@ int plan_residency(pdhcg_handle* h, SolveParams& p) {
   HIPX(hipGetDevice(&dev));
   HIPX(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HIPX(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
-  HIPX(solve_kernel_lds(&stat));
+  HIPX(solve_kernel_lds(h->threads, &stat));
   const int per_cu = (h->nb + cus - 1) / std::max(cus, 1);
   const int64_t budget = (int64_t)lds_cu / std::max(per_cu, 1) - stat - 256;
   auto block = [&](const std::vector<int32_t>& bnd, const std::vector<int64_t>& rp) {
@@ -554,7 +580,7 @@ int plan_residency(pdhcg_handle* h, SolveParams& p) {
   p.own_off = (int32_t)(q_end + (p.res_m ? ba : 0));
   if (total > 0) {
     int occ = 0;
-    HIPX(solve_occupancy_dyn((int)total, &occ));
+    HIPX(solve_occupancy_dyn(h->threads, (int)total, &occ));
     if (occ * cus < h->nb) {  // would break co-residency: keep everything in device memory
       p.res_cg = p.res_m = p.own_cg = 0;
       total = 0;
@@ -651,7 +677,7 @@ int estimate_norm(pdhcg_handle* h) {
   pp.pm = h->pm.view();
   pp.iters = h->s.power_iters;
   HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * kBarWords, h->stream));
-  HIPX(launch_power(pp, h->nb, h->stream));
+  HIPX(launch_power(h->threads, pp, h->nb, h->stream));
   double v = 0.0;
   uint64_t abort_word = 0;
   HIPX(hipMemcpyAsync(&v, h->scratch, sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -692,6 +718,7 @@ void pdhcg_default_settings(pdhcg_settings* s) {
   s->ruiz_iters = 0;
   s->pock_chambolle = 0;
   s->step_rule = 0;
+  s->threads = 0;
 }
 
 }  // extern "C"
@@ -814,8 +841,11 @@ int create_impl(pdhcg_handle** out, const pdhcg_csr* Qc, const pdhcg_csr* Ac, co
   h->setup_s = now_s() - t0;
   if (s->verbose && lowrank) fprintf(stderr, "[pdhcg] low-rank Q = P P' + diag(d), k=%lld\n", (long long)h->k);
   if (s->verbose)
-    fprintf(stderr, "[pdhcg] n=%lld m=%lld nnzQ=%lld nnzA=%lld nb=%d groups n1=%d q=%d m=%d ||A||=%.6g setup=%.3fs\n",
-            (long long)n, (long long)m, (long long)h->nnzQ, (long long)h->nnzA, h->nb, h->pn1.group, h->pcg.group,
+    fprintf(stderr,
+            "[pdhcg] n=%lld m=%lld nnzQ=%lld nnzA=%lld nb=%d x %d threads groups n1=%d q=%d m=%d ||A||=%.6g "
+            "setup=%.3fs\n",
+            (long long)n, (long long)m, (long long)h->nnzQ, (long long)h->nnzA, h->nb, h->threads, h->pn1.group,
+            h->pcg.group,
             h->pm.group, h->norm_A, h->setup_s);
   *out = h;
   return 0;
@@ -844,10 +874,15 @@ int pdhcg_set_settings(pdhcg_handle* h, const pdhcg_settings* s) {
     return fail(PDHCG_ERR_INVALID_ARGUMENT, "a low-rank Q takes the constant step rule (step_rule = 0)");
   if (s->ruiz_iters != h->s.ruiz_iters || s->pock_chambolle != h->s.pock_chambolle)
     return fail(PDHCG_ERR_INVALID_ARGUMENT, "ruiz_iters and pock_chambolle are fixed at pdhcg_create");
-  const bool replan = s->num_blocks != 0 && s->num_blocks != h->nb;
+  const int threads = solve_threads(h, *s);
+  const bool replan = (s->num_blocks != 0 && s->num_blocks != h->nb) || threads != h->threads;
   const int32_t old_power = h->s.power_iters;
   h->s = *s;
-  if (replan && (rc = plan_grid(h, s->num_blocks, h->gscale))) return rc;
+  if (threads != h->threads) {  // other kernels: their co-residency and tile sizes
+    h->threads = threads;
+    if ((rc = set_max_nb(h))) return rc;
+  }
+  if (replan && (rc = plan_grid(h, s->num_blocks ? s->num_blocks : default_nb(h), h->gscale))) return rc;
   if (s->precision == 1 && (rc = ensure_mixed(h))) return rc;
   if (s->power_iters != old_power && (rc = estimate_norm(h))) return rc;
   return 0;
@@ -908,7 +943,7 @@ int pdhcg_solve(pdhcg_handle* h, const double* x0, const double* y0, double* x_o
   for (;;) {
     HIPX(hipMemsetAsync(h->bar, 0, sizeof(uint64_t) * kBarWords, h->stream));
     HIPX(hipEventRecord(h->ev0, h->stream));
-    HIPX(launch_solve(h->d_params, h->nb, h->res_bytes, h->stream));
+    HIPX(launch_solve(h->threads, h->d_params, h->nb, h->res_bytes, h->stream));
     HIPX(hipEventRecord(h->ev1, h->stream));
     HIPX(hipMemcpyAsync(&st, h->st, sizeof(st), hipMemcpyDeviceToHost, h->stream));
     HIPX(hipStreamSynchronize(h->stream));
@@ -1033,13 +1068,14 @@ int pdhcg_autotune(pdhcg_handle* h, int32_t iters, int32_t* num_blocks, int32_t*
 }
 
 int pdhcg_plan_info(const pdhcg_handle* h, int32_t* num_blocks, int32_t* group_n, int32_t* group_q, int32_t* group_m,
-                    int64_t* long_rows) {
+                    int64_t* long_rows, int32_t* threads) {
   if (!h) return fail(PDHCG_ERR_INVALID_ARGUMENT, "null handle");
   if (num_blocks) *num_blocks = h->nb;
   if (group_n) *group_n = h->pn1.group;
   if (group_q) *group_q = h->pcg.group;
   if (group_m) *group_m = h->pm.group;
   if (long_rows) *long_rows = h->pn1.nlong + h->pcg.nlong + h->pm.nlong;
+  if (threads) *threads = h->threads;
   return 0;
 }
 

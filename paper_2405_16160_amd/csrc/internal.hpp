@@ -293,12 +293,17 @@ int solve_batch_in_region(int32_t count, const pdhcg_csr* Qs, const pdhcg_csr* A
 hipError_t launch_batch_clock(uint64_t* t0, hipStream_t s);
 hipError_t launch_batch_256(const BatchParams& p, int count, hipStream_t s);
 hipError_t launch_batch_512(const BatchParams& p, int count, hipStream_t s);
-hipError_t launch_solve(const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s);
+// the cooperative kernels at `threads` per workgroup (512: solve_kernels.hip;
+// 256: solve_kernels_256.hip, whose kernels solve_kernel_256() and
+// power_kernel_256() return)
+hipError_t launch_solve(int threads, const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s);
+const void* solve_kernel_256();
+const void* power_kernel_256();
 // static LDS bytes of the solve kernel, and the co-resident workgroups per CU
 // it reaches with dyn_lds bytes of dynamic LDS
-hipError_t solve_kernel_lds(int* static_bytes);
-hipError_t solve_occupancy_dyn(int dyn_lds, int* per_cu);
-hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s);
+hipError_t solve_kernel_lds(int threads, int* static_bytes);
+hipError_t solve_occupancy_dyn(int threads, int dyn_lds, int* per_cu);
+hipError_t launch_power(int threads, const PowerParams& p, int nb, hipStream_t s);
 hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hipStream_t s);
 // standalone product y = M x over host-cut tiles (spmv_kernels.hip)
 hipError_t launch_spmv_stream(const int32_t* rowptr, const int32_t* col, const double* val, const float* val32,
@@ -346,6 +351,6 @@ int precond_lanes(int64_t nnz, int64_t nrows);
 hipError_t launch_diag(const double* x, const double* scale, int64_t n, int op, double* out, hipStream_t s);
 // workgroups per CU that the persistent kernels can keep resident (the
 // smaller of the solve and power kernels)
-hipError_t solve_occupancy(int* per_cu);
+hipError_t solve_occupancy(int threads, int* per_cu);
 
 }  // namespace pdhcg

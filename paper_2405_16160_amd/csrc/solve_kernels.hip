@@ -7,74 +7,12 @@
 #include "solver.hpp"
 
 namespace pdhcg {
-namespace {
 
-// Copy the workgroup's rows of M (row pointers, columns, values of vbytes)
-// into its resident block at base and record the block in w.
-__device__ void place_resident(WgPart& w, const DevMat& M, char* base, int vbytes) {
-  const int nr = w.r1 - w.r0;
-  const int e0 = M.rowptr[w.r0], ne = M.rowptr[w.r1] - e0;
-  int32_t* lrp = (int32_t*)base;
-  int32_t* lcol = (int32_t*)(base + align16(4 * (int64_t)(nr + 1)));
-  char* lval = (char*)lcol + align16(4 * (int64_t)ne);
-  for (int j = threadIdx.x; j <= nr; j += kBlock) lrp[j] = gld(M.rowptr + w.r0 + j);
-  for (int k = threadIdx.x; k < ne; k += kBlock) lcol[k] = gld(M.col + e0 + k);
-  if (vbytes == 4)
-    for (int k = threadIdx.x; k < ne; k += kBlock) ((float*)lval)[k] = gld(M.val32 + e0 + k);
-  else
-    for (int k = threadIdx.x; k < ne; k += kBlock) ((double*)lval)[k] = gld(M.val + e0 + k);
-  if (threadIdx.x == 0) {
-    w.e0 = e0;
-    w.lrp = lrp;
-    w.lcol = lcol;
-    w.lval = lval;
-  }
-}
-
-}  // namespace
-
-__global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) {
-  __shared__ SolveParams Ps;
-  extern __shared__ __align__(16) char dyn_lds[];
-  load_params(Ps, Pg, (int)blockIdx.x);
-  if (Ps.res_cg) place_resident(Ps.w_cg, Ps.Q, dyn_lds, Ps.res_vbytes);
-  if (Ps.res_m) place_resident(Ps.w_m, Ps.A, dyn_lds + Ps.res_m_off, Ps.res_vbytes);
-  if (threadIdx.x == 0) Ps.cg_own = Ps.own_cg ? (double*)(dyn_lds + Ps.own_off) : nullptr;
-  __syncthreads();
-  const SolveParams& P = Ps;
-  const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
-  __shared__ double lds[kWaves * 16];
-  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
-  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
-  if (!gs.init()) {
-    if (B.b == 0 && B.tid == 0) P.st->done = -1;  // barrier failure: reported as a HIP error
-    return;
-  }
-  __shared__ Ctl C;
-  if (B.tid == 0) C.S = *P.st;
-  __syncthreads();
-  if (C.S.done) return;
-  const bool ok = drive<false>(P, B, gs, C, nb_inf, nc_inf, lds, nullptr, P.iters_this_launch);
-  if (B.b == 0 && B.tid == 0) {
-    if (!ok)
-      P.st->done = -1;  // barrier failure: reported as a HIP error
-    else
-      *P.st = C.S;
-  }
-}
+__global__ void __launch_bounds__(kBlock) pdhcg_solve_kernel(const SolveParams* __restrict__ Pg) { solve_body(Pg); }
 
 // -------------------------------------------------------- power iteration
 
-__global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) {
-  __shared__ double lds[kWaves * 8];
-  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
-  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
-  if (!gs.init()) return;  // (the host finds the abort word raised)
-  double nrm = 0.0;
-  if (power_norm(P.A, P.At, P.v, P.w, P.u, P.part, P.pn, P.pm, P.iters, B, gs, lds, &nrm) && B.b == 0 &&
-      B.tid == 0)
-    P.out[0] = nrm;
-}
+__global__ void __launch_bounds__(kBlock) pdhcg_power_kernel(PowerParams P) { power_body(P); }
 
 // ------------------------------------------------------ small helper kernels
 
@@ -107,39 +45,50 @@ __global__ void to_f32_kernel(const double* in, float* out, int64_t n) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_solve(const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s) {
-  const SolveParams* pc = p_dev;
-  void* args[] = {&pc};
-  if (dyn_lds > 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)pdhcg_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       dyn_lds);
-    if (e != hipSuccess) return e;
-  }
-  return hipLaunchCooperativeKernel((const void*)pdhcg_solve_kernel, dim3(nb), dim3(kBlock), args,
-                                    (unsigned)dyn_lds, s);
+// the solve kernel for `threads` per workgroup: this unit's (512 threads), or
+// the 256-thread copy of solve_kernels_256.hip
+static const void* solve_kernel_for(int threads) {
+  return threads == kBlock ? (const void*)pdhcg_solve_kernel : solve_kernel_256();
 }
 
-hipError_t solve_kernel_lds(int* static_bytes) {
+// the power iteration at the same workgroup size (it walks the same row
+// partitions, whose tiles are sized for it)
+static const void* power_kernel_for(int threads) {
+  return threads == kBlock ? (const void*)pdhcg_power_kernel : power_kernel_256();
+}
+
+hipError_t launch_solve(int threads, const SolveParams* p_dev, int nb, int dyn_lds, hipStream_t s) {
+  const SolveParams* pc = p_dev;
+  void* args[] = {&pc};
+  const void* k = solve_kernel_for(threads);
+  if (dyn_lds > 0) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipLaunchCooperativeKernel(k, dim3(nb), dim3(threads), args, (unsigned)dyn_lds, s);
+}
+
+hipError_t solve_kernel_lds(int threads, int* static_bytes) {
   hipFuncAttributes a;
-  hipError_t e = hipFuncGetAttributes(&a, (const void*)pdhcg_solve_kernel);
+  hipError_t e = hipFuncGetAttributes(&a, solve_kernel_for(threads));
   if (e != hipSuccess) return e;
   *static_bytes = (int)a.sharedSizeBytes;
   return hipSuccess;
 }
 
-hipError_t solve_occupancy_dyn(int dyn_lds, int* per_cu) {
+hipError_t solve_occupancy_dyn(int threads, int dyn_lds, int* per_cu) {
+  const void* k = solve_kernel_for(threads);
   if (dyn_lds > 0) {
-    hipError_t e = hipFuncSetAttribute((const void*)pdhcg_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       dyn_lds);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn_lds);
     if (e != hipSuccess) return e;
   }
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)pdhcg_solve_kernel, kBlock, dyn_lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, threads, dyn_lds);
 }
 
-hipError_t launch_power(const PowerParams& p, int nb, hipStream_t s) {
+hipError_t launch_power(int threads, const PowerParams& p, int nb, hipStream_t s) {
   PowerParams pc = p;
   void* args[] = {&pc};
-  return hipLaunchCooperativeKernel((const void*)pdhcg_power_kernel, dim3(nb), dim3(kBlock), args, 0, s);
+  return hipLaunchCooperativeKernel(power_kernel_for(threads), dim3(nb), dim3(threads), args, 0, s);
 }
 
 hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hipStream_t s) {
@@ -151,11 +100,11 @@ hipError_t launch_init_point(const SolveParams* p_dev, int64_t n, int64_t m, hip
   return hipGetLastError();
 }
 
-hipError_t solve_occupancy(int* per_cu) {
+hipError_t solve_occupancy(int threads, int* per_cu) {
   int a = 0, b = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)pdhcg_solve_kernel, kBlock, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, solve_kernel_for(threads), threads, 0);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)pdhcg_power_kernel, kBlock, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, power_kernel_for(threads), threads, 0);
   if (e != hipSuccess) return e;
   *per_cu = a < b ? a : b;
   return hipSuccess;

@@ -1789,6 +1789,64 @@ __device__ bool power_norm(const DevMat& A, const DevMat& At, double* v, double*
   return true;
 }
 
+// ------------------------------------------------------- cooperative solve
+
+// Copy the workgroup's rows of M (row pointers, columns, values of vbytes)
+// into its resident block at base and record the block in w.
+__device__ __forceinline__ void place_resident(WgPart& w, const DevMat& M, char* base, int vbytes) {
+  const int nr = w.r1 - w.r0;
+  const int e0 = M.rowptr[w.r0], ne = M.rowptr[w.r1] - e0;
+  int32_t* lrp = (int32_t*)base;
+  int32_t* lcol = (int32_t*)(base + align16(4 * (int64_t)(nr + 1)));
+  char* lval = (char*)lcol + align16(4 * (int64_t)ne);
+  for (int j = threadIdx.x; j <= nr; j += kBlock) lrp[j] = gld(M.rowptr + w.r0 + j);
+  for (int k = threadIdx.x; k < ne; k += kBlock) lcol[k] = gld(M.col + e0 + k);
+  if (vbytes == 4)
+    for (int k = threadIdx.x; k < ne; k += kBlock) ((float*)lval)[k] = gld(M.val32 + e0 + k);
+  else
+    for (int k = threadIdx.x; k < ne; k += kBlock) ((double*)lval)[k] = gld(M.val + e0 + k);
+  if (threadIdx.x == 0) {
+    w.e0 = e0;
+    w.lrp = lrp;
+    w.lcol = lcol;
+    w.lval = lval;
+  }
+}
+
+// The cooperative solve of one QP (the body of the solve kernels of both
+// workgroup sizes): parameter block and partition share into LDS, the rows
+// planned resident copied there, then the driver; the state goes back to
+// device memory at the end (or a barrier failure is flagged).
+__device__ __forceinline__ void solve_body(const SolveParams* __restrict__ Pg) {
+  __shared__ SolveParams Ps;
+  extern __shared__ __align__(16) char dyn_lds[];
+  load_params(Ps, Pg, (int)blockIdx.x);
+  if (Ps.res_cg) place_resident(Ps.w_cg, Ps.Q, dyn_lds, Ps.res_vbytes);
+  if (Ps.res_m) place_resident(Ps.w_m, Ps.A, dyn_lds + Ps.res_m_off, Ps.res_vbytes);
+  if (threadIdx.x == 0) Ps.cg_own = Ps.own_cg ? (double*)(dyn_lds + Ps.own_off) : nullptr;
+  __syncthreads();
+  const SolveParams& P = Ps;
+  const double nb_inf = P.nb_inf, nc_inf = P.nc_inf;
+  __shared__ double lds[kWaves * 16];
+  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
+  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  if (!gs.init()) {
+    if (B.b == 0 && B.tid == 0) P.st->done = -1;  // barrier failure: reported as a HIP error
+    return;
+  }
+  __shared__ Ctl C;
+  if (B.tid == 0) C.S = *P.st;
+  __syncthreads();
+  if (C.S.done) return;
+  const bool ok = drive<false>(P, B, gs, C, nb_inf, nc_inf, lds, nullptr, P.iters_this_launch);
+  if (B.b == 0 && B.tid == 0) {
+    if (!ok)
+      P.st->done = -1;  // barrier failure: reported as a HIP error
+    else
+      *P.st = C.S;
+  }
+}
+
 // -------------------------------------------------------------- batched solve
 
 // One workgroup per QP: workgroup g solves instance order[g] (the host sorts
@@ -1854,6 +1912,19 @@ __device__ __forceinline__ void batch_solve(const BatchParams& BP) {
   else
     drive<false>(P, B, gs, C, P.nb_inf, P.nc_inf, lds, svec, INT64_MAX);
   if (B.tid == 0) BP.st[idx] = C.S;
+}
+
+// ||A||_2 by the power iteration on A'A, every workgroup taking its rows of
+// A' and A (the launch of the single-QP path before its first solve)
+__device__ __forceinline__ void power_body(const PowerParams& P) {
+  __shared__ double lds[kWaves * 8];
+  Block B{(int)blockIdx.x, (int)gridDim.x, (int)threadIdx.x};
+  GridSync gs{P.bar, (uint32_t)gridDim.x, 0};
+  if (!gs.init()) return;  // (the host finds the abort word raised)
+  double nrm = 0.0;
+  if (power_norm(P.A, P.At, P.v, P.w, P.u, P.part, P.pn, P.pm, P.iters, B, gs, lds, &nrm) && B.b == 0 &&
+      B.tid == 0)
+    P.out[0] = nrm;
 }
 
 }  // namespace

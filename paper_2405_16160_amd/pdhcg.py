@@ -55,7 +55,8 @@ class pdhcg_settings(C.Structure):
                 ("primal_weight_init", C.c_double), ("step_eta_factor", C.c_double), ("power_iters", C.c_int32),
                 ("precision", C.c_int32), ("time_limit_s", C.c_double), ("num_blocks", C.c_int32),
                 ("warm_fallback", C.c_int32), ("verbose", C.c_int32), ("cg_form", C.c_int32),
-                ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32), ("step_rule", C.c_int32)]
+                ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32), ("step_rule", C.c_int32),
+                ("threads", C.c_int32)]
 
 
 class pdhcg_lowrank(C.Structure):
@@ -119,7 +120,7 @@ def lib():
         L.pdhcg_solve_multi_rhs.argtypes = [C.c_int32, C.POINTER(pdhcg_csr), C.POINTER(pdhcg_csr), P, P, P, P, P, P,
                                             P, C.POINTER(pdhcg_settings), P]
         L.pdhcg_spmv.argtypes = [P, C.c_int32, C.c_int32, P, P, C.c_int32]
-        L.pdhcg_plan_info.argtypes = [P, P, P, P, P, P]
+        L.pdhcg_plan_info.argtypes = [P, P, P, P, P, P, P]
         L.pdhcg_get_scaling.argtypes = [P, P, P, C.c_int32]
         L.pdhcg_autotune.argtypes = [P, C.c_int32, P, P]
         L.pdhcg_destroy.argtypes = [P]
@@ -171,6 +172,7 @@ class Settings:
     ruiz_iters: int = 0
     pock_chambolle: int = 0
     step_rule: int = 0
+    threads: int = 0
 
     def c(self) -> pdhcg_settings:
         s = pdhcg_settings()
@@ -287,10 +289,10 @@ class Solver:
         return {"num_blocks": nb.value, "group_scale": g.value}
 
     def plan_info(self) -> dict:
-        v = [C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()]
+        v = [C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32()]
         _check(lib().pdhcg_plan_info(self.h, *[C.byref(a) for a in v]))
         return dict(num_blocks=v[0].value, group_n=v[1].value, group_q=v[2].value, group_m=v[3].value,
-                    long_rows=v[4].value)
+                    long_rows=v[4].value, threads=v[5].value)
 
     def close(self):
         if getattr(self, "h", None):

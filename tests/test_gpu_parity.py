@@ -325,6 +325,62 @@ def test_autotune_then_solve():
     sol.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("form", [1, 2])
+def test_256_thread_workgroups(form, precision):
+    """The cooperative kernels compiled for 256-thread workgroups (two per
+    CU), forced on a small QP, meet the same contract in both CG forms and
+    both precisions."""
+    say(f"[solve] random_qp n=1000 instance=2 threads=256 cg_form={form} precision={precision}")
+    qp = I.random_qp(family=1, instance=2)
+    ref = oracle_ref(qp, ("rq1", 2))
+    x, y, r, info = gpu_solve(qp, tol_rel_kkt=1e-6, precision=precision, cg_form=form, threads=256)
+    say(f"  status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} plan={info}")
+    assert info["threads"] == 256
+    assert r["status"] == 0
+    check_contract(qp, x, y, ref)
+
+
+def test_256_thread_workgroups_long_rows():
+    """256-thread workgroups on the power-law QP with rows longer than a tile."""
+    say("[solve] power-law QP n=60000 m=30000 threads=256")
+    qp = I.powerlaw_qp(60_000, 30_000, family=3, instance=1)
+    x, y, r, info = gpu_solve(qp, tol_rel_kkt=1e-6, max_iters=200_000, threads=256)
+    say(f"  status={r['status_name']} iters={r['iters']} cg={r['cg_iters_total']} plan={info}")
+    assert info["long_rows"] > 0 and info["threads"] == 256
+    assert r["status"] == 0
+    assert O.kkt(qp, x, y)["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+
+
+def test_planner_workgroup_size_and_switch():
+    """Past the L2 of one XCD (16 n bytes) the planner takes 256-thread
+    workgroups and up to twice the grid; switching to 512 threads through the
+    settings re-plans the partitions, and both solves reach the tolerance on
+    the FP64 data in nearly the same iterations with nearly the same x."""
+    say("[solve] random_qp n=300000 m=150000 planner threads, then 512")
+    qp = I.random_qp(300_000, 150_000, 150_000, 1e-5, 7e-5, family=2, instance=3)
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-5, precision=1))
+    out = {}
+    try:
+        for threads in (0, 512):
+            if threads:
+                sol.set_settings(pdhcg.Settings(tol_rel_kkt=1e-5, precision=1, threads=threads))
+            x, y, r = sol.solve()
+            info = sol.plan_info()
+            say(f"  threads={threads} status={r['status_name']} iters={r['iters']} plan={info}")
+            assert r["status"] == 0
+            x, y = x.cpu().numpy(), y.cpu().numpy()
+            assert O.kkt(qp, x, y)["rel_kkt"] <= 1e-5 * (1 + 1e-6)
+            out[threads] = (x, r, info)
+    finally:
+        sol.close()
+    (x0, r0, i0), (x1, r1, i1) = out[0], out[512]
+    assert i0["threads"] == 256 and i1["threads"] == 512
+    assert i0["num_blocks"] > 256 >= i1["num_blocks"]
+    assert abs(r0["iters"] - r1["iters"]) <= max(64, r1["iters"] // 10)
+    assert np.linalg.norm(x0 - x1) / np.linalg.norm(x1) <= 1e-3
+
+
 # ----------------------------------------------- full-size power-law (2e6 x 1e6)
 
 def test_powerlaw_full_size_products_and_solve_properties():
