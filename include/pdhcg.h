@@ -331,13 +331,15 @@ int pdhcg_get_scaling(const pdhcg_handle* h, double* d1_out, double* d2_out, int
 int pdhcg_spmv(pdhcg_handle* h, int32_t which, int32_t precision, const double* x, double* y,
                int32_t repeats);
 
-/* Autotuner of the single-QP kernel: for each candidate grid size (64, 128,
- * 256, 512 workgroups, within what fits on the device) and lane-group scaling
- * (the planner's lane group per row halved, as planned, doubled) run `iters`
- * iterations from (0, 0) and time the solve kernel (HIP events); keep the
- * fastest per iteration and re-plan the row partitions for it.  The settings'
- * num_blocks becomes the chosen grid size.  num_blocks and group_scale
- * (log2 of the scaling) may be NULL. */
+/* Autotuner of the single-QP kernel: for each workgroup size (512 and 256
+ * threads), candidate grid size (64, 128, 256, 512 workgroups, within what
+ * stays co-resident at that size) and lane-group scaling (the planner's lane
+ * group per row halved, as planned, doubled) run `iters` iterations from
+ * (0, 0) and time the solve kernel (HIP events); keep the fastest per
+ * iteration and re-plan the row partitions for it.  The settings' num_blocks
+ * and threads become the chosen grid and workgroup sizes (pdhcg_plan_info
+ * reports both).  num_blocks and group_scale (log2 of the scaling) may be
+ * NULL. */
 int pdhcg_autotune(pdhcg_handle* h, int32_t iters, int32_t* num_blocks, int32_t* group_scale);
 
 /* Grid size, row-split parameters and threads per workgroup of the

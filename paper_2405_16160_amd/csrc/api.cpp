@@ -1038,30 +1038,41 @@ int pdhcg_autotune(pdhcg_handle* h, int32_t iters, int32_t* num_blocks, int32_t*
   h->s.time_limit_s = 0.0;
   h->s.verbose = 0;
   double best = 1e300;
-  int best_nb = h->nb, best_g = h->gscale;
-  for (int nb : {64, 128, 256, 512}) {
-    if (nb > h->max_nb) continue;
-    for (int g : {-1, 0, 1}) {
-      if ((rc = plan_grid(h, nb, g))) break;
-      pdhcg_result r;
-      if ((rc = pdhcg_solve(h, nullptr, nullptr, xs, ys, 1, &r))) break;
-      const double per = r.kernel_s / (double)std::max<int64_t>(r.iters, 1);
-      if (per < best) {
-        best = per;
-        best_nb = h->nb;
-        best_g = g;
+  int best_nb = h->nb, best_g = h->gscale, best_t = h->threads;
+  for (int t : {kSolveBlock, 256}) {
+    h->threads = t;
+    if ((rc = set_max_nb(h))) break;
+    for (int nb : {64, 128, 256, 512}) {
+      if (nb > h->max_nb) continue;
+      for (int g : {-1, 0, 1}) {
+        if ((rc = plan_grid(h, nb, g))) break;
+        pdhcg_result r;
+        if ((rc = pdhcg_solve(h, nullptr, nullptr, xs, ys, 1, &r))) break;
+        const double per = r.kernel_s / (double)std::max<int64_t>(r.iters, 1);
+        if (per < best) {
+          best = per;
+          best_nb = h->nb;
+          best_g = g;
+          best_t = t;
+        }
       }
+      if (rc) break;
     }
     if (rc) break;
   }
   h->s = saved;
+  // the best plan found so far, also after a failed candidate
+  h->threads = best_t;
+  int rc_plan = set_max_nb(h);
+  if (!rc_plan) rc_plan = plan_grid(h, best_nb, best_g);
   for (double* p : {xs, ys}) {
     (void)hipFree(p);
     h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), (void*)p), h->allocs.end());
   }
   if (rc) return rc;
-  if ((rc = plan_grid(h, best_nb, best_g))) return rc;
+  if (rc_plan) return rc_plan;
   h->s.num_blocks = best_nb;
+  h->s.threads = best_t;
   if (num_blocks) *num_blocks = best_nb;
   if (group_scale) *group_scale = best_g;
   return 0;

@@ -285,8 +285,10 @@ class Solver:
     def autotune(self, iters: int = 50) -> dict:
         nb, g = C.c_int32(), C.c_int32()
         _check(lib().pdhcg_autotune(self.h, iters, C.byref(nb), C.byref(g)))
+        threads = self.plan_info()["threads"]
         self.settings.num_blocks = nb.value
-        return {"num_blocks": nb.value, "group_scale": g.value}
+        self.settings.threads = threads
+        return {"num_blocks": nb.value, "group_scale": g.value, "threads": threads}
 
     def plan_info(self) -> dict:
         v = [C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32()]

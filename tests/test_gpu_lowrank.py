@@ -81,6 +81,18 @@ def test_random_lowrank_parity(precision):
     assert abs(r["cg_iters_total"] - re_["cg_iters_total"]) <= max(64, 0.02 * re_["cg_iters_total"])
 
 
+def test_lowrank_at_256_thread_workgroups():
+    """The low-rank products in the cooperative kernels compiled for
+    256-thread workgroups (forced; the planner keeps 512 for a low-rank Q)."""
+    say("[lowrank] n=2000 k=300 threads=256")
+    qp, P, d = I.lowrank_qp(n=2000, m=1000, k=300, p_density=0.01, a_density=0.005, instance=1)
+    ref = O.solve(qp, O.Settings(tol=1e-9, max_iters=400_000))
+    x, y, r = solve(qp, lowrank=(P, d), tol_rel_kkt=1e-6, precision=1, threads=256)
+    say(f"  iters={r['iters']} cg={r['cg_iters_total']}")
+    assert r["status"] == 0
+    contract(qp, x, y, ref, 1e-6)
+
+
 def test_zero_diagonal_full_row_rank():
     say("[lowrank] d = 0, n=60 k=90")
     qp, P, d = I.lowrank_qp(n=60, m=30, k=90, p_density=0.2, a_density=0.2, instance=2)

@@ -319,6 +319,7 @@ def test_autotune_then_solve():
     choice = sol.autotune(iters=20)
     say(f"  chose {choice}")
     assert choice["num_blocks"] in (64, 128, 256, 512) and choice["group_scale"] in (-1, 0, 1)
+    assert choice["threads"] in (256, 512) and sol.plan_info()["threads"] == choice["threads"]
     x, y, r = sol.solve()
     assert r["status"] == 0
     check_contract(qp, x.cpu().numpy(), y.cpu().numpy(), ref)
