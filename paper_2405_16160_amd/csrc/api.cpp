@@ -464,12 +464,12 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
 }
 
 // Threads per workgroup of the cooperative kernels: the setting, else 256
-// (two workgroups per CU, twice the gathers in flight per CU at twice the
-// arrivals per grid barrier) once the gathered vectors stream from the
-// last-level cache (16 n bytes beyond the L2 of one XCD, where the planner
-// also takes the textbook CG form), and 512 below that size or for a
-// low-rank Q.  (Power-law QP n = 2e6 to 1e-4: 606 ms against 654 ms;
-// random QP n = 1e5: 66.6 ms against 60.0 ms.)
+// (two workgroups per CU that wait apart, at twice the arrivals per grid
+// barrier) once the gathered vectors stream from the last-level cache (16 n
+// bytes beyond the L2 of one XCD, where the planner also takes the textbook
+// CG form), and 512 below that size or for a low-rank Q.  (Power-law QP
+// n = 2e6 to 1e-4: 606 ms against 654 ms; random QP n = 1e5: 66.6 ms against
+// 60.0 ms.)
 int solve_threads(const pdhcg_handle* h, const pdhcg_settings& s) {
   if (s.threads) return s.threads;
   return (!h->lowrank && 16 * h->n > h->l2_bytes) ? 256 : kSolveBlock;

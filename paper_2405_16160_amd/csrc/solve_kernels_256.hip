@@ -2,9 +2,10 @@
 // workgroups, two per CU (the device code of solver.hpp at that size, LDS
 // tiles of 2 048 entries).
 // The planner takes it for QPs whose gathered vectors stream from the
-// last-level cache (the textbook CG form's sizes): twice the workgroups keep
-// twice the gathers in flight per CU, at the cost of twice the arrivals at
-// every grid barrier.
+// last-level cache (the textbook CG form's sizes): a CU holds eight waves
+// either way, but two workgroups wait apart, so one's gathers stay in flight
+// while the other sums a tile or waits at a workgroup barrier, at the cost of
+// twice the arrivals at every grid barrier.
 #define PDHCG_BLOCK_SIZE 256
 #include "solver.hpp"
 
