@@ -120,7 +120,7 @@ typedef struct {
     int32_t threads;                 /* threads per workgroup of the single-QP solve and power
                                         kernels: 0 = planner's choice (256, two workgroups per CU,
                                         once the gathered vectors outgrow the L2 of one XCD,
-                                        16 n bytes, for a sparse Q; else 512, one per CU), 256
+                                        12 n bytes, for a sparse Q; else 512, one per CU), 256
                                         or 512.  Every setting computes the same iterates up to
                                         the order of the FP64 reductions (the row partitions
                                         follow the workgroup count) */

@@ -465,14 +465,14 @@ int plan_grid(pdhcg_handle* h, int nb, int gscale) {
 
 // Threads per workgroup of the cooperative kernels: the setting, else 256
 // (two workgroups per CU that wait apart, at twice the arrivals per grid
-// barrier) once the gathered vectors stream from the last-level cache (16 n
-// bytes beyond the L2 of one XCD, where the planner also takes the textbook
-// CG form), and 512 below that size or for a low-rank Q.  (Power-law QP
-// n = 2e6 to 1e-4: 606 ms against 654 ms; random QP n = 1e5: 66.6 ms against
-// 60.0 ms.)
+// barrier) once the gathered vectors stream from the last-level cache (the
+// textbook CG's FP32 (r, p) records and the FP32 x, 12 n bytes, beyond the
+// L2 of one XCD), and 512 below that size or for a low-rank Q.  Random QPs
+// to 1e-4, 512 against 256 threads: n = 3e5 160 ms / 167 ms, n = 6e5
+// 324 / 310 ms, n = 1e6 1 717 / 1 622 ms; power-law QP n = 2e6: 654 / 606 ms.
 int solve_threads(const pdhcg_handle* h, const pdhcg_settings& s) {
   if (s.threads) return s.threads;
-  return (!h->lowrank && 16 * h->n > h->l2_bytes) ? 256 : kSolveBlock;
+  return (!h->lowrank && 12 * h->n > h->l2_bytes) ? 256 : kSolveBlock;
 }
 
 // the co-resident workgroups of the cooperative kernels at h->threads

@@ -354,12 +354,12 @@ def test_256_thread_workgroups_long_rows():
 
 
 def test_planner_workgroup_size_and_switch():
-    """Past the L2 of one XCD (16 n bytes) the planner takes 256-thread
+    """Past the L2 of one XCD (12 n bytes) the planner takes 256-thread
     workgroups and up to twice the grid; switching to 512 threads through the
     settings re-plans the partitions, and both solves reach the tolerance on
     the FP64 data in nearly the same iterations with nearly the same x."""
-    say("[solve] random_qp n=300000 m=150000 planner threads, then 512")
-    qp = I.random_qp(300_000, 150_000, 150_000, 1e-5, 7e-5, family=2, instance=3)
+    say("[solve] random_qp n=600000 m=300000 planner threads, then 512")
+    qp = I.random_qp(600_000, 300_000, 300_000, 5e-6, 3.5e-5, family=2, instance=3)
     sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-5, precision=1))
     out = {}
     try:
@@ -380,6 +380,27 @@ def test_planner_workgroup_size_and_switch():
     assert i0["num_blocks"] > 256 >= i1["num_blocks"]
     assert abs(r0["iters"] - r1["iters"]) <= max(64, r1["iters"] // 10)
     assert np.linalg.norm(x0 - x1) / np.linalg.norm(x1) <= 1e-3
+
+
+def test_autotune_across_workgroup_sizes_large():
+    """The autotuner re-plans the partitions of a QP past one XCD's L2 for
+    every workgroup size and grid it times (up to 512 workgroups of 256
+    threads); the plan it keeps solves to the tolerance on the FP64 data."""
+    say("[autotune] random_qp n=300000 m=150000")
+    qp = I.random_qp(300_000, 150_000, 150_000, 1e-5, 7e-5, family=2, instance=3)
+    sol = pdhcg.Solver(qp, pdhcg.Settings(tol_rel_kkt=1e-5, precision=1))
+    try:
+        choice = sol.autotune(iters=10)
+        info = sol.plan_info()
+        say(f"  chose {choice}, plan {info}")
+        assert choice["threads"] in (256, 512) and info["threads"] == choice["threads"]
+        assert info["num_blocks"] == choice["num_blocks"] <= (512 if choice["threads"] == 256 else 256)
+        x, y, r = sol.solve()
+        say(f"  status={r['status_name']} iters={r['iters']}")
+        assert r["status"] == 0
+        assert O.kkt(qp, x.cpu().numpy(), y.cpu().numpy())["rel_kkt"] <= 1e-5 * (1 + 1e-6)
+    finally:
+        sol.close()
 
 
 # ----------------------------------------------- full-size power-law (2e6 x 1e6)
